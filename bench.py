@@ -1,0 +1,331 @@
+#!/usr/bin/env python3
+"""Throughput of the PPO learning hot path on one MI355X.
+
+One step = one learning iteration of the massively parallel set-up over a
+resident synthetic rollout of 4096 environments x 24 steps (the paper's
+Table 3 batch, B = 98304):
+  * policy inference + Philox action sampling for each of the 24 steps, and
+    the critic on the observation after the last step;
+  * GAE with time-out bootstrapping and float64 advantage statistics;
+  * the PPO update: 5 epochs x 4 mini-batches of 24576 (forward, loss,
+    hand-written backward, float64 global-norm clip, Adam), each epoch
+    replayed from a captured HIP graph.
+value = B / (time per step), in samples/s, bf16 GEMM operands with float32
+accumulation.  The float32 plain path is timed the same way for the speedup.
+Also reported: a roofline entry for the dominant kernel (HIP events around
+each launch of one eagerly launched epoch) and the FP64 CPU oracle timed on
+a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "PPO update samples/s at 4096 envs x 24 steps, BF16 vs FP32, at stated tol"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="flat")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the float32 plain-path timing")
+    ap.add_argument("--fp32-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+class Workload:
+    """Device-resident rollout storage, parameters and workspaces."""
+
+    def __init__(self, cfg, precision, device):
+        import torch
+        import paper_2109_11978_amd as ppo
+        import synth
+
+        self.cfg = cfg
+        net = cfg.net
+        self.ctx = ppo.Context(net.obs_dim, net.act_dim, net.hidden, precision)
+        T, N, D, A = cfg.n_steps, cfg.n_envs, net.obs_dim, net.act_dim
+        B, M = cfg.batch, cfg.minibatch
+        roll = synth.make_rollout(cfg, with_timeouts=True)
+        self.theta0 = synth.xavier_theta(net, seed=cfg.seed)
+        self.params = ppo.Params(self.ctx, self.theta0, lr=cfg.lr, device=device)
+        f32 = torch.float32
+        self.obs = torch.as_tensor(roll["obs"]).to(device)                  # [T, N, D]
+        self.last_obs = torch.as_tensor(roll["last_obs"]).to(device)        # [N, D]
+        self.rewards = torch.as_tensor(roll["rewards"]).to(device)
+        self.dones = torch.as_tensor(roll["dones"]).to(device)
+        self.timeouts = torch.as_tensor(roll["timeouts"]).to(device)
+        self.actions = torch.empty(T, N, A, dtype=f32, device=device)
+        self.logp = torch.empty(T, N, dtype=f32, device=device)
+        self.values = torch.empty(T, N, dtype=f32, device=device)
+        self.last_values = torch.empty(N, dtype=f32, device=device)
+        self.adv = torch.empty(T, N, dtype=f32, device=device)
+        self.returns = torch.empty(T, N, dtype=f32, device=device)
+        self.adv_stats = torch.empty(2, dtype=torch.float64, device=device)
+        self.perms = torch.as_tensor(synth.make_permutations(B, cfg.epochs, seed=cfg.seed)).to(device)
+        self.stats = torch.zeros(cfg.epochs, cfg.minibatches, ppo.PPO_STATS_WIDTH, dtype=f32, device=device)
+        self.ws = self.ctx.new_workspace(N=N, T=T, M=M, device=device)
+        self.hp = ppo.UpdateHParams(clip=cfg.clip, value_coef=cfg.value_coef, entropy_coef=cfg.entropy_coef,
+                                    max_grad_norm=cfg.max_grad_norm, use_graph=True)
+        self.batch = dict(obs=self.obs.view(B, D), actions=self.actions.view(B, A), logp=self.logp.view(B),
+                          adv=self.adv.view(B), returns=self.returns.view(B))
+        self.iteration = 0
+        self.ppo = ppo
+
+    def collect(self):
+        ppo, cfg = self.ppo, self.cfg
+        for t in range(cfg.n_steps):
+            ppo.ppo_rollout_infer(self.ctx, self.params, self.obs[t], t, cfg.seed, self.iteration,
+                                  actions=self.actions[t], logp=self.logp[t], values=self.values[t], ws=self.ws)
+        ppo.ppo_rollout_infer(self.ctx, self.params, self.last_obs, cfg.n_steps, cfg.seed, self.iteration,
+                              values=self.last_values, ws=self.ws)
+
+    def advantages(self):
+        self.ppo.ppo_gae(self.ctx, self.rewards, self.dones, self.values, self.last_values, self.cfg.gamma,
+                         self.cfg.lam, self.adv, self.returns, self.adv_stats, timeouts=self.timeouts,
+                         normalize=True, ws=self.ws)
+
+    def update(self):
+        for e in range(self.cfg.epochs):
+            self.ppo.ppo_update_epoch(self.ctx, self.params, self.batch, self.perms[e], self.cfg.minibatches,
+                                      self.hp, self.stats[e], self.ws)
+
+    def step(self):
+        self.collect()
+        self.advantages()
+        self.update()
+        self.iteration += 1
+
+
+def time_steps(wl, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        wl.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        wl.step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def time_parts(wl, reps=5):
+    """Wall time of collection, GAE and update separately (milliseconds)."""
+    import torch
+    out = {}
+    for name, fn in (("rollout_infer", wl.collect), ("gae", wl.advantages), ("update", wl.update)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) / reps * 1e3
+    return out
+
+
+def gemm_flops(cfg):
+    """Useful GEMM FLOPs per mini-batch step, by phase (both networks)."""
+    net, M = cfg.net, cfg.minibatch
+    dims = [net.obs_dim, *net.hidden]
+    fwd = sum(2 * M * dims[l] * dims[l + 1] for l in range(len(net.hidden))) * 2
+    dx = sum(2 * M * dims[l] * dims[l + 1] for l in range(1, len(net.hidden))) * 2
+    dw = fwd + 2 * M * net.hidden[-1] * (net.act_dim + 1)
+    return {"forward": fwd, "input_grad": dx, "weight_grad": dw}
+
+
+def roofline(wl, precision):
+    """Per-phase HIP-event durations of one eager epoch; roofline of the dominant kernel."""
+    import torch
+    cfg = wl.cfg
+    prof = wl.ppo.ppo_update_epoch_profiled(wl.ctx, wl.params, wl.batch, wl.perms[0], cfg.minibatches,
+                                            wl.hp, wl.stats[0], wl.ws)
+    torch.cuda.synchronize()
+    flops = gemm_flops(cfg)
+    P = wl.ctx.param_count
+    M, D = cfg.minibatch, cfg.net.obs_dim
+    esz = 2 if precision == "bf16" else 4
+    kpad = -(-D // 8) * 8
+    algo_bytes = {  # per mini-batch step
+        "adam": 30.0 * P if precision == "bf16" else 28.0 * P,
+        "gather": M * D * 4.0 + M * kpad * esz + M * 4.0,
+        "grad_reduce": 4.0 * P,
+    }
+    phases = {}
+    for name, (ms, launches) in prof.items():
+        if launches == 0:
+            continue
+        phases[name] = {"ms_per_epoch": round(ms, 4), "launches": launches,
+                        "us_per_launch": round(ms * 1e3 / launches, 2)}
+    dominant = max(phases, key=lambda k: phases[k]["ms_per_epoch"])
+    ms, launches = prof[dominant]
+    steps = cfg.minibatches
+    avg_s = ms / launches * 1e-3
+    if dominant in flops:
+        per_launch = flops[dominant] * steps / launches
+        achieved = per_launch / avg_s / 1e12
+        peak = MFMA_PEAK_TFLOPS[precision]
+        roof = {"kernel": dominant, "bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "algorithmic_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
+    else:
+        per_launch = algo_bytes.get(dominant, 0.0) * steps / launches
+        achieved = per_launch / avg_s / 1e9
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
+    # every GEMM phase, for context
+    gemm = {}
+    for name in flops:
+        if name in prof and prof[name][1]:
+            t = prof[name][0] * 1e-3
+            gemm[name] = round(flops[name] * steps / t / 1e12, 2)
+    return roof, phases, gemm
+
+
+def cpu_baseline(wl, precision):
+    """The FP64 oracle on a bounded sample of the same workload.
+
+    Sample: one policy step over all 4096 environments, GAE over the whole
+    [24, 4096] rollout, and one mini-batch step (loss, gradient, clip, Adam)
+    over 24576 samples.  The per-iteration time is assembled from those
+    (25 policy steps + 1 GAE + 20 mini-batch steps); value = B / that time.
+    The same mini-batch is also run through the HIP path at the same
+    parameters to report the gradient's distance to the oracle.
+    """
+    import torch
+    import oracle
+    from oracle.ppo import minibatch
+    cfg = wl.cfg
+    net = cfg.net
+    spec = oracle.NetSpec(net.obs_dim, net.act_dim, tuple(net.hidden))
+    theta = wl.params.theta.cpu().numpy().astype(np.float64)
+    obs = wl.obs.cpu().numpy()
+    T, N, B, M = cfg.n_steps, cfg.n_envs, cfg.batch, cfg.minibatch
+
+    t0 = time.perf_counter()
+    oracle.rollout_infer(theta, spec, obs[0], cfg.seed, 0, 0)
+    t_inf = time.perf_counter() - t0
+
+    rewards = wl.rewards.cpu().numpy()
+    dones = wl.dones.cpu().numpy()
+    timeouts = wl.timeouts.cpu().numpy()
+    values = wl.values.cpu().numpy()
+    last = wl.last_values.cpu().numpy()
+    t0 = time.perf_counter()
+    adv, ret = oracle.gae(rewards, values, dones, last, cfg.gamma, cfg.lam, timeouts=timeouts)
+    mean, std = oracle.advantage_stats(adv)
+    oracle.normalize_advantages(adv, mean, std)
+    t_gae = time.perf_counter() - t0
+
+    perm = wl.perms[0].cpu().numpy()
+    idx = perm[:M]
+    full = dict(obs=obs.reshape(B, -1), actions=wl.actions.cpu().numpy().reshape(B, -1),
+                logp_old=wl.logp.cpu().numpy().reshape(B), adv=wl.adv.cpu().numpy().reshape(B),
+                returns=wl.returns.cpu().numpy().reshape(B))
+    hp = oracle.PPOHyper(clip=cfg.clip, value_coef=cfg.value_coef, entropy_coef=cfg.entropy_coef,
+                         max_grad_norm=cfg.max_grad_norm, lr=cfg.lr)
+    P = theta.size
+    t0 = time.perf_counter()
+    res = oracle.ppo_loss_grad(theta, spec, minibatch(full, idx), hp)
+    c, _ = oracle.clip_coef(res["grad"], hp.max_grad_norm)
+    oracle.adam_step(theta, np.zeros(P), np.zeros(P), c * res["grad"], 0, hp)
+    t_mb = time.perf_counter() - t0
+
+    t_iter = (T + 1) * t_inf + t_gae + cfg.epochs * cfg.minibatches * t_mb
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:
+        threads = os.cpu_count()
+
+    # the same mini-batch through the HIP path at the same parameters
+    gstats = torch.zeros(wl.ppo.PPO_STATS_WIDTH, device=wl.params.theta.device)
+    grad = torch.zeros(P, device=wl.params.theta.device)
+    wl.ppo.ppo_loss_grad(wl.ctx, wl.params, wl.batch, wl.perms[0][:M].contiguous(), wl.hp, gstats, grad, wl.ws)
+    torch.cuda.synchronize()
+    g = grad.cpu().numpy().astype(np.float64)
+    r = res["grad"]
+    normwise = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+    return {"value": round(B / t_iter, 1), "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle: 1 policy step over {N} envs ({t_inf:.3f} s), GAE over "
+                       f"[{T},{N}] ({t_gae:.3f} s), 1 mini-batch step of {M} samples ({t_mb:.2f} s); "
+                       f"iteration time assembled as {T + 1} policy steps + GAE + "
+                       f"{cfg.epochs * cfg.minibatches} mini-batch steps = {t_iter:.1f} s"),
+            "host_cpus": os.cpu_count(),
+            "gpu_grad_vs_oracle_normwise": normwise}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    import synth
+    cfg = synth.get_config(args.config)
+    dev = torch.device("cuda")
+
+    wl = Workload(cfg, "bf16", dev)
+    s_step = time_steps(wl, args.steps, args.warmup)
+    parts = time_parts(wl)
+    roof, phases, gemm_tflops = roofline(wl, "bf16")
+    B = cfg.batch
+    out = {
+        "metric": METRIC,
+        "value": round(B / s_step, 1),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(s_step * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "n_envs": cfg.n_envs, "n_steps": cfg.n_steps, "batch": B,
+                   "obs_dim": cfg.net.obs_dim, "act_dim": cfg.net.act_dim, "hidden": list(cfg.net.hidden),
+                   "epochs": cfg.epochs, "minibatches": cfg.minibatches, "minibatch": cfg.minibatch},
+        "update_samples_per_s": round(B / (parts["update"] * 1e-3), 1),
+        "breakdown_ms": {k: round(v, 3) for k, v in parts.items()},
+        "roofline": roof,
+        "phases_bf16": phases,
+        "gemm_tflops_bf16": gemm_tflops,
+    }
+    if not args.no_fp32:
+        wl32 = Workload(cfg, "fp32", dev)
+        s32 = time_steps(wl32, args.fp32_steps, 1)
+        parts32 = time_parts(wl32, reps=2)
+        _, phases32, gemm32 = roofline(wl32, "fp32")
+        out["fp32_plain"] = {"value": round(B / s32, 1), "ms_per_step": round(s32 * 1e3, 3),
+                             "update_samples_per_s": round(B / (parts32["update"] * 1e-3), 1),
+                             "breakdown_ms": {k: round(v, 3) for k, v in parts32.items()},
+                             "gemm_tflops_fp32": gemm32}
+        out["bf16_speedup_vs_fp32"] = round(s32 / s_step, 2)
+        out["bf16_update_speedup_vs_fp32"] = round(parts32["update"] / parts["update"], 2)
+        del wl32
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, "bf16")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

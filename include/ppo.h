@@ -1,0 +1,251 @@
+/*
+ * ppo.h -- C ABI of the MI355X (gfx950) learning hot path of massively
+ * parallel PPO (Rudin, Hoeller, Reist and Hutter, "Learning to Walk in
+ * Minutes Using Massively Parallel Deep Reinforcement Learning", CoRL 2021).
+ *
+ * The paper keeps the whole on-policy loop on one GPU (Section 2: data
+ * collection and policy update both on the device; Section 2.2: a custom PPO
+ * that stores every tensor on the GPU).  This library implements the learner
+ * half of that loop as hand-written HIP kernels:
+ *   - ppo_rollout_infer : actor-critic inference for every environment plus
+ *                         diagonal-Gaussian action sampling (Philox4x32-10);
+ *   - ppo_gae           : GAE over a [T, N] rollout with time-out
+ *                         bootstrapping (Sections 2.2.1 and 2.2.2) and the
+ *                         batch advantage statistics;
+ *   - ppo_update_epoch  : one PPO epoch of K mini-batch steps (clipped
+ *                         surrogate, value loss, entropy bonus, global
+ *                         gradient-norm clip, Adam) (Section 2.2.1,
+ *                         Appendix A.4 Table 3).
+ *
+ * Conventions shared by every entry point
+ *   - Return value: PPO_OK (0) or a negative PPO_E_* code.  On error,
+ *     ppo_last_error() returns a thread-local message.  No C++ exception
+ *     crosses this boundary.
+ *   - All arguments are validated on the host BEFORE anything is enqueued;
+ *     a call that returns an error has enqueued nothing.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call is asynchronous on that stream and never synchronises the
+ *     host, except ppo_ctx_create/destroy.
+ *   - Ownership: the caller allocates and owns all device memory (rollout
+ *     buffers, parameters, optimiser state, statistics, workspace) and keeps
+ *     it alive until the enqueued work has completed.  The library never
+ *     allocates device memory; a context owns host-side state only (network
+ *     shape, precision, tile choices, cached HIP graphs).
+ *   - Pointers to device memory must be 16-byte aligned; arrays are dense
+ *     (no strides) in the layouts given below.
+ *   - Sample index s = t * N + n over a rollout (time-major, environment
+ *     contiguous).
+ */
+#ifndef PPO_MI355X_PPO_H
+#define PPO_MI355X_PPO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PPO_OK             0
+#define PPO_E_INVAL       -1  /* NULL or misaligned pointer, bad enum value   */
+#define PPO_E_SHAPE       -2  /* dimension out of range or inconsistent       */
+#define PPO_E_UNSUPPORTED -3  /* device is not gfx950 / precision not built   */
+#define PPO_E_HIP         -4  /* HIP runtime, launch or graph error           */
+#define PPO_E_NOMEM       -5  /* caller's workspace smaller than required     */
+
+/* ---- precision of the GEMM operands ------------------------------------ */
+#define PPO_FP32 0  /* all arithmetic in float32 (the plain path)              */
+#define PPO_BF16 1  /* bf16 GEMM operands, float32 accumulation; float32
+                       master weights, Adam state, heads, log-prob and loss    */
+
+/* ---- limits ------------------------------------------------------------- */
+#define PPO_MAX_HIDDEN   4      /* hidden layers per network                 */
+#define PPO_MAX_WIDTH    2048   /* hidden width (multiple of 16)             */
+#define PPO_MAX_OBS      4096   /* observation dimension                     */
+#define PPO_MAX_ACT      16     /* action dimension                          */
+#define PPO_MAX_T        4096   /* rollout horizon                           */
+#define PPO_STATS_WIDTH  8      /* floats per mini-batch statistics row      */
+
+/* Statistics row written per mini-batch step (floats):
+ *   [0] total loss L = L_pi + c_v L_V - c_e H
+ *   [1] policy loss L_pi      [2] value loss L_V      [3] entropy H
+ *   [4] clip fraction (|rho - 1| > clip)
+ *   [5] approximate KL, mean((rho - 1) - log rho)
+ *   [6] global gradient norm before clipping (accumulated in float64)
+ *   [7] flags: bit 0 = non-finite gradient norm (the Adam step was skipped)
+ */
+
+/* Network shape.  Actor: obs_dim -> hidden[0] -> ... -> act_dim; critic:
+ * obs_dim -> hidden[0] -> ... -> 1.  ELU (alpha = 1) on hidden layers,
+ * linear outputs, a state-independent log standard deviation per action.
+ * The paper fixes none of this (Sections 2.2 and 3.2 name a policy and a
+ * critic only); these are the project's workload definitions. */
+typedef struct ppo_net_desc {
+    int32_t obs_dim;                  /* D, 1..PPO_MAX_OBS                   */
+    int32_t act_dim;                  /* A, 1..PPO_MAX_ACT                   */
+    int32_t n_hidden;                 /* L, 1..PPO_MAX_HIDDEN                */
+    int32_t hidden[PPO_MAX_HIDDEN];   /* widths, multiples of 16, <= 2048    */
+} ppo_net_desc;
+
+/* Flat parameter vector (float32, P entries): actor W1, b1, ..., W_{L+1},
+ * b_{L+1}, actor log-std [A], then critic W1, b1, ..., W_{L+1}, b_{L+1}.
+ * Every W is row-major [out, in]. */
+typedef struct ppo_params {
+    float    *theta;   /* [P] float32 master weights                          */
+    float    *grad;    /* [P] raw (pre-clip) gradient of the latest step      */
+    float    *adam_m;  /* [P] Adam first moment                               */
+    float    *adam_v;  /* [P] Adam second moment                              */
+    uint16_t *shadow;  /* [P] bf16 copy of theta (round to nearest even);
+                          required for PPO_BF16, ignored for PPO_FP32         */
+    int32_t  *step;    /* device scalar: Adam steps taken so far              */
+    float    *lr;      /* device scalar: learning rate                        */
+} ppo_params;
+
+/* One rollout batch flattened over samples (B = T * N). */
+typedef struct ppo_batch {
+    const float *obs;      /* [B, D]                                          */
+    const float *actions;  /* [B, A]                                          */
+    const float *logp;     /* [B] log-probabilities at collection time        */
+    const float *adv;      /* [B] normalised advantages                       */
+    const float *returns;  /* [B] returns R = A + V (un-normalised A)         */
+    const float *values;   /* [B] values at collection (value clipping only;
+                              may be NULL when clip_value == 0)               */
+    int32_t B;
+} ppo_batch;
+
+/* Update hyper-parameters (Appendix A.4 Table 3 gives clip 0.2, entropy
+ * coefficient 0.01, 5 epochs; the rest are the project's settings). */
+typedef struct ppo_hparams {
+    float   clip;           /* surrogate (and value) clip range, > 0          */
+    float   value_coef;     /* c_v >= 0                                       */
+    float   entropy_coef;   /* c_e >= 0                                       */
+    float   max_grad_norm;  /* > 0                                            */
+    float   beta1, beta2;   /* Adam, in [0, 1)                                */
+    float   adam_eps;       /* > 0, added outside the square root             */
+    int32_t clip_value;     /* 0/1: clipped value loss (needs batch.values)   */
+    int32_t use_graph;      /* 0/1: capture the epoch into a HIP graph and
+                               replay it (cached per pointer/shape set)       */
+} ppo_hparams;
+
+typedef struct ppo_ctx ppo_ctx;
+
+/* Thread-local message of the last error on this thread ("" if none). */
+const char *ppo_last_error(void);
+
+/* Creates a context for one network shape and precision.  Checks the shape
+ * (PPO_E_SHAPE) and precision (PPO_E_INVAL).  Does not touch the GPU. */
+int ppo_ctx_create(const ppo_net_desc *net, int32_t precision, ppo_ctx **out);
+
+/* Destroys the context and its cached graphs.  Synchronises nothing; the
+ * caller must have completed work that used the context's graphs. */
+int ppo_ctx_destroy(ppo_ctx *ctx);
+
+/* Number of float32 parameters P of the flat vector. */
+int ppo_param_count(const ppo_net_desc *net, int64_t *count);
+
+/* Offsets of every tensor in the flat vector, in the order given above:
+ * 2 (L + 1) actor entries, 1 log-std entry, 2 (L + 1) critic entries.
+ * `capacity` is the length of `offsets`; PPO_E_SHAPE if it is too small. */
+int ppo_param_offsets(const ppo_net_desc *net, int64_t *offsets, int32_t capacity);
+
+/* Bytes of device workspace the calls below need for N environments per
+ * rollout step, T steps and mini-batch size M.  One workspace of this size
+ * serves ppo_rollout_infer (N rows), ppo_gae (T x N) and
+ * ppo_update_epoch / ppo_loss_grad (M rows). */
+int ppo_workspace_size(const ppo_ctx *ctx, int32_t N, int32_t T, int32_t M, size_t *bytes);
+
+/* Rounds theta to bf16 (round to nearest even) into `shadow` [P].  Needed
+ * once after theta is written by anything other than ppo_update_epoch. */
+int ppo_pack_weights(const ppo_ctx *ctx, void *stream, const float *theta, uint16_t *shadow);
+
+/* Policy inference for one rollout step (Section 2: policy inference for
+ * every robot on the GPU).  obs [N, D] float32.  Writes, when non-NULL:
+ * actions [N, A] = mu + sigma * eps, logp [N] (log-density of the action),
+ * values [N] (critic), mu [N, A].  eps is drawn from Philox4x32-10 with key
+ * (seed mod 2^32, seed >> 32) and counter (n * ceil(A/4) + g, t, iteration,
+ * 1) for action group g; uniforms ((x >> 9) + 1/2) 2^-23; Box-Muller pairs.
+ * With actions == NULL only the critic runs (value-only mode, e.g. for the
+ * bootstrap values of the observation after the last step); values must be
+ * non-NULL.  `ws` must hold ppo_workspace_size(ctx, N, *, *) bytes. */
+int ppo_rollout_infer(const ppo_ctx *ctx, void *stream, const ppo_params *p,
+                      const float *obs, int32_t N, int32_t t, uint64_t seed,
+                      uint32_t iteration, float *actions, float *logp,
+                      float *values, float *mu, void *ws, size_t ws_bytes);
+
+/* GAE over a [T, N] rollout (Section 2.2.1; time-out bootstrap of Section
+ * 2.2.2 read as r'_t = r_t + gamma V_t timeout_t).  rewards, values [T, N]
+ * float32; dones, timeouts [T, N] uint8 (timeouts may be NULL; a time-out
+ * must also be a done); last_values [N].  Writes returns [T, N] = A + V,
+ * adv_stats[2] = (mean, unbiased std) of A in float64, and adv [T, N]: the
+ * raw advantages, or (A - mean) / (std + 1e-8) when normalize != 0.
+ * T in 1..PPO_MAX_T, T * N >= 2. */
+int ppo_gae(const ppo_ctx *ctx, void *stream, const float *rewards, const uint8_t *dones,
+            const uint8_t *timeouts, const float *values, const float *last_values,
+            int32_t T, int32_t N, float gamma, float lam, float *adv, float *returns,
+            double *adv_stats, int32_t normalize, void *ws, size_t ws_bytes);
+
+/* One PPO epoch: for k in 0..K-1 the mini-batch perm[k M : (k+1) M]
+ * (M = B / K) goes through forward, loss, hand-written backward, global
+ * norm clip and Adam (step count and lr read from p->step / p->lr; step is
+ * advanced by K).  perm [B] int32 is a permutation of [0, B) chosen by the
+ * caller.  stats [K, PPO_STATS_WIDTH] float32.  p->grad holds the raw
+ * gradient of the last step afterwards.  B % K must be 0. */
+int ppo_update_epoch(ppo_ctx *ctx, void *stream, const ppo_params *p, const ppo_batch *b,
+                     const int32_t *perm, int32_t n_minibatches, const ppo_hparams *hp,
+                     float *stats, void *ws, size_t ws_bytes);
+
+/* Loss and gradient of one mini-batch (rows idx[0..M)) without an optimiser
+ * step: writes stats[PPO_STATS_WIDTH] (entry 6 = gradient norm, entry 7 =
+ * flags) and grad_out [P] (the raw gradient).  Used by the autograd wrapper
+ * and gradient checks. */
+int ppo_loss_grad(const ppo_ctx *ctx, void *stream, const ppo_params *p, const ppo_batch *b,
+                  const int32_t *idx, int32_t M, const ppo_hparams *hp, float *stats,
+                  float *grad_out, void *ws, size_t ws_bytes);
+
+/* Kernel phases of one mini-batch step, in launch order. */
+#define PPO_PHASE_GATHER       0  /* mini-batch rows of obs -> GEMM operand     */
+#define PPO_PHASE_FORWARD      1  /* hidden-layer GEMMs + bias + ELU (L launches) */
+#define PPO_PHASE_HEAD_LOSS    2  /* output layers, PPO loss, output gradients  */
+#define PPO_PHASE_INPUT_GRAD   3  /* dz W times ELU' GEMMs (L - 1 launches)     */
+#define PPO_PHASE_WEIGHT_GRAD  4  /* split-sample weight-gradient GEMMs         */
+#define PPO_PHASE_GRAD_REDUCE  5  /* split sums, flat gradient, float64 norm^2  */
+#define PPO_PHASE_ADAM         6  /* clip coefficient + Adam + bf16 shadow      */
+#define PPO_N_PHASES           7
+
+/* Same computation as ppo_update_epoch, launched eagerly with a HIP event
+ * pair recorded on `stream` around every kernel launch.  Synchronises the
+ * stream before returning, then writes phase_ms[PPO_N_PHASES] (summed
+ * event-measured milliseconds per phase over the epoch) and
+ * phase_launches[PPO_N_PHASES] (launch counts).  For measurement only. */
+int ppo_update_epoch_profiled(ppo_ctx *ctx, void *stream, const ppo_params *p, const ppo_batch *b,
+                              const int32_t *perm, int32_t n_minibatches, const ppo_hparams *hp,
+                              float *stats, void *ws, size_t ws_bytes, float *phase_ms,
+                              int32_t *phase_launches);
+
+/* Verification: one launch of the library's GEMM kernel on caller data.
+ * C[M, N] = A[M, K] B[N, K]^T with float32 accumulation; operands are float32
+ * (PPO_FP32) or bf16 bit patterns (PPO_BF16).  a_mode / b_mode: 0 = row-major
+ * [rows, K], 1 = stored transposed [K, rows].  Supported combinations:
+ *   (0, 0, epilogue 0): C = ELU(acc + bias[n])              (C in operand type)
+ *   (0, 1, epilogue 1): C = acc * ELU'(z), with h = ELU(z) read from H[M, ldh]
+ *   (1, 1, epilogue 2): C[s, M, ldc] float32 partial sums over `splits` slices
+ *                       of K, rowsum[s, M] = per-slice row sums of A.
+ * The number of slices actually used is ceil(K / kps), kps = ceil(K / splits)
+ * rounded up to the kernel's k-slab. */
+int ppo_gemm_check(void *stream, int32_t precision, int32_t a_mode, int32_t b_mode, int32_t epilogue,
+                   int32_t M, int32_t N, int32_t K, const void *A, int32_t lda, const void *B,
+                   int32_t ldb, void *C, int32_t ldc, const float *bias, const void *H, int32_t ldh,
+                   float *rowsum, int32_t splits);
+
+/* Debug/verification: raw Philox4x32-10 blocks.  out[4 i + w] = word w of
+ * Philox(counter = (c0_base + i mod 2^32, c1, c2, c3), key = (seed mod 2^32,
+ * seed >> 32)) for i in [0, n).  n in 1..2^28. */
+int ppo_philox_blocks(void *stream, uint64_t seed, uint32_t c0_base, uint32_t c1, uint32_t c2,
+                      uint32_t c3, int64_t n, uint32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPO_MI355X_PPO_H */

@@ -1,0 +1,186 @@
+// Internal declarations shared by the HIP kernels and the host runtime of the
+// PPO learner library.  Nothing here is part of the public ABI (include/ppo.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ppo {
+
+constexpr int kMaxHidden = 4;
+constexpr int kMaxLayers = kMaxHidden + 1;
+constexpr int kStatsWidth = 8;
+constexpr int kHeadPad = 16;        // output-layer gradient rows padded to 16 columns
+constexpr int kGemmMaxProblems = 8;
+
+enum Precision { kFP32 = 0, kBF16 = 1 };
+
+// ---------------------------------------------------------------- bf16 ----
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+    union { uint32_t u; float f; } v;
+    v.u = static_cast<uint32_t>(h) << 16;
+    return v.f;
+}
+
+// Round to nearest, ties to even; NaN stays NaN (quiet bit set).
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    union { uint32_t u; float f; } v;
+    v.f = f;
+    if ((v.u & 0x7F800000u) == 0x7F800000u && (v.u & 0x007FFFFFu))
+        return static_cast<uint16_t>((v.u >> 16) | 0x0040u);
+    uint32_t lsb = (v.u >> 16) & 1u;
+    return static_cast<uint16_t>((v.u + 0x7FFFu + lsb) >> 16);
+}
+
+template <typename T> struct Elem;
+template <> struct Elem<float> {
+    __device__ static inline float load(const float *p, long long i) { return p[i]; }
+    __device__ static inline float to_f(float x) { return x; }
+    __device__ static inline float from_f(float x) { return x; }
+};
+template <> struct Elem<uint16_t> {
+    __device__ static inline float load(const uint16_t *p, long long i) { return bf16_to_f32(p[i]); }
+    __device__ static inline float to_f(uint16_t x) { return bf16_to_f32(x); }
+    __device__ static inline uint16_t from_f(float x) { return f32_to_bf16(x); }
+};
+
+// -------------------------------------------------------------- GEMMs -----
+// C[M, N] = A[M, K] * B[N, K]^T (float32 accumulation) with a fused epilogue.
+// Operand modes: 0 = row-major [rows, K] (K contiguous);
+//                1 = stored transposed, [K, rows] (rows contiguous).
+enum GemmEpilogue {
+    kEpiBiasElu = 0,   // C(T) = ELU(acc + bias[n])
+    kEpiDElu = 1,      // C(T) = acc * ELU'(z), with ELU'(z) recovered from h = ELU(z) in H
+    kEpiPartial = 2,   // C(float) partial sums of split s at C + s * c_split_stride;
+                       // rowsum[s * M + m] = sum_k A[m, k] over the split (bias gradient)
+};
+
+struct GemmProblem {
+    const void *A;
+    const void *B;
+    void *C;
+    const float *bias;
+    const void *H;
+    float *rowsum;
+    long long c_split_stride;
+    int M, N, K;
+    int lda, ldb, ldc, ldh;
+    int tiles_m, tiles_n, splits, kps;
+    int tile_begin;
+};
+
+struct GemmArgs {
+    GemmProblem p[kGemmMaxProblems];
+    int count;
+    int total_tiles;
+};
+
+// Tile geometry shared with the host planner.
+template <typename T> struct GemmTile;
+template <> struct GemmTile<uint16_t> { static constexpr int BM = 128, BN = 128, BK = 64; };
+template <> struct GemmTile<float> { static constexpr int BM = 128, BN = 128, BK = 32; };
+
+hipError_t launch_gemm(Precision prec, int a_mode, int b_mode, int epi, const GemmArgs &args,
+                       hipStream_t stream);
+
+// -------------------------------------------------------- other kernels ---
+hipError_t launch_philox_blocks(hipStream_t s, uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                                uint32_t c3, long long n, uint32_t *out);
+
+// Rows of obs (gathered by idx when non-null) converted to T, zero-padded to ld.
+// Indices are clamped to [0, src_rows).
+hipError_t launch_gather_obs(Precision prec, hipStream_t s, const float *obs, const int32_t *idx,
+                             int src_rows, int rows, int D, int ld, void *out);
+
+struct HeadSampleArgs {
+    const void *ha;      // actor last hidden [N, Hl] (T)
+    const void *hc;      // critic last hidden [N, Hl] (T)
+    const float *Wa;     // [A, Hl]
+    const float *ba;     // [A]
+    const float *logstd; // [A]
+    const float *Wc;     // [1, Hl]
+    const float *bc;     // [1]
+    float *actions, *logp, *values, *mu;
+    int N, A, Hl;
+    uint32_t key0, key1, t, iteration;
+    int value_only;
+};
+hipError_t launch_head_sample(Precision prec, const HeadSampleArgs &a, hipStream_t s);
+
+struct HeadLossArgs {
+    const void *ha, *hc;           // last hidden [M, Hl] (T)
+    const float *Wa, *ba, *logstd, *Wc, *bc;
+    const float *actions, *logp_old, *adv, *returns, *values_old;  // full batch, indexed by idx
+    const int32_t *idx;            // [M] rows of the batch, clamped to [0, B)
+    int B;
+    void *dza, *dzc;               // [M, Hl] (T): gradient wrt the last hidden pre-activations
+    void *dz_head_a, *dz_head_c;   // [M, kHeadPad] (T): gradient wrt the output layer
+    float *partials;               // [blocks, A + 8]; row 0, column 4 + A holds the entropy
+    int M, A, Hl;
+    float clip, value_coef, inv_m;
+    int clip_value;
+};
+int head_loss_blocks(int M);
+int head_loss_partial_width(int A);
+hipError_t launch_head_loss(Precision prec, const HeadLossArgs &a, hipStream_t s);
+
+struct GaeArgs {
+    const float *rewards, *values, *last_values;
+    const uint8_t *dones, *timeouts;
+    float *adv, *returns;
+    double *partials;   // [blocks, 3]: count, mean, M2
+    int T, N;
+    float gamma, lam;
+};
+int gae_blocks(int N);
+hipError_t launch_gae(const GaeArgs &a, hipStream_t s);
+hipError_t launch_adv_finalize(const double *partials, int nparts, float *adv, long long count,
+                               double *stats_out, int normalize, hipStream_t s);
+
+// Gradient assembly: sum split-K partials per segment into the flat gradient,
+// and per-block float64 sums of squares.
+struct ReduceSegment {
+    const float *src;         // partial s, row r, col c at src + s * split_stride + r * ld + c
+    long long split_stride;
+    int splits, rows, cols, ld;
+    long long dst_offset;     // into the flat gradient
+    long long begin;          // first global element index of this segment
+    float add;                // constant added after the split sum
+};
+constexpr int kMaxSegments = 24;
+struct ReduceArgs {
+    ReduceSegment seg[kMaxSegments];
+    int count;
+    long long total;
+    float *grad;
+    double *sumsq_partials;   // [blocks]
+    // loss partials of the head/loss kernel, reduced by the last block
+    const float *loss_partials;  // [n_loss, loss_width]
+    int n_loss, loss_width, A;
+    long long logstd_offset;
+    float entropy_coef;
+    float *loss_sums;            // [8]: policy, value, clipped count, kl sums; entropy
+};
+int reduce_blocks(long long total);  // includes the loss-partial block
+hipError_t launch_grad_reduce(const ReduceArgs &a, hipStream_t s);
+
+struct AdamArgs {
+    float *theta, *grad, *m, *v;
+    uint16_t *shadow;          // may be null
+    const int32_t *step;       // steps already taken before this epoch
+    int step_offset;           // this launch is step (*step + step_offset + 1)
+    const float *lr;
+    const double *sumsq_partials;
+    int n_sumsq;
+    const float *loss_sums;      // [8], written by the gradient reduction
+    float max_grad_norm, beta1, beta2, eps, inv_m, value_coef, entropy_coef;
+    float *stats;                // [kStatsWidth]
+    long long P;
+    int apply;                   // 0: only statistics (loss/grad without an optimiser step)
+};
+int adam_blocks(long long P);
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
+hipError_t launch_step_advance(int32_t *step, int k, hipStream_t s);
+hipError_t launch_pack_bf16(const float *theta, uint16_t *shadow, long long n, hipStream_t s);
+
+}  // namespace ppo

@@ -1,0 +1,411 @@
+// MFMA GEMMs of the actor-critic MLPs for gfx950 (CDNA4).
+//
+// C[M, N] = A[M, K] * B[N, K]^T with float32 accumulation, for every layer of
+// the forward pass (z = h W^T + b, then ELU), the input-gradient chain
+// (dh = dz W, times ELU'), and the weight gradients (dW = dz^T h, split over
+// the sample dimension).  Several independent problems (actor and critic, or
+// all layers of both) share one launch: blockIdx.x is mapped to a
+// (problem, split, tile) triple through the prefix sums in GemmArgs.
+//
+// Work decomposition: 256 threads = 4 wave64s per 128 x 128 tile, 2 x 2 waves
+// of 64 x 64, each wave 2 x 2 MFMA blocks of 32 x 32.  bf16 operands use
+// v_mfma_f32_32x32x16_bf16; float32 operands use four v_mfma_f32_32x32x2_f32
+// per 8-wide k chunk.  Tiles are staged in LDS with K contiguous and a 16-byte
+// row pad (conflict-free 16-byte reads for 16 consecutive rows); the next
+// k-slab is fetched into registers while the current one is multiplied (two
+// LDS buffers, one barrier per slab).  Operands stored transposed in memory
+// (the sample-major activations used by dW) are transposed in registers, one
+// 16-byte vector per row of an 8 x 8 (bf16) or 4 x 4 (float32) block.
+#include "common.hpp"
+
+namespace ppo {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kThreads = 256;
+
+template <typename T> struct Mma;
+
+template <> struct Mma<uint16_t> {
+    // One 16-byte vector per lane = 8 consecutive k of one row: a full
+    // 32x32x16 MFMA (lane l holds row l % 32, k = 8 (l / 32) .. + 7).
+    __device__ static inline void mac(floatx16 &acc, const u32x4 &a, const u32x4 &b) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                       __builtin_bit_cast(bf16x8_t, b), acc, 0, 0, 0);
+    }
+};
+
+template <> struct Mma<float> {
+    // One 16-byte vector per lane = 4 consecutive k.  MFMA e (0..3) pairs
+    // lane-half 0's element e with lane-half 1's element e, i.e. k = e and
+    // k = 4 + e of the 8-wide chunk; A and B use the same pairing.
+    __device__ static inline void mac(floatx16 &acc, const u32x4 &a, const u32x4 &b) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+    }
+};
+
+template <typename T> __device__ inline uint32_t raw_bits(T v);
+template <> __device__ inline uint32_t raw_bits<float>(float v) { return __float_as_uint(v); }
+template <> __device__ inline uint32_t raw_bits<uint16_t>(uint16_t v) { return v; }
+
+// Output-side arithmetic: float32 outputs keep expm1 (the float32 path is
+// held to float32 accuracy); bf16 outputs use the hardware exponential and
+// the hardware round-to-nearest-even conversion, whose errors are far below
+// one bf16 ulp.
+template <typename T> struct Act;
+template <> struct Act<float> {
+    __device__ static inline float elu(float v) { return v > 0.0f ? v : expm1f(v); }
+    __device__ static inline float store(float v) { return v; }
+};
+template <> struct Act<uint16_t> {
+    __device__ static inline float elu(float v) { return v > 0.0f ? v : __expf(v) - 1.0f; }
+    __device__ static inline uint16_t store(float v) { return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v)); }
+};
+
+// Pack VEC scalars (zero where invalid) into a 16-byte vector.
+template <typename T, int VEC>
+__device__ inline u32x4 pack_elems(const T (&e)[VEC]) {
+    u32x4 r;
+    if constexpr (sizeof(T) == 4) {
+        r.x = raw_bits<T>(e[0]); r.y = raw_bits<T>(e[1]); r.z = raw_bits<T>(e[2]); r.w = raw_bits<T>(e[3]);
+    } else {
+        r.x = raw_bits<T>(e[0]) | (raw_bits<T>(e[1]) << 16);
+        r.y = raw_bits<T>(e[2]) | (raw_bits<T>(e[3]) << 16);
+        r.z = raw_bits<T>(e[4]) | (raw_bits<T>(e[5]) << 16);
+        r.w = raw_bits<T>(e[6]) | (raw_bits<T>(e[7]) << 16);
+    }
+    return r;
+}
+
+// Row-major operand: element (r, k) at src[r * ld + k]; zero outside
+// r < R, k < kend.
+template <typename T>
+__device__ inline u32x4 load_rowmajor(const T *src, int ld, int r, int k, int R, int kend, bool vec_ok) {
+    constexpr int VEC = 16 / sizeof(T);
+    if (r < R && k + VEC <= kend && vec_ok)
+        return *reinterpret_cast<const u32x4 *>(src + static_cast<long long>(r) * ld + k);
+    T e[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+        e[i] = (r < R && k + i < kend) ? src[static_cast<long long>(r) * ld + k + i] : T(0);
+    return pack_elems<T, VEC>(e);
+}
+
+// Transposed operand: element (r, k) at src[k * ld + r]; loads VEC
+// consecutive r for one k.
+template <typename T>
+__device__ inline u32x4 load_transposed(const T *src, int ld, int r, int k, int R, int kend, bool vec_ok) {
+    constexpr int VEC = 16 / sizeof(T);
+    if (k < kend && r + VEC <= R && vec_ok)
+        return *reinterpret_cast<const u32x4 *>(src + static_cast<long long>(k) * ld + r);
+    T e[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+        e[i] = (k < kend && r + i < R) ? src[static_cast<long long>(k) * ld + r + i] : T(0);
+    return pack_elems<T, VEC>(e);
+}
+
+// in[e] holds VEC elements along r for k = e; returns the VEC elements along
+// k for r = i.
+template <typename T>
+__device__ inline u32x4 transpose_col(const u32x4 *in, int i) {
+    u32x4 o;
+    if constexpr (sizeof(T) == 4) {
+        o.x = in[0][i]; o.y = in[1][i]; o.z = in[2][i]; o.w = in[3][i];
+    } else {
+        const int w = i >> 1;
+        if (i & 1) {
+            o.x = (in[0][w] >> 16) | (in[1][w] & 0xFFFF0000u);
+            o.y = (in[2][w] >> 16) | (in[3][w] & 0xFFFF0000u);
+            o.z = (in[4][w] >> 16) | (in[5][w] & 0xFFFF0000u);
+            o.w = (in[6][w] >> 16) | (in[7][w] & 0xFFFF0000u);
+        } else {
+            o.x = (in[0][w] & 0xFFFFu) | (in[1][w] << 16);
+            o.y = (in[2][w] & 0xFFFFu) | (in[3][w] << 16);
+            o.z = (in[4][w] & 0xFFFFu) | (in[5][w] << 16);
+            o.w = (in[6][w] & 0xFFFFu) | (in[7][w] << 16);
+        }
+    }
+    return o;
+}
+
+template <typename T, int MODE, int ROWS, int BK>
+struct TileLoader {
+    static constexpr int VEC = 16 / sizeof(T);
+    static constexpr int PITCH = BK + VEC;
+    // MODE 0: units are 16-byte vectors along k; MODE 1: VEC x VEC blocks.
+    static constexpr int UNITS = MODE == 0 ? ROWS * BK / VEC : (ROWS / VEC) * (BK / VEC);
+    static constexpr int NT = UNITS < kThreads ? UNITS : kThreads;
+    static constexpr int PER = UNITS / NT;
+    static constexpr int REGS = MODE == 0 ? PER : PER * VEC;
+    static_assert(UNITS % NT == 0, "tile units must divide evenly");
+    u32x4 r[REGS];
+
+    __device__ inline void load(const T *src, int ld, int R, int r0, int k0, int kend, int t, bool vec_ok) {
+        if (t < 0 || t >= NT) return;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int u = t + p * NT;
+            if constexpr (MODE == 0) {
+                const int row = u / (BK / VEC);
+                const int kv = (u % (BK / VEC)) * VEC;
+                r[p] = load_rowmajor<T>(src, ld, r0 + row, k0 + kv, R, kend, vec_ok);
+            } else {
+                const int rb = u % (ROWS / VEC);
+                const int kb = u / (ROWS / VEC);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    r[p * VEC + e] = load_transposed<T>(src, ld, r0 + rb * VEC, k0 + kb * VEC + e, R, kend, vec_ok);
+            }
+        }
+    }
+
+    __device__ inline void store(T *lds, int t) const {
+        if (t < 0 || t >= NT) return;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int u = t + p * NT;
+            if constexpr (MODE == 0) {
+                const int row = u / (BK / VEC);
+                const int kv = (u % (BK / VEC)) * VEC;
+                *reinterpret_cast<u32x4 *>(lds + row * PITCH + kv) = r[p];
+            } else {
+                const int rb = u % (ROWS / VEC);
+                const int kb = u / (ROWS / VEC);
+#pragma unroll
+                for (int i = 0; i < VEC; ++i)
+                    *reinterpret_cast<u32x4 *>(lds + (rb * VEC + i) * PITCH + kb * VEC) =
+                        transpose_col<T>(&r[p * VEC], i);
+            }
+        }
+    }
+};
+
+template <typename T, int AMODE, int BMODE, int EPI>
+__global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) {
+    constexpr int BM = GemmTile<T>::BM, BN = GemmTile<T>::BN, BK = GemmTile<T>::BK;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int PITCH = BK + VEC;
+    constexpr int KC = 2 * VEC;  // k covered by one 16-byte read in each lane-half
+    using LA = TileLoader<T, AMODE, BM, BK>;
+    using LB = TileLoader<T, BMODE, BN, BK>;
+    // Split the threads between the two operands when neither needs all of them.
+    constexpr int B_OFF = (LA::NT + LB::NT <= kThreads) ? LA::NT : 0;
+
+    __shared__ __attribute__((aligned(16))) T lds[2][(BM + BN) * PITCH];
+
+    const int bid = blockIdx.x;
+    int pi = 0;
+    while (pi + 1 < args.count && bid >= args.p[pi + 1].tile_begin) ++pi;
+    const GemmProblem &P = args.p[pi];
+
+    const int local = bid - P.tile_begin;
+    const int per_split = P.tiles_m * P.tiles_n;
+    const int split = local / per_split;
+    const int rem = local - split * per_split;
+    const int tm = rem / P.tiles_n;
+    const int tn = rem - tm * P.tiles_n;
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int kbeg = split * P.kps;
+    const int kend = min(P.K, kbeg + P.kps);
+    const int nk = (kend - kbeg + BK - 1) / BK;
+
+    const T *A = static_cast<const T *>(P.A);
+    const T *B = static_cast<const T *>(P.B);
+    // 16-byte vector loads need a 16-byte aligned base and row pitch.
+    const bool a_vec = (P.lda % VEC) == 0 && (reinterpret_cast<uintptr_t>(A) & 15u) == 0;
+    const bool b_vec = (P.ldb % VEC) == 0 && (reinterpret_cast<uintptr_t>(B) & 15u) == 0;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int lrow = lane & 31;
+    const int lk = (lane >> 5) * VEC;
+
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    const bool do_rowsum = (EPI == kEpiPartial) && tn == 0;
+    float rowsum = 0.0f;
+
+    LA la;
+    LB lb;
+    if (nk > 0) {
+        la.load(A, P.lda, P.M, m0, kbeg, kend, tid, a_vec);
+        lb.load(B, P.ldb, P.N, n0, kbeg, kend, tid - B_OFF, b_vec);
+        la.store(&lds[0][0], tid);
+        lb.store(&lds[0][BM * PITCH], tid - B_OFF);
+    }
+    __syncthreads();
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) {
+            const int k0 = kbeg + (kt + 1) * BK;
+            la.load(A, P.lda, P.M, m0, k0, kend, tid, a_vec);
+            lb.load(B, P.ldb, P.N, n0, k0, kend, tid - B_OFF, b_vec);
+        }
+        const T *As = &lds[cur][0];
+        const T *Bs = &lds[cur][BM * PITCH];
+#pragma unroll
+        for (int kc = 0; kc < BK / KC; ++kc) {
+            u32x4 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                a[i] = *reinterpret_cast<const u32x4 *>(As + (wm * 64 + i * 32 + lrow) * PITCH + kc * KC + lk);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                b[j] = *reinterpret_cast<const u32x4 *>(Bs + (wn * 64 + j * 32 + lrow) * PITCH + kc * KC + lk);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) Mma<T>::mac(acc[i][j], a[i], b[j]);
+        }
+        if (do_rowsum) {
+            // Two threads per row of A, each summing half of the slab.
+            const int row = tid >> 1;
+            const T *src = As + row * PITCH + (tid & 1) * (BK / 2);
+#pragma unroll
+            for (int e = 0; e < BK / 2; ++e) rowsum += Elem<T>::to_f(src[e]);
+        }
+        if (more) {
+            la.store(&lds[cur ^ 1][0], tid);
+            lb.store(&lds[cur ^ 1][BM * PITCH], tid - B_OFF);
+        }
+        __syncthreads();
+    }
+
+    if constexpr (EPI == kEpiPartial) {
+        if (do_rowsum) {
+            rowsum += __shfl_xor(rowsum, 1);
+            const int row = m0 + (tid >> 1);
+            if ((tid & 1) == 0 && row < P.M) P.rowsum[static_cast<long long>(split) * P.M + row] = rowsum;
+        }
+    }
+
+    // Epilogue: accumulators -> LDS (float32, per-wave 64 x 64 tile) -> each
+    // lane takes 8 consecutive columns of a row, applies the epilogue and
+    // writes them with one 16-byte (bf16) or two 16-byte (float32) stores.
+    // Rows are padded to 72 floats so the two lane halves hit disjoint banks.
+    constexpr int EP = 72;
+    static_assert(4 * 64 * EP * 4 <= sizeof(lds), "epilogue staging must fit in the tile buffers");
+    float *stage = reinterpret_cast<float *>(&lds[0][0]) + wave * 64 * EP;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                stage[(i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * EP + j * 32 + lrow] = acc[i][j][r];
+    __syncthreads();
+
+    const int sub_r = lane >> 3;
+    const int sub_c = (lane & 7) * 8;
+    const int col = n0 + wn * 64 + sub_c;
+    const bool full_cols = col + 8 <= P.N;
+    if (col >= P.N) return;
+    float bias[8];
+    if constexpr (EPI == kEpiBiasElu) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bias[e] = (col + e < P.N) ? P.bias[col + e] : 0.0f;
+    }
+    const bool c_vec = full_cols && (P.ldc % 8) == 0 && (reinterpret_cast<uintptr_t>(P.C) & 15u) == 0;
+    const bool h_vec = full_cols && (P.ldh % 8) == 0 && (reinterpret_cast<uintptr_t>(P.H) & 15u) == 0;
+#pragma unroll 2
+    for (int it = 0; it < 8; ++it) {
+        const int lr = it * 8 + sub_r;
+        const int row = m0 + wm * 64 + lr;
+        if (row >= P.M) break;
+        float v[8];
+        *reinterpret_cast<float4 *>(&v[0]) = *reinterpret_cast<const float4 *>(stage + lr * EP + sub_c);
+        *reinterpret_cast<float4 *>(&v[4]) = *reinterpret_cast<const float4 *>(stage + lr * EP + sub_c + 4);
+        if constexpr (EPI == kEpiPartial) {
+            float *dst = static_cast<float *>(P.C) + split * P.c_split_stride + static_cast<long long>(row) * P.ldc + col;
+            if (c_vec) {
+                reinterpret_cast<float4 *>(dst)[0] = *reinterpret_cast<const float4 *>(&v[0]);
+                reinterpret_cast<float4 *>(dst)[1] = *reinterpret_cast<const float4 *>(&v[4]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (col + e < P.N) dst[e] = v[e];
+            }
+        } else {
+            if constexpr (EPI == kEpiBiasElu) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = Act<T>::elu(v[e] + bias[e]);
+            } else {
+                const T *hsrc = static_cast<const T *>(P.H) + static_cast<long long>(row) * P.ldh + col;
+                T h[8];
+                if (h_vec) {
+                    if constexpr (sizeof(T) == 2) {
+                        *reinterpret_cast<u32x4 *>(h) = *reinterpret_cast<const u32x4 *>(hsrc);
+                    } else {
+                        reinterpret_cast<u32x4 *>(h)[0] = reinterpret_cast<const u32x4 *>(hsrc)[0];
+                        reinterpret_cast<u32x4 *>(h)[1] = reinterpret_cast<const u32x4 *>(hsrc)[1];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) h[e] = (col + e < P.N) ? hsrc[e] : T(0);
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float hv = Elem<T>::to_f(h[e]);
+                    v[e] *= hv > 0.0f ? 1.0f : hv + 1.0f;
+                }
+            }
+            T out[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) out[e] = Act<T>::store(v[e]);
+            T *dst = static_cast<T *>(P.C) + static_cast<long long>(row) * P.ldc + col;
+            if (c_vec) {
+                if constexpr (sizeof(T) == 2) {
+                    *reinterpret_cast<u32x4 *>(dst) = *reinterpret_cast<const u32x4 *>(out);
+                } else {
+                    reinterpret_cast<u32x4 *>(dst)[0] = reinterpret_cast<const u32x4 *>(out)[0];
+                    reinterpret_cast<u32x4 *>(dst)[1] = reinterpret_cast<const u32x4 *>(out)[1];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (col + e < P.N) dst[e] = out[e];
+            }
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_typed(int a_mode, int b_mode, int epi, const GemmArgs &args, hipStream_t s) {
+    dim3 grid(args.total_tiles), block(kThreads);
+    if (a_mode == 0 && b_mode == 0 && epi == kEpiBiasElu)
+        hipLaunchKernelGGL((gemm_kernel<T, 0, 0, kEpiBiasElu>), grid, block, 0, s, args);
+    else if (a_mode == 0 && b_mode == 1 && epi == kEpiDElu)
+        hipLaunchKernelGGL((gemm_kernel<T, 0, 1, kEpiDElu>), grid, block, 0, s, args);
+    else if (a_mode == 1 && b_mode == 1 && epi == kEpiPartial)
+        hipLaunchKernelGGL((gemm_kernel<T, 1, 1, kEpiPartial>), grid, block, 0, s, args);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gemm(Precision prec, int a_mode, int b_mode, int epi, const GemmArgs &args, hipStream_t s) {
+    if (args.total_tiles <= 0) return hipSuccess;
+    return prec == kBF16 ? launch_typed<uint16_t>(a_mode, b_mode, epi, args, s)
+                         : launch_typed<float>(a_mode, b_mode, epi, args, s);
+}
+
+}  // namespace ppo

@@ -1,0 +1,610 @@
+// Non-GEMM kernels of the PPO learner for gfx950: Philox4x32-10 action noise,
+// the policy/critic output heads fused with sampling (rollout) or with the
+// PPO loss and its output gradients (update), GAE with the float64 advantage
+// statistics, gradient assembly with the float64 global norm, and Adam.
+#include "common.hpp"
+
+namespace ppo {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kLog2Pi = 1.8378770664093453f;
+constexpr int kMaxAct = 16;
+
+// ------------------------------------------------------------------ Philox
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// multiplies with key bumps by the Weyl constants between rounds.
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a = c[0], b = c[2];
+        const uint32_t hi_a = __umulhi(0xD2511F53u, a), lo_a = 0xD2511F53u * a;
+        const uint32_t hi_b = __umulhi(0xCD9E8D57u, b), lo_b = 0xCD9E8D57u * b;
+        c[0] = hi_b ^ c[1] ^ k0;
+        c[1] = lo_b;
+        c[2] = hi_a ^ c[3] ^ k1;
+        c[3] = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Top 23 bits plus half a step: exact in float32, strictly inside (0, 1).
+__device__ inline float uniform23(uint32_t x) { return (static_cast<float>(x >> 9) + 0.5f) * 1.1920928955078125e-07f; }
+
+__device__ inline void box_muller(uint32_t xa, uint32_t xb, float &ea, float &eb) {
+    const float r = sqrtf(-2.0f * logf(uniform23(xa)));
+    float s, c;
+    sincospif(2.0f * uniform23(xb), &s, &c);
+    ea = r * c;
+    eb = r * s;
+}
+
+__global__ void philox_blocks_kernel(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                                     uint32_t c3, long long n, uint32_t *out) {
+    for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<long long>(gridDim.x) * blockDim.x) {
+        uint32_t c[4] = {c0 + static_cast<uint32_t>(i), c1, c2, c3};
+        philox4x32_10(c, k0, k1);
+        *reinterpret_cast<u32x4 *>(out + 4 * i) = u32x4{c[0], c[1], c[2], c[3]};
+    }
+}
+
+// --------------------------------------------------------------- reductions
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// ------------------------------------------------------------ obs gather
+template <typename T>
+__global__ void gather_obs_kernel(const float *obs, const int32_t *idx, int src_rows, int rows, int D, int ld,
+                                  T *out) {
+    const long long total = static_cast<long long>(rows) * ld;
+    for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < total;
+         e += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const int r = static_cast<int>(e / ld);
+        const int k = static_cast<int>(e - static_cast<long long>(r) * ld);
+        // indices outside [0, src_rows) are clamped so a bad permutation cannot fault
+        const long long src_row = idx ? min(max(idx[r], 0), src_rows - 1) : r;
+        const float v = k < D ? obs[src_row * D + k] : 0.0f;
+        out[e] = Elem<T>::from_f(v);
+    }
+}
+
+// ------------------------------------------------- output-layer helpers
+constexpr int kHeadThreads = 256;
+constexpr int kHeadRows = 64;   // samples (or environments) per block
+
+// 8 consecutive activations of one row as float32.
+template <typename T>
+__device__ inline void load8(const T *src, float (&x)[8]) {
+    if constexpr (sizeof(T) == 2) {
+        const u32x4 r = *reinterpret_cast<const u32x4 *>(src);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            x[2 * w] = __uint_as_float(r[w] << 16);
+            x[2 * w + 1] = __uint_as_float(r[w] & 0xFFFF0000u);
+        }
+    } else {
+        const float4 p = reinterpret_cast<const float4 *>(src)[0];
+        const float4 q = reinterpret_cast<const float4 *>(src)[1];
+        x[0] = p.x; x[1] = p.y; x[2] = p.z; x[3] = p.w;
+        x[4] = q.x; x[5] = q.y; x[6] = q.z; x[7] = q.w;
+    }
+}
+
+// Output layers for a block of rows: out[i][j] = b_j + h_i . W_j for the A
+// actor outputs (j < A) and the critic value (j == A); one dot product per
+// thread, rows shared through L1.  Hl is a multiple of 16.
+template <typename T>
+__device__ inline void output_layers(const T *ha, const T *hc, const float *Wa, const float *ba, const float *Wc,
+                                     const float *bc, int r0, int rows, int A, int Hl, bool actor,
+                                     float (*out)[kMaxAct + 1]) {
+    const int n_out = A + 1;
+    for (int q = threadIdx.x; q < kHeadRows * n_out; q += kHeadThreads) {
+        const int i = q / n_out, j = q - (q / n_out) * n_out;
+        if (i >= rows || (j < A && !actor)) continue;
+        const T *h = (j < A ? ha : hc) + static_cast<long long>(r0 + i) * Hl;
+        const float *w = j < A ? Wa + static_cast<long long>(j) * Hl : Wc;
+        float acc = j < A ? ba[j] : bc[0];
+        for (int k = 0; k < Hl; k += 8) {
+            float x[8];
+            load8<T>(h + k, x);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc += x[e] * w[k + e];
+        }
+        out[i][j] = acc;
+    }
+}
+
+// ----------------------------------------------------------- head + sample
+// Rollout: mu = h_a Wa^T + ba and V = h_c Wc^T + bc for 64 environments per
+// block, then one lane per environment draws the diagonal-Gaussian action
+// a = mu + sigma * eps with Philox noise and its log-density
+// sum_j(-eps_j^2 / 2 - log sigma_j) - (A/2) log(2 pi).
+template <typename T>
+__global__ __launch_bounds__(kHeadThreads) void head_sample_kernel(const HeadSampleArgs a) {
+    __shared__ float s_out[kHeadRows][kMaxAct + 1];
+    const int r0 = blockIdx.x * kHeadRows;
+    const int rows = min(kHeadRows, a.N - r0);
+    const int A = a.A;
+    output_layers<T>(static_cast<const T *>(a.ha), static_cast<const T *>(a.hc), a.Wa, a.ba, a.Wc, a.bc, r0, rows,
+                     A, a.Hl, !a.value_only, s_out);
+    __syncthreads();
+    const int i = threadIdx.x;
+    if (i >= rows) return;
+    const int n = r0 + i;
+    if (a.values) a.values[n] = s_out[i][A];
+    if (a.value_only) return;
+    const int groups = (A + 3) / 4;
+    double logp = -0.5 * A * 1.8378770664093453;
+    for (int g = 0; g < groups; ++g) {
+        uint32_t c[4] = {static_cast<uint32_t>(n) * groups + g, a.t, a.iteration, 1u};
+        philox4x32_10(c, a.key0, a.key1);
+        float eps[4];
+        box_muller(c[0], c[1], eps[0], eps[1]);
+        box_muller(c[2], c[3], eps[2], eps[3]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * g + q;
+            if (j >= A) break;
+            const float m = s_out[i][j];
+            const float ls = a.logstd[j];
+            logp += -0.5 * static_cast<double>(eps[q]) * eps[q] - ls;
+            if (a.actions) a.actions[static_cast<long long>(n) * A + j] = m + expf(ls) * eps[q];
+            if (a.mu) a.mu[static_cast<long long>(n) * A + j] = m;
+        }
+    }
+    if (a.logp) a.logp[n] = static_cast<float>(logp);
+}
+
+// ------------------------------------------------------------- head + loss
+// Update: for 64 mini-batch samples per block, the output layers, the
+// log-probability of the stored action, the ratio, clipped surrogate and
+// value loss with their gradients wrt mu and V (one lane per sample), then
+// the gradient through the output layers and the last ELU into the last
+// hidden pre-activations (8-wide row segments, coalesced).  Per-block sums of
+// the loss terms and of the log-std gradient go to `partials` (wave-0
+// shuffle reduction, fixed order).
+constexpr int kLossThreads = kHeadThreads;
+
+template <typename T>
+__global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossArgs a) {
+    __shared__ float s_out[kHeadRows][kMaxAct + 1];
+    const int r0 = blockIdx.x * kHeadRows;
+    const int rows = min(kHeadRows, a.M - r0);
+    const int A = a.A, Hl = a.Hl;
+    const int W = A + 8;
+    const T *ha = static_cast<const T *>(a.ha);
+    const T *hc = static_cast<const T *>(a.hc);
+    output_layers<T>(ha, hc, a.Wa, a.ba, a.Wc, a.bc, r0, rows, A, Hl, true, s_out);
+    __syncthreads();
+
+    const int tid = threadIdx.x;
+    if (tid < 64) {
+        float pl = 0.0f, vl = 0.0f, clipped = 0.0f, kl = 0.0f;
+        float dls[kMaxAct];
+#pragma unroll
+        for (int j = 0; j < kMaxAct; ++j) dls[j] = 0.0f;
+        if (tid < rows) {
+            const int i = tid;
+            const long long row = a.idx ? min(max(a.idx[r0 + i], 0), a.B - 1) : r0 + i;
+            // Log-probability of the stored action, accumulated in float64: a sum of A
+            // terms of order 1 whose float32 rounding would dominate the ratio's error.
+            float z[kMaxAct];
+            double logp = -0.5 * A * 1.8378770664093453;
+#pragma unroll
+            for (int j = 0; j < kMaxAct; ++j) {
+                z[j] = 0.0f;
+                if (j < A) {
+                    const float ls = a.logstd[j];
+                    z[j] = (a.actions[row * A + j] - s_out[i][j]) * expf(-ls);
+                    logp += -0.5 * static_cast<double>(z[j]) * z[j] - ls;
+                }
+            }
+            const float adv = a.adv[row];
+            const float ratio = static_cast<float>(exp(logp - static_cast<double>(a.logp_old[row])));
+            const float lo = 1.0f - a.clip, hi = 1.0f + a.clip;
+            pl = -fminf(ratio * adv, fminf(fmaxf(ratio, lo), hi) * adv);
+            const bool active = adv >= 0.0f ? (ratio <= hi) : (ratio >= lo);
+            clipped = fabsf(ratio - 1.0f) > a.clip ? 1.0f : 0.0f;
+            kl = (ratio - 1.0f) - logf(ratio);
+            const float g_lp = active ? -a.inv_m * adv * ratio : 0.0f;
+
+            const float V = s_out[i][A];
+            const float ret = a.returns[row];
+            const float diff = V - ret;
+            float pass = 1.0f;
+            vl = diff * diff;
+            if (a.clip_value) {
+                const float v_old = a.values_old[row];
+                const float vc = v_old + fminf(fmaxf(V - v_old, -a.clip), a.clip);
+                const float sqc = (vc - ret) * (vc - ret);
+                pass = vl >= sqc ? 1.0f : 0.0f;
+                vl = fmaxf(vl, sqc);
+            }
+            const float g_v = 2.0f * a.value_coef * a.inv_m * diff * pass;
+
+            T *dha = static_cast<T *>(a.dz_head_a) + static_cast<long long>(r0 + i) * kHeadPad;
+            T *dhc = static_cast<T *>(a.dz_head_c) + static_cast<long long>(r0 + i) * kHeadPad;
+#pragma unroll
+            for (int j = 0; j < kMaxAct; ++j) {
+                float gm = 0.0f;
+                if (j < A) {
+                    gm = g_lp * z[j] * expf(-a.logstd[j]);
+                    dls[j] = g_lp * (z[j] * z[j] - 1.0f);
+                    s_out[i][j] = gm;
+                }
+                dha[j] = Elem<T>::from_f(gm);
+                dhc[j] = Elem<T>::from_f(j == 0 ? g_v : 0.0f);
+            }
+            s_out[i][A] = g_v;
+        }
+        // wave 0 holds every sample of the block: shuffle-reduce in a fixed order
+        const float w_pl = wave_sum(pl), w_vl = wave_sum(vl), w_cl = wave_sum(clipped), w_kl = wave_sum(kl);
+        float w_dls[kMaxAct];
+#pragma unroll
+        for (int j = 0; j < kMaxAct; ++j) w_dls[j] = wave_sum(dls[j]);
+        if (tid == 0) {
+            float *out = a.partials + static_cast<long long>(blockIdx.x) * W;
+            out[0] = w_pl;
+            out[1] = w_vl;
+            out[2] = w_cl;
+            out[3] = w_kl;
+#pragma unroll
+            for (int j = 0; j < kMaxAct; ++j)
+                if (j < A) out[4 + j] = w_dls[j];
+            if (blockIdx.x == 0) {
+                // entropy of the state-independent policy at this step's parameters
+                float ent = 0.5f * A * (1.0f + kLog2Pi);
+                for (int j = 0; j < A; ++j) ent += a.logstd[j];
+                out[4 + A] = ent;
+            }
+        }
+    }
+    __syncthreads();
+
+    // gradient into the last hidden pre-activations, both networks
+    const int chunks = Hl / 8;
+    for (int q = tid; q < 2 * kHeadRows * chunks; q += kHeadThreads) {
+        const int net = q / (kHeadRows * chunks);
+        const int rem = q - net * kHeadRows * chunks;
+        const int i = rem / chunks;
+        const int k = (rem - i * chunks) * 8;
+        if (i >= rows) continue;
+        const long long off = static_cast<long long>(r0 + i) * Hl + k;
+        float x[8], g[8];
+        load8<T>((net == 0 ? ha : hc) + off, x);
+        if (net == 0) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) g[e] = 0.0f;
+            for (int j = 0; j < A; ++j) {
+                const float gm = s_out[i][j];
+                const float *w = a.Wa + static_cast<long long>(j) * Hl + k;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) g[e] += gm * w[e];
+            }
+        } else {
+            const float gv = s_out[i][A];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) g[e] = gv * a.Wc[k + e];
+        }
+        T o[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = Elem<T>::from_f(g[e] * (x[e] > 0.0f ? 1.0f : x[e] + 1.0f));
+        T *dst = static_cast<T *>(net == 0 ? a.dza : a.dzc) + off;
+        if constexpr (sizeof(T) == 2) {
+            *reinterpret_cast<u32x4 *>(dst) = *reinterpret_cast<const u32x4 *>(o);
+        } else {
+            reinterpret_cast<u32x4 *>(dst)[0] = reinterpret_cast<const u32x4 *>(o)[0];
+            reinterpret_cast<u32x4 *>(dst)[1] = reinterpret_cast<const u32x4 *>(o)[1];
+        }
+    }
+}
+
+// ------------------------------------------------------------------- GAE
+// One lane per environment walks t = T-1 .. 0 (coalesced across lanes):
+//   r' = r + gamma V timeout;  delta = r' + gamma (1 - d) V_next - V;
+//   A = delta + gamma lambda (1 - d) A_next;  R = A + V.
+// Each lane keeps a float64 Welford (count, mean, M2) of its advantages; the
+// block merges them (Chan et al.) in a fixed order into one partial.
+constexpr int kGaeThreads = 64;
+
+struct Welford { double n, mean, m2; };
+
+__device__ inline Welford merge(const Welford &x, const Welford &y) {
+    if (x.n == 0.0) return y;
+    if (y.n == 0.0) return x;
+    const double n = x.n + y.n;
+    const double d = y.mean - x.mean;
+    return {n, x.mean + d * (y.n / n), x.m2 + y.m2 + d * d * (x.n * y.n / n)};
+}
+
+__device__ inline Welford shfl_xor_w(const Welford &w, int o) {
+    return {__shfl_xor(w.n, o), __shfl_xor(w.mean, o), __shfl_xor(w.m2, o)};
+}
+
+__global__ __launch_bounds__(kGaeThreads) void gae_kernel(const GaeArgs a) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    Welford w{0.0, 0.0, 0.0};
+    if (n < a.N) {
+        float next_v = a.last_values[n];
+        float next_a = 0.0f;
+        const float gl = a.gamma * a.lam;
+        for (int t = a.T - 1; t >= 0; --t) {
+            const long long s = static_cast<long long>(t) * a.N + n;
+            const float v = a.values[s];
+            float r = a.rewards[s];
+            if (a.timeouts && a.timeouts[s]) r += a.gamma * v;
+            const float nd = a.dones[s] ? 0.0f : 1.0f;
+            const float delta = r + a.gamma * nd * next_v - v;
+            const float adv = delta + gl * nd * next_a;
+            a.adv[s] = adv;
+            a.returns[s] = adv + v;
+            next_v = v;
+            next_a = adv;
+            const double x = adv;
+            w.n += 1.0;
+            const double d = x - w.mean;
+            w.mean += d / w.n;
+            w.m2 += d * (x - w.mean);
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const Welford other = shfl_xor_w(w, o);
+        // merge in lane order so every lane holds the same value
+        const bool lower = (threadIdx.x & o) == 0;
+        w = lower ? merge(w, other) : merge(other, w);
+    }
+    if (threadIdx.x == 0) {
+        a.partials[3 * blockIdx.x + 0] = w.n;
+        a.partials[3 * blockIdx.x + 1] = w.mean;
+        a.partials[3 * blockIdx.x + 2] = w.m2;
+    }
+}
+
+// Every block merges all partials in index order (identical result in each),
+// block 0 publishes (mean, unbiased std), and all blocks optionally normalise.
+__global__ void adv_finalize_kernel(const double *partials, int nparts, float *adv, long long count,
+                                    double *stats_out, int normalize) {
+    __shared__ double s_mean, s_std;
+    if (threadIdx.x == 0) {
+        Welford w{0.0, 0.0, 0.0};
+        for (int p = 0; p < nparts; ++p) w = merge(w, Welford{partials[3 * p], partials[3 * p + 1], partials[3 * p + 2]});
+        s_mean = w.mean;
+        s_std = w.n > 1.0 ? sqrt(w.m2 / (w.n - 1.0)) : 0.0;
+        if (blockIdx.x == 0) {
+            stats_out[0] = s_mean;
+            stats_out[1] = s_std;
+        }
+    }
+    __syncthreads();
+    if (!normalize) return;
+    const double mean = s_mean;
+    const double inv = 1.0 / (s_std + 1e-8);
+    for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < count;
+         e += static_cast<long long>(gridDim.x) * blockDim.x)
+        adv[e] = static_cast<float>((static_cast<double>(adv[e]) - mean) * inv);
+}
+
+// -------------------------------------------------------- gradient reduce
+// Blocks 0 .. gridDim-2 sum the split partials of every segment into the
+// flat gradient; the last block sums the loss partials column-wise (8 row
+// stripes, then the stripes in order) into the log-std gradient and the
+// loss sums.  Every block writes the float64 sum of squares of what it wrote.
+constexpr int kReduceThreads = 256;
+
+__global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(const ReduceArgs a) {
+    __shared__ double red[kReduceThreads / 64];
+    double ss = 0.0;
+    if (blockIdx.x + 1 < gridDim.x) {
+        const long long stride = static_cast<long long>(gridDim.x - 1) * blockDim.x;
+        for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < a.total; e += stride) {
+            int si = 0;
+            while (si + 1 < a.count && e >= a.seg[si + 1].begin) ++si;
+            const ReduceSegment &S = a.seg[si];
+            const long long local = e - S.begin;
+            const int r = static_cast<int>(local / S.cols);
+            const int c = static_cast<int>(local - static_cast<long long>(r) * S.cols);
+            const float *src = S.src + static_cast<long long>(r) * S.ld + c;
+            float sum = 0.0f;
+            for (int s = 0; s < S.splits; ++s) sum += src[s * S.split_stride];
+            sum += S.add;
+            a.grad[S.dst_offset + local] = sum;
+            ss += static_cast<double>(sum) * sum;
+        }
+    } else {
+        __shared__ float stripe[8][kMaxAct + 8];
+        const int cols = 4 + a.A;
+        const int c = threadIdx.x & 31, st = threadIdx.x >> 5;
+        if (c < cols) {
+            float acc = 0.0f;
+            for (int b = st; b < a.n_loss; b += 8) acc += a.loss_partials[static_cast<long long>(b) * a.loss_width + c];
+            stripe[st][c] = acc;
+        }
+        __syncthreads();
+        if (threadIdx.x < cols) {
+            float v = 0.0f;
+            for (int q = 0; q < 8; ++q) v += stripe[q][threadIdx.x];
+            if (threadIdx.x < 4) {
+                a.loss_sums[threadIdx.x] = v;
+            } else {
+                const float g = v - a.entropy_coef;
+                a.grad[a.logstd_offset + threadIdx.x - 4] = g;
+                ss = static_cast<double>(g) * g;
+            }
+        }
+        if (threadIdx.x == 0) a.loss_sums[4] = a.loss_partials[4 + a.A];
+    }
+    ss = wave_sum_d(ss);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kReduceThreads / 64; ++w) t += red[w];
+        a.sumsq_partials[blockIdx.x] = t;
+    }
+}
+
+// ------------------------------------------------------------------ Adam
+constexpr int kAdamThreads = 256;
+
+__global__ __launch_bounds__(kAdamThreads) void adam_kernel(const AdamArgs a) {
+    __shared__ double s_sumsq;
+    __shared__ double red[kAdamThreads / 64];
+    // global norm: every block sums the same partials in the same order
+    double ss = 0.0;
+    for (int p = threadIdx.x; p < a.n_sumsq; p += kAdamThreads) ss += a.sumsq_partials[p];
+    ss = wave_sum_d(ss);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kAdamThreads / 64; ++w) t += red[w];
+        s_sumsq = t;
+    }
+    __syncthreads();
+    const double norm = sqrt(s_sumsq);
+    const bool finite = isfinite(norm);
+    const float coef = static_cast<float>(fmin(1.0, static_cast<double>(a.max_grad_norm) / (norm + 1e-6)));
+
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const float pl = a.loss_sums[0] * a.inv_m, vl = a.loss_sums[1] * a.inv_m;
+        const float ent = a.loss_sums[4];
+        a.stats[0] = pl + a.value_coef * vl - a.entropy_coef * ent;
+        a.stats[1] = pl;
+        a.stats[2] = vl;
+        a.stats[3] = ent;
+        a.stats[4] = a.loss_sums[2] * a.inv_m;
+        a.stats[5] = a.loss_sums[3] * a.inv_m;
+        a.stats[6] = static_cast<float>(norm);
+        a.stats[7] = finite ? 0.0f : 1.0f;
+    }
+    if (!a.apply || !finite) return;
+
+    const int t = *a.step + a.step_offset + 1;
+    const float bc1 = static_cast<float>(1.0 - pow(static_cast<double>(a.beta1), t));
+    const float bc2 = static_cast<float>(1.0 - pow(static_cast<double>(a.beta2), t));
+    const float lr = *a.lr;
+    for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < a.P;
+         e += static_cast<long long>(gridDim.x) * blockDim.x) {
+        const float g = a.grad[e] * coef;
+        const float m = a.beta1 * a.m[e] + (1.0f - a.beta1) * g;
+        const float v = a.beta2 * a.v[e] + (1.0f - a.beta2) * g * g;
+        a.m[e] = m;
+        a.v[e] = v;
+        const float th = a.theta[e] - lr * (m / bc1) / (sqrtf(v / bc2) + a.eps);
+        a.theta[e] = th;
+        if (a.shadow) a.shadow[e] = f32_to_bf16(th);
+    }
+}
+
+__global__ void step_advance_kernel(int32_t *step, int k) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step += k;
+}
+
+__global__ void pack_bf16_kernel(const float *theta, uint16_t *shadow, long long n) {
+    for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < n;
+         e += static_cast<long long>(gridDim.x) * blockDim.x)
+        shadow[e] = f32_to_bf16(theta[e]);
+}
+
+int grid_for(long long n, int threads, int cap) {
+    long long b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    return static_cast<int>(b < cap ? b : cap);
+}
+
+}  // namespace
+
+hipError_t launch_philox_blocks(hipStream_t s, uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                                uint32_t c3, long long n, uint32_t *out) {
+    const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+    hipLaunchKernelGGL(philox_blocks_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, k0, k1, c0, c1, c2, c3,
+                       n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_obs(Precision prec, hipStream_t s, const float *obs, const int32_t *idx, int src_rows,
+                             int rows, int D, int ld, void *out) {
+    const long long total = static_cast<long long>(rows) * ld;
+    const dim3 grid(grid_for(total, 256, 8192)), block(256);
+    if (prec == kBF16)
+        hipLaunchKernelGGL(gather_obs_kernel<uint16_t>, grid, block, 0, s, obs, idx, src_rows, rows, D, ld,
+                           static_cast<uint16_t *>(out));
+    else
+        hipLaunchKernelGGL(gather_obs_kernel<float>, grid, block, 0, s, obs, idx, src_rows, rows, D, ld,
+                           static_cast<float *>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_head_sample(Precision prec, const HeadSampleArgs &a, hipStream_t s) {
+    const dim3 grid((a.N + kHeadRows - 1) / kHeadRows), block(kHeadThreads);
+    if (prec == kBF16)
+        hipLaunchKernelGGL(head_sample_kernel<uint16_t>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(head_sample_kernel<float>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+int head_loss_blocks(int M) { return (M + kHeadRows - 1) / kHeadRows; }
+int head_loss_partial_width(int A) { return A + 8; }
+
+hipError_t launch_head_loss(Precision prec, const HeadLossArgs &a, hipStream_t s) {
+    const dim3 grid(head_loss_blocks(a.M)), block(kLossThreads);
+    if (prec == kBF16)
+        hipLaunchKernelGGL(head_loss_kernel<uint16_t>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(head_loss_kernel<float>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+int gae_blocks(int N) { return (N + kGaeThreads - 1) / kGaeThreads; }
+
+hipError_t launch_gae(const GaeArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(gae_kernel, dim3(gae_blocks(a.N)), dim3(kGaeThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adv_finalize(const double *partials, int nparts, float *adv, long long count, double *stats_out,
+                               int normalize, hipStream_t s) {
+    const int blocks = normalize ? grid_for(count, 256, 1024) : 1;
+    hipLaunchKernelGGL(adv_finalize_kernel, dim3(blocks), dim3(256), 0, s, partials, nparts, adv, count, stats_out,
+                       normalize);
+    return hipGetLastError();
+}
+
+int reduce_blocks(long long total) { return grid_for(total, kReduceThreads, 1023) + 1; }
+
+hipError_t launch_grad_reduce(const ReduceArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3(reduce_blocks(a.total)), dim3(kReduceThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+int adam_blocks(long long P) { return grid_for(P, kAdamThreads, 1024); }
+
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(adam_kernel, dim3(adam_blocks(a.P)), dim3(kAdamThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_advance(int32_t *step, int k, hipStream_t s) {
+    hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(64), 0, s, step, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_bf16(const float *theta, uint16_t *shadow, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(pack_bf16_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, theta, shadow, n);
+    return hipGetLastError();
+}
+
+}  // namespace ppo

@@ -1,0 +1,959 @@
+// Host runtime behind include/ppo.h: argument validation (always before any
+// enqueue), the flat parameter layout, workspace planning, the launch
+// sequence of each entry point, and the cache of captured HIP graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ppo.h"
+#include "common.hpp"
+
+using namespace ppo;
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(PPO_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define PPO_HIP(expr, what)                          \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int check_ptr(const void *p, const char *name, bool nullable = false) {
+    if (!p) return nullable ? PPO_OK : fail(PPO_E_INVAL, "%s is NULL", name);
+    if (!aligned16(p)) return fail(PPO_E_INVAL, "%s is not 16-byte aligned", name);
+    return PPO_OK;
+}
+
+#define PPO_CHECK(expr)              \
+    do {                             \
+        int _rc = (expr);            \
+        if (_rc != PPO_OK) return _rc; \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+int cdiv(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
+
+// ------------------------------------------------------------- net layout
+struct NetLayout {
+    int L = 0;          // hidden layers
+    int D = 0, A = 0;
+    int H[kMaxHidden] = {0};
+    int dims_a[kMaxLayers + 1] = {0};  // actor widths, input first
+    int dims_c[kMaxLayers + 1] = {0};
+    long long Wa[kMaxLayers] = {0}, ba[kMaxLayers] = {0};
+    long long Wc[kMaxLayers] = {0}, bc[kMaxLayers] = {0};
+    long long logstd = 0, P = 0;
+};
+
+int validate_net(const ppo_net_desc *net) {
+    if (!net) return fail(PPO_E_INVAL, "net is NULL");
+    if (net->obs_dim < 1 || net->obs_dim > PPO_MAX_OBS)
+        return fail(PPO_E_SHAPE, "obs_dim %d outside 1..%d", net->obs_dim, PPO_MAX_OBS);
+    if (net->act_dim < 1 || net->act_dim > PPO_MAX_ACT)
+        return fail(PPO_E_SHAPE, "act_dim %d outside 1..%d", net->act_dim, PPO_MAX_ACT);
+    if (net->n_hidden < 1 || net->n_hidden > PPO_MAX_HIDDEN)
+        return fail(PPO_E_SHAPE, "n_hidden %d outside 1..%d", net->n_hidden, PPO_MAX_HIDDEN);
+    for (int l = 0; l < net->n_hidden; ++l) {
+        const int h = net->hidden[l];
+        if (h < 16 || h > PPO_MAX_WIDTH || h % 16 != 0)
+            return fail(PPO_E_SHAPE, "hidden[%d] = %d must be a multiple of 16 in 16..%d", l, h, PPO_MAX_WIDTH);
+    }
+    return PPO_OK;
+}
+
+NetLayout make_layout(const ppo_net_desc &net) {
+    NetLayout g;
+    g.L = net.n_hidden;
+    g.D = net.obs_dim;
+    g.A = net.act_dim;
+    g.dims_a[0] = g.dims_c[0] = g.D;
+    for (int l = 0; l < g.L; ++l) {
+        g.H[l] = net.hidden[l];
+        g.dims_a[l + 1] = g.dims_c[l + 1] = g.H[l];
+    }
+    g.dims_a[g.L + 1] = g.A;
+    g.dims_c[g.L + 1] = 1;
+    long long off = 0;
+    for (int l = 0; l <= g.L; ++l) {
+        g.Wa[l] = off;
+        off += static_cast<long long>(g.dims_a[l + 1]) * g.dims_a[l];
+        g.ba[l] = off;
+        off += g.dims_a[l + 1];
+    }
+    g.logstd = off;
+    off += g.A;
+    for (int l = 0; l <= g.L; ++l) {
+        g.Wc[l] = off;
+        off += static_cast<long long>(g.dims_c[l + 1]) * g.dims_c[l];
+        g.bc[l] = off;
+        off += g.dims_c[l + 1];
+    }
+    g.P = off;
+    return g;
+}
+
+// --------------------------------------------------------- workspace plan
+struct Region {
+    size_t off = 0, bytes = 0;
+};
+
+struct WsPlan {
+    // rows of the GEMM chain
+    int rows = 0;
+    int kpad = 0;      // padded observation width of the gathered input
+    size_t esz = 4;    // bytes per activation element
+    Region xg;
+    Region h_a[kMaxHidden], h_c[kMaxHidden];
+    Region dz_a[kMaxHidden], dz_c[kMaxHidden];
+    Region dzh_a, dzh_c;
+    Region part, rowsum, loss_part, loss_sums, sumsq, gae_part;
+    int splits = 1, kps = 0;
+    size_t total = 0;
+};
+
+struct Alloc {
+    size_t cur = 0;
+    Region take(size_t bytes) {
+        Region r;
+        r.off = cur;
+        r.bytes = bytes;
+        cur = align_up(cur + bytes, 256);
+        return r;
+    }
+};
+
+template <typename T> int bk_of() { return GemmTile<T>::BK; }
+
+int gemm_bk(Precision p) { return p == kBF16 ? GemmTile<uint16_t>::BK : GemmTile<float>::BK; }
+constexpr int kTileM = 128, kTileN = 128;
+
+// Output shape of the weight-gradient problem of layer l (0-based, l == L is
+// the output layer) for one network.
+void dw_shape(const NetLayout &g, bool actor, int l, int &rows, int &cols) {
+    rows = actor ? g.dims_a[l + 1] : g.dims_c[l + 1];
+    cols = l == 0 ? g.D : g.H[l - 1];
+}
+
+void choose_splits(const NetLayout &g, Precision prec, int M, int &splits, int &kps) {
+    int tiles = 0;
+    for (int net = 0; net < 2; ++net)
+        for (int l = 0; l <= g.L; ++l) {
+            int r, c;
+            dw_shape(g, net == 0, l, r, c);
+            tiles += cdiv(r, kTileM) * cdiv(c, kTileN);
+        }
+    const int bk = gemm_bk(prec);
+    const int target = 512;  // two resident workgroups on each of 256 CUs
+    int s = std::max(1, cdiv(target, tiles));
+    s = std::min(s, std::max(1, M / (2 * bk)));
+    kps = cdiv(cdiv(M, s), bk) * bk;
+    splits = cdiv(M, kps);
+}
+
+WsPlan plan_workspace(const NetLayout &g, Precision prec, int N, int T, int M) {
+    WsPlan w;
+    w.esz = prec == kBF16 ? 2 : 4;
+    w.kpad = static_cast<int>(align_up(g.D, 8));
+    const int rows = std::max(N, M);
+    w.rows = rows;
+    Alloc a;
+    w.xg = a.take(static_cast<size_t>(rows) * w.kpad * w.esz);
+    for (int l = 0; l < g.L; ++l) {
+        w.h_a[l] = a.take(static_cast<size_t>(rows) * g.H[l] * w.esz);
+        w.h_c[l] = a.take(static_cast<size_t>(rows) * g.H[l] * w.esz);
+    }
+    const int mm = std::max(M, 1);
+    for (int l = 0; l < g.L; ++l) {
+        w.dz_a[l] = a.take(static_cast<size_t>(mm) * g.H[l] * w.esz);
+        w.dz_c[l] = a.take(static_cast<size_t>(mm) * g.H[l] * w.esz);
+    }
+    w.dzh_a = a.take(static_cast<size_t>(mm) * kHeadPad * w.esz);
+    w.dzh_c = a.take(static_cast<size_t>(mm) * kHeadPad * w.esz);
+    choose_splits(g, prec, mm, w.splits, w.kps);
+    size_t part_floats = 0, rowsum_floats = 0;
+    for (int net = 0; net < 2; ++net)
+        for (int l = 0; l <= g.L; ++l) {
+            int r, c;
+            dw_shape(g, net == 0, l, r, c);
+            part_floats += align_up(static_cast<size_t>(w.splits) * r * c, 64);
+            rowsum_floats += align_up(static_cast<size_t>(w.splits) * r, 64);
+        }
+    w.part = a.take(part_floats * 4);
+    w.rowsum = a.take(rowsum_floats * 4);
+    w.loss_part = a.take(static_cast<size_t>(head_loss_blocks(mm)) * head_loss_partial_width(g.A) * 4);
+    w.loss_sums = a.take(8 * 4);
+    w.sumsq = a.take(static_cast<size_t>(1024) * 8);
+    w.gae_part = a.take(static_cast<size_t>(gae_blocks(std::max(N, 1))) * 3 * 8);
+    (void)T;
+    w.total = a.cur;
+    return w;
+}
+
+// --------------------------------------------------------------- device
+std::mutex g_dev_mu;
+std::map<int, int> g_dev_ok;  // device -> PPO_OK or error code
+
+int check_device() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_dev_ok.find(dev);
+    if (it != g_dev_ok.end()) {
+        if (it->second != PPO_OK) return fail(it->second, "device %d is not gfx950", dev);
+        return PPO_OK;
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    const bool ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    g_dev_ok[dev] = ok ? PPO_OK : PPO_E_UNSUPPORTED;
+    if (!ok) return fail(PPO_E_UNSUPPORTED, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+    return PPO_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct ppo_ctx {
+    ppo_net_desc net{};
+    NetLayout g;
+    Precision prec = kFP32;
+    std::mutex mu;
+    hipStream_t capture = nullptr;
+    int capture_dev = -1;
+    std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+    std::vector<std::vector<uint64_t>> graph_order;  // insertion order for eviction
+};
+
+namespace {
+
+constexpr size_t kMaxGraphs = 16;
+
+struct Weights {
+    const void *W[2][kMaxLayers];  // [net][layer] GEMM operand pointers (T)
+};
+
+Weights gemm_weights(const ppo_ctx *c, const ppo_params *p) {
+    Weights w{};
+    const NetLayout &g = c->g;
+    for (int l = 0; l <= g.L; ++l) {
+        if (c->prec == kBF16) {
+            w.W[0][l] = p->shadow + g.Wa[l];
+            w.W[1][l] = p->shadow + g.Wc[l];
+        } else {
+            w.W[0][l] = p->theta + g.Wa[l];
+            w.W[1][l] = p->theta + g.Wc[l];
+        }
+    }
+    return w;
+}
+
+char *wsp(void *ws, const Region &r) { return static_cast<char *>(ws) + r.off; }
+
+// Event pairs recorded on the launch stream around each kernel of a step.
+struct Profiler {
+    hipStream_t s = nullptr;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> phase;
+    size_t used = 0;
+    hipError_t begin(int ph) {
+        while (ev.size() < used + 2) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            ev.push_back(e);
+        }
+        phase.push_back(ph);
+        return hipEventRecord(ev[used], s);
+    }
+    hipError_t end() {
+        hipError_t r = hipEventRecord(ev[used + 1], s);
+        used += 2;
+        return r;
+    }
+    ~Profiler() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+// Wraps one launch expression with profiling events when a profiler is set.
+#define PROFILED(prof, ph, expr)                                  \
+    do {                                                          \
+        if (prof) {                                               \
+            hipError_t _pe = (prof)->begin(ph);                   \
+            if (_pe != hipSuccess) return _pe;                    \
+        }                                                         \
+        hipError_t _le = (expr);                                  \
+        if (_le != hipSuccess) return _le;                        \
+        if (prof) {                                               \
+            hipError_t _pe = (prof)->end();                       \
+            if (_pe != hipSuccess) return _pe;                    \
+        }                                                         \
+    } while (0)
+
+void add_problem(GemmArgs &args, const GemmProblem &proto, int bk) {
+    GemmProblem p = proto;
+    p.tiles_m = cdiv(p.M, kTileM);
+    p.tiles_n = cdiv(p.N, kTileN);
+    if (p.splits <= 0) {
+        p.splits = 1;
+        p.kps = cdiv(p.K, bk) * bk;
+    }
+    p.tile_begin = args.total_tiles;
+    args.p[args.count++] = p;
+    args.total_tiles += p.tiles_m * p.tiles_n * p.splits;
+}
+
+// Forward through the hidden layers of the selected networks for `rows`
+// rows whose gathered input is already in the xg region.
+hipError_t enqueue_forward(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *ws, int rows,
+                           bool actor, bool critic, hipStream_t s, Profiler *prof = nullptr) {
+    const NetLayout &g = c->g;
+    const Weights W = gemm_weights(c, p);
+    const int bk = gemm_bk(c->prec);
+    for (int l = 0; l < g.L; ++l) {
+        GemmArgs args{};
+        for (int net = 0; net < 2; ++net) {
+            if ((net == 0 && !actor) || (net == 1 && !critic)) continue;
+            GemmProblem q{};
+            q.A = l == 0 ? static_cast<const void *>(wsp(ws, w.xg))
+                         : static_cast<const void *>(wsp(ws, net == 0 ? w.h_a[l - 1] : w.h_c[l - 1]));
+            q.lda = l == 0 ? w.kpad : g.H[l - 1];
+            q.K = l == 0 ? g.D : g.H[l - 1];
+            q.B = W.W[net][l];
+            q.ldb = q.K;
+            q.C = wsp(ws, net == 0 ? w.h_a[l] : w.h_c[l]);
+            q.ldc = g.H[l];
+            q.bias = p->theta + (net == 0 ? g.ba[l] : g.bc[l]);
+            q.M = rows;
+            q.N = g.H[l];
+            add_problem(args, q, bk);
+        }
+        PROFILED(prof, PPO_PHASE_FORWARD, launch_gemm(c->prec, 0, 0, kEpiBiasElu, args, s));
+    }
+    return hipSuccess;
+}
+
+struct StepBuffers {
+    const ppo_batch *b;
+    const int32_t *idx;  // M rows of this step
+    int M;
+    float *grad;         // destination of the assembled gradient
+    float *stats;        // [kStatsWidth]
+    int apply;           // Adam step or statistics only
+    int step_offset;
+};
+
+// One mini-batch step: gather, forward, head+loss, input-gradient chain,
+// weight gradients, gradient assembly with the float64 norm, Adam.
+hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp, const WsPlan &w, void *ws,
+                        const StepBuffers &sb, hipStream_t s, Profiler *prof = nullptr) {
+    const NetLayout &g = c->g;
+    const Precision prec = c->prec;
+    const int M = sb.M;
+    const int bk = gemm_bk(prec);
+    const int L = g.L;
+    hipError_t e;
+
+    PROFILED(prof, PPO_PHASE_GATHER, launch_gather_obs(prec, s, sb.b->obs, sb.idx, sb.b->B, M, g.D, w.kpad,
+                                                       wsp(ws, w.xg)));
+    e = enqueue_forward(c, p, w, ws, M, true, true, s, prof);
+    if (e != hipSuccess) return e;
+
+    HeadLossArgs hl{};
+    hl.ha = wsp(ws, w.h_a[L - 1]);
+    hl.hc = wsp(ws, w.h_c[L - 1]);
+    hl.Wa = p->theta + g.Wa[L];
+    hl.ba = p->theta + g.ba[L];
+    hl.logstd = p->theta + g.logstd;
+    hl.Wc = p->theta + g.Wc[L];
+    hl.bc = p->theta + g.bc[L];
+    hl.actions = sb.b->actions;
+    hl.logp_old = sb.b->logp;
+    hl.adv = sb.b->adv;
+    hl.returns = sb.b->returns;
+    hl.values_old = sb.b->values;
+    hl.idx = sb.idx;
+    hl.B = sb.b->B;
+    hl.dza = wsp(ws, w.dz_a[L - 1]);
+    hl.dzc = wsp(ws, w.dz_c[L - 1]);
+    hl.dz_head_a = wsp(ws, w.dzh_a);
+    hl.dz_head_c = wsp(ws, w.dzh_c);
+    hl.partials = reinterpret_cast<float *>(wsp(ws, w.loss_part));
+    hl.M = M;
+    hl.A = g.A;
+    hl.Hl = g.H[L - 1];
+    hl.clip = hp->clip;
+    hl.value_coef = hp->value_coef;
+    hl.inv_m = 1.0f / static_cast<float>(M);
+    hl.clip_value = hp->clip_value;
+    PROFILED(prof, PPO_PHASE_HEAD_LOSS, launch_head_loss(prec, hl, s));
+
+    // input-gradient chain: dz_{l-1} = (dz_l W_l) * ELU'(z_{l-1}), l = L-1 .. 1
+    const Weights W = gemm_weights(c, p);
+    for (int l = L - 1; l >= 1; --l) {
+        GemmArgs args{};
+        for (int net = 0; net < 2; ++net) {
+            GemmProblem q{};
+            q.A = wsp(ws, net == 0 ? w.dz_a[l] : w.dz_c[l]);
+            q.lda = g.H[l];
+            q.K = g.H[l];
+            q.B = W.W[net][l];
+            q.ldb = g.H[l - 1];
+            q.C = wsp(ws, net == 0 ? w.dz_a[l - 1] : w.dz_c[l - 1]);
+            q.ldc = g.H[l - 1];
+            q.H = wsp(ws, net == 0 ? w.h_a[l - 1] : w.h_c[l - 1]);
+            q.ldh = g.H[l - 1];
+            q.M = M;
+            q.N = g.H[l - 1];
+            add_problem(args, q, bk);
+        }
+        PROFILED(prof, PPO_PHASE_INPUT_GRAD, launch_gemm(prec, 0, 1, kEpiDElu, args, s));
+    }
+
+    // weight gradients (split over samples) and the gradient segments
+    ReduceArgs red{};
+    long long pos = 0;
+    float *part = reinterpret_cast<float *>(wsp(ws, w.part));
+    float *rows_part = reinterpret_cast<float *>(wsp(ws, w.rowsum));
+    size_t part_off = 0, row_off = 0;
+    GemmArgs args{};
+    auto flush = [&](void) -> hipError_t {
+        PROFILED(prof, PPO_PHASE_WEIGHT_GRAD, launch_gemm(prec, 1, 1, kEpiPartial, args, s));
+        args = GemmArgs{};
+        return hipSuccess;
+    };
+    for (int net = 0; net < 2; ++net) {
+        for (int l = 0; l <= L; ++l) {
+            int r, cc;
+            dw_shape(g, net == 0, l, r, cc);
+            GemmProblem q{};
+            if (l == L) {
+                q.A = wsp(ws, net == 0 ? w.dzh_a : w.dzh_c);
+                q.lda = kHeadPad;
+            } else {
+                q.A = wsp(ws, net == 0 ? w.dz_a[l] : w.dz_c[l]);
+                q.lda = g.H[l];
+            }
+            if (l == 0) {
+                q.B = wsp(ws, w.xg);
+                q.ldb = w.kpad;
+            } else {
+                q.B = wsp(ws, net == 0 ? w.h_a[l - 1] : w.h_c[l - 1]);
+                q.ldb = g.H[l - 1];
+            }
+            q.M = r;
+            q.N = cc;
+            q.K = M;
+            q.C = part + part_off;
+            q.ldc = cc;
+            q.c_split_stride = static_cast<long long>(r) * cc;
+            q.rowsum = rows_part + row_off;
+            q.splits = w.splits;
+            q.kps = w.kps;
+            if (args.count == kGemmMaxProblems) {
+                e = flush();
+                if (e != hipSuccess) return e;
+            }
+            add_problem(args, q, bk);
+
+            const long long woff = net == 0 ? g.Wa[l] : g.Wc[l];
+            const long long boff = net == 0 ? g.ba[l] : g.bc[l];
+            ReduceSegment sw{part + part_off, static_cast<long long>(r) * cc, w.splits, r, cc, cc, woff, pos, 0.0f};
+            red.seg[red.count++] = sw;
+            pos += static_cast<long long>(r) * cc;
+            ReduceSegment sbias{rows_part + row_off, r, w.splits, 1, r, 0, boff, pos, 0.0f};
+            red.seg[red.count++] = sbias;
+            pos += r;
+            part_off += align_up(static_cast<size_t>(w.splits) * r * cc, 64);
+            row_off += align_up(static_cast<size_t>(w.splits) * r, 64);
+        }
+    }
+    e = flush();
+    if (e != hipSuccess) return e;
+    const int lw = head_loss_partial_width(g.A);
+    red.total = pos;
+    red.grad = sb.grad;
+    red.sumsq_partials = reinterpret_cast<double *>(wsp(ws, w.sumsq));
+    red.loss_partials = reinterpret_cast<const float *>(wsp(ws, w.loss_part));
+    red.n_loss = head_loss_blocks(M);
+    red.loss_width = lw;
+    red.A = g.A;
+    red.logstd_offset = g.logstd;
+    red.entropy_coef = hp->entropy_coef;
+    red.loss_sums = reinterpret_cast<float *>(wsp(ws, w.loss_sums));
+    PROFILED(prof, PPO_PHASE_GRAD_REDUCE, launch_grad_reduce(red, s));
+
+    AdamArgs ad{};
+    ad.theta = p->theta;
+    ad.grad = sb.grad;
+    ad.m = p->adam_m;
+    ad.v = p->adam_v;
+    ad.shadow = prec == kBF16 ? p->shadow : nullptr;
+    ad.step = p->step;
+    ad.step_offset = sb.step_offset;
+    ad.lr = p->lr;
+    ad.sumsq_partials = red.sumsq_partials;
+    ad.n_sumsq = reduce_blocks(red.total);
+    ad.loss_sums = red.loss_sums;
+    ad.max_grad_norm = hp->max_grad_norm;
+    ad.beta1 = hp->beta1;
+    ad.beta2 = hp->beta2;
+    ad.eps = hp->adam_eps;
+    ad.inv_m = 1.0f / static_cast<float>(M);
+    ad.value_coef = hp->value_coef;
+    ad.entropy_coef = hp->entropy_coef;
+    ad.stats = sb.stats;
+    ad.P = g.P;
+    ad.apply = sb.apply;
+    PROFILED(prof, PPO_PHASE_ADAM, launch_adam(ad, s));
+    return hipSuccess;
+}
+
+int validate_hparams(const ppo_hparams *hp) {
+    if (!hp) return fail(PPO_E_INVAL, "hparams is NULL");
+    if (!(hp->clip > 0.0f) || !(hp->value_coef >= 0.0f) || !(hp->entropy_coef >= 0.0f) ||
+        !(hp->max_grad_norm > 0.0f) || !(hp->beta1 >= 0.0f && hp->beta1 < 1.0f) ||
+        !(hp->beta2 >= 0.0f && hp->beta2 < 1.0f) || !(hp->adam_eps > 0.0f))
+        return fail(PPO_E_INVAL, "hyper-parameter out of range");
+    if (hp->clip_value != 0 && hp->clip_value != 1) return fail(PPO_E_INVAL, "clip_value must be 0 or 1");
+    if (hp->use_graph != 0 && hp->use_graph != 1) return fail(PPO_E_INVAL, "use_graph must be 0 or 1");
+    return PPO_OK;
+}
+
+int validate_params(const ppo_ctx *c, const ppo_params *p, bool need_optimizer) {
+    if (!p) return fail(PPO_E_INVAL, "params is NULL");
+    PPO_CHECK(check_ptr(p->theta, "params.theta"));
+    if (c->prec == kBF16) PPO_CHECK(check_ptr(p->shadow, "params.shadow"));
+    if (need_optimizer) {
+        PPO_CHECK(check_ptr(p->grad, "params.grad"));
+        PPO_CHECK(check_ptr(p->adam_m, "params.adam_m"));
+        PPO_CHECK(check_ptr(p->adam_v, "params.adam_v"));
+        if (!p->step) return fail(PPO_E_INVAL, "params.step is NULL");
+        if (!p->lr) return fail(PPO_E_INVAL, "params.lr is NULL");
+    }
+    return PPO_OK;
+}
+
+int validate_batch(const ppo_ctx *c, const ppo_batch *b, const ppo_hparams *hp) {
+    if (!b) return fail(PPO_E_INVAL, "batch is NULL");
+    if (b->B < 1) return fail(PPO_E_SHAPE, "batch.B = %d must be positive", b->B);
+    PPO_CHECK(check_ptr(b->obs, "batch.obs"));
+    PPO_CHECK(check_ptr(b->actions, "batch.actions"));
+    PPO_CHECK(check_ptr(b->logp, "batch.logp"));
+    PPO_CHECK(check_ptr(b->adv, "batch.adv"));
+    PPO_CHECK(check_ptr(b->returns, "batch.returns"));
+    if (hp->clip_value) PPO_CHECK(check_ptr(b->values, "batch.values"));
+    (void)c;
+    return PPO_OK;
+}
+
+int validate_ws(const ppo_ctx *c, int N, int T, int M, const void *ws, size_t ws_bytes) {
+    PPO_CHECK(check_ptr(ws, "ws"));
+    const WsPlan w = plan_workspace(c->g, c->prec, N, T, M);
+    if (ws_bytes < w.total)
+        return fail(PPO_E_NOMEM, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, w.total);
+    return PPO_OK;
+}
+
+int ensure_capture_stream(ppo_ctx *c) {
+    int dev = 0;
+    PPO_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (c->capture && c->capture_dev != dev) {
+        // graphs and the capture stream belong to the previous device
+        for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+        c->graphs.clear();
+        c->graph_order.clear();
+        (void)hipStreamDestroy(c->capture);
+        c->capture = nullptr;
+    }
+    if (!c->capture) {
+        PPO_HIP(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking), "hipStreamCreate");
+        c->capture_dev = dev;
+    }
+    return PPO_OK;
+}
+
+uint64_t u64(const void *p) { return static_cast<uint64_t>(reinterpret_cast<uintptr_t>(p)); }
+uint64_t fbits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+}
+
+}  // namespace
+
+// ================================================================ C ABI ====
+extern "C" {
+
+const char *ppo_last_error(void) { return g_error.c_str(); }
+
+int ppo_param_count(const ppo_net_desc *net, int64_t *count) {
+    PPO_CHECK(validate_net(net));
+    if (!count) return fail(PPO_E_INVAL, "count is NULL");
+    *count = make_layout(*net).P;
+    return PPO_OK;
+}
+
+int ppo_param_offsets(const ppo_net_desc *net, int64_t *offsets, int32_t capacity) {
+    PPO_CHECK(validate_net(net));
+    if (!offsets) return fail(PPO_E_INVAL, "offsets is NULL");
+    const NetLayout g = make_layout(*net);
+    const int need = 4 * (g.L + 1) + 1;
+    if (capacity < need) return fail(PPO_E_SHAPE, "offsets capacity %d < %d", capacity, need);
+    int k = 0;
+    for (int l = 0; l <= g.L; ++l) {
+        offsets[k++] = g.Wa[l];
+        offsets[k++] = g.ba[l];
+    }
+    offsets[k++] = g.logstd;
+    for (int l = 0; l <= g.L; ++l) {
+        offsets[k++] = g.Wc[l];
+        offsets[k++] = g.bc[l];
+    }
+    return PPO_OK;
+}
+
+int ppo_ctx_create(const ppo_net_desc *net, int32_t precision, ppo_ctx **out) {
+    PPO_CHECK(validate_net(net));
+    if (!out) return fail(PPO_E_INVAL, "out is NULL");
+    if (precision != PPO_FP32 && precision != PPO_BF16) return fail(PPO_E_INVAL, "precision %d", precision);
+    ppo_ctx *c = new (std::nothrow) ppo_ctx();
+    if (!c) return fail(PPO_E_INVAL, "out of host memory");
+    c->net = *net;
+    c->g = make_layout(*net);
+    c->prec = precision == PPO_BF16 ? kBF16 : kFP32;
+    *out = c;
+    return PPO_OK;
+}
+
+int ppo_ctx_destroy(ppo_ctx *c) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
+    delete c;
+    return PPO_OK;
+}
+
+int ppo_workspace_size(const ppo_ctx *c, int32_t N, int32_t T, int32_t M, size_t *bytes) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    if (!bytes) return fail(PPO_E_INVAL, "bytes is NULL");
+    if (N < 0 || T < 0 || M < 0) return fail(PPO_E_SHAPE, "negative size");
+    *bytes = plan_workspace(c->g, c->prec, N, T, M).total;
+    return PPO_OK;
+}
+
+int ppo_pack_weights(const ppo_ctx *c, void *stream, const float *theta, uint16_t *shadow) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    PPO_CHECK(check_ptr(theta, "theta"));
+    PPO_CHECK(check_ptr(shadow, "shadow"));
+    PPO_CHECK(check_device());
+    PPO_HIP(launch_pack_bf16(theta, shadow, c->g.P, static_cast<hipStream_t>(stream)), "pack_bf16");
+    return PPO_OK;
+}
+
+int ppo_rollout_infer(const ppo_ctx *c, void *stream, const ppo_params *p, const float *obs, int32_t N, int32_t t,
+                      uint64_t seed, uint32_t iteration, float *actions, float *logp, float *values, float *mu,
+                      void *ws, size_t ws_bytes) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    if (N < 1) return fail(PPO_E_SHAPE, "N = %d must be positive", N);
+    if (t < 0) return fail(PPO_E_SHAPE, "t = %d must be non-negative", t);
+    PPO_CHECK(validate_params(c, p, false));
+    PPO_CHECK(check_ptr(obs, "obs"));
+    const bool value_only = actions == nullptr;
+    PPO_CHECK(check_ptr(actions, "actions", true));
+    PPO_CHECK(check_ptr(logp, "logp", true));
+    PPO_CHECK(check_ptr(values, "values", !value_only));
+    PPO_CHECK(check_ptr(mu, "mu", true));
+    if (value_only && !values) return fail(PPO_E_INVAL, "value-only mode needs values");
+    PPO_CHECK(validate_ws(c, N, 0, 0, ws, ws_bytes));
+    PPO_CHECK(check_device());
+
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const NetLayout &g = c->g;
+    const WsPlan w = plan_workspace(g, c->prec, N, 0, 0);
+    PPO_HIP(launch_gather_obs(c->prec, s, obs, nullptr, N, N, g.D, w.kpad, wsp(ws, w.xg)), "gather_obs");
+    PPO_HIP(enqueue_forward(c, p, w, ws, N, !value_only, values != nullptr, s), "forward GEMM");
+    HeadSampleArgs a{};
+    a.ha = wsp(ws, w.h_a[g.L - 1]);
+    a.hc = wsp(ws, w.h_c[g.L - 1]);
+    a.Wa = p->theta + g.Wa[g.L];
+    a.ba = p->theta + g.ba[g.L];
+    a.logstd = p->theta + g.logstd;
+    a.Wc = p->theta + g.Wc[g.L];
+    a.bc = p->theta + g.bc[g.L];
+    a.actions = actions;
+    a.logp = logp;
+    a.values = values;
+    a.mu = mu;
+    a.N = N;
+    a.A = g.A;
+    a.Hl = g.H[g.L - 1];
+    a.key0 = static_cast<uint32_t>(seed);
+    a.key1 = static_cast<uint32_t>(seed >> 32);
+    a.t = static_cast<uint32_t>(t);
+    a.iteration = iteration;
+    a.value_only = value_only ? 1 : 0;
+    PPO_HIP(launch_head_sample(c->prec, a, s), "head_sample");
+    return PPO_OK;
+}
+
+int ppo_gae(const ppo_ctx *c, void *stream, const float *rewards, const uint8_t *dones, const uint8_t *timeouts,
+            const float *values, const float *last_values, int32_t T, int32_t N, float gamma, float lam, float *adv,
+            float *returns, double *adv_stats, int32_t normalize, void *ws, size_t ws_bytes) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    if (T < 1 || T > PPO_MAX_T) return fail(PPO_E_SHAPE, "T = %d outside 1..%d", T, PPO_MAX_T);
+    if (N < 1) return fail(PPO_E_SHAPE, "N = %d must be positive", N);
+    if (static_cast<long long>(T) * N < 2) return fail(PPO_E_SHAPE, "T * N must be at least 2");
+    PPO_CHECK(check_ptr(rewards, "rewards"));
+    PPO_CHECK(check_ptr(dones, "dones"));
+    PPO_CHECK(check_ptr(timeouts, "timeouts", true));
+    PPO_CHECK(check_ptr(values, "values"));
+    PPO_CHECK(check_ptr(last_values, "last_values"));
+    PPO_CHECK(check_ptr(adv, "adv"));
+    PPO_CHECK(check_ptr(returns, "returns"));
+    PPO_CHECK(check_ptr(adv_stats, "adv_stats"));
+    if (!(gamma >= 0.0f && gamma <= 1.0f) || !(lam >= 0.0f && lam <= 1.0f))
+        return fail(PPO_E_INVAL, "gamma and lambda must lie in [0, 1]");
+    if (normalize != 0 && normalize != 1) return fail(PPO_E_INVAL, "normalize must be 0 or 1");
+    PPO_CHECK(validate_ws(c, N, T, 0, ws, ws_bytes));
+    PPO_CHECK(check_device());
+
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const WsPlan w = plan_workspace(c->g, c->prec, N, T, 0);
+    GaeArgs a{};
+    a.rewards = rewards;
+    a.values = values;
+    a.last_values = last_values;
+    a.dones = dones;
+    a.timeouts = timeouts;
+    a.adv = adv;
+    a.returns = returns;
+    a.partials = reinterpret_cast<double *>(wsp(ws, w.gae_part));
+    a.T = T;
+    a.N = N;
+    a.gamma = gamma;
+    a.lam = lam;
+    PPO_HIP(launch_gae(a, s), "gae");
+    PPO_HIP(launch_adv_finalize(a.partials, gae_blocks(N), adv, static_cast<long long>(T) * N, adv_stats, normalize, s),
+            "adv_finalize");
+    return PPO_OK;
+}
+
+int ppo_loss_grad(const ppo_ctx *c, void *stream, const ppo_params *p, const ppo_batch *b, const int32_t *idx,
+                  int32_t M, const ppo_hparams *hp, float *stats, float *grad_out, void *ws, size_t ws_bytes) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    PPO_CHECK(validate_hparams(hp));
+    PPO_CHECK(validate_params(c, p, false));
+    PPO_CHECK(validate_batch(c, b, hp));
+    if (M < 1 || M > b->B) return fail(PPO_E_SHAPE, "M = %d outside 1..B", M);
+    PPO_CHECK(check_ptr(idx, "idx"));
+    PPO_CHECK(check_ptr(stats, "stats"));
+    PPO_CHECK(check_ptr(grad_out, "grad_out"));
+    PPO_CHECK(validate_ws(c, 0, 0, M, ws, ws_bytes));
+    PPO_CHECK(check_device());
+    const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
+    StepBuffers sb{b, idx, M, grad_out, stats, 0, 0};
+    PPO_HIP(enqueue_step(c, p, hp, w, ws, sb, static_cast<hipStream_t>(stream)), "loss_grad");
+    return PPO_OK;
+}
+
+int ppo_update_epoch(ppo_ctx *c, void *stream, const ppo_params *p, const ppo_batch *b, const int32_t *perm,
+                     int32_t n_minibatches, const ppo_hparams *hp, float *stats, void *ws, size_t ws_bytes) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    PPO_CHECK(validate_hparams(hp));
+    PPO_CHECK(validate_params(c, p, true));
+    PPO_CHECK(validate_batch(c, b, hp));
+    if (!perm) return fail(PPO_E_SHAPE, "perm is NULL");
+    PPO_CHECK(check_ptr(perm, "perm"));
+    if (n_minibatches < 1 || n_minibatches > b->B) return fail(PPO_E_SHAPE, "n_minibatches = %d", n_minibatches);
+    if (b->B % n_minibatches != 0)
+        return fail(PPO_E_SHAPE, "B = %d is not divisible by n_minibatches = %d", b->B, n_minibatches);
+    PPO_CHECK(check_ptr(stats, "stats"));
+    const int M = b->B / n_minibatches;
+    PPO_CHECK(validate_ws(c, 0, 0, M, ws, ws_bytes));
+    PPO_CHECK(check_device());
+
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
+    auto enqueue_all = [&](hipStream_t target) -> hipError_t {
+        for (int k = 0; k < n_minibatches; ++k) {
+            StepBuffers sb{b, perm + static_cast<long long>(k) * M, M, p->grad, stats + k * PPO_STATS_WIDTH, 1, k};
+            hipError_t e = enqueue_step(c, p, hp, w, ws, sb, target);
+            if (e != hipSuccess) return e;
+        }
+        return launch_step_advance(p->step, n_minibatches, target);
+    };
+    if (!hp->use_graph) {
+        PPO_HIP(enqueue_all(s), "update_epoch");
+        return PPO_OK;
+    }
+
+    std::lock_guard<std::mutex> lk(c->mu);
+    PPO_CHECK(ensure_capture_stream(c));
+    std::vector<uint64_t> key = {u64(p->theta), u64(p->grad), u64(p->adam_m), u64(p->adam_v), u64(p->shadow),
+                                 u64(p->step), u64(p->lr), u64(b->obs), u64(b->actions), u64(b->logp),
+                                 u64(b->adv), u64(b->returns), u64(b->values), static_cast<uint64_t>(b->B),
+                                 u64(perm), static_cast<uint64_t>(n_minibatches), u64(stats), u64(ws),
+                                 fbits(hp->clip), fbits(hp->value_coef), fbits(hp->entropy_coef),
+                                 fbits(hp->max_grad_norm), fbits(hp->beta1), fbits(hp->beta2), fbits(hp->adam_eps),
+                                 static_cast<uint64_t>(hp->clip_value)};
+    auto it = c->graphs.find(key);
+    hipGraphExec_t exec = nullptr;
+    if (it != c->graphs.end()) {
+        exec = it->second;
+    } else {
+        PPO_HIP(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        hipError_t e = enqueue_all(c->capture);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->capture, &graph);
+        if (e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(e, "capture of update_epoch");
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        if (c->graphs.size() >= kMaxGraphs) {
+            auto old = c->graphs.find(c->graph_order.front());
+            if (old != c->graphs.end()) {
+                (void)hipGraphExecDestroy(old->second);
+                c->graphs.erase(old);
+            }
+            c->graph_order.erase(c->graph_order.begin());
+        }
+        c->graphs[key] = exec;
+        c->graph_order.push_back(key);
+    }
+    PPO_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
+    return PPO_OK;
+}
+
+int ppo_update_epoch_profiled(ppo_ctx *c, void *stream, const ppo_params *p, const ppo_batch *b,
+                              const int32_t *perm, int32_t n_minibatches, const ppo_hparams *hp, float *stats,
+                              void *ws, size_t ws_bytes, float *phase_ms, int32_t *phase_launches) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    if (!phase_ms || !phase_launches) return fail(PPO_E_INVAL, "phase_ms and phase_launches are required");
+    PPO_CHECK(validate_hparams(hp));
+    PPO_CHECK(validate_params(c, p, true));
+    PPO_CHECK(validate_batch(c, b, hp));
+    if (!perm) return fail(PPO_E_SHAPE, "perm is NULL");
+    PPO_CHECK(check_ptr(perm, "perm"));
+    if (n_minibatches < 1 || n_minibatches > b->B) return fail(PPO_E_SHAPE, "n_minibatches = %d", n_minibatches);
+    if (b->B % n_minibatches != 0)
+        return fail(PPO_E_SHAPE, "B = %d is not divisible by n_minibatches = %d", b->B, n_minibatches);
+    PPO_CHECK(check_ptr(stats, "stats"));
+    const int M = b->B / n_minibatches;
+    PPO_CHECK(validate_ws(c, 0, 0, M, ws, ws_bytes));
+    PPO_CHECK(check_device());
+
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
+    Profiler prof;
+    prof.s = s;
+    for (int k = 0; k < n_minibatches; ++k) {
+        StepBuffers sb{b, perm + static_cast<long long>(k) * M, M, p->grad, stats + k * PPO_STATS_WIDTH, 1, k};
+        PPO_HIP(enqueue_step(c, p, hp, w, ws, sb, s, &prof), "update_epoch (profiled)");
+    }
+    PPO_HIP(launch_step_advance(p->step, n_minibatches, s), "step_advance");
+    PPO_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int q = 0; q < PPO_N_PHASES; ++q) {
+        phase_ms[q] = 0.0f;
+        phase_launches[q] = 0;
+    }
+    for (size_t i = 0; i < prof.phase.size(); ++i) {
+        float ms = 0.0f;
+        PPO_HIP(hipEventElapsedTime(&ms, prof.ev[2 * i], prof.ev[2 * i + 1]), "hipEventElapsedTime");
+        phase_ms[prof.phase[i]] += ms;
+        phase_launches[prof.phase[i]] += 1;
+    }
+    return PPO_OK;
+}
+
+int ppo_gemm_check(void *stream, int32_t precision, int32_t a_mode, int32_t b_mode, int32_t epilogue, int32_t M,
+                   int32_t N, int32_t K, const void *A, int32_t lda, const void *B, int32_t ldb, void *C,
+                   int32_t ldc, const float *bias, const void *H, int32_t ldh, float *rowsum, int32_t splits) {
+    if (precision != PPO_FP32 && precision != PPO_BF16) return fail(PPO_E_INVAL, "precision %d", precision);
+    const bool combo_ok = (a_mode == 0 && b_mode == 0 && epilogue == kEpiBiasElu) ||
+                          (a_mode == 0 && b_mode == 1 && epilogue == kEpiDElu) ||
+                          (a_mode == 1 && b_mode == 1 && epilogue == kEpiPartial);
+    if (!combo_ok) return fail(PPO_E_INVAL, "unsupported operand modes / epilogue combination");
+    if (M < 1 || N < 1 || K < 1) return fail(PPO_E_SHAPE, "M, N, K must be positive");
+    if (lda < (a_mode == 0 ? K : M) || ldb < (b_mode == 0 ? K : N) || ldc < N)
+        return fail(PPO_E_SHAPE, "leading dimension too small");
+    PPO_CHECK(check_ptr(A, "A"));
+    PPO_CHECK(check_ptr(B, "B"));
+    PPO_CHECK(check_ptr(C, "C"));
+    if (epilogue == kEpiBiasElu) PPO_CHECK(check_ptr(bias, "bias"));
+    if (epilogue == kEpiDElu) {
+        PPO_CHECK(check_ptr(H, "H"));
+        if (ldh < N) return fail(PPO_E_SHAPE, "ldh too small");
+    }
+    if (epilogue == kEpiPartial) PPO_CHECK(check_ptr(rowsum, "rowsum"));
+    if (splits < 1 || (epilogue != kEpiPartial && splits != 1)) return fail(PPO_E_SHAPE, "splits = %d", splits);
+    PPO_CHECK(check_device());
+    const Precision prec = precision == PPO_BF16 ? kBF16 : kFP32;
+    const int bk = gemm_bk(prec);
+    GemmArgs args{};
+    GemmProblem q{};
+    q.A = A;
+    q.B = B;
+    q.C = C;
+    q.bias = bias;
+    q.H = H;
+    q.rowsum = rowsum;
+    q.M = M;
+    q.N = N;
+    q.K = K;
+    q.lda = lda;
+    q.ldb = ldb;
+    q.ldc = ldc;
+    q.ldh = ldh;
+    q.c_split_stride = static_cast<long long>(M) * ldc;
+    if (epilogue == kEpiPartial) {
+        q.kps = cdiv(cdiv(K, splits), bk) * bk;
+        q.splits = cdiv(K, q.kps);
+    }
+    add_problem(args, q, bk);
+    PPO_HIP(launch_gemm(prec, a_mode, b_mode, epilogue, args, static_cast<hipStream_t>(stream)), "gemm");
+    return PPO_OK;
+}
+
+int ppo_philox_blocks(void *stream, uint64_t seed, uint32_t c0_base, uint32_t c1, uint32_t c2, uint32_t c3,
+                      int64_t n, uint32_t *out) {
+    if (n < 1 || n > (static_cast<int64_t>(1) << 28)) return fail(PPO_E_SHAPE, "n = %lld outside 1..2^28", (long long)n);
+    PPO_CHECK(check_ptr(out, "out"));
+    PPO_CHECK(check_device());
+    PPO_HIP(launch_philox_blocks(static_cast<hipStream_t>(stream), seed, c0_base, c1, c2, c3, n, out), "philox");
+    return PPO_OK;
+}
+
+}  // extern "C"
