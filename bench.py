@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 plain-path timing")
     ap.add_argument("--fp32-steps", type=int, default=3)
+    ap.add_argument("--quick", action="store_true",
+                    help="only the timed steps (for profiler runs): no parts, roofline, fp32 or CPU legs")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -285,9 +289,22 @@ def main():
 
     wl = Workload(cfg, "bf16", dev)
     s_step = time_steps(wl, args.steps, args.warmup)
+    B = cfg.batch
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.quick:
+        print(json.dumps({"metric": METRIC, "value": round(B / s_step, 1), "unit": "samples/s",
+                          "ms_per_step": round(s_step * 1e3, 3), "steps": args.steps, "warmup": args.warmup,
+                          "quick": True}), flush=True)
+        return
     parts = time_parts(wl)
     roof, phases, gemm_tflops = roofline(wl, "bf16")
-    B = cfg.batch
     out = {
         "metric": METRIC,
         "value": round(B / s_step, 1),
@@ -309,6 +326,8 @@ def main():
         "roofline": roof,
         "phases_bf16": phases,
         "gemm_tflops_bf16": gemm_tflops,
+        "autotuned_tiles": {"update": wl.ctx.tuning(cfg.minibatch, True),
+                            "rollout": wl.ctx.tuning(cfg.n_envs, False)},
     }
     if not args.no_fp32:
         wl32 = Workload(cfg, "fp32", dev)

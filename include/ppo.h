@@ -25,7 +25,8 @@
  *     a call that returns an error has enqueued nothing.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Every call is asynchronous on that stream and never synchronises the
- *     host, except ppo_ctx_create/destroy.
+ *     host, except ppo_ctx_create/destroy, first-use autotuning (below) and
+ *     ppo_update_epoch_profiled.
  *   - Ownership: the caller allocates and owns all device memory (rollout
  *     buffers, parameters, optimiser state, statistics, workspace) and keeps
  *     it alive until the enqueued work has completed.  The library never
@@ -35,6 +36,12 @@
  *     (no strides) in the layouts given below.
  *   - Sample index s = t * N + n over a rollout (time-major, environment
  *     contiguous).
+ *   - Autotuning: the first call for a given row count (N for inference, M
+ *     for the update) times the GEMM tile candidates of every launch site
+ *     with HIP events on the caller's stream and waits for them (the only
+ *     host synchronisation outside ctx create/destroy); the choice is cached
+ *     in the context, and in the file named by the environment variable
+ *     PPO_TUNE_CACHE if set.  PPO_AUTOTUNE=0 keeps 128 x 128 tiles.
  */
 #ifndef PPO_MI355X_PPO_H
 #define PPO_MI355X_PPO_H
@@ -232,11 +239,19 @@ int ppo_update_epoch_profiled(ppo_ctx *ctx, void *stream, const ppo_params *p, c
  *   (1, 1, epilogue 2): C[s, M, ldc] float32 partial sums over `splits` slices
  *                       of K, rowsum[s, M] = per-slice row sums of A.
  * The number of slices actually used is ceil(K / kps), kps = ceil(K / splits)
- * rounded up to the kernel's k-slab. */
+ * rounded up to the kernel's k-slab.  tile: output tile per workgroup,
+ * 0 = 128 x 128, 1 = 64 x 128, 2 = 128 x 64, 3 = 64 x 64 (rows x columns). */
 int ppo_gemm_check(void *stream, int32_t precision, int32_t a_mode, int32_t b_mode, int32_t epilogue,
                    int32_t M, int32_t N, int32_t K, const void *A, int32_t lda, const void *B,
                    int32_t ldb, void *C, int32_t ldc, const float *bias, const void *H, int32_t ldh,
-                   float *rowsum, int32_t splits);
+                   float *rowsum, int32_t splits, int32_t tile);
+
+/* Tile choices recorded for `rows` GEMM rows (update != 0: the update's
+ * sites, else inference).  choices[2 s] = tile shape (as in
+ * ppo_gemm_check), choices[2 s + 1] = split rounds, for sites
+ * s = 0..3 forward layer s, 4..7 input gradient of layer s - 4, 8 weight
+ * gradients.  capacity >= 18.  PPO_E_SHAPE if nothing was tuned yet. */
+int ppo_ctx_tuning(const ppo_ctx *ctx, int32_t rows, int32_t update, int32_t *choices, int32_t capacity);
 
 /* Debug/verification: raw Philox4x32-10 blocks.  out[4 i + w] = word w of
  * Philox(counter = (c0_base + i mod 2^32, c1, c2, c3), key = (seed mod 2^32,

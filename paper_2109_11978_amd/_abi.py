@@ -67,7 +67,8 @@ EXPORTS = {
                                             POINTER(c_int32)]),
     "ppo_gemm_check": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32, c_int32,
                                  c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_int32, c_void_p, c_void_p,
-                                 c_int32, c_void_p, c_int32]),
+                                 c_int32, c_void_p, c_int32, c_int32]),
+    "ppo_ctx_tuning": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), c_int32]),
     "ppo_philox_blocks": (c_int32, [c_void_p, c_uint64, c_uint32, c_uint32, c_uint32, c_uint32, c_int64,
                                     c_void_p]),
 }

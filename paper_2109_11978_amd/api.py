@@ -115,6 +115,21 @@ class Context:
         check(_lib().ppo_workspace_size(self.handle, N, T, M, ctypes.byref(n)))
         return n.value
 
+    TILE_NAMES = ("128x128", "64x128", "128x64", "64x64")
+
+    def tuning(self, rows: int, update: bool) -> Dict[str, object]:
+        """Tile choices the autotuner recorded for `rows` GEMM rows."""
+        arr = (ctypes.c_int32 * 18)()
+        check(_lib().ppo_ctx_tuning(self.handle, rows, int(update), arr, 18))
+        out = {}
+        for l in range(len(self.hidden)):
+            out[f"forward_{l + 1}"] = self.TILE_NAMES[arr[2 * l]]
+        if update:
+            for l in range(1, len(self.hidden)):
+                out[f"input_grad_{l + 1}"] = self.TILE_NAMES[arr[2 * (4 + l)]]
+            out["weight_grad"] = f"{self.TILE_NAMES[arr[16]]} x {arr[17]} round(s) of splits"
+        return out
+
     def new_workspace(self, N: int = 0, T: int = 0, M: int = 0, device="cuda") -> torch.Tensor:
         nbytes = self.workspace_size(N, T, M)
         return torch.empty(max(nbytes, 16), dtype=torch.uint8, device=device)
@@ -233,14 +248,15 @@ def ppo_update_epoch_profiled(ctx: Context, params: Params, batch: Dict[str, tor
 
 def ppo_gemm_check(precision: str, a_mode: int, b_mode: int, epilogue: int, M: int, N: int, K: int,
                    A: torch.Tensor, lda: int, B: torch.Tensor, ldb: int, C: torch.Tensor, ldc: int,
-                   bias=None, H=None, ldh: int = 0, rowsum=None, splits: int = 1, stream=None) -> None:
+                   bias=None, H=None, ldh: int = 0, rowsum=None, splits: int = 1, tile: int = 0,
+                   stream=None) -> None:
     """One launch of the library GEMM (verification entry point)."""
     et = torch.int16 if precision == "bf16" else torch.float32
     ct = torch.float32 if epilogue == 2 else et
     check(_lib().ppo_gemm_check(_stream(stream), PPO_BF16 if precision == "bf16" else PPO_FP32, a_mode, b_mode,
                                 epilogue, M, N, K, _ptr(A, et, "A"), lda, _ptr(B, et, "B"), ldb, _ptr(C, ct, "C"),
                                 ldc, _ptr(bias, torch.float32, "bias", True), _ptr(H, et, "H", True), ldh,
-                                _ptr(rowsum, torch.float32, "rowsum", True), splits))
+                                _ptr(rowsum, torch.float32, "rowsum", True), splits, tile))
 
 
 def ppo_philox_blocks(seed: int, c0: int, c1: int, c2: int, c3: int, out: torch.Tensor, stream=None) -> None:

@@ -11,7 +11,7 @@ constexpr int kMaxHidden = 4;
 constexpr int kMaxLayers = kMaxHidden + 1;
 constexpr int kStatsWidth = 8;
 constexpr int kHeadPad = 16;        // output-layer gradient rows padded to 16 columns
-constexpr int kGemmMaxProblems = 8;
+constexpr int kGemmMaxProblems = 16;
 
 enum Precision { kFP32 = 0, kBF16 = 1 };
 
@@ -69,16 +69,22 @@ struct GemmProblem {
     int tile_begin;
 };
 
+// Output tile shapes (rows x columns per workgroup of 4 wave64s).
+enum GemmTileShape { kTile128x128 = 0, kTile64x128 = 1, kTile128x64 = 2, kTile64x64 = 3, kNumTileShapes = 4 };
+inline int tile_rows(int t) { return (t == kTile64x128 || t == kTile64x64) ? 64 : 128; }
+inline int tile_cols(int t) { return (t == kTile128x64 || t == kTile64x64) ? 64 : 128; }
+
 struct GemmArgs {
     GemmProblem p[kGemmMaxProblems];
     int count;
     int total_tiles;
+    int tile;    // GemmTileShape shared by every problem of the launch
 };
 
-// Tile geometry shared with the host planner.
+// k-slab depth per operand type (shared with the host planner).
 template <typename T> struct GemmTile;
-template <> struct GemmTile<uint16_t> { static constexpr int BM = 128, BN = 128, BK = 64; };
-template <> struct GemmTile<float> { static constexpr int BM = 128, BN = 128, BK = 32; };
+template <> struct GemmTile<uint16_t> { static constexpr int BK = 64; };
+template <> struct GemmTile<float> { static constexpr int BK = 32; };
 
 hipError_t launch_gemm(Precision prec, int a_mode, int b_mode, int epi, const GemmArgs &args,
                        hipStream_t stream);

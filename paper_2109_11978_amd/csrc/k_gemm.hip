@@ -157,8 +157,10 @@ struct TileLoader {
                 const int kv = (u % (BK / VEC)) * VEC;
                 r[p] = load_rowmajor<T>(src, ld, r0 + row, k0 + kv, R, kend, vec_ok);
             } else {
-                const int rb = u % (ROWS / VEC);
-                const int kb = u / (ROWS / VEC);
+                // k-block fastest across lanes: the transposed LDS rows written by
+                // neighbouring lanes then fall on disjoint banks (see store()).
+                const int kb = u % (BK / VEC);
+                const int rb = u / (BK / VEC);
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
                     r[p * VEC + e] = load_transposed<T>(src, ld, r0 + rb * VEC, k0 + kb * VEC + e, R, kend, vec_ok);
@@ -176,8 +178,8 @@ struct TileLoader {
                 const int kv = (u % (BK / VEC)) * VEC;
                 *reinterpret_cast<u32x4 *>(lds + row * PITCH + kv) = r[p];
             } else {
-                const int rb = u % (ROWS / VEC);
-                const int kb = u / (ROWS / VEC);
+                const int kb = u % (BK / VEC);
+                const int rb = u / (BK / VEC);
 #pragma unroll
                 for (int i = 0; i < VEC; ++i)
                     *reinterpret_cast<u32x4 *>(lds + (rb * VEC + i) * PITCH + kb * VEC) =
@@ -187,9 +189,22 @@ struct TileLoader {
     }
 };
 
-template <typename T, int AMODE, int BMODE, int EPI>
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Give XCD x a contiguous range of logical tiles, so neighbouring
+// tiles -- which share an A row block (forward, input gradient) or a k-range
+// of both operands (weight gradient) -- are served from the same L2.
+constexpr int kXcds = 8;
+__device__ inline int xcd_swizzle(int b, int n) {
+    const int xcd = b % kXcds, slot = b / kXcds;
+    const int q = n / kXcds, r = n % kXcds;
+    return xcd * q + min(xcd, r) + slot;
+}
+
+template <typename T, int BM, int BN, int AMODE, int BMODE, int EPI>
 __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) {
-    constexpr int BM = GemmTile<T>::BM, BN = GemmTile<T>::BN, BK = GemmTile<T>::BK;
+    constexpr int BK = GemmTile<T>::BK;
+    constexpr int WM = BM / 2, WN = BN / 2;   // per-wave tile (2 x 2 waves)
+    constexpr int MI = WM / 32, NJ = WN / 32;  // 32 x 32 MFMA blocks per wave
     constexpr int VEC = 16 / sizeof(T);
     constexpr int PITCH = BK + VEC;
     constexpr int KC = 2 * VEC;  // k covered by one 16-byte read in each lane-half
@@ -200,7 +215,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
 
     __shared__ __attribute__((aligned(16))) T lds[2][(BM + BN) * PITCH];
 
-    const int bid = blockIdx.x;
+    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
     int pi = 0;
     while (pi + 1 < args.count && bid >= args.p[pi + 1].tile_begin) ++pi;
     const GemmProblem &P = args.p[pi];
@@ -229,15 +244,16 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     const int lrow = lane & 31;
     const int lk = (lane >> 5) * VEC;
 
-    floatx16 acc[2][2];
+    floatx16 acc[MI][NJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
     const bool do_rowsum = (EPI == kEpiPartial) && tn == 0;
+    constexpr int TPR = kThreads / BM;
     float rowsum = 0.0f;
 
     LA la;
@@ -262,24 +278,24 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
         const T *Bs = &lds[cur][BM * PITCH];
 #pragma unroll
         for (int kc = 0; kc < BK / KC; ++kc) {
-            u32x4 a[2], b[2];
+            u32x4 a[MI], b[NJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a[i] = *reinterpret_cast<const u32x4 *>(As + (wm * 64 + i * 32 + lrow) * PITCH + kc * KC + lk);
+            for (int i = 0; i < MI; ++i)
+                a[i] = *reinterpret_cast<const u32x4 *>(As + (wm * WM + i * 32 + lrow) * PITCH + kc * KC + lk);
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                b[j] = *reinterpret_cast<const u32x4 *>(Bs + (wn * 64 + j * 32 + lrow) * PITCH + kc * KC + lk);
+            for (int j = 0; j < NJ; ++j)
+                b[j] = *reinterpret_cast<const u32x4 *>(Bs + (wn * WN + j * 32 + lrow) * PITCH + kc * KC + lk);
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < MI; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) Mma<T>::mac(acc[i][j], a[i], b[j]);
+                for (int j = 0; j < NJ; ++j) Mma<T>::mac(acc[i][j], a[i], b[j]);
         }
         if (do_rowsum) {
-            // Two threads per row of A, each summing half of the slab.
-            const int row = tid >> 1;
-            const T *src = As + row * PITCH + (tid & 1) * (BK / 2);
+            // TPR adjacent threads per row of A, each summing a part of the slab.
+            const int row = tid / TPR;
+            const T *src = As + row * PITCH + (tid % TPR) * (BK / TPR);
 #pragma unroll
-            for (int e = 0; e < BK / 2; ++e) rowsum += Elem<T>::to_f(src[e]);
+            for (int e = 0; e < BK / TPR; ++e) rowsum += Elem<T>::to_f(src[e]);
         }
         if (more) {
             la.store(&lds[cur ^ 1][0], tid);
@@ -290,114 +306,128 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
 
     if constexpr (EPI == kEpiPartial) {
         if (do_rowsum) {
-            rowsum += __shfl_xor(rowsum, 1);
-            const int row = m0 + (tid >> 1);
-            if ((tid & 1) == 0 && row < P.M) P.rowsum[static_cast<long long>(split) * P.M + row] = rowsum;
+#pragma unroll
+            for (int o = 1; o < TPR; o <<= 1) rowsum += __shfl_xor(rowsum, o);
+            const int row = m0 + tid / TPR;
+            if (tid % TPR == 0 && row < P.M) P.rowsum[static_cast<long long>(split) * P.M + row] = rowsum;
         }
     }
 
-    // Epilogue: accumulators -> LDS (float32, per-wave 64 x 64 tile) -> each
-    // lane takes 8 consecutive columns of a row, applies the epilogue and
-    // writes them with one 16-byte (bf16) or two 16-byte (float32) stores.
-    // Rows are padded to 72 floats so the two lane halves hit disjoint banks.
-    constexpr int EP = 72;
-    static_assert(4 * 64 * EP * 4 <= sizeof(lds), "epilogue staging must fit in the tile buffers");
-    float *stage = reinterpret_cast<float *>(&lds[0][0]) + wave * 64 * EP;
+    // Epilogue: accumulators -> LDS (float32, per-wave WM x WN tile) -> each
+    // lane takes 4 consecutive columns of a row, applies the epilogue and
+    // writes them with one 8-byte (bf16) or 16-byte (float32) store.  Rows are
+    // padded to EP = WN + 8 floats (EP = 8 mod 16), so the two lane halves of
+    // the scattered accumulator writes (rows 4 apart) hit disjoint banks.
+    constexpr int EP = WN + 8;
+    static_assert(4 * WM * EP * 4 <= sizeof(lds), "epilogue staging must fit in the tile buffers");
+    float *stage = reinterpret_cast<float *>(&lds[0][0]) + wave * WM * EP;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 stage[(i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * EP + j * 32 + lrow] = acc[i][j][r];
     __syncthreads();
 
-    const int sub_r = lane >> 3;
-    const int sub_c = (lane & 7) * 8;
-    const int col = n0 + wn * 64 + sub_c;
-    const bool full_cols = col + 8 <= P.N;
+    // WN / 4 lanes cover one staged row (4 floats each): for WN = 64 every
+    // 16-lane group of a 16-byte LDS read touches all 64 banks once.
+    constexpr int CW = 4;
+    constexpr int LPR = WN / CW;         // lanes per staged row
+    constexpr int RPI = 64 / LPR;        // rows per iteration
+    const int sub_r = lane / LPR;
+    const int sub_c = (lane % LPR) * CW;
+    const int col = n0 + wn * WN + sub_c;
+    const bool full_cols = col + CW <= P.N;
     if (col >= P.N) return;
-    float bias[8];
+    float bias[CW];
     if constexpr (EPI == kEpiBiasElu) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bias[e] = (col + e < P.N) ? P.bias[col + e] : 0.0f;
+        for (int e = 0; e < CW; ++e) bias[e] = (col + e < P.N) ? P.bias[col + e] : 0.0f;
     }
-    const bool c_vec = full_cols && (P.ldc % 8) == 0 && (reinterpret_cast<uintptr_t>(P.C) & 15u) == 0;
-    const bool h_vec = full_cols && (P.ldh % 8) == 0 && (reinterpret_cast<uintptr_t>(P.H) & 15u) == 0;
-#pragma unroll 2
-    for (int it = 0; it < 8; ++it) {
-        const int lr = it * 8 + sub_r;
-        const int row = m0 + wm * 64 + lr;
+    const bool c_vec = full_cols && (P.ldc % CW) == 0 && (reinterpret_cast<uintptr_t>(P.C) & 15u) == 0;
+    const bool h_vec = full_cols && (P.ldh % CW) == 0 && (reinterpret_cast<uintptr_t>(P.H) & 15u) == 0;
+#pragma unroll 4
+    for (int it = 0; it < WM / RPI; ++it) {
+        const int lr = it * RPI + sub_r;
+        const int row = m0 + wm * WM + lr;
         if (row >= P.M) break;
-        float v[8];
+        float v[CW];
         *reinterpret_cast<float4 *>(&v[0]) = *reinterpret_cast<const float4 *>(stage + lr * EP + sub_c);
-        *reinterpret_cast<float4 *>(&v[4]) = *reinterpret_cast<const float4 *>(stage + lr * EP + sub_c + 4);
         if constexpr (EPI == kEpiPartial) {
             float *dst = static_cast<float *>(P.C) + split * P.c_split_stride + static_cast<long long>(row) * P.ldc + col;
             if (c_vec) {
-                reinterpret_cast<float4 *>(dst)[0] = *reinterpret_cast<const float4 *>(&v[0]);
-                reinterpret_cast<float4 *>(dst)[1] = *reinterpret_cast<const float4 *>(&v[4]);
+                *reinterpret_cast<float4 *>(dst) = *reinterpret_cast<const float4 *>(&v[0]);
             } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
+                for (int e = 0; e < CW; ++e)
                     if (col + e < P.N) dst[e] = v[e];
             }
         } else {
             if constexpr (EPI == kEpiBiasElu) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = Act<T>::elu(v[e] + bias[e]);
+                for (int e = 0; e < CW; ++e) v[e] = Act<T>::elu(v[e] + bias[e]);
             } else {
                 const T *hsrc = static_cast<const T *>(P.H) + static_cast<long long>(row) * P.ldh + col;
-                T h[8];
+                T h[CW];
                 if (h_vec) {
                     if constexpr (sizeof(T) == 2) {
-                        *reinterpret_cast<u32x4 *>(h) = *reinterpret_cast<const u32x4 *>(hsrc);
+                        *reinterpret_cast<uint2 *>(h) = *reinterpret_cast<const uint2 *>(hsrc);
                     } else {
-                        reinterpret_cast<u32x4 *>(h)[0] = reinterpret_cast<const u32x4 *>(hsrc)[0];
-                        reinterpret_cast<u32x4 *>(h)[1] = reinterpret_cast<const u32x4 *>(hsrc)[1];
+                        *reinterpret_cast<u32x4 *>(h) = *reinterpret_cast<const u32x4 *>(hsrc);
                     }
                 } else {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) h[e] = (col + e < P.N) ? hsrc[e] : T(0);
+                    for (int e = 0; e < CW; ++e) h[e] = (col + e < P.N) ? hsrc[e] : T(0);
                 }
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
+                for (int e = 0; e < CW; ++e) {
                     const float hv = Elem<T>::to_f(h[e]);
                     v[e] *= hv > 0.0f ? 1.0f : hv + 1.0f;
                 }
             }
-            T out[8];
+            T out[CW];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) out[e] = Act<T>::store(v[e]);
+            for (int e = 0; e < CW; ++e) out[e] = Act<T>::store(v[e]);
             T *dst = static_cast<T *>(P.C) + static_cast<long long>(row) * P.ldc + col;
             if (c_vec) {
                 if constexpr (sizeof(T) == 2) {
-                    *reinterpret_cast<u32x4 *>(dst) = *reinterpret_cast<const u32x4 *>(out);
+                    *reinterpret_cast<uint2 *>(dst) = *reinterpret_cast<const uint2 *>(out);
                 } else {
-                    reinterpret_cast<u32x4 *>(dst)[0] = reinterpret_cast<const u32x4 *>(out)[0];
-                    reinterpret_cast<u32x4 *>(dst)[1] = reinterpret_cast<const u32x4 *>(out)[1];
+                    *reinterpret_cast<u32x4 *>(dst) = *reinterpret_cast<const u32x4 *>(out);
                 }
             } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
+                for (int e = 0; e < CW; ++e)
                     if (col + e < P.N) dst[e] = out[e];
             }
         }
     }
 }
 
-template <typename T>
-hipError_t launch_typed(int a_mode, int b_mode, int epi, const GemmArgs &args, hipStream_t s) {
+template <typename T, int BM, int BN>
+hipError_t launch_tiled(int a_mode, int b_mode, int epi, const GemmArgs &args, hipStream_t s) {
     dim3 grid(args.total_tiles), block(kThreads);
     if (a_mode == 0 && b_mode == 0 && epi == kEpiBiasElu)
-        hipLaunchKernelGGL((gemm_kernel<T, 0, 0, kEpiBiasElu>), grid, block, 0, s, args);
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 0, kEpiBiasElu>), grid, block, 0, s, args);
     else if (a_mode == 0 && b_mode == 1 && epi == kEpiDElu)
-        hipLaunchKernelGGL((gemm_kernel<T, 0, 1, kEpiDElu>), grid, block, 0, s, args);
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 1, kEpiDElu>), grid, block, 0, s, args);
     else if (a_mode == 1 && b_mode == 1 && epi == kEpiPartial)
-        hipLaunchKernelGGL((gemm_kernel<T, 1, 1, kEpiPartial>), grid, block, 0, s, args);
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 1, 1, kEpiPartial>), grid, block, 0, s, args);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_typed(int a_mode, int b_mode, int epi, const GemmArgs &args, hipStream_t s) {
+    switch (args.tile) {
+        case kTile128x128: return launch_tiled<T, 128, 128>(a_mode, b_mode, epi, args, s);
+        case kTile64x128: return launch_tiled<T, 64, 128>(a_mode, b_mode, epi, args, s);
+        case kTile128x64: return launch_tiled<T, 128, 64>(a_mode, b_mode, epi, args, s);
+        case kTile64x64: return launch_tiled<T, 64, 64>(a_mode, b_mode, epi, args, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace

@@ -81,7 +81,9 @@ __global__ void gather_obs_kernel(const float *obs, const int32_t *idx, int src_
 
 // ------------------------------------------------- output-layer helpers
 constexpr int kHeadThreads = 256;
-constexpr int kHeadRows = 64;   // samples (or environments) per block
+constexpr int kLossRows = 64;     // mini-batch samples per block (loss)
+constexpr int kSampleRows = 16;   // environments per block (rollout)
+constexpr int kWPad = 4;          // floats of row padding for staged output-layer weights
 
 // 8 consecutive activations of one row as float32.
 template <typename T>
@@ -101,19 +103,44 @@ __device__ inline void load8(const T *src, float (&x)[8]) {
     }
 }
 
-// Output layers for a block of rows: out[i][j] = b_j + h_i . W_j for the A
-// actor outputs (j < A) and the critic value (j == A); one dot product per
-// thread, rows shared through L1.  Hl is a multiple of 16.
-template <typename T>
-__device__ inline void output_layers(const T *ha, const T *hc, const float *Wa, const float *ba, const float *Wc,
-                                     const float *bc, int r0, int rows, int A, int Hl, bool actor,
-                                     float (*out)[kMaxAct + 1]) {
+// Output-layer weights of both networks: rows j < A are the actor's, row A
+// the critic's, each padded to Hl + kWPad floats.  Staged in LDS when they
+// fit (dynamic shared memory), else read from global memory.
+struct HeadWeights {
+    const float *w;
+    int pitch;
+};
+
+__device__ inline HeadWeights stage_head_weights(float *s_w, bool in_lds, const float *Wa, const float *Wc, int A,
+                                                 int Hl) {
+    if (!in_lds) return HeadWeights{nullptr, 0};
+    const int pitch = Hl + kWPad;
+    for (int q = threadIdx.x; q < (A + 1) * Hl; q += blockDim.x) {
+        const int j = q / Hl, k = q - (q / Hl) * Hl;
+        s_w[j * pitch + k] = j < A ? Wa[static_cast<long long>(j) * Hl + k] : Wc[k];
+    }
+    __syncthreads();
+    return HeadWeights{s_w, pitch};
+}
+
+__device__ inline const float *head_row(const HeadWeights &hw, const float *Wa, const float *Wc, int A, int Hl,
+                                        int j) {
+    if (hw.w) return hw.w + j * hw.pitch;
+    return j < A ? Wa + static_cast<long long>(j) * Hl : Wc;
+}
+
+// out[i][j] = b_j + h_i . W_j for the A actor outputs (j < A) and the critic
+// value (j == A); one dot product per thread.  Hl is a multiple of 16.
+template <typename T, int ROWS>
+__device__ inline void output_layers(const T *ha, const T *hc, const HeadWeights &hw, const float *Wa,
+                                     const float *ba, const float *Wc, const float *bc, int r0, int rows, int A,
+                                     int Hl, bool actor, float (*out)[kMaxAct + 1]) {
     const int n_out = A + 1;
-    for (int q = threadIdx.x; q < kHeadRows * n_out; q += kHeadThreads) {
+    for (int q = threadIdx.x; q < ROWS * n_out; q += kHeadThreads) {
         const int i = q / n_out, j = q - (q / n_out) * n_out;
         if (i >= rows || (j < A && !actor)) continue;
         const T *h = (j < A ? ha : hc) + static_cast<long long>(r0 + i) * Hl;
-        const float *w = j < A ? Wa + static_cast<long long>(j) * Hl : Wc;
+        const float *w = head_row(hw, Wa, Wc, A, Hl, j);
         float acc = j < A ? ba[j] : bc[0];
         for (int k = 0; k < Hl; k += 8) {
             float x[8];
@@ -126,18 +153,20 @@ __device__ inline void output_layers(const T *ha, const T *hc, const float *Wa, 
 }
 
 // ----------------------------------------------------------- head + sample
-// Rollout: mu = h_a Wa^T + ba and V = h_c Wc^T + bc for 64 environments per
+// Rollout: mu = h_a Wa^T + ba and V = h_c Wc^T + bc for 16 environments per
 // block, then one lane per environment draws the diagonal-Gaussian action
 // a = mu + sigma * eps with Philox noise and its log-density
 // sum_j(-eps_j^2 / 2 - log sigma_j) - (A/2) log(2 pi).
 template <typename T>
-__global__ __launch_bounds__(kHeadThreads) void head_sample_kernel(const HeadSampleArgs a) {
-    __shared__ float s_out[kHeadRows][kMaxAct + 1];
-    const int r0 = blockIdx.x * kHeadRows;
-    const int rows = min(kHeadRows, a.N - r0);
+__global__ __launch_bounds__(kHeadThreads) void head_sample_kernel(const HeadSampleArgs a, int w_in_lds) {
+    extern __shared__ float s_w[];
+    __shared__ float s_out[kSampleRows][kMaxAct + 1];
+    const int r0 = blockIdx.x * kSampleRows;
+    const int rows = min(kSampleRows, a.N - r0);
     const int A = a.A;
-    output_layers<T>(static_cast<const T *>(a.ha), static_cast<const T *>(a.hc), a.Wa, a.ba, a.Wc, a.bc, r0, rows,
-                     A, a.Hl, !a.value_only, s_out);
+    const HeadWeights hw = stage_head_weights(s_w, w_in_lds, a.Wa, a.Wc, A, a.Hl);
+    output_layers<T, kSampleRows>(static_cast<const T *>(a.ha), static_cast<const T *>(a.hc), hw, a.Wa, a.ba, a.Wc,
+                                  a.bc, r0, rows, A, a.Hl, !a.value_only, s_out);
     __syncthreads();
     const int i = threadIdx.x;
     if (i >= rows) return;
@@ -174,18 +203,18 @@ __global__ __launch_bounds__(kHeadThreads) void head_sample_kernel(const HeadSam
 // hidden pre-activations (8-wide row segments, coalesced).  Per-block sums of
 // the loss terms and of the log-std gradient go to `partials` (wave-0
 // shuffle reduction, fixed order).
-constexpr int kLossThreads = kHeadThreads;
-
 template <typename T>
-__global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossArgs a) {
-    __shared__ float s_out[kHeadRows][kMaxAct + 1];
-    const int r0 = blockIdx.x * kHeadRows;
-    const int rows = min(kHeadRows, a.M - r0);
+__global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossArgs a, int w_in_lds) {
+    extern __shared__ float s_w[];
+    __shared__ float s_out[kLossRows][kMaxAct + 1];
+    const int r0 = blockIdx.x * kLossRows;
+    const int rows = min(kLossRows, a.M - r0);
     const int A = a.A, Hl = a.Hl;
     const int W = A + 8;
     const T *ha = static_cast<const T *>(a.ha);
     const T *hc = static_cast<const T *>(a.hc);
-    output_layers<T>(ha, hc, a.Wa, a.ba, a.Wc, a.bc, r0, rows, A, Hl, true, s_out);
+    const HeadWeights hw = stage_head_weights(s_w, w_in_lds, a.Wa, a.Wc, A, Hl);
+    output_layers<T, kLossRows>(ha, hc, hw, a.Wa, a.ba, a.Wc, a.bc, r0, rows, A, Hl, true, s_out);
     __syncthreads();
 
     const int tid = threadIdx.x;
@@ -274,9 +303,9 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
 
     // gradient into the last hidden pre-activations, both networks
     const int chunks = Hl / 8;
-    for (int q = tid; q < 2 * kHeadRows * chunks; q += kHeadThreads) {
-        const int net = q / (kHeadRows * chunks);
-        const int rem = q - net * kHeadRows * chunks;
+    for (int q = tid; q < 2 * kLossRows * chunks; q += kHeadThreads) {
+        const int net = q / (kLossRows * chunks);
+        const int rem = q - net * kLossRows * chunks;
         const int i = rem / chunks;
         const int k = (rem - i * chunks) * 8;
         if (i >= rows) continue;
@@ -288,14 +317,15 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
             for (int e = 0; e < 8; ++e) g[e] = 0.0f;
             for (int j = 0; j < A; ++j) {
                 const float gm = s_out[i][j];
-                const float *w = a.Wa + static_cast<long long>(j) * Hl + k;
+                const float *w = head_row(hw, a.Wa, a.Wc, A, Hl, j) + k;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) g[e] += gm * w[e];
             }
         } else {
             const float gv = s_out[i][A];
+            const float *w = head_row(hw, a.Wa, a.Wc, A, Hl, A) + k;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) g[e] = gv * a.Wc[k + e];
+            for (int e = 0; e < 8; ++e) g[e] = gv * w[e];
         }
         T o[8];
 #pragma unroll
@@ -547,24 +577,32 @@ hipError_t launch_gather_obs(Precision prec, hipStream_t s, const float *obs, co
     return hipGetLastError();
 }
 
+// Dynamic LDS for the staged output-layer weights, 0 when they do not fit.
+size_t head_weight_lds(int A, int Hl) {
+    const size_t bytes = static_cast<size_t>(A + 1) * (Hl + kWPad) * sizeof(float);
+    return bytes <= 48 * 1024 ? bytes : 0;
+}
+
 hipError_t launch_head_sample(Precision prec, const HeadSampleArgs &a, hipStream_t s) {
-    const dim3 grid((a.N + kHeadRows - 1) / kHeadRows), block(kHeadThreads);
+    const dim3 grid((a.N + kSampleRows - 1) / kSampleRows), block(kHeadThreads);
+    const size_t shm = head_weight_lds(a.A, a.Hl);
     if (prec == kBF16)
-        hipLaunchKernelGGL(head_sample_kernel<uint16_t>, grid, block, 0, s, a);
+        hipLaunchKernelGGL(head_sample_kernel<uint16_t>, grid, block, shm, s, a, shm > 0 ? 1 : 0);
     else
-        hipLaunchKernelGGL(head_sample_kernel<float>, grid, block, 0, s, a);
+        hipLaunchKernelGGL(head_sample_kernel<float>, grid, block, shm, s, a, shm > 0 ? 1 : 0);
     return hipGetLastError();
 }
 
-int head_loss_blocks(int M) { return (M + kHeadRows - 1) / kHeadRows; }
+int head_loss_blocks(int M) { return (M + kLossRows - 1) / kLossRows; }
 int head_loss_partial_width(int A) { return A + 8; }
 
 hipError_t launch_head_loss(Precision prec, const HeadLossArgs &a, hipStream_t s) {
-    const dim3 grid(head_loss_blocks(a.M)), block(kLossThreads);
+    const dim3 grid(head_loss_blocks(a.M)), block(kHeadThreads);
+    const size_t shm = head_weight_lds(a.A, a.Hl);
     if (prec == kBF16)
-        hipLaunchKernelGGL(head_loss_kernel<uint16_t>, grid, block, 0, s, a);
+        hipLaunchKernelGGL(head_loss_kernel<uint16_t>, grid, block, shm, s, a, shm > 0 ? 1 : 0);
     else
-        hipLaunchKernelGGL(head_loss_kernel<float>, grid, block, 0, s, a);
+        hipLaunchKernelGGL(head_loss_kernel<float>, grid, block, shm, s, a, shm > 0 ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -133,7 +134,7 @@ struct WsPlan {
     Region dz_a[kMaxHidden], dz_c[kMaxHidden];
     Region dzh_a, dzh_c;
     Region part, rowsum, loss_part, loss_sums, sumsq, gae_part;
-    int splits = 1, kps = 0;
+    int max_splits = 1;
     size_t total = 0;
 };
 
@@ -148,10 +149,7 @@ struct Alloc {
     }
 };
 
-template <typename T> int bk_of() { return GemmTile<T>::BK; }
-
 int gemm_bk(Precision p) { return p == kBF16 ? GemmTile<uint16_t>::BK : GemmTile<float>::BK; }
-constexpr int kTileM = 128, kTileN = 128;
 
 // Output shape of the weight-gradient problem of layer l (0-based, l == L is
 // the output layer) for one network.
@@ -160,20 +158,41 @@ void dw_shape(const NetLayout &g, bool actor, int l, int &rows, int &cols) {
     cols = l == 0 ? g.D : g.H[l - 1];
 }
 
-void choose_splits(const NetLayout &g, Precision prec, int M, int &splits, int &kps) {
+int dw_tiles(const NetLayout &g, int tile) {
     int tiles = 0;
     for (int net = 0; net < 2; ++net)
         for (int l = 0; l <= g.L; ++l) {
             int r, c;
             dw_shape(g, net == 0, l, r, c);
-            tiles += cdiv(r, kTileM) * cdiv(c, kTileN);
+            tiles += cdiv(r, tile_rows(tile)) * cdiv(c, tile_cols(tile));
         }
+    return tiles;
+}
+
+// Two workgroups are resident on each of 256 CUs.  A weight-gradient
+// workgroup streams its k-range at a roughly fixed time per k-slab, so a
+// launch takes (rounds of resident workgroups) x (slabs per workgroup):
+// split into `rounds` whole rounds, never a partial extra round.
+constexpr int kResidentSlots = 512;
+
+void dw_splits(const NetLayout &g, Precision prec, int M, int tile, int rounds, int &splits, int &kps) {
     const int bk = gemm_bk(prec);
-    const int target = 512;  // two resident workgroups on each of 256 CUs
-    int s = std::max(1, cdiv(target, tiles));
+    int s = std::max(1, rounds * kResidentSlots / dw_tiles(g, tile));
     s = std::min(s, std::max(1, M / (2 * bk)));
     kps = cdiv(cdiv(M, s), bk) * bk;
     splits = cdiv(M, kps);
+}
+
+// Largest split count any tuning candidate may use (sizes the partials).
+int dw_max_splits(const NetLayout &g, Precision prec, int M) {
+    int best = 1;
+    for (int t = 0; t < kNumTileShapes; ++t)
+        for (int rounds = 1; rounds <= 2; ++rounds) {
+            int sp, kps;
+            dw_splits(g, prec, M, t, rounds, sp, kps);
+            best = std::max(best, sp);
+        }
+    return best;
 }
 
 WsPlan plan_workspace(const NetLayout &g, Precision prec, int N, int T, int M) {
@@ -195,14 +214,14 @@ WsPlan plan_workspace(const NetLayout &g, Precision prec, int N, int T, int M) {
     }
     w.dzh_a = a.take(static_cast<size_t>(mm) * kHeadPad * w.esz);
     w.dzh_c = a.take(static_cast<size_t>(mm) * kHeadPad * w.esz);
-    choose_splits(g, prec, mm, w.splits, w.kps);
+    w.max_splits = dw_max_splits(g, prec, mm);
     size_t part_floats = 0, rowsum_floats = 0;
     for (int net = 0; net < 2; ++net)
         for (int l = 0; l <= g.L; ++l) {
             int r, c;
             dw_shape(g, net == 0, l, r, c);
-            part_floats += align_up(static_cast<size_t>(w.splits) * r * c, 64);
-            rowsum_floats += align_up(static_cast<size_t>(w.splits) * r, 64);
+            part_floats += align_up(static_cast<size_t>(w.max_splits) * r * c, 64);
+            rowsum_floats += align_up(static_cast<size_t>(w.max_splits) * r, 64);
         }
     w.part = a.take(part_floats * 4);
     w.rowsum = a.take(rowsum_floats * 4);
@@ -238,6 +257,19 @@ int check_device() {
     return PPO_OK;
 }
 
+// ----------------------------------------------------------- tile choices
+// GEMM launch sites of one mini-batch step (or one rollout step).
+enum Site { kSiteFwd = 0, kSiteDx = kMaxHidden, kSiteDw = 2 * kMaxHidden, kNumSites = 2 * kMaxHidden + 1 };
+
+struct TileChoice {
+    int tile = kTile128x128;
+    int rounds = 1;  // weight-gradient splits: whole rounds of resident workgroups
+};
+
+struct Tuning {
+    TileChoice site[kNumSites];
+};
+
 }  // namespace
 
 // ------------------------------------------------------------------ context
@@ -250,6 +282,7 @@ struct ppo_ctx {
     int capture_dev = -1;
     std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
     std::vector<std::vector<uint64_t>> graph_order;  // insertion order for eviction
+    std::map<int, Tuning> tuned;                      // GEMM rows -> measured tile choices
 };
 
 namespace {
@@ -320,8 +353,8 @@ struct Profiler {
 
 void add_problem(GemmArgs &args, const GemmProblem &proto, int bk) {
     GemmProblem p = proto;
-    p.tiles_m = cdiv(p.M, kTileM);
-    p.tiles_n = cdiv(p.N, kTileN);
+    p.tiles_m = cdiv(p.M, tile_rows(args.tile));
+    p.tiles_n = cdiv(p.N, tile_cols(args.tile));
     if (p.splits <= 0) {
         p.splits = 1;
         p.kps = cdiv(p.K, bk) * bk;
@@ -331,31 +364,301 @@ void add_problem(GemmArgs &args, const GemmProblem &proto, int bk) {
     args.total_tiles += p.tiles_m * p.tiles_n * p.splits;
 }
 
+// Forward GEMM of hidden layer l for `rows` rows (input gathered in xg).
+GemmArgs build_fwd(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *ws, int rows, int l, bool actor,
+                   bool critic, int tile) {
+    const NetLayout &g = c->g;
+    const Weights W = gemm_weights(c, p);
+    GemmArgs args{};
+    args.tile = tile;
+    for (int net = 0; net < 2; ++net) {
+        if ((net == 0 && !actor) || (net == 1 && !critic)) continue;
+        GemmProblem q{};
+        q.A = l == 0 ? static_cast<const void *>(wsp(ws, w.xg))
+                     : static_cast<const void *>(wsp(ws, net == 0 ? w.h_a[l - 1] : w.h_c[l - 1]));
+        q.lda = l == 0 ? w.kpad : g.H[l - 1];
+        q.K = l == 0 ? g.D : g.H[l - 1];
+        q.B = W.W[net][l];
+        q.ldb = q.K;
+        q.C = wsp(ws, net == 0 ? w.h_a[l] : w.h_c[l]);
+        q.ldc = g.H[l];
+        q.bias = p->theta + (net == 0 ? g.ba[l] : g.bc[l]);
+        q.M = rows;
+        q.N = g.H[l];
+        add_problem(args, q, gemm_bk(c->prec));
+    }
+    return args;
+}
+
+// Input-gradient GEMM: dz_{l-1} = (dz_l W_l) * ELU'(z_{l-1}) for both networks.
+GemmArgs build_dx(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *ws, int M, int l, int tile) {
+    const NetLayout &g = c->g;
+    const Weights W = gemm_weights(c, p);
+    GemmArgs args{};
+    args.tile = tile;
+    for (int net = 0; net < 2; ++net) {
+        GemmProblem q{};
+        q.A = wsp(ws, net == 0 ? w.dz_a[l] : w.dz_c[l]);
+        q.lda = g.H[l];
+        q.K = g.H[l];
+        q.B = W.W[net][l];
+        q.ldb = g.H[l - 1];
+        q.C = wsp(ws, net == 0 ? w.dz_a[l - 1] : w.dz_c[l - 1]);
+        q.ldc = g.H[l - 1];
+        q.H = wsp(ws, net == 0 ? w.h_a[l - 1] : w.h_c[l - 1]);
+        q.ldh = g.H[l - 1];
+        q.M = M;
+        q.N = g.H[l - 1];
+        add_problem(args, q, gemm_bk(c->prec));
+    }
+    return args;
+}
+
+// Weight-gradient GEMMs of every layer of both networks (split over the
+// samples) and the gradient segments that sum their partials.
+struct DwPlan {
+    GemmArgs launch[2];
+    int n_launch = 0;
+    ReduceArgs red{};
+};
+
+DwPlan build_dw(const ppo_ctx *c, const WsPlan &w, void *ws, int M, const TileChoice &tc) {
+    const NetLayout &g = c->g;
+    const int L = g.L;
+    DwPlan d;
+    int splits, kps;
+    dw_splits(g, c->prec, M, tc.tile, tc.rounds, splits, kps);
+    long long pos = 0;
+    float *part = reinterpret_cast<float *>(wsp(ws, w.part));
+    float *rows_part = reinterpret_cast<float *>(wsp(ws, w.rowsum));
+    size_t part_off = 0, row_off = 0;
+    d.launch[0] = GemmArgs{};
+    d.launch[0].tile = tc.tile;
+    for (int net = 0; net < 2; ++net) {
+        for (int l = 0; l <= L; ++l) {
+            int r, cc;
+            dw_shape(g, net == 0, l, r, cc);
+            GemmProblem q{};
+            if (l == L) {
+                q.A = wsp(ws, net == 0 ? w.dzh_a : w.dzh_c);
+                q.lda = kHeadPad;
+            } else {
+                q.A = wsp(ws, net == 0 ? w.dz_a[l] : w.dz_c[l]);
+                q.lda = g.H[l];
+            }
+            if (l == 0) {
+                q.B = wsp(ws, w.xg);
+                q.ldb = w.kpad;
+            } else {
+                q.B = wsp(ws, net == 0 ? w.h_a[l - 1] : w.h_c[l - 1]);
+                q.ldb = g.H[l - 1];
+            }
+            q.M = r;
+            q.N = cc;
+            q.K = M;
+            q.C = part + part_off;
+            q.ldc = cc;
+            q.c_split_stride = static_cast<long long>(r) * cc;
+            q.rowsum = rows_part + row_off;
+            q.splits = splits;
+            q.kps = kps;
+            GemmArgs &cur = d.launch[d.n_launch];
+            add_problem(cur, q, gemm_bk(c->prec));
+            if (cur.count == kGemmMaxProblems && !(net == 1 && l == L)) {
+                ++d.n_launch;
+                d.launch[d.n_launch] = GemmArgs{};
+                d.launch[d.n_launch].tile = tc.tile;
+            }
+
+            const long long woff = net == 0 ? g.Wa[l] : g.Wc[l];
+            const long long boff = net == 0 ? g.ba[l] : g.bc[l];
+            d.red.seg[d.red.count++] = ReduceSegment{part + part_off, static_cast<long long>(r) * cc, splits, r, cc,
+                                                     cc, woff, pos, 0.0f};
+            pos += static_cast<long long>(r) * cc;
+            d.red.seg[d.red.count++] = ReduceSegment{rows_part + row_off, r, splits, 1, r, 0, boff, pos, 0.0f};
+            pos += r;
+            part_off += align_up(static_cast<size_t>(splits) * r * cc, 64);
+            row_off += align_up(static_cast<size_t>(splits) * r, 64);
+        }
+    }
+    ++d.n_launch;
+    d.red.total = pos;
+    return d;
+}
+
+// ------------------------------------------------------------- autotuner
+// Each GEMM launch site picks its tile shape (and, for the weight
+// gradients, its split rounds) by timing every candidate with HIP events on
+// the caller's stream the first time a row count is seen.  Candidates touch
+// only the workspace regions they would write anyway, so the timing launches
+// leave no trace.  Results are kept per context and row count, and in the
+// file named by PPO_TUNE_CACHE if set; PPO_AUTOTUNE=0 keeps the defaults.
+std::mutex g_tune_file_mu;
+
+std::string tune_key(const ppo_ctx *c, int rows, bool update) {
+    std::string k = std::string(c->prec == kBF16 ? "bf16" : "fp32") + "|" + std::to_string(c->g.D) + "|" +
+                    std::to_string(c->g.A) + "|";
+    for (int l = 0; l < c->g.L; ++l) k += std::to_string(c->g.H[l]) + ",";
+    k += "|" + std::to_string(rows) + (update ? "|u" : "|r");
+    return k;
+}
+
+bool tune_file_lookup(const std::string &key, Tuning &t) {
+    const char *path = std::getenv("PPO_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::lock_guard<std::mutex> lk(g_tune_file_mu);
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        char k[512];
+        int n = 0;
+        if (std::sscanf(line, "%511s%n", k, &n) != 1 || key != k) continue;
+        const char *q = line + n;
+        Tuning tmp;
+        bool ok = true;
+        for (int i = 0; i < kNumSites && ok; ++i) {
+            int used = 0;
+            ok = std::sscanf(q, "%d %d%n", &tmp.site[i].tile, &tmp.site[i].rounds, &used) == 2 &&
+                 tmp.site[i].tile >= 0 && tmp.site[i].tile < kNumTileShapes && tmp.site[i].rounds >= 1 &&
+                 tmp.site[i].rounds <= 2;
+            q += used;
+        }
+        if (ok) {
+            t = tmp;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_file_store(const std::string &key, const Tuning &t) {
+    const char *path = std::getenv("PPO_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lk(g_tune_file_mu);
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s", key.c_str());
+    for (int i = 0; i < kNumSites; ++i) std::fprintf(f, " %d %d", t.site[i].tile, t.site[i].rounds);
+    std::fprintf(f, "\n");
+    std::fclose(f);
+}
+
+// Median-free small timing: one warm-up launch, then `reps` launches between
+// two events.
+template <typename F>
+hipError_t time_launch(hipStream_t s, F &&launch, int reps, float &ms) {
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return e;
+    }
+    e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return e;
+}
+
+bool autotune_enabled() {
+    const char *v = std::getenv("PPO_AUTOTUNE");
+    return !(v && std::strcmp(v, "0") == 0);
+}
+
+// Tile choices for `rows` GEMM rows; `update` adds the input- and
+// weight-gradient sites.  Must not be called while the stream is captured.
+int ensure_tuned(const ppo_ctx *cc, const ppo_params *p, const WsPlan &w, void *ws, int rows, bool update,
+                 hipStream_t s, Tuning &out) {
+    ppo_ctx *c = const_cast<ppo_ctx *>(cc);
+    const int key_rows = update ? -rows : rows;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->tuned.find(key_rows);
+        if (it != c->tuned.end()) {
+            out = it->second;
+            return PPO_OK;
+        }
+    }
+    Tuning t;
+    const std::string key = tune_key(c, rows, update);
+    if (autotune_enabled() && !tune_file_lookup(key, t)) {
+        const NetLayout &g = c->g;
+        const Precision prec = c->prec;
+        const int reps = 3;
+        for (int l = 0; l < g.L; ++l) {
+            float best = 1e30f;
+            for (int tile = 0; tile < kNumTileShapes; ++tile) {
+                GemmArgs a = build_fwd(c, p, w, ws, rows, l, true, true, tile);
+                float ms = 0.0f;
+                PPO_HIP(time_launch(s, [&] { return launch_gemm(prec, 0, 0, kEpiBiasElu, a, s); }, reps, ms),
+                        "autotune forward");
+                if (ms < best) {
+                    best = ms;
+                    t.site[kSiteFwd + l].tile = tile;
+                }
+            }
+        }
+        if (update) {
+            for (int l = 1; l < g.L; ++l) {
+                float best = 1e30f;
+                for (int tile = 0; tile < kNumTileShapes; ++tile) {
+                    GemmArgs a = build_dx(c, p, w, ws, rows, l, tile);
+                    float ms = 0.0f;
+                    PPO_HIP(time_launch(s, [&] { return launch_gemm(prec, 0, 1, kEpiDElu, a, s); }, reps, ms),
+                            "autotune input gradient");
+                    if (ms < best) {
+                        best = ms;
+                        t.site[kSiteDx + l].tile = tile;
+                    }
+                }
+            }
+            float best = 1e30f;
+            for (int tile = 0; tile < kNumTileShapes; ++tile)
+                for (int rounds = 1; rounds <= 2; ++rounds) {
+                    TileChoice tc;
+                    tc.tile = tile;
+                    tc.rounds = rounds;
+                    DwPlan d = build_dw(c, w, ws, rows, tc);
+                    float ms = 0.0f;
+                    PPO_HIP(time_launch(
+                                s,
+                                [&] {
+                                    hipError_t r = hipSuccess;
+                                    for (int i = 0; i < d.n_launch && r == hipSuccess; ++i)
+                                        r = launch_gemm(prec, 1, 1, kEpiPartial, d.launch[i], s);
+                                    return r;
+                                },
+                                reps, ms),
+                            "autotune weight gradient");
+                    if (ms < best) {
+                        best = ms;
+                        t.site[kSiteDw] = tc;
+                    }
+                }
+        }
+        tune_file_store(key, t);
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->tuned[key_rows] = t;
+    out = t;
+    return PPO_OK;
+}
+
 // Forward through the hidden layers of the selected networks for `rows`
 // rows whose gathered input is already in the xg region.
 hipError_t enqueue_forward(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *ws, int rows,
-                           bool actor, bool critic, hipStream_t s, Profiler *prof = nullptr) {
-    const NetLayout &g = c->g;
-    const Weights W = gemm_weights(c, p);
-    const int bk = gemm_bk(c->prec);
-    for (int l = 0; l < g.L; ++l) {
-        GemmArgs args{};
-        for (int net = 0; net < 2; ++net) {
-            if ((net == 0 && !actor) || (net == 1 && !critic)) continue;
-            GemmProblem q{};
-            q.A = l == 0 ? static_cast<const void *>(wsp(ws, w.xg))
-                         : static_cast<const void *>(wsp(ws, net == 0 ? w.h_a[l - 1] : w.h_c[l - 1]));
-            q.lda = l == 0 ? w.kpad : g.H[l - 1];
-            q.K = l == 0 ? g.D : g.H[l - 1];
-            q.B = W.W[net][l];
-            q.ldb = q.K;
-            q.C = wsp(ws, net == 0 ? w.h_a[l] : w.h_c[l]);
-            q.ldc = g.H[l];
-            q.bias = p->theta + (net == 0 ? g.ba[l] : g.bc[l]);
-            q.M = rows;
-            q.N = g.H[l];
-            add_problem(args, q, bk);
-        }
+                           bool actor, bool critic, const Tuning &t, hipStream_t s, Profiler *prof = nullptr) {
+    for (int l = 0; l < c->g.L; ++l) {
+        const GemmArgs args = build_fwd(c, p, w, ws, rows, l, actor, critic, t.site[kSiteFwd + l].tile);
         PROFILED(prof, PPO_PHASE_FORWARD, launch_gemm(c->prec, 0, 0, kEpiBiasElu, args, s));
     }
     return hipSuccess;
@@ -374,17 +677,16 @@ struct StepBuffers {
 // One mini-batch step: gather, forward, head+loss, input-gradient chain,
 // weight gradients, gradient assembly with the float64 norm, Adam.
 hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp, const WsPlan &w, void *ws,
-                        const StepBuffers &sb, hipStream_t s, Profiler *prof = nullptr) {
+                        const StepBuffers &sb, const Tuning &t, hipStream_t s, Profiler *prof = nullptr) {
     const NetLayout &g = c->g;
     const Precision prec = c->prec;
     const int M = sb.M;
-    const int bk = gemm_bk(prec);
     const int L = g.L;
     hipError_t e;
 
     PROFILED(prof, PPO_PHASE_GATHER, launch_gather_obs(prec, s, sb.b->obs, sb.idx, sb.b->B, M, g.D, w.kpad,
                                                        wsp(ws, w.xg)));
-    e = enqueue_forward(c, p, w, ws, M, true, true, s, prof);
+    e = enqueue_forward(c, p, w, ws, M, true, true, t, s, prof);
     if (e != hipSuccess) return e;
 
     HeadLossArgs hl{};
@@ -416,90 +718,17 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
     hl.clip_value = hp->clip_value;
     PROFILED(prof, PPO_PHASE_HEAD_LOSS, launch_head_loss(prec, hl, s));
 
-    // input-gradient chain: dz_{l-1} = (dz_l W_l) * ELU'(z_{l-1}), l = L-1 .. 1
-    const Weights W = gemm_weights(c, p);
     for (int l = L - 1; l >= 1; --l) {
-        GemmArgs args{};
-        for (int net = 0; net < 2; ++net) {
-            GemmProblem q{};
-            q.A = wsp(ws, net == 0 ? w.dz_a[l] : w.dz_c[l]);
-            q.lda = g.H[l];
-            q.K = g.H[l];
-            q.B = W.W[net][l];
-            q.ldb = g.H[l - 1];
-            q.C = wsp(ws, net == 0 ? w.dz_a[l - 1] : w.dz_c[l - 1]);
-            q.ldc = g.H[l - 1];
-            q.H = wsp(ws, net == 0 ? w.h_a[l - 1] : w.h_c[l - 1]);
-            q.ldh = g.H[l - 1];
-            q.M = M;
-            q.N = g.H[l - 1];
-            add_problem(args, q, bk);
-        }
+        const GemmArgs args = build_dx(c, p, w, ws, M, l, t.site[kSiteDx + l].tile);
         PROFILED(prof, PPO_PHASE_INPUT_GRAD, launch_gemm(prec, 0, 1, kEpiDElu, args, s));
     }
 
-    // weight gradients (split over samples) and the gradient segments
-    ReduceArgs red{};
-    long long pos = 0;
-    float *part = reinterpret_cast<float *>(wsp(ws, w.part));
-    float *rows_part = reinterpret_cast<float *>(wsp(ws, w.rowsum));
-    size_t part_off = 0, row_off = 0;
-    GemmArgs args{};
-    auto flush = [&](void) -> hipError_t {
-        PROFILED(prof, PPO_PHASE_WEIGHT_GRAD, launch_gemm(prec, 1, 1, kEpiPartial, args, s));
-        args = GemmArgs{};
-        return hipSuccess;
-    };
-    for (int net = 0; net < 2; ++net) {
-        for (int l = 0; l <= L; ++l) {
-            int r, cc;
-            dw_shape(g, net == 0, l, r, cc);
-            GemmProblem q{};
-            if (l == L) {
-                q.A = wsp(ws, net == 0 ? w.dzh_a : w.dzh_c);
-                q.lda = kHeadPad;
-            } else {
-                q.A = wsp(ws, net == 0 ? w.dz_a[l] : w.dz_c[l]);
-                q.lda = g.H[l];
-            }
-            if (l == 0) {
-                q.B = wsp(ws, w.xg);
-                q.ldb = w.kpad;
-            } else {
-                q.B = wsp(ws, net == 0 ? w.h_a[l - 1] : w.h_c[l - 1]);
-                q.ldb = g.H[l - 1];
-            }
-            q.M = r;
-            q.N = cc;
-            q.K = M;
-            q.C = part + part_off;
-            q.ldc = cc;
-            q.c_split_stride = static_cast<long long>(r) * cc;
-            q.rowsum = rows_part + row_off;
-            q.splits = w.splits;
-            q.kps = w.kps;
-            if (args.count == kGemmMaxProblems) {
-                e = flush();
-                if (e != hipSuccess) return e;
-            }
-            add_problem(args, q, bk);
+    DwPlan d = build_dw(c, w, ws, M, t.site[kSiteDw]);
+    for (int i = 0; i < d.n_launch; ++i)
+        PROFILED(prof, PPO_PHASE_WEIGHT_GRAD, launch_gemm(prec, 1, 1, kEpiPartial, d.launch[i], s));
 
-            const long long woff = net == 0 ? g.Wa[l] : g.Wc[l];
-            const long long boff = net == 0 ? g.ba[l] : g.bc[l];
-            ReduceSegment sw{part + part_off, static_cast<long long>(r) * cc, w.splits, r, cc, cc, woff, pos, 0.0f};
-            red.seg[red.count++] = sw;
-            pos += static_cast<long long>(r) * cc;
-            ReduceSegment sbias{rows_part + row_off, r, w.splits, 1, r, 0, boff, pos, 0.0f};
-            red.seg[red.count++] = sbias;
-            pos += r;
-            part_off += align_up(static_cast<size_t>(w.splits) * r * cc, 64);
-            row_off += align_up(static_cast<size_t>(w.splits) * r, 64);
-        }
-    }
-    e = flush();
-    if (e != hipSuccess) return e;
+    ReduceArgs &red = d.red;
     const int lw = head_loss_partial_width(g.A);
-    red.total = pos;
     red.grad = sb.grad;
     red.sumsq_partials = reinterpret_cast<double *>(wsp(ws, w.sumsq));
     red.loss_partials = reinterpret_cast<const float *>(wsp(ws, w.loss_part));
@@ -699,8 +928,10 @@ int ppo_rollout_infer(const ppo_ctx *c, void *stream, const ppo_params *p, const
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const NetLayout &g = c->g;
     const WsPlan w = plan_workspace(g, c->prec, N, 0, 0);
+    Tuning tune;
+    PPO_CHECK(ensure_tuned(c, p, w, ws, N, false, s, tune));
     PPO_HIP(launch_gather_obs(c->prec, s, obs, nullptr, N, N, g.D, w.kpad, wsp(ws, w.xg)), "gather_obs");
-    PPO_HIP(enqueue_forward(c, p, w, ws, N, !value_only, values != nullptr, s), "forward GEMM");
+    PPO_HIP(enqueue_forward(c, p, w, ws, N, !value_only, values != nullptr, tune, s), "forward GEMM");
     HeadSampleArgs a{};
     a.ha = wsp(ws, w.h_a[g.L - 1]);
     a.hc = wsp(ws, w.h_c[g.L - 1]);
@@ -781,7 +1012,9 @@ int ppo_loss_grad(const ppo_ctx *c, void *stream, const ppo_params *p, const ppo
     PPO_CHECK(check_device());
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
     StepBuffers sb{b, idx, M, grad_out, stats, 0, 0};
-    PPO_HIP(enqueue_step(c, p, hp, w, ws, sb, static_cast<hipStream_t>(stream)), "loss_grad");
+    Tuning tune;
+    PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, static_cast<hipStream_t>(stream), tune));
+    PPO_HIP(enqueue_step(c, p, hp, w, ws, sb, tune, static_cast<hipStream_t>(stream)), "loss_grad");
     return PPO_OK;
 }
 
@@ -803,10 +1036,12 @@ int ppo_update_epoch(ppo_ctx *c, void *stream, const ppo_params *p, const ppo_ba
 
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
+    Tuning tune;
+    PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, s, tune));
     auto enqueue_all = [&](hipStream_t target) -> hipError_t {
         for (int k = 0; k < n_minibatches; ++k) {
             StepBuffers sb{b, perm + static_cast<long long>(k) * M, M, p->grad, stats + k * PPO_STATS_WIDTH, 1, k};
-            hipError_t e = enqueue_step(c, p, hp, w, ws, sb, target);
+            hipError_t e = enqueue_step(c, p, hp, w, ws, sb, tune, target);
             if (e != hipSuccess) return e;
         }
         return launch_step_advance(p->step, n_minibatches, target);
@@ -877,11 +1112,13 @@ int ppo_update_epoch_profiled(ppo_ctx *c, void *stream, const ppo_params *p, con
 
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
+    Tuning tune;
+    PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, s, tune));
     Profiler prof;
     prof.s = s;
     for (int k = 0; k < n_minibatches; ++k) {
         StepBuffers sb{b, perm + static_cast<long long>(k) * M, M, p->grad, stats + k * PPO_STATS_WIDTH, 1, k};
-        PPO_HIP(enqueue_step(c, p, hp, w, ws, sb, s, &prof), "update_epoch (profiled)");
+        PPO_HIP(enqueue_step(c, p, hp, w, ws, sb, tune, s, &prof), "update_epoch (profiled)");
     }
     PPO_HIP(launch_step_advance(p->step, n_minibatches, s), "step_advance");
     PPO_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
@@ -900,8 +1137,10 @@ int ppo_update_epoch_profiled(ppo_ctx *c, void *stream, const ppo_params *p, con
 
 int ppo_gemm_check(void *stream, int32_t precision, int32_t a_mode, int32_t b_mode, int32_t epilogue, int32_t M,
                    int32_t N, int32_t K, const void *A, int32_t lda, const void *B, int32_t ldb, void *C,
-                   int32_t ldc, const float *bias, const void *H, int32_t ldh, float *rowsum, int32_t splits) {
+                   int32_t ldc, const float *bias, const void *H, int32_t ldh, float *rowsum, int32_t splits,
+                   int32_t tile) {
     if (precision != PPO_FP32 && precision != PPO_BF16) return fail(PPO_E_INVAL, "precision %d", precision);
+    if (tile < 0 || tile >= kNumTileShapes) return fail(PPO_E_INVAL, "tile %d", tile);
     const bool combo_ok = (a_mode == 0 && b_mode == 0 && epilogue == kEpiBiasElu) ||
                           (a_mode == 0 && b_mode == 1 && epilogue == kEpiDElu) ||
                           (a_mode == 1 && b_mode == 1 && epilogue == kEpiPartial);
@@ -942,8 +1181,24 @@ int ppo_gemm_check(void *stream, int32_t precision, int32_t a_mode, int32_t b_mo
         q.kps = cdiv(cdiv(K, splits), bk) * bk;
         q.splits = cdiv(K, q.kps);
     }
+    args.tile = tile;
     add_problem(args, q, bk);
     PPO_HIP(launch_gemm(prec, a_mode, b_mode, epilogue, args, static_cast<hipStream_t>(stream)), "gemm");
+    return PPO_OK;
+}
+
+int ppo_ctx_tuning(const ppo_ctx *c, int32_t rows, int32_t update, int32_t *choices, int32_t capacity) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    if (!choices) return fail(PPO_E_INVAL, "choices is NULL");
+    if (capacity < 2 * kNumSites) return fail(PPO_E_SHAPE, "capacity %d < %d", capacity, 2 * kNumSites);
+    ppo_ctx *cc = const_cast<ppo_ctx *>(c);
+    std::lock_guard<std::mutex> lk(cc->mu);
+    auto it = cc->tuned.find(update ? -rows : rows);
+    if (it == cc->tuned.end()) return fail(PPO_E_SHAPE, "no tile choice recorded for %d rows", rows);
+    for (int i = 0; i < kNumSites; ++i) {
+        choices[2 * i] = it->second.site[i].tile;
+        choices[2 * i + 1] = it->second.site[i].rounds;
+    }
     return PPO_OK;
 }
 

@@ -55,9 +55,13 @@ def check(got, ref, prec, what, K):
 FWD = [(1, 16, 8), (100, 64, 48), (333, 200, 235), (4103, 512, 48), (257, 128, 512), (64, 48, 7)]
 
 
+TILES = [0, 1, 2, 3]   # 128x128, 64x128, 128x64, 64x64
+
+
+@pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("M,N,K", FWD)
-def test_forward_bias_elu(prec, M, N, K):
+def test_forward_bias_elu(prec, M, N, K, tile):
     require_gpu()
     rng = np.random.default_rng(M * 7 + N * 3 + K)
     lda = -(-K // 8) * 8          # padded rows like the gathered observations
@@ -67,7 +71,7 @@ def test_forward_bias_elu(prec, M, N, K):
     b, tb = operand((N, K), prec, rng, scale=1 / np.sqrt(K))   # ldb = K (unaligned when K % 8 != 0)
     bias = rng.standard_normal(N).astype(np.float32)
     C = torch.zeros(M, N, dtype=tb.dtype, device="cuda")
-    ppo.ppo_gemm_check(prec, 0, 0, 0, M, N, K, ta, lda, tb, K, C, N, bias=torch.as_tensor(bias).cuda())
+    ppo.ppo_gemm_check(prec, 0, 0, 0, M, N, K, ta, lda, tb, K, C, N, bias=torch.as_tensor(bias).cuda(), tile=tile)
     torch.cuda.synchronize()
     z = a[:, :K] @ b.T + bias
     ref = np.where(z > 0, z, np.expm1(np.minimum(z, 0)))
@@ -77,9 +81,10 @@ def test_forward_bias_elu(prec, M, N, K):
 DX = [(1, 16, 16), (300, 48, 64), (1536, 64, 64), (4100, 256, 128), (777, 512, 256)]
 
 
+@pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("M,N,K", DX)
-def test_input_grad_delu(prec, M, N, K):
+def test_input_grad_delu(prec, M, N, K, tile):
     require_gpu()
     rng = np.random.default_rng(M + 11 * N + K)
     a, ta = operand((M, K), prec, rng)
@@ -94,7 +99,7 @@ def test_input_grad_delu(prec, M, N, K):
         hv = hval.astype(np.float64)
         th = torch.as_tensor(hval).cuda()
     C = torch.zeros(M, N, dtype=ta.dtype, device="cuda")
-    ppo.ppo_gemm_check(prec, 0, 1, 1, M, N, K, ta, K, tw, N, C, N, H=th, ldh=N)
+    ppo.ppo_gemm_check(prec, 0, 1, 1, M, N, K, ta, K, tw, N, C, N, H=th, ldh=N, tile=tile)
     torch.cuda.synchronize()
     ref = (a @ w) * np.where(hv > 0, 1.0, hv + 1.0)
     check(output_values(C, prec), ref, prec, "input_grad", K)
@@ -105,9 +110,10 @@ DW = [(12, 64, 1536, 12, 16), (1, 64, 1536, 12, 16), (64, 48, 1536, 12, 64), (51
       (64, 235, 700, 3, 64)]
 
 
+@pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("M,N,K,splits,lda", DW)
-def test_weight_grad_partials(prec, M, N, K, splits, lda):
+def test_weight_grad_partials(prec, M, N, K, splits, lda, tile):
     require_gpu()
     rng = np.random.default_rng(M + 13 * N + K + splits)
     a_store, ta = operand((K, lda), prec, rng)     # dz stored [samples][lda], first M columns used
@@ -118,7 +124,7 @@ def test_weight_grad_partials(prec, M, N, K, splits, lda):
     used = -(-K // kps)
     C = torch.full((used, M, N), float("nan"), dtype=torch.float32, device="cuda")
     rs = torch.full((used, M), float("nan"), dtype=torch.float32, device="cuda")
-    ppo.ppo_gemm_check(prec, 1, 1, 2, M, N, K, ta, lda, tb, ldb, C, N, rowsum=rs, splits=splits)
+    ppo.ppo_gemm_check(prec, 1, 1, 2, M, N, K, ta, lda, tb, ldb, C, N, rowsum=rs, splits=splits, tile=tile)
     torch.cuda.synchronize()
     got = C.cpu().numpy().astype(np.float64)
     rows = rs.cpu().numpy().astype(np.float64)
