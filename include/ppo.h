@@ -73,6 +73,7 @@ extern "C" {
 #define PPO_MAX_ACT      16     /* action dimension                          */
 #define PPO_MAX_T        4096   /* rollout horizon                           */
 #define PPO_STATS_WIDTH  8      /* floats per mini-batch statistics row      */
+#define PPO_MAX_RUNS     64     /* runs in one batched update                */
 
 /* Statistics row written per mini-batch step (floats):
  *   [0] total loss L = L_pi + c_v L_V - c_e H
@@ -201,6 +202,24 @@ int ppo_gae(const ppo_ctx *ctx, void *stream, const float *rewards, const uint8_
 int ppo_update_epoch(ppo_ctx *ctx, void *stream, const ppo_params *p, const ppo_batch *b,
                      const int32_t *perm, int32_t n_minibatches, const ppo_hparams *hp,
                      float *stats, void *ws, size_t ws_bytes);
+
+/* One epoch of R independent PPO runs of uneven size in the same launches
+ * (sweep-style training of several policies at once, each with its own
+ * network shape, data, permutation, optimiser state and workspace).  Runs
+ * must share the precision, the number of hidden layers and n_minibatches;
+ * observation widths, hidden widths and batch sizes may differ.  Mini-batch
+ * step k of every run goes through one grouped launch per GEMM site (all
+ * runs' actor and critic problems in one grid, 128 x 128 tiles) with per-run
+ * gather, loss, gradient-reduce and Adam kernels in between; with
+ * hp->use_graph the whole batched epoch is one cached HIP graph.  Each run's
+ * weight gradients keep the split count the run would use alone, so every
+ * run's result equals ppo_update_epoch of that run with 128 x 128 tiles
+ * (PPO_AUTOTUNE=0).  Arrays have R entries; ws_bytes[i] must cover
+ * ppo_workspace_size(ctxs[i], 0, 0, B_i / n_minibatches). */
+int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_params *params,
+                       const ppo_batch *batches, const int32_t *const *perms, int32_t n_minibatches,
+                       const ppo_hparams *hp, float *const *stats, void *const *ws,
+                       const size_t *ws_bytes);
 
 /* Loss and gradient of one mini-batch (rows idx[0..M)) without an optimiser
  * step: writes stats[PPO_STATS_WIDTH] (entry 6 = gradient norm, entry 7 =

@@ -215,6 +215,24 @@ def ppo_update_epoch(ctx: Context, params: Params, batch: Dict[str, torch.Tensor
                                   _ptr(stats, torch.float32, "stats"), _ptr(ws, torch.uint8, "ws"), ws.numel()))
 
 
+def ppo_update_batched(ctxs: Sequence[Context], params: Sequence[Params], batches: Sequence[Dict[str, torch.Tensor]],
+                       perms: Sequence[torch.Tensor], n_minibatches: int, hp: UpdateHParams,
+                       stats: Sequence[torch.Tensor], ws: Sequence[torch.Tensor], stream=None) -> None:
+    """One epoch of R independent runs through shared grouped launches."""
+    R = len(ctxs)
+    c_ctx = (ctypes.c_void_p * R)(*[c.handle.value for c in ctxs])
+    c_par = (_abi.Params * R)(*[p.abi() for p in params])
+    c_bat = (_abi.Batch * R)(*[make_batch(b["obs"], b["actions"], b["logp"], b["adv"], b["returns"],
+                                          b.get("values")) for b in batches])
+    c_perm = (ctypes.c_void_p * R)(*[_ptr(p, torch.int32, "perm") for p in perms])
+    c_stats = (ctypes.c_void_p * R)(*[_ptr(s, torch.float32, "stats") for s in stats])
+    c_ws = (ctypes.c_void_p * R)(*[_ptr(w, torch.uint8, "ws") for w in ws])
+    c_wsb = (ctypes.c_size_t * R)(*[w.numel() for w in ws])
+    h = hp.abi()
+    check(_lib().ppo_update_batched(c_ctx, R, _stream(stream), c_par, c_bat, c_perm, n_minibatches,
+                                    ctypes.byref(h), c_stats, c_ws, c_wsb))
+
+
 def ppo_loss_grad(ctx: Context, params: Params, batch: Dict[str, torch.Tensor], idx: torch.Tensor,
                   hp: UpdateHParams, stats: torch.Tensor, grad_out: torch.Tensor, ws: torch.Tensor,
                   stream=None) -> None:

@@ -81,7 +81,7 @@ __global__ void gather_obs_kernel(const float *obs, const int32_t *idx, int src_
 
 // ------------------------------------------------- output-layer helpers
 constexpr int kHeadThreads = 256;
-constexpr int kLossRows = 64;     // mini-batch samples per block (loss)
+constexpr int kLossRows = 32;     // mini-batch samples per block (loss)
 constexpr int kSampleRows = 16;   // environments per block (rollout)
 constexpr int kWPad = 4;          // floats of row padding for staged output-layer weights
 
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kHeadThreads) void head_sample_kernel(const HeadSam
 }
 
 // ------------------------------------------------------------- head + loss
-// Update: for 64 mini-batch samples per block, the output layers, the
+// Update: for 32 mini-batch samples per block, the output layers, the
 // log-probability of the stored action, the ratio, clipped surrogate and
 // value loss with their gradients wrt mu and V (one lane per sample), then
 // the gradient through the output layers and the last ELU into the last
@@ -457,9 +457,16 @@ __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(const Reduc
         const int cols = 4 + a.A;
         const int c = threadIdx.x & 31, st = threadIdx.x >> 5;
         if (c < cols) {
-            float acc = 0.0f;
-            for (int b = st; b < a.n_loss; b += 8) acc += a.loss_partials[static_cast<long long>(b) * a.loss_width + c];
-            stripe[st][c] = acc;
+            // four independent running sums keep four loads in flight; they are
+            // combined in a fixed order, so the result does not depend on timing
+            float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            int b = st;
+            for (; b + 24 < a.n_loss; b += 32)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc[u] += a.loss_partials[static_cast<long long>(b + 8 * u) * a.loss_width + c];
+            for (; b < a.n_loss; b += 8) acc[0] += a.loss_partials[static_cast<long long>(b) * a.loss_width + c];
+            stripe[st][c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
         }
         __syncthreads();
         if (threadIdx.x < cols) {

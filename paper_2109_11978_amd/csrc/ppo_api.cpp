@@ -1187,6 +1187,266 @@ int ppo_gemm_check(void *stream, int32_t precision, int32_t a_mode, int32_t b_mo
     return PPO_OK;
 }
 
+// ------------------------------------------------------ batched update
+namespace {
+
+// Appends every problem of `src` to `dst`, starting new launches when one
+// fills up; all launches share `tile`.
+void append_problems(std::vector<GemmArgs> &dst, const GemmArgs &src, int tile, int bk) {
+    for (int i = 0; i < src.count; ++i) {
+        if (dst.empty() || dst.back().count == kGemmMaxProblems) {
+            dst.push_back(GemmArgs{});
+            dst.back().tile = tile;
+        }
+        add_problem(dst.back(), src.p[i], bk);
+    }
+}
+
+struct BatchedRun {
+    const ppo_ctx *c;
+    const ppo_params *p;
+    const ppo_batch *b;
+    const int32_t *perm;
+    float *stats;
+    void *ws;
+    WsPlan w;
+    int M;
+};
+
+constexpr int kBatchedTile = kTile128x128;
+
+// Step k of every run: per-run gathers, then one grouped launch per GEMM
+// site covering all runs, per-run loss, reduce and Adam kernels.
+hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams *hp, int k, hipStream_t s) {
+    const int R = static_cast<int>(runs.size());
+    const NetLayout &g0 = runs[0].c->g;
+    const Precision prec = runs[0].c->prec;
+    const int bk = gemm_bk(prec);
+    const int L = g0.L;
+    hipError_t e;
+    for (BatchedRun &r : runs) {
+        const int32_t *idx = r.perm + static_cast<long long>(k) * r.M;
+        e = launch_gather_obs(prec, s, r.b->obs, idx, r.b->B, r.M, r.c->g.D, r.w.kpad, wsp(r.ws, r.w.xg));
+        if (e != hipSuccess) return e;
+    }
+    for (int l = 0; l < L; ++l) {
+        std::vector<GemmArgs> launches;
+        for (BatchedRun &r : runs)
+            append_problems(launches, build_fwd(r.c, r.p, r.w, r.ws, r.M, l, true, true, kBatchedTile),
+                            kBatchedTile, bk);
+        for (const GemmArgs &a : launches) {
+            e = launch_gemm(prec, 0, 0, kEpiBiasElu, a, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    for (BatchedRun &r : runs) {
+        const NetLayout &g = r.c->g;
+        HeadLossArgs hl{};
+        hl.ha = wsp(r.ws, r.w.h_a[L - 1]);
+        hl.hc = wsp(r.ws, r.w.h_c[L - 1]);
+        hl.Wa = r.p->theta + g.Wa[L];
+        hl.ba = r.p->theta + g.ba[L];
+        hl.logstd = r.p->theta + g.logstd;
+        hl.Wc = r.p->theta + g.Wc[L];
+        hl.bc = r.p->theta + g.bc[L];
+        hl.actions = r.b->actions;
+        hl.logp_old = r.b->logp;
+        hl.adv = r.b->adv;
+        hl.returns = r.b->returns;
+        hl.values_old = r.b->values;
+        hl.idx = r.perm + static_cast<long long>(k) * r.M;
+        hl.B = r.b->B;
+        hl.dza = wsp(r.ws, r.w.dz_a[L - 1]);
+        hl.dzc = wsp(r.ws, r.w.dz_c[L - 1]);
+        hl.dz_head_a = wsp(r.ws, r.w.dzh_a);
+        hl.dz_head_c = wsp(r.ws, r.w.dzh_c);
+        hl.partials = reinterpret_cast<float *>(wsp(r.ws, r.w.loss_part));
+        hl.M = r.M;
+        hl.A = g.A;
+        hl.Hl = g.H[L - 1];
+        hl.clip = hp->clip;
+        hl.value_coef = hp->value_coef;
+        hl.inv_m = 1.0f / static_cast<float>(r.M);
+        hl.clip_value = hp->clip_value;
+        e = launch_head_loss(prec, hl, s);
+        if (e != hipSuccess) return e;
+    }
+    for (int l = L - 1; l >= 1; --l) {
+        std::vector<GemmArgs> launches;
+        for (BatchedRun &r : runs)
+            append_problems(launches, build_dx(r.c, r.p, r.w, r.ws, r.M, l, kBatchedTile), kBatchedTile, bk);
+        for (const GemmArgs &a : launches) {
+            e = launch_gemm(prec, 0, 1, kEpiDElu, a, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    // weight gradients: each run keeps the split count it would use alone
+    std::vector<DwPlan> plans(R);
+    std::vector<GemmArgs> launches;
+    for (int i = 0; i < R; ++i) {
+        TileChoice tc;
+        tc.tile = kBatchedTile;
+        tc.rounds = 1;
+        plans[i] = build_dw(runs[i].c, runs[i].w, runs[i].ws, runs[i].M, tc);
+        for (int q = 0; q < plans[i].n_launch; ++q) append_problems(launches, plans[i].launch[q], kBatchedTile, bk);
+    }
+    for (const GemmArgs &a : launches) {
+        e = launch_gemm(prec, 1, 1, kEpiPartial, a, s);
+        if (e != hipSuccess) return e;
+    }
+    for (int i = 0; i < R; ++i) {
+        BatchedRun &r = runs[i];
+        const NetLayout &g = r.c->g;
+        ReduceArgs &red = plans[i].red;
+        red.grad = r.p->grad;
+        red.sumsq_partials = reinterpret_cast<double *>(wsp(r.ws, r.w.sumsq));
+        red.loss_partials = reinterpret_cast<const float *>(wsp(r.ws, r.w.loss_part));
+        red.n_loss = head_loss_blocks(r.M);
+        red.loss_width = head_loss_partial_width(g.A);
+        red.A = g.A;
+        red.logstd_offset = g.logstd;
+        red.entropy_coef = hp->entropy_coef;
+        red.loss_sums = reinterpret_cast<float *>(wsp(r.ws, r.w.loss_sums));
+        e = launch_grad_reduce(red, s);
+        if (e != hipSuccess) return e;
+        AdamArgs ad{};
+        ad.theta = r.p->theta;
+        ad.grad = r.p->grad;
+        ad.m = r.p->adam_m;
+        ad.v = r.p->adam_v;
+        ad.shadow = prec == kBF16 ? r.p->shadow : nullptr;
+        ad.step = r.p->step;
+        ad.step_offset = k;
+        ad.lr = r.p->lr;
+        ad.sumsq_partials = red.sumsq_partials;
+        ad.n_sumsq = reduce_blocks(red.total);
+        ad.loss_sums = red.loss_sums;
+        ad.max_grad_norm = hp->max_grad_norm;
+        ad.beta1 = hp->beta1;
+        ad.beta2 = hp->beta2;
+        ad.eps = hp->adam_eps;
+        ad.inv_m = 1.0f / static_cast<float>(r.M);
+        ad.value_coef = hp->value_coef;
+        ad.entropy_coef = hp->entropy_coef;
+        ad.stats = r.stats + k * PPO_STATS_WIDTH;
+        ad.P = g.P;
+        ad.apply = 1;
+        e = launch_adam(ad, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+std::mutex g_batched_mu;
+std::map<std::vector<uint64_t>, hipGraphExec_t> g_batched_graphs;
+std::vector<std::vector<uint64_t>> g_batched_order;
+hipStream_t g_batched_capture = nullptr;
+int g_batched_dev = -1;
+
+}  // namespace
+
+int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_params *params,
+                       const ppo_batch *batches, const int32_t *const *perms, int32_t n_minibatches,
+                       const ppo_hparams *hp, float *const *stats, void *const *ws, const size_t *ws_bytes) {
+    if (!ctxs || !params || !batches || !perms || !stats || !ws || !ws_bytes)
+        return fail(PPO_E_INVAL, "NULL array argument");
+    if (R < 1 || R > PPO_MAX_RUNS) return fail(PPO_E_SHAPE, "R = %d outside 1..%d", R, PPO_MAX_RUNS);
+    PPO_CHECK(validate_hparams(hp));
+    std::vector<BatchedRun> runs(R);
+    for (int i = 0; i < R; ++i) {
+        const ppo_ctx *c = ctxs[i];
+        if (!c) return fail(PPO_E_INVAL, "ctxs[%d] is NULL", i);
+        if (c->prec != ctxs[0]->prec) return fail(PPO_E_INVAL, "runs differ in precision");
+        if (c->g.L != ctxs[0]->g.L) return fail(PPO_E_SHAPE, "runs differ in the number of hidden layers");
+        PPO_CHECK(validate_params(c, &params[i], true));
+        PPO_CHECK(validate_batch(c, &batches[i], hp));
+        if (!perms[i]) return fail(PPO_E_SHAPE, "perms[%d] is NULL", i);
+        PPO_CHECK(check_ptr(perms[i], "perm"));
+        if (n_minibatches < 1 || n_minibatches > batches[i].B || batches[i].B % n_minibatches != 0)
+            return fail(PPO_E_SHAPE, "run %d: B = %d is not divisible by n_minibatches = %d", i, batches[i].B,
+                        n_minibatches);
+        PPO_CHECK(check_ptr(stats[i], "stats"));
+        const int M = batches[i].B / n_minibatches;
+        PPO_CHECK(validate_ws(c, 0, 0, M, ws[i], ws_bytes[i]));
+        runs[i] = BatchedRun{c, &params[i], &batches[i], perms[i], stats[i], ws[i],
+                             plan_workspace(c->g, c->prec, 0, 0, M), M};
+    }
+    PPO_CHECK(check_device());
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    auto enqueue_all = [&](hipStream_t target) -> hipError_t {
+        for (int k = 0; k < n_minibatches; ++k) {
+            hipError_t e = enqueue_batched_step(runs, hp, k, target);
+            if (e != hipSuccess) return e;
+        }
+        for (int i = 0; i < R; ++i) {
+            hipError_t e = launch_step_advance(params[i].step, n_minibatches, target);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (!hp->use_graph) {
+        PPO_HIP(enqueue_all(s), "update_batched");
+        return PPO_OK;
+    }
+    std::vector<uint64_t> key = {static_cast<uint64_t>(R), static_cast<uint64_t>(n_minibatches),
+                                 fbits(hp->clip), fbits(hp->value_coef), fbits(hp->entropy_coef),
+                                 fbits(hp->max_grad_norm), fbits(hp->beta1), fbits(hp->beta2), fbits(hp->adam_eps),
+                                 static_cast<uint64_t>(hp->clip_value)};
+    for (int i = 0; i < R; ++i) {
+        const ppo_params &p = params[i];
+        const ppo_batch &b = batches[i];
+        for (uint64_t v : {u64(ctxs[i]), u64(p.theta), u64(p.grad), u64(p.adam_m), u64(p.adam_v), u64(p.shadow),
+                           u64(p.step), u64(p.lr), u64(b.obs), u64(b.actions), u64(b.logp), u64(b.adv),
+                           u64(b.returns), u64(b.values), static_cast<uint64_t>(b.B), u64(perms[i]), u64(stats[i]),
+                           u64(ws[i])})
+            key.push_back(v);
+    }
+    std::lock_guard<std::mutex> lk(g_batched_mu);
+    int dev = 0;
+    PPO_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (g_batched_capture && g_batched_dev != dev) {
+        for (auto &kv : g_batched_graphs) (void)hipGraphExecDestroy(kv.second);
+        g_batched_graphs.clear();
+        g_batched_order.clear();
+        (void)hipStreamDestroy(g_batched_capture);
+        g_batched_capture = nullptr;
+    }
+    if (!g_batched_capture) {
+        PPO_HIP(hipStreamCreateWithFlags(&g_batched_capture, hipStreamNonBlocking), "hipStreamCreate");
+        g_batched_dev = dev;
+    }
+    hipGraphExec_t exec = nullptr;
+    auto it = g_batched_graphs.find(key);
+    if (it != g_batched_graphs.end()) {
+        exec = it->second;
+    } else {
+        PPO_HIP(hipStreamBeginCapture(g_batched_capture, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        hipError_t e = enqueue_all(g_batched_capture);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(g_batched_capture, &graph);
+        if (e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(e, "capture of update_batched");
+        }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        if (g_batched_graphs.size() >= kMaxGraphs) {
+            auto old = g_batched_graphs.find(g_batched_order.front());
+            if (old != g_batched_graphs.end()) {
+                (void)hipGraphExecDestroy(old->second);
+                g_batched_graphs.erase(old);
+            }
+            g_batched_order.erase(g_batched_order.begin());
+        }
+        g_batched_graphs[key] = exec;
+        g_batched_order.push_back(key);
+    }
+    PPO_HIP(hipGraphLaunch(exec, s), "hipGraphLaunch");
+    return PPO_OK;
+}
+
 int ppo_ctx_tuning(const ppo_ctx *c, int32_t rows, int32_t update, int32_t *choices, int32_t capacity) {
     if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
     if (!choices) return fail(PPO_E_INVAL, "choices is NULL");

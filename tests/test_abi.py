@@ -137,3 +137,23 @@ def test_misuse_codes():
     assert lib.ppo_philox_blocks(None, 0, 0, 0, 0, 0, 0, FAKE) == ppo.PPO_E_SHAPE
     # null context
     assert lib.ppo_ctx_destroy(None) == ppo.PPO_E_INVAL
+
+
+def test_batched_rejects_mismatched_runs():
+    a = ppo.Context(48, 12, (64, 32), "bf16")
+    b = ppo.Context(48, 12, (64,), "bf16")
+    import ctypes
+    from paper_2109_11978_amd import _abi
+    lib = ppo.load()
+    ctxs = (ctypes.c_void_p * 2)(a.handle.value, b.handle.value)
+    pars = (_abi.Params * 2)()
+    bats = (_abi.Batch * 2)()
+    arr = (ctypes.c_void_p * 2)(0x10000, 0x10000)
+    wsb = (ctypes.c_size_t * 2)(1 << 30, 1 << 30)
+    h = ppo.UpdateHParams().abi()
+    for i in range(2):
+        pars[i] = _abi.Params(0x10000, 0x10000, 0x10000, 0x10000, 0x10000, 0x10000, 0x10000)
+        bats[i] = _abi.Batch(0x10000, 0x10000, 0x10000, 0x10000, 0x10000, None, 64)
+    rc = lib.ppo_update_batched(ctxs, 2, None, pars, bats, arr, 4, ctypes.byref(h), arr, arr, wsb)
+    assert rc == ppo.PPO_E_SHAPE
+    assert b"hidden layers" in lib.ppo_last_error()

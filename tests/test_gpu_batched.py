@@ -1,0 +1,79 @@
+"""Uneven concurrent runs in shared grouped launches (needs an MI355X).
+
+Every run's epoch in ppo_update_batched must equal the same run updated alone
+by ppo_update_epoch with the same (128 x 128) tiles, bit for bit, and the
+graph-replayed batched epoch must equal its eager launch."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2109_11978_amd as ppo
+import synth
+from tests.gpu_common import dev, require_gpu, teacher_batch
+
+pytestmark = pytest.mark.gpu
+
+# (n_envs, n_steps, obs_dim): uneven sizes and both observation widths
+RUNS = [(64, 16, 48), (96, 24, 235), (160, 24, 48), (40, 50, 235)]
+HIDDEN = (128, 64, 32)
+K = 4
+
+
+def _runs(prec):
+    out = []
+    for r, (N, T, D) in enumerate(RUNS):
+        cfg = synth.configs.PPOConfig(name=f"run{r}", n_envs=N, n_steps=T, net=synth.NetShape(D, 12, HIDDEN),
+                                      epochs=1, minibatches=K, seed=r)
+        theta = synth.xavier_theta(cfg.net, seed=r, logstd=-0.3)
+        batch = teacher_batch(cfg, theta, cfg.batch, seed=10 + r, shift="mixed")
+        perm = np.random.default_rng(20 + r).permutation(cfg.batch).astype(np.int32)
+        out.append((cfg, theta, batch, perm))
+    return out
+
+
+def _state(params):
+    return [params.theta.cpu().numpy().copy(), params.adam_m.cpu().numpy().copy(),
+            params.adam_v.cpu().numpy().copy(), int(params.step[0].item())]
+
+
+@pytest.fixture
+def fixed_tiles(monkeypatch):
+    monkeypatch.setenv("PPO_AUTOTUNE", "0")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batched_equals_solo(prec, fixed_tiles):
+    d = require_gpu()
+    runs = _runs(prec)
+    print(f"[gpu-case] batched vs solo {prec} runs={RUNS}", flush=True)
+    hp = ppo.UpdateHParams()
+    ctxs, solo_state, solo_stats = [], [], []
+    for cfg, theta, batch, perm in runs:
+        ctx = ppo.Context(cfg.net.obs_dim, cfg.net.act_dim, cfg.net.hidden, prec)
+        ctxs.append(ctx)
+        params = ppo.Params(ctx, theta, device=d)
+        stats = torch.zeros(K, ppo.PPO_STATS_WIDTH, device=d)
+        ws = ctx.new_workspace(M=cfg.minibatch)
+        ppo.ppo_update_epoch(ctx, params, {k: dev(v, d) for k, v in batch.items()}, dev(perm, d), K, hp, stats, ws)
+        torch.cuda.synchronize()
+        solo_state.append(_state(params))
+        solo_stats.append(stats.cpu().numpy())
+
+    for use_graph in (False, True):
+        params, batches, perms, stats, wss = [], [], [], [], []
+        for (cfg, theta, batch, perm), ctx in zip(runs, ctxs):
+            params.append(ppo.Params(ctx, theta, device=d))
+            batches.append({k: dev(v, d) for k, v in batch.items()})
+            perms.append(dev(perm, d))
+            stats.append(torch.zeros(K, ppo.PPO_STATS_WIDTH, device=d))
+            wss.append(ctx.new_workspace(M=cfg.minibatch))
+        ppo.ppo_update_batched(ctxs, params, batches, perms, K, ppo.UpdateHParams(use_graph=use_graph), stats, wss)
+        torch.cuda.synchronize()
+        for r in range(len(runs)):
+            got = _state(params[r])
+            for a, b in zip(got[:3], solo_state[r][:3]):
+                np.testing.assert_array_equal(a, b)
+            assert got[3] == solo_state[r][3] == K
+            np.testing.assert_array_equal(stats[r].cpu().numpy(), solo_stats[r])
