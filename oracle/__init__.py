@@ -26,6 +26,10 @@ Parity status per function (what pins it; see tests/test_oracle_*.py):
                     policy gradient on the active clip side
   clip_coef         numpy.linalg.norm; post-clip norm equals the limit
   adam_step         torch.optim.Adam in float64 on CPU; first-step closed form
+  gaussian_kl       numeric integration of the 1-D KL (scipy.integrate.quad);
+                    zero for equal distributions; pure mean shift and pure
+                    scale closed forms
+  adaptive_lr       the thresholds and clamps of Algorithm 1, case by case
   update_epoch      composition of the above (no independent pin beyond its
                     parts: parity unpinned as a whole against the paper, which
                     prints no intermediate values)
@@ -40,6 +44,8 @@ from .ppo import (
     clip_coef,
     adam_step,
     update_epoch,
+    gaussian_kl,
+    adaptive_lr,
 )
 
 __all__ = [
@@ -47,5 +53,5 @@ __all__ = [
     "NetSpec", "param_layout", "unpack",
     "elu", "elu_grad", "mlp_forward", "gaussian_logp", "gaussian_entropy", "rollout_infer",
     "gae", "advantage_stats", "normalize_advantages",
-    "PPOHyper", "ppo_loss_grad", "clip_coef", "adam_step", "update_epoch",
+    "PPOHyper", "ppo_loss_grad", "clip_coef", "adam_step", "update_epoch", "gaussian_kl", "adaptive_lr",
 ]

@@ -54,6 +54,34 @@ class PPOHyper:
     beta2: float = 0.999
     adam_eps: float = 1e-8
     clip_value: bool = False
+    # Appendix A.4, Algorithm 1 (0 disables the adaptive rate)
+    desired_kl: float = 0.0
+    lr_factor: float = 1.5
+    lr_min: float = 1e-5
+    lr_max: float = 1e-2
+
+
+def gaussian_kl(mu_old, logstd_old, mu_new, logstd_new):
+    """KL(pi_old || pi_new) per sample for diagonal Gaussians:
+    sum_j [log(sigma_new/sigma_old) + (sigma_old^2 + (mu_old - mu_new)^2) / (2 sigma_new^2) - 1/2]."""
+    mu_old = np.asarray(mu_old, dtype=np.float64)
+    mu_new = np.asarray(mu_new, dtype=np.float64)
+    ls_old = np.asarray(logstd_old, dtype=np.float64)
+    ls_new = np.asarray(logstd_new, dtype=np.float64)
+    var_old = np.exp(2.0 * ls_old)
+    var_new = np.exp(2.0 * ls_new)
+    return np.sum(ls_new - ls_old + (var_old + (mu_old - mu_new) ** 2) / (2.0 * var_new) - 0.5, axis=-1)
+
+
+def adaptive_lr(lr: float, kl: float, hp: "PPOHyper") -> float:
+    """Algorithm 1 of Appendix A.4: divide the rate by the factor when the KL
+    exceeds twice the target, multiply it when the KL is below half the
+    target, within [lr_min, lr_max]."""
+    if kl > 2.0 * hp.desired_kl:
+        return max(hp.lr_min, lr / hp.lr_factor)
+    if kl < 0.5 * hp.desired_kl:
+        return min(hp.lr_max, lr * hp.lr_factor)
+    return lr
 
 
 def _mlp_backward(layers, zs, hs, g_out):
@@ -119,6 +147,8 @@ def ppo_loss_grad(theta, spec: NetSpec, batch: Dict[str, np.ndarray], hp: PPOHyp
         approx_kl=float(np.mean((ratio - 1.0) - np.log(ratio))),
         ratio=ratio, active=active, margin=margin, mu=mu, values=V, logp=logp,
     )
+    if "mu_old" in batch and "logstd_old" in batch:
+        out["kl"] = float(np.mean(gaussian_kl(batch["mu_old"], batch["logstd_old"], mu, logstd)))
     if not want_grad:
         return out
 
@@ -170,28 +200,38 @@ def adam_step(theta, m, v, grad, step: int, hp: PPOHyper, lr: Optional[float] = 
 
 
 def minibatch(batch: Dict[str, np.ndarray], idx) -> Dict[str, np.ndarray]:
-    return {k: np.asarray(v)[idx] for k, v in batch.items()}
+    """Rows `idx` of every per-sample array; the state-independent old
+    log-std (key "logstd_old") is shared by all samples."""
+    return {k: (np.asarray(v) if k == "logstd_old" else np.asarray(v)[idx]) for k, v in batch.items()}
 
 
 def update_epoch(theta, m, v, step: int, spec: NetSpec, batch: Dict[str, np.ndarray],
-                 perm, n_minibatches: int, hp: PPOHyper):
+                 perm, n_minibatches: int, hp: PPOHyper, lr: Optional[float] = None):
     """One epoch: K mini-batch steps of loss/gradient, clip, Adam.
 
     batch arrays are flattened over the rollout (sample s = t * N + n);
-    perm is this epoch's permutation of [0, B).  Returns (theta, m, v, step,
-    per-step records).
+    perm is this epoch's permutation of [0, B).  With hp.desired_kl > 0 and
+    the collection-time means and log-std in the batch (mu_old, logstd_old),
+    each step first adapts the learning rate from the mini-batch KL at the
+    current parameters (Algorithm 1), then takes the Adam step with it.
+    Returns (theta, m, v, step, per-step records); each record holds the
+    rate it used under "lr".
     """
     B = len(perm)
     assert B % n_minibatches == 0
     M = B // n_minibatches
+    lr = hp.lr if lr is None else lr
     records: List[dict] = []
     for k in range(n_minibatches):
         idx = np.asarray(perm[k * M:(k + 1) * M])
         res = ppo_loss_grad(theta, spec, minibatch(batch, idx), hp)
+        if hp.desired_kl > 0.0 and "kl" in res:
+            lr = adaptive_lr(lr, res["kl"], hp)
         c, norm = clip_coef(res["grad"], hp.max_grad_norm)
-        theta, m, v = adam_step(theta, m, v, c * res["grad"], step, hp)
+        theta, m, v = adam_step(theta, m, v, c * res["grad"], step, hp, lr=lr)
         step += 1
         res["grad_norm"] = norm
         res["clip_coef"] = c
+        res["lr"] = lr
         records.append(res)
     return theta, m, v, step, records

@@ -200,3 +200,60 @@ def test_update_epoch_composes_steps():
         c, _ = O.clip_coef(r["grad"], hp.max_grad_norm)
         th2, m2, v2 = O.adam_step(th2, m2, v2, c * r["grad"], 4 + k, hp)
     np.testing.assert_array_equal(th, th2)
+
+
+def test_gaussian_kl_pins():
+    import scipy.integrate
+    import scipy.stats
+    # one dimension against numeric integration of p log(p / q)
+    for mo, so, mn, sn in [(0.0, 1.0, 0.3, 0.8), (1.0, 0.5, -0.2, 1.3), (0.1, 2.0, 0.1, 2.0)]:
+        p = scipy.stats.norm(mo, so)
+        q = scipy.stats.norm(mn, sn)
+        num, _ = scipy.integrate.quad(lambda x: p.pdf(x) * (p.logpdf(x) - q.logpdf(x)), -30, 30, limit=200)
+        got = O.gaussian_kl([mo], [np.log(so)], [mn], [np.log(sn)])
+        assert got == pytest.approx(num, abs=1e-9)
+    rng = np.random.default_rng(20)
+    mu = rng.normal(0, 1, (5, 4))
+    ls = rng.normal(0, 0.3, 4)
+    np.testing.assert_allclose(O.gaussian_kl(mu, ls, mu, ls), 0.0, atol=1e-15)
+    # pure mean shift: sum d^2 / (2 sigma^2); pure scale: sum (r^2 - 1)/2 - log r with r = so/sn
+    d = rng.normal(0, 1, (5, 4))
+    np.testing.assert_allclose(O.gaussian_kl(mu, ls, mu + d, ls), np.sum(d ** 2 / (2 * np.exp(2 * ls)), axis=1),
+                               rtol=1e-13)
+    r = np.exp(ls - (ls + 0.2))
+    np.testing.assert_allclose(O.gaussian_kl(mu, ls, mu, ls + 0.2), np.sum((r ** 2 - 1) / 2 - np.log(r)) * np.ones(5),
+                               rtol=1e-12)
+
+
+def test_adaptive_lr_rule():
+    hp = O.PPOHyper(desired_kl=0.01)
+    assert O.adaptive_lr(1e-3, 0.021, hp) == pytest.approx(1e-3 / 1.5)
+    assert O.adaptive_lr(1e-3, 0.02, hp) == 1e-3          # not above 2 kl*
+    assert O.adaptive_lr(1e-3, 0.005, hp) == 1e-3         # not below kl*/2
+    assert O.adaptive_lr(1e-3, 0.0049, hp) == pytest.approx(1.5e-3)
+    assert O.adaptive_lr(1.2e-5, 1.0, hp) == 1e-5         # lower clamp
+    assert O.adaptive_lr(9e-3, 0.0, hp) == 1e-2           # upper clamp
+
+
+def test_update_epoch_adapts_rate_per_minibatch():
+    theta = _theta(TINY, 30)
+    B, K = 12, 3
+    batch = _batch(TINY, theta, B, 31)
+    actor, logstd, _ = O.unpack(theta, TINY)
+    mu, _, _ = P.mlp_forward(actor, batch["obs"])
+    batch["mu_old"] = mu + 0.05
+    batch["logstd_old"] = logstd.copy()
+    perm = np.random.default_rng(32).permutation(B)
+    hp = O.PPOHyper(desired_kl=0.01, lr=1e-3)
+    n = len(theta)
+    th, m, v, step, rec = O.update_epoch(theta, np.zeros(n), np.zeros(n), 0, TINY, batch, perm, K, hp)
+    lr = hp.lr
+    th2, m2, v2 = theta, np.zeros(n), np.zeros(n)
+    for k in range(K):
+        mb = O.minibatch(batch, perm[k * 4:(k + 1) * 4])
+        r = O.ppo_loss_grad(th2, TINY, mb, hp)
+        lr = O.adaptive_lr(lr, r["kl"], hp)
+        assert rec[k]["lr"] == lr
+        c, _ = O.clip_coef(r["grad"], hp.max_grad_norm)
+        th2, m2, v2 = O.adam_step(th2, m2, v2, c * r["grad"], k, hp, lr=lr)
+    np.testing.assert_array_equal(th, th2)
