@@ -11,9 +11,9 @@
 // of 64 x 64, each wave 2 x 2 MFMA blocks of 32 x 32.  bf16 operands use
 // v_mfma_f32_32x32x16_bf16; float32 operands use four v_mfma_f32_32x32x2_f32
 // per 8-wide k chunk.  Tiles are staged in LDS with K contiguous and a 16-byte
-// row pad (conflict-free 16-byte reads for 16 consecutive rows); the next
-// k-slab is fetched into registers while the current one is multiplied (two
-// LDS buffers, one barrier per slab).  Operands stored transposed in memory
+// row pad (conflict-free 16-byte reads for 16 consecutive rows); two k-slabs
+// are in flight while the current one is multiplied (two register staging
+// sets, two LDS buffers, one barrier per slab).  Operands stored transposed in memory
 // (the sample-major activations used by dW) are transposed in registers, one
 // 16-byte vector per row of an 8 x 8 (bf16) or 4 x 4 (float32) block.
 #include "common.hpp"
@@ -256,26 +256,14 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     constexpr int TPR = kThreads / BM;
     float rowsum = 0.0f;
 
-    LA la;
-    LB lb;
-    if (nk > 0) {
-        la.load(A, P.lda, P.M, m0, kbeg, kend, tid, a_vec);
-        lb.load(B, P.ldb, P.N, n0, kbeg, kend, tid - B_OFF, b_vec);
-        la.store(&lds[0][0], tid);
-        lb.store(&lds[0][BM * PITCH], tid - B_OFF);
-    }
-    __syncthreads();
-
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        const bool more = kt + 1 < nk;
-        if (more) {
-            const int k0 = kbeg + (kt + 1) * BK;
-            la.load(A, P.lda, P.M, m0, k0, kend, tid, a_vec);
-            lb.load(B, P.ldb, P.N, n0, k0, kend, tid - B_OFF, b_vec);
-        }
-        const T *As = &lds[cur][0];
-        const T *Bs = &lds[cur][BM * PITCH];
+    // Two k-slabs in flight: staging set 0 holds even slabs, set 1 odd ones.
+    // While slab kt is multiplied out of one LDS buffer, slab kt + 1 sits in
+    // registers on its way to the other buffer and slab kt + 2 is loading.
+    LA la0, la1;
+    LB lb0, lb1;
+    auto compute = [&](int buf) {
+        const T *As = &lds[0][0] + buf * ((BM + BN) * PITCH);
+        const T *Bs = As + BM * PITCH;
 #pragma unroll
         for (int kc = 0; kc < BK / KC; ++kc) {
             u32x4 a[MI], b[NJ];
@@ -297,11 +285,67 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
 #pragma unroll
             for (int e = 0; e < BK / TPR; ++e) rowsum += Elem<T>::to_f(src[e]);
         }
-        if (more) {
-            la.store(&lds[cur ^ 1][0], tid);
-            lb.store(&lds[cur ^ 1][BM * PITCH], tid - B_OFF);
+    };
+
+    // The bf16 128 x 128 input-gradient variant does not fit two staging
+    // sets into the 256 registers of two waves per SIMD (it would spill):
+    // it keeps one slab of lookahead.
+    constexpr bool kTwoAhead = !(sizeof(T) == 2 && BM == 128 && BN == 128 && AMODE == 0 && BMODE == 1);
+
+    if (nk > 0) {
+        la0.load(A, P.lda, P.M, m0, kbeg, kend, tid, a_vec);
+        lb0.load(B, P.ldb, P.N, n0, kbeg, kend, tid - B_OFF, b_vec);
+        la0.store(&lds[0][0], tid);
+        lb0.store(&lds[0][BM * PITCH], tid - B_OFF);
+    }
+    if constexpr (!kTwoAhead) {
+        __syncthreads();
+        for (int kt = 0; kt < nk; ++kt) {
+            const int cur = kt & 1;
+            const bool more = kt + 1 < nk;
+            if (more) {
+                la0.load(A, P.lda, P.M, m0, kbeg + (kt + 1) * BK, kend, tid, a_vec);
+                lb0.load(B, P.ldb, P.N, n0, kbeg + (kt + 1) * BK, kend, tid - B_OFF, b_vec);
+            }
+            compute(cur);
+            if (more) {
+                la0.store(&lds[cur ^ 1][0], tid);
+                lb0.store(&lds[cur ^ 1][BM * PITCH], tid - B_OFF);
+            }
+            __syncthreads();
+        }
+    } else {
+    if (nk > 1) {
+        la1.load(A, P.lda, P.M, m0, kbeg + BK, kend, tid, a_vec);
+        lb1.load(B, P.ldb, P.N, n0, kbeg + BK, kend, tid - B_OFF, b_vec);
+    }
+    __syncthreads();
+
+    for (int kt = 0; kt < nk; kt += 2) {
+        // even slab kt in buffer 0
+        if (kt + 2 < nk) {
+            la0.load(A, P.lda, P.M, m0, kbeg + (kt + 2) * BK, kend, tid, a_vec);
+            lb0.load(B, P.ldb, P.N, n0, kbeg + (kt + 2) * BK, kend, tid - B_OFF, b_vec);
+        }
+        compute(0);
+        if (kt + 1 < nk) {
+            la1.store(&lds[1][0], tid);
+            lb1.store(&lds[1][BM * PITCH], tid - B_OFF);
         }
         __syncthreads();
+        if (kt + 1 >= nk) break;
+        // odd slab kt + 1 in buffer 1
+        if (kt + 3 < nk) {
+            la1.load(A, P.lda, P.M, m0, kbeg + (kt + 3) * BK, kend, tid, a_vec);
+            lb1.load(B, P.ldb, P.N, n0, kbeg + (kt + 3) * BK, kend, tid - B_OFF, b_vec);
+        }
+        compute(1);
+        if (kt + 2 < nk) {
+            la0.store(&lds[0][0], tid);
+            lb0.store(&lds[0][BM * PITCH], tid - B_OFF);
+        }
+        __syncthreads();
+    }
     }
 
     if constexpr (EPI == kEpiPartial) {

@@ -52,7 +52,8 @@ def check(got, ref, prec, what, K):
                            f"got {got[bad][0]}, expected {ref[bad][0]}")
 
 
-FWD = [(1, 16, 8), (100, 64, 48), (333, 200, 235), (4103, 512, 48), (257, 128, 512), (64, 48, 7)]
+FWD = [(1, 16, 8), (100, 64, 48), (333, 200, 235), (4103, 512, 48), (257, 128, 512), (64, 48, 7),
+       (129, 80, 192), (77, 144, 320)]   # 3 and 5 bf16 k-slabs: odd tails of the two-slab pipeline
 
 
 TILES = [0, 1, 2, 3]   # 128x128, 64x128, 128x64, 64x64
@@ -78,7 +79,7 @@ def test_forward_bias_elu(prec, M, N, K, tile):
     check(output_values(C, prec), ref, prec, "forward", K)
 
 
-DX = [(1, 16, 16), (300, 48, 64), (1536, 64, 64), (4100, 256, 128), (777, 512, 256)]
+DX = [(1, 16, 16), (300, 48, 64), (1536, 64, 64), (4100, 256, 128), (777, 512, 256), (200, 64, 192)]
 
 
 @pytest.mark.parametrize("tile", TILES)
