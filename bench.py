@@ -17,6 +17,8 @@ each launch of one eagerly launched epoch) and the FP64 CPU oracle timed on
 a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32]
+       python bench.py --config large   (16384 x 24 envs, 235-dim obs, [1024, 512, 256])
+       python bench.py --config sweep   (8 uneven runs, batched update vs run after run)
 """
 from __future__ import annotations
 
@@ -273,6 +275,64 @@ def cpu_baseline(wl, precision):
             "gpu_grad_vs_oracle_normwise": normwise}
 
 
+def sweep_bench(args, dev):
+    """Eight uneven sweep-style runs: per iteration each run collects its own
+    rollout (policy steps + GAE); the update is one batched epoch per epoch
+    over all runs.  Also times the same updates done run after run."""
+    import torch
+    import paper_2109_11978_amd as ppo
+    import synth
+    runs = [Workload(cfg, "bf16", dev) for cfg in synth.configs.sweep_runs()]
+    epochs, K = runs[0].cfg.epochs, runs[0].cfg.minibatches
+    total_b = sum(w.cfg.batch for w in runs)
+
+    def batched_update():
+        for e in range(epochs):
+            ppo.ppo_update_batched([w.ctx for w in runs], [w.params for w in runs], [w.batch for w in runs],
+                                   [w.perms[e] for w in runs], K, runs[0].hp, [w.stats[e] for w in runs],
+                                   [w.ws for w in runs])
+
+    def step():
+        for w in runs:
+            w.collect()
+            w.advantages()
+        batched_update()
+        for w in runs:
+            w.iteration += 1
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    s_step = (time.perf_counter() - t0) / args.steps
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    t_batched = timed(batched_update)
+    t_serial = timed(lambda: [w.update() for w in runs])
+    out = {
+        "metric": "PPO update samples/s, 8 uneven sweep runs updated together",
+        "value": round(total_b / s_step, 1), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(s_step * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "sweep_8_uneven_runs", "runs": [w.cfg.name for w in runs], "total_batch": total_b},
+        "update_samples_per_s_batched": round(total_b / t_batched, 1),
+        "update_samples_per_s_run_after_run": round(total_b / t_serial, 1),
+        "batched_speedup": round(t_serial / t_batched, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -284,8 +344,11 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     import synth
-    cfg = synth.get_config(args.config)
     dev = torch.device("cuda")
+    if args.config == "sweep":
+        sweep_bench(args, dev)
+        return
+    cfg = synth.get_config(args.config)
 
     wl = Workload(cfg, "bf16", dev)
     s_step = time_steps(wl, args.steps, args.warmup)

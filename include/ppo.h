@@ -72,7 +72,7 @@ extern "C" {
 #define PPO_MAX_OBS      4096   /* observation dimension                     */
 #define PPO_MAX_ACT      16     /* action dimension                          */
 #define PPO_MAX_T        4096   /* rollout horizon                           */
-#define PPO_STATS_WIDTH  8      /* floats per mini-batch statistics row      */
+#define PPO_STATS_WIDTH  10     /* floats per mini-batch statistics row      */
 #define PPO_MAX_RUNS     64     /* runs in one batched update                */
 
 /* Statistics row written per mini-batch step (floats):
@@ -82,6 +82,10 @@ extern "C" {
  *   [5] approximate KL, mean((rho - 1) - log rho)
  *   [6] global gradient norm before clipping (accumulated in float64)
  *   [7] flags: bit 0 = non-finite gradient norm (the Adam step was skipped)
+ *   [8] KL(pi_old || pi_new) of the diagonal Gaussians, mean over the
+ *       mini-batch at the step's parameters (0 when batch.mu_old is NULL)
+ *   [9] learning rate the step used (after the KL adaptation, if enabled;
+ *       0 when no learning rate is given)
  */
 
 /* Network shape.  Actor: obs_dim -> hidden[0] -> ... -> act_dim; critic:
@@ -119,6 +123,10 @@ typedef struct ppo_batch {
     const float *returns;  /* [B] returns R = A + V (un-normalised A)         */
     const float *values;   /* [B] values at collection (value clipping only;
                               may be NULL when clip_value == 0)               */
+    const float *mu_old;   /* [B, A] action means at collection (the mu output
+                              of ppo_rollout_infer); NULL unless the KL is
+                              wanted (required when desired_kl > 0)           */
+    const float *logstd_old; /* [A] log-std at collection; with mu_old      */
     int32_t B;
 } ppo_batch;
 
@@ -134,6 +142,16 @@ typedef struct ppo_hparams {
     int32_t clip_value;     /* 0/1: clipped value loss (needs batch.values)   */
     int32_t use_graph;      /* 0/1: capture the epoch into a HIP graph and
                                replay it (cached per pointer/shape set)       */
+    /* KL-adaptive learning rate (App. A.4, Algorithm 1).  With desired_kl > 0
+     * each mini-batch step first measures KL(pi_old || pi_new) over its rows
+     * at the current parameters, then sets, on the device,
+     *   lr = max(lr_min, lr / lr_factor)  if KL > 2 desired_kl,
+     *   lr = min(lr_max, lr * lr_factor)  if KL < desired_kl / 2,
+     * and takes its Adam step with that rate (written back to params.lr, so a
+     * replayed graph continues from it).  0 keeps params.lr unchanged. */
+    float   desired_kl;     /* >= 0 (Table 3: 0.01)                           */
+    float   lr_factor;      /* >= 1 (Algorithm 1: 1.5)                        */
+    float   lr_min, lr_max; /* 0 < lr_min <= lr_max (Algorithm 1: 1e-5, 1e-2) */
 } ppo_hparams;
 
 typedef struct ppo_ctx ppo_ctx;
@@ -209,13 +227,16 @@ int ppo_update_epoch(ppo_ctx *ctx, void *stream, const ppo_params *p, const ppo_
  * must share the precision, the number of hidden layers and n_minibatches;
  * observation widths, hidden widths and batch sizes may differ.  Mini-batch
  * step k of every run goes through one grouped launch per GEMM site (all
- * runs' actor and critic problems in one grid, 128 x 128 tiles) with per-run
- * gather, loss, gradient-reduce and Adam kernels in between; with
- * hp->use_graph the whole batched epoch is one cached HIP graph.  Each run's
- * weight gradients keep the split count the run would use alone, so every
- * run's result equals ppo_update_epoch of that run with 128 x 128 tiles
- * (PPO_AUTOTUNE=0).  Arrays have R entries; ws_bytes[i] must cover
- * ppo_workspace_size(ctxs[i], 0, 0, B_i / n_minibatches). */
+ * runs' actor and critic problems in one grid) with per-run gather, loss,
+ * gradient-reduce and Adam kernels in between; with hp->use_graph the whole
+ * batched epoch is one cached HIP graph.  The first call for a set of run
+ * shapes times the tile candidates of every grouped site (see autotuning
+ * above) and gives the weight-gradient workgroups of all runs one common
+ * k-length.  With PPO_AUTOTUNE=0 every site uses 128 x 128 tiles and each
+ * run keeps the weight-gradient split count it would use alone, so every
+ * run's result equals its own ppo_update_epoch bit for bit.  Arrays have R
+ * entries; ws_bytes[i] must cover ppo_workspace_size(ctxs[i], 0, 0,
+ * B_i / n_minibatches). */
 int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_params *params,
                        const ppo_batch *batches, const int32_t *const *perms, int32_t n_minibatches,
                        const ppo_hparams *hp, float *const *stats, void *const *ws,

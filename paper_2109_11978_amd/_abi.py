@@ -16,7 +16,7 @@ PPO_E_NOMEM = -5
 PPO_FP32 = 0
 PPO_BF16 = 1
 PPO_MAX_HIDDEN = 4
-PPO_STATS_WIDTH = 8
+PPO_STATS_WIDTH = 10
 PHASES = ("gather", "forward", "head_loss", "input_grad", "weight_grad", "grad_reduce", "adam")
 
 ERROR_NAMES = {
@@ -37,13 +37,15 @@ class Params(ctypes.Structure):
 
 class Batch(ctypes.Structure):
     _fields_ = [("obs", c_void_p), ("actions", c_void_p), ("logp", c_void_p), ("adv", c_void_p),
-                ("returns", c_void_p), ("values", c_void_p), ("B", c_int32)]
+                ("returns", c_void_p), ("values", c_void_p), ("mu_old", c_void_p), ("logstd_old", c_void_p),
+                ("B", c_int32)]
 
 
 class HParams(ctypes.Structure):
     _fields_ = [("clip", c_float), ("value_coef", c_float), ("entropy_coef", c_float),
                 ("max_grad_norm", c_float), ("beta1", c_float), ("beta2", c_float), ("adam_eps", c_float),
-                ("clip_value", c_int32), ("use_graph", c_int32)]
+                ("clip_value", c_int32), ("use_graph", c_int32), ("desired_kl", c_float), ("lr_factor", c_float),
+                ("lr_min", c_float), ("lr_max", c_float)]
 
 
 EXPORTS = {

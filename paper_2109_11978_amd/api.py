@@ -17,7 +17,8 @@ import torch
 from . import _abi
 from ._abi import PPO_BF16, PPO_FP32, PPO_STATS_WIDTH, PPOError, check
 
-STATS_FIELDS = ("loss", "policy_loss", "value_loss", "entropy", "clip_frac", "approx_kl", "grad_norm", "flags")
+STATS_FIELDS = ("loss", "policy_loss", "value_loss", "entropy", "clip_frac", "approx_kl", "grad_norm", "flags", "kl",
+                "lr")
 
 
 def _lib():
@@ -54,10 +55,16 @@ class UpdateHParams:
     adam_eps: float = 1e-8
     clip_value: bool = False
     use_graph: bool = True
+    # KL-adaptive learning rate (Algorithm 1); 0 keeps the rate fixed
+    desired_kl: float = 0.0
+    lr_factor: float = 1.5
+    lr_min: float = 1e-5
+    lr_max: float = 1e-2
 
     def abi(self) -> _abi.HParams:
         return _abi.HParams(self.clip, self.value_coef, self.entropy_coef, self.max_grad_norm, self.beta1,
-                            self.beta2, self.adam_eps, int(self.clip_value), int(self.use_graph))
+                            self.beta2, self.adam_eps, int(self.clip_value), int(self.use_graph),
+                            self.desired_kl, self.lr_factor, self.lr_min, self.lr_max)
 
 
 def net_desc(obs_dim: int, act_dim: int, hidden: Sequence[int]) -> _abi.NetDesc:
@@ -164,11 +171,20 @@ class Params:
                            _ptr(self.lr, torch.float32, "lr"))
 
 
-def make_batch(obs, actions, logp, adv, returns, values=None) -> _abi.Batch:
+def make_batch(obs, actions, logp, adv, returns, values=None, mu_old=None, logstd_old=None) -> _abi.Batch:
     B = obs.shape[0]
     return _abi.Batch(_ptr(obs, torch.float32, "obs"), _ptr(actions, torch.float32, "actions"),
                       _ptr(logp, torch.float32, "logp"), _ptr(adv, torch.float32, "adv"),
-                      _ptr(returns, torch.float32, "returns"), _ptr(values, torch.float32, "values", True), B)
+                      _ptr(returns, torch.float32, "returns"), _ptr(values, torch.float32, "values", True),
+                      _ptr(mu_old, torch.float32, "mu_old", True), _ptr(logstd_old, torch.float32, "logstd_old", True),
+                      B)
+
+
+def batch_abi(batch: Dict[str, torch.Tensor]) -> _abi.Batch:
+    """The ABI batch of a dict with keys obs, actions, logp, adv, returns and
+    optionally values, mu_old, logstd_old (the caller keeps the tensors alive)."""
+    return make_batch(batch["obs"], batch["actions"], batch["logp"], batch["adv"], batch["returns"],
+                      batch.get("values"), batch.get("mu_old"), batch.get("logstd_old"))
 
 
 def ppo_pack_weights(ctx: Context, theta: torch.Tensor, shadow: torch.Tensor, stream=None) -> None:
@@ -206,8 +222,7 @@ def ppo_gae(ctx: Context, rewards, dones, values, last_values, gamma: float, lam
 def ppo_update_epoch(ctx: Context, params: Params, batch: Dict[str, torch.Tensor], perm: torch.Tensor,
                      n_minibatches: int, hp: UpdateHParams, stats: torch.Tensor, ws: torch.Tensor,
                      stream=None) -> None:
-    b = make_batch(batch["obs"], batch["actions"], batch["logp"], batch["adv"], batch["returns"],
-                   batch.get("values"))
+    b = batch_abi(batch)
     p = params.abi()
     h = hp.abi()
     check(_lib().ppo_update_epoch(ctx.handle, _stream(stream), ctypes.byref(p), ctypes.byref(b),
@@ -222,8 +237,7 @@ def ppo_update_batched(ctxs: Sequence[Context], params: Sequence[Params], batche
     R = len(ctxs)
     c_ctx = (ctypes.c_void_p * R)(*[c.handle.value for c in ctxs])
     c_par = (_abi.Params * R)(*[p.abi() for p in params])
-    c_bat = (_abi.Batch * R)(*[make_batch(b["obs"], b["actions"], b["logp"], b["adv"], b["returns"],
-                                          b.get("values")) for b in batches])
+    c_bat = (_abi.Batch * R)(*[batch_abi(b) for b in batches])
     c_perm = (ctypes.c_void_p * R)(*[_ptr(p, torch.int32, "perm") for p in perms])
     c_stats = (ctypes.c_void_p * R)(*[_ptr(s, torch.float32, "stats") for s in stats])
     c_ws = (ctypes.c_void_p * R)(*[_ptr(w, torch.uint8, "ws") for w in ws])
@@ -236,8 +250,7 @@ def ppo_update_batched(ctxs: Sequence[Context], params: Sequence[Params], batche
 def ppo_loss_grad(ctx: Context, params: Params, batch: Dict[str, torch.Tensor], idx: torch.Tensor,
                   hp: UpdateHParams, stats: torch.Tensor, grad_out: torch.Tensor, ws: torch.Tensor,
                   stream=None) -> None:
-    b = make_batch(batch["obs"], batch["actions"], batch["logp"], batch["adv"], batch["returns"],
-                   batch.get("values"))
+    b = batch_abi(batch)
     p = params.abi()
     h = hp.abi()
     check(_lib().ppo_loss_grad(ctx.handle, _stream(stream), ctypes.byref(p), ctypes.byref(b),
@@ -250,8 +263,7 @@ def ppo_update_epoch_profiled(ctx: Context, params: Params, batch: Dict[str, tor
                               n_minibatches: int, hp: UpdateHParams, stats: torch.Tensor, ws: torch.Tensor,
                               stream=None) -> Dict[str, tuple]:
     """Eager epoch with HIP events around each launch; returns {phase: (ms, launches)}."""
-    b = make_batch(batch["obs"], batch["actions"], batch["logp"], batch["adv"], batch["returns"],
-                   batch.get("values"))
+    b = batch_abi(batch)
     p = params.abi()
     h = hp.abi()
     n = len(_abi.PHASES)

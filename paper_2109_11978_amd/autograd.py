@@ -14,7 +14,7 @@ from typing import Dict, Optional
 import torch
 
 from . import _abi
-from .api import Context, UpdateHParams, _ptr, _stream, make_batch, ppo_pack_weights
+from .api import Context, UpdateHParams, _ptr, _stream, batch_abi, ppo_pack_weights
 from ._abi import check
 
 
@@ -41,8 +41,7 @@ class PPOLoss(torch.autograd.Function):
         view = _ParamsView(ctx, theta)
         stats = torch.zeros(_abi.PPO_STATS_WIDTH, dtype=torch.float32, device=theta.device)
         grad = torch.empty_like(view.theta)
-        b = make_batch(batch["obs"], batch["actions"], batch["logp"], batch["adv"], batch["returns"],
-                       batch.get("values"))
+        b = batch_abi(batch)
         p = view.abi()
         h = hp.abi()
         import ctypes

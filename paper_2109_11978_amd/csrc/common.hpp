@@ -9,7 +9,7 @@ namespace ppo {
 
 constexpr int kMaxHidden = 4;
 constexpr int kMaxLayers = kMaxHidden + 1;
-constexpr int kStatsWidth = 8;
+constexpr int kStatsWidth = 10;
 constexpr int kHeadPad = 16;        // output-layer gradient rows padded to 16 columns
 constexpr int kGemmMaxProblems = 16;
 
@@ -117,11 +117,16 @@ struct HeadLossArgs {
     const void *ha, *hc;           // last hidden [M, Hl] (T)
     const float *Wa, *ba, *logstd, *Wc, *bc;
     const float *actions, *logp_old, *adv, *returns, *values_old;  // full batch, indexed by idx
+    const float *mu_old;           // [B, A] collection-time means, or null (no KL)
+    const float *logstd_old;       // [A] collection-time log-std (with mu_old)
     const int32_t *idx;            // [M] rows of the batch, clamped to [0, B)
     int B;
     void *dza, *dzc;               // [M, Hl] (T): gradient wrt the last hidden pre-activations
     void *dz_head_a, *dz_head_c;   // [M, kHeadPad] (T): gradient wrt the output layer
-    float *partials;               // [blocks, A + 8]; row 0, column 4 + A holds the entropy
+    // [blocks, A + 8]: policy, value, clipped, ratio-KL sums, log-std gradient [A],
+    // entropy, mean-shift KL sum, log-std KL part (entropy and the log-std part
+    // in block 0, zero in the other blocks)
+    float *partials;
     int M, A, Hl;
     float clip, value_coef, inv_m;
     int clip_value;
@@ -165,7 +170,11 @@ struct ReduceArgs {
     int n_loss, loss_width, A;
     long long logstd_offset;
     float entropy_coef;
-    float *loss_sums;            // [8]: policy, value, clipped count, kl sums; entropy
+    float *loss_sums;            // [8]: policy, value, clipped count, ratio-KL sums; entropy; mean KL
+    // KL-adaptive rate: with lr non-null and desired_kl > 0 the last block
+    // rescales *lr from the mean KL (inv_m = 1 / M)
+    float *lr;
+    float inv_m, desired_kl, lr_factor, lr_min, lr_max;
 };
 int reduce_blocks(long long total);  // includes the loss-partial block
 hipError_t launch_grad_reduce(const ReduceArgs &a, hipStream_t s);

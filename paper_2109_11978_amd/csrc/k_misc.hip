@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
 
     const int tid = threadIdx.x;
     if (tid < 64) {
-        float pl = 0.0f, vl = 0.0f, clipped = 0.0f, kl = 0.0f;
+        float pl = 0.0f, vl = 0.0f, clipped = 0.0f, kl = 0.0f, kl_mu = 0.0f;
         float dls[kMaxAct];
 #pragma unroll
         for (int j = 0; j < kMaxAct; ++j) dls[j] = 0.0f;
@@ -235,8 +235,14 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
                 z[j] = 0.0f;
                 if (j < A) {
                     const float ls = a.logstd[j];
-                    z[j] = (a.actions[row * A + j] - s_out[i][j]) * expf(-ls);
+                    const float inv_sigma = expf(-ls);
+                    z[j] = (a.actions[row * A + j] - s_out[i][j]) * inv_sigma;
                     logp += -0.5 * static_cast<double>(z[j]) * z[j] - ls;
+                    if (a.mu_old) {
+                        // mean-shift part of KL(pi_old || pi_new): (mu_old - mu)^2 / (2 sigma^2)
+                        const float dm = (a.mu_old[row * A + j] - s_out[i][j]) * inv_sigma;
+                        kl_mu += 0.5f * dm * dm;
+                    }
                 }
             }
             const float adv = a.adv[row];
@@ -279,6 +285,7 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
         }
         // wave 0 holds every sample of the block: shuffle-reduce in a fixed order
         const float w_pl = wave_sum(pl), w_vl = wave_sum(vl), w_cl = wave_sum(clipped), w_kl = wave_sum(kl);
+        const float w_klmu = wave_sum(kl_mu);
         float w_dls[kMaxAct];
 #pragma unroll
         for (int j = 0; j < kMaxAct; ++j) w_dls[j] = wave_sum(dls[j]);
@@ -291,12 +298,22 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
 #pragma unroll
             for (int j = 0; j < kMaxAct; ++j)
                 if (j < A) out[4 + j] = w_dls[j];
+            float ent = 0.0f, kl_ls = 0.0f;
             if (blockIdx.x == 0) {
                 // entropy of the state-independent policy at this step's parameters
-                float ent = 0.5f * A * (1.0f + kLog2Pi);
+                ent = 0.5f * A * (1.0f + kLog2Pi);
                 for (int j = 0; j < A; ++j) ent += a.logstd[j];
-                out[4 + A] = ent;
+                // sample-independent part of the KL:
+                //   sum_j log(sigma / sigma_old) + sigma_old^2 / (2 sigma^2) - 1/2
+                if (a.mu_old)
+                    for (int j = 0; j < A; ++j) {
+                        const float d = a.logstd_old[j] - a.logstd[j];
+                        kl_ls += -d + 0.5f * expf(2.0f * d) - 0.5f;
+                    }
             }
+            out[4 + A] = ent;
+            out[5 + A] = w_klmu;
+            out[6 + A] = kl_ls;
         }
     }
     __syncthreads();
@@ -453,8 +470,10 @@ __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(const Reduc
             ss += static_cast<double>(sum) * sum;
         }
     } else {
+        // columns: 4 loss sums, A log-std gradients, entropy, mean-shift KL, log-std KL
         __shared__ float stripe[8][kMaxAct + 8];
-        const int cols = 4 + a.A;
+        __shared__ float total[kMaxAct + 8];
+        const int cols = 7 + a.A;
         const int c = threadIdx.x & 31, st = threadIdx.x >> 5;
         if (c < cols) {
             // four independent running sums keep four loads in flight; they are
@@ -472,15 +491,31 @@ __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(const Reduc
         if (threadIdx.x < cols) {
             float v = 0.0f;
             for (int q = 0; q < 8; ++q) v += stripe[q][threadIdx.x];
+            total[threadIdx.x] = v;
             if (threadIdx.x < 4) {
                 a.loss_sums[threadIdx.x] = v;
-            } else {
+            } else if (threadIdx.x < 4 + a.A) {
                 const float g = v - a.entropy_coef;
                 a.grad[a.logstd_offset + threadIdx.x - 4] = g;
                 ss = static_cast<double>(g) * g;
             }
         }
-        if (threadIdx.x == 0) a.loss_sums[4] = a.loss_partials[4 + a.A];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.loss_sums[4] = total[4 + a.A];
+            const float kl = total[5 + a.A] * a.inv_m + total[6 + a.A];
+            a.loss_sums[5] = kl;
+            if (a.lr && a.desired_kl > 0.0f) {
+                // Algorithm 1: shrink the rate when the step moved the policy too
+                // far, grow it when it moved too little, within [lr_min, lr_max]
+                float lr = *a.lr;
+                if (kl > 2.0f * a.desired_kl)
+                    lr = fmaxf(a.lr_min, lr / a.lr_factor);
+                else if (kl < 0.5f * a.desired_kl)
+                    lr = fminf(a.lr_max, lr * a.lr_factor);
+                *a.lr = lr;
+            }
+        }
     }
     ss = wave_sum_d(ss);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
@@ -525,6 +560,8 @@ __global__ __launch_bounds__(kAdamThreads) void adam_kernel(const AdamArgs a) {
         a.stats[5] = a.loss_sums[3] * a.inv_m;
         a.stats[6] = static_cast<float>(norm);
         a.stats[7] = finite ? 0.0f : 1.0f;
+        a.stats[8] = a.loss_sums[5];
+        a.stats[9] = a.lr ? *a.lr : 0.0f;
     }
     if (!a.apply || !finite) return;
 

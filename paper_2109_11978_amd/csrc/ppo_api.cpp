@@ -422,12 +422,16 @@ struct DwPlan {
     ReduceArgs red{};
 };
 
-DwPlan build_dw(const ppo_ctx *c, const WsPlan &w, void *ws, int M, const TileChoice &tc) {
+DwPlan build_dw(const ppo_ctx *c, const WsPlan &w, void *ws, int M, const TileChoice &tc, int kps_override = 0) {
     const NetLayout &g = c->g;
     const int L = g.L;
     DwPlan d;
     int splits, kps;
     dw_splits(g, c->prec, M, tc.tile, tc.rounds, splits, kps);
+    if (kps_override > 0) {
+        kps = kps_override;
+        splits = cdiv(M, kps);
+    }
     long long pos = 0;
     float *part = reinterpret_cast<float *>(wsp(ws, w.part));
     float *rows_part = reinterpret_cast<float *>(wsp(ws, w.rowsum));
@@ -674,6 +678,92 @@ struct StepBuffers {
     int step_offset;
 };
 
+// Head/loss arguments of one mini-batch step over the rows idx[0 .. M).
+HeadLossArgs head_loss_args(const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp, const WsPlan &w,
+                            void *ws, const ppo_batch *b, const int32_t *idx, int M) {
+    const NetLayout &g = c->g;
+    const int L = g.L;
+    HeadLossArgs hl{};
+    hl.ha = wsp(ws, w.h_a[L - 1]);
+    hl.hc = wsp(ws, w.h_c[L - 1]);
+    hl.Wa = p->theta + g.Wa[L];
+    hl.ba = p->theta + g.ba[L];
+    hl.logstd = p->theta + g.logstd;
+    hl.Wc = p->theta + g.Wc[L];
+    hl.bc = p->theta + g.bc[L];
+    hl.actions = b->actions;
+    hl.logp_old = b->logp;
+    hl.adv = b->adv;
+    hl.returns = b->returns;
+    hl.values_old = b->values;
+    hl.mu_old = b->mu_old;
+    hl.logstd_old = b->mu_old ? b->logstd_old : nullptr;
+    hl.idx = idx;
+    hl.B = b->B;
+    hl.dza = wsp(ws, w.dz_a[L - 1]);
+    hl.dzc = wsp(ws, w.dz_c[L - 1]);
+    hl.dz_head_a = wsp(ws, w.dzh_a);
+    hl.dz_head_c = wsp(ws, w.dzh_c);
+    hl.partials = reinterpret_cast<float *>(wsp(ws, w.loss_part));
+    hl.M = M;
+    hl.A = g.A;
+    hl.Hl = g.H[L - 1];
+    hl.clip = hp->clip;
+    hl.value_coef = hp->value_coef;
+    hl.inv_m = 1.0f / static_cast<float>(M);
+    hl.clip_value = hp->clip_value;
+    return hl;
+}
+
+// The loss-partial half of the gradient assembly (the segments come from
+// build_dw).  The learning rate adapts only in an optimiser step.
+void set_reduce_loss(ReduceArgs &red, const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp,
+                     const WsPlan &w, void *ws, float *grad, int M, int apply) {
+    const NetLayout &g = c->g;
+    red.grad = grad;
+    red.sumsq_partials = reinterpret_cast<double *>(wsp(ws, w.sumsq));
+    red.loss_partials = reinterpret_cast<const float *>(wsp(ws, w.loss_part));
+    red.n_loss = head_loss_blocks(M);
+    red.loss_width = head_loss_partial_width(g.A);
+    red.A = g.A;
+    red.logstd_offset = g.logstd;
+    red.entropy_coef = hp->entropy_coef;
+    red.loss_sums = reinterpret_cast<float *>(wsp(ws, w.loss_sums));
+    red.inv_m = 1.0f / static_cast<float>(M);
+    red.lr = apply && hp->desired_kl > 0.0f ? p->lr : nullptr;
+    red.desired_kl = hp->desired_kl;
+    red.lr_factor = hp->lr_factor;
+    red.lr_min = hp->lr_min;
+    red.lr_max = hp->lr_max;
+}
+
+AdamArgs adam_args(const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp, const ReduceArgs &red,
+                   float *grad, float *stats, int M, int step_offset, int apply) {
+    AdamArgs ad{};
+    ad.theta = p->theta;
+    ad.grad = grad;
+    ad.m = p->adam_m;
+    ad.v = p->adam_v;
+    ad.shadow = c->prec == kBF16 ? p->shadow : nullptr;
+    ad.step = p->step;
+    ad.step_offset = step_offset;
+    ad.lr = p->lr;
+    ad.sumsq_partials = red.sumsq_partials;
+    ad.n_sumsq = reduce_blocks(red.total);
+    ad.loss_sums = red.loss_sums;
+    ad.max_grad_norm = hp->max_grad_norm;
+    ad.beta1 = hp->beta1;
+    ad.beta2 = hp->beta2;
+    ad.eps = hp->adam_eps;
+    ad.inv_m = 1.0f / static_cast<float>(M);
+    ad.value_coef = hp->value_coef;
+    ad.entropy_coef = hp->entropy_coef;
+    ad.stats = stats;
+    ad.P = c->g.P;
+    ad.apply = apply;
+    return ad;
+}
+
 // One mini-batch step: gather, forward, head+loss, input-gradient chain,
 // weight gradients, gradient assembly with the float64 norm, Adam.
 hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp, const WsPlan &w, void *ws,
@@ -689,33 +779,7 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
     e = enqueue_forward(c, p, w, ws, M, true, true, t, s, prof);
     if (e != hipSuccess) return e;
 
-    HeadLossArgs hl{};
-    hl.ha = wsp(ws, w.h_a[L - 1]);
-    hl.hc = wsp(ws, w.h_c[L - 1]);
-    hl.Wa = p->theta + g.Wa[L];
-    hl.ba = p->theta + g.ba[L];
-    hl.logstd = p->theta + g.logstd;
-    hl.Wc = p->theta + g.Wc[L];
-    hl.bc = p->theta + g.bc[L];
-    hl.actions = sb.b->actions;
-    hl.logp_old = sb.b->logp;
-    hl.adv = sb.b->adv;
-    hl.returns = sb.b->returns;
-    hl.values_old = sb.b->values;
-    hl.idx = sb.idx;
-    hl.B = sb.b->B;
-    hl.dza = wsp(ws, w.dz_a[L - 1]);
-    hl.dzc = wsp(ws, w.dz_c[L - 1]);
-    hl.dz_head_a = wsp(ws, w.dzh_a);
-    hl.dz_head_c = wsp(ws, w.dzh_c);
-    hl.partials = reinterpret_cast<float *>(wsp(ws, w.loss_part));
-    hl.M = M;
-    hl.A = g.A;
-    hl.Hl = g.H[L - 1];
-    hl.clip = hp->clip;
-    hl.value_coef = hp->value_coef;
-    hl.inv_m = 1.0f / static_cast<float>(M);
-    hl.clip_value = hp->clip_value;
+    const HeadLossArgs hl = head_loss_args(c, p, hp, w, ws, sb.b, sb.idx, M);
     PROFILED(prof, PPO_PHASE_HEAD_LOSS, launch_head_loss(prec, hl, s));
 
     for (int l = L - 1; l >= 1; --l) {
@@ -728,40 +792,10 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
         PROFILED(prof, PPO_PHASE_WEIGHT_GRAD, launch_gemm(prec, 1, 1, kEpiPartial, d.launch[i], s));
 
     ReduceArgs &red = d.red;
-    const int lw = head_loss_partial_width(g.A);
-    red.grad = sb.grad;
-    red.sumsq_partials = reinterpret_cast<double *>(wsp(ws, w.sumsq));
-    red.loss_partials = reinterpret_cast<const float *>(wsp(ws, w.loss_part));
-    red.n_loss = head_loss_blocks(M);
-    red.loss_width = lw;
-    red.A = g.A;
-    red.logstd_offset = g.logstd;
-    red.entropy_coef = hp->entropy_coef;
-    red.loss_sums = reinterpret_cast<float *>(wsp(ws, w.loss_sums));
+    set_reduce_loss(red, c, p, hp, w, ws, sb.grad, M, sb.apply);
     PROFILED(prof, PPO_PHASE_GRAD_REDUCE, launch_grad_reduce(red, s));
 
-    AdamArgs ad{};
-    ad.theta = p->theta;
-    ad.grad = sb.grad;
-    ad.m = p->adam_m;
-    ad.v = p->adam_v;
-    ad.shadow = prec == kBF16 ? p->shadow : nullptr;
-    ad.step = p->step;
-    ad.step_offset = sb.step_offset;
-    ad.lr = p->lr;
-    ad.sumsq_partials = red.sumsq_partials;
-    ad.n_sumsq = reduce_blocks(red.total);
-    ad.loss_sums = red.loss_sums;
-    ad.max_grad_norm = hp->max_grad_norm;
-    ad.beta1 = hp->beta1;
-    ad.beta2 = hp->beta2;
-    ad.eps = hp->adam_eps;
-    ad.inv_m = 1.0f / static_cast<float>(M);
-    ad.value_coef = hp->value_coef;
-    ad.entropy_coef = hp->entropy_coef;
-    ad.stats = sb.stats;
-    ad.P = g.P;
-    ad.apply = sb.apply;
+    const AdamArgs ad = adam_args(c, p, hp, red, sb.grad, sb.stats, M, sb.step_offset, sb.apply);
     PROFILED(prof, PPO_PHASE_ADAM, launch_adam(ad, s));
     return hipSuccess;
 }
@@ -774,6 +808,12 @@ int validate_hparams(const ppo_hparams *hp) {
         return fail(PPO_E_INVAL, "hyper-parameter out of range");
     if (hp->clip_value != 0 && hp->clip_value != 1) return fail(PPO_E_INVAL, "clip_value must be 0 or 1");
     if (hp->use_graph != 0 && hp->use_graph != 1) return fail(PPO_E_INVAL, "use_graph must be 0 or 1");
+    if (!(hp->desired_kl >= 0.0f) || !std::isfinite(hp->desired_kl))
+        return fail(PPO_E_INVAL, "desired_kl must be finite and >= 0");
+    if (hp->desired_kl > 0.0f &&
+        (!(hp->lr_factor >= 1.0f) || !std::isfinite(hp->lr_factor) || !(hp->lr_min > 0.0f) ||
+         !(hp->lr_max >= hp->lr_min) || !std::isfinite(hp->lr_max)))
+        return fail(PPO_E_INVAL, "adaptive rate needs lr_factor >= 1 and 0 < lr_min <= lr_max");
     return PPO_OK;
 }
 
@@ -800,6 +840,12 @@ int validate_batch(const ppo_ctx *c, const ppo_batch *b, const ppo_hparams *hp) 
     PPO_CHECK(check_ptr(b->adv, "batch.adv"));
     PPO_CHECK(check_ptr(b->returns, "batch.returns"));
     if (hp->clip_value) PPO_CHECK(check_ptr(b->values, "batch.values"));
+    if (hp->desired_kl > 0.0f && !b->mu_old)
+        return fail(PPO_E_INVAL, "desired_kl > 0 needs batch.mu_old and batch.logstd_old");
+    if (b->mu_old) {
+        PPO_CHECK(check_ptr(b->mu_old, "batch.mu_old"));
+        if (!b->logstd_old) return fail(PPO_E_INVAL, "batch.logstd_old is NULL while batch.mu_old is set");
+    }
     (void)c;
     return PPO_OK;
 }
@@ -1055,11 +1101,13 @@ int ppo_update_epoch(ppo_ctx *c, void *stream, const ppo_params *p, const ppo_ba
     PPO_CHECK(ensure_capture_stream(c));
     std::vector<uint64_t> key = {u64(p->theta), u64(p->grad), u64(p->adam_m), u64(p->adam_v), u64(p->shadow),
                                  u64(p->step), u64(p->lr), u64(b->obs), u64(b->actions), u64(b->logp),
-                                 u64(b->adv), u64(b->returns), u64(b->values), static_cast<uint64_t>(b->B),
+                                 u64(b->adv), u64(b->returns), u64(b->values), u64(b->mu_old),
+                                 u64(b->logstd_old), static_cast<uint64_t>(b->B),
                                  u64(perm), static_cast<uint64_t>(n_minibatches), u64(stats), u64(ws),
                                  fbits(hp->clip), fbits(hp->value_coef), fbits(hp->entropy_coef),
                                  fbits(hp->max_grad_norm), fbits(hp->beta1), fbits(hp->beta2), fbits(hp->adam_eps),
-                                 static_cast<uint64_t>(hp->clip_value)};
+                                 static_cast<uint64_t>(hp->clip_value), fbits(hp->desired_kl),
+                                 fbits(hp->lr_factor), fbits(hp->lr_min), fbits(hp->lr_max)};
     auto it = c->graphs.find(key);
     hipGraphExec_t exec = nullptr;
     if (it != c->graphs.end()) {
@@ -1187,6 +1235,8 @@ int ppo_gemm_check(void *stream, int32_t precision, int32_t a_mode, int32_t b_mo
     return PPO_OK;
 }
 
+}  // extern "C"
+
 // ------------------------------------------------------ batched update
 namespace {
 
@@ -1213,11 +1263,38 @@ struct BatchedRun {
     int M;
 };
 
-constexpr int kBatchedTile = kTile128x128;
+// Tile choices of the grouped launches.  With autotuning off every site
+// uses 128 x 128 tiles and each run keeps the weight-gradient split count it
+// would use alone (results then equal each run's own ppo_update_epoch bit
+// for bit); with autotuning on, the tiles are timed per grouped site and the
+// weight-gradient workgroups of all runs get one common k-length, so the
+// uneven runs finish their workgroups at about the same time.
+struct BatchedTuning {
+    int fwd[kMaxHidden] = {kTile128x128, kTile128x128, kTile128x128, kTile128x128};
+    int dx[kMaxHidden] = {kTile128x128, kTile128x128, kTile128x128, kTile128x128};
+    int dw = kTile128x128;
+    int dw_kps = 0;   // 0: each run's own split count
+};
+
+// Common k-length for `rounds` rounds of resident workgroups over all runs.
+int batched_dw_kps(const std::vector<BatchedRun> &runs, int tile, int rounds) {
+    long long work = 0;  // tile-samples
+    for (const BatchedRun &r : runs) work += static_cast<long long>(dw_tiles(r.c->g, tile)) * r.M;
+    const int bk = gemm_bk(runs[0].c->prec);
+    long long kps = (work + static_cast<long long>(rounds) * kResidentSlots - 1) / (rounds * kResidentSlots);
+    kps = std::max<long long>(kps, 2 * bk);
+    for (const BatchedRun &r : runs) {
+        // never more splits than the workspace holds for that run
+        const int min_kps = cdiv(cdiv(r.M, r.w.max_splits), bk) * bk;
+        kps = std::max<long long>(kps, min_kps);
+    }
+    return static_cast<int>(cdiv(kps, bk) * bk);
+}
 
 // Step k of every run: per-run gathers, then one grouped launch per GEMM
 // site covering all runs, per-run loss, reduce and Adam kernels.
-hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams *hp, int k, hipStream_t s) {
+hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams *hp, int k,
+                                const BatchedTuning &bt, hipStream_t s) {
     const int R = static_cast<int>(runs.size());
     const NetLayout &g0 = runs[0].c->g;
     const Precision prec = runs[0].c->prec;
@@ -1232,63 +1309,35 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
     for (int l = 0; l < L; ++l) {
         std::vector<GemmArgs> launches;
         for (BatchedRun &r : runs)
-            append_problems(launches, build_fwd(r.c, r.p, r.w, r.ws, r.M, l, true, true, kBatchedTile),
-                            kBatchedTile, bk);
+            append_problems(launches, build_fwd(r.c, r.p, r.w, r.ws, r.M, l, true, true, bt.fwd[l]), bt.fwd[l], bk);
         for (const GemmArgs &a : launches) {
             e = launch_gemm(prec, 0, 0, kEpiBiasElu, a, s);
             if (e != hipSuccess) return e;
         }
     }
     for (BatchedRun &r : runs) {
-        const NetLayout &g = r.c->g;
-        HeadLossArgs hl{};
-        hl.ha = wsp(r.ws, r.w.h_a[L - 1]);
-        hl.hc = wsp(r.ws, r.w.h_c[L - 1]);
-        hl.Wa = r.p->theta + g.Wa[L];
-        hl.ba = r.p->theta + g.ba[L];
-        hl.logstd = r.p->theta + g.logstd;
-        hl.Wc = r.p->theta + g.Wc[L];
-        hl.bc = r.p->theta + g.bc[L];
-        hl.actions = r.b->actions;
-        hl.logp_old = r.b->logp;
-        hl.adv = r.b->adv;
-        hl.returns = r.b->returns;
-        hl.values_old = r.b->values;
-        hl.idx = r.perm + static_cast<long long>(k) * r.M;
-        hl.B = r.b->B;
-        hl.dza = wsp(r.ws, r.w.dz_a[L - 1]);
-        hl.dzc = wsp(r.ws, r.w.dz_c[L - 1]);
-        hl.dz_head_a = wsp(r.ws, r.w.dzh_a);
-        hl.dz_head_c = wsp(r.ws, r.w.dzh_c);
-        hl.partials = reinterpret_cast<float *>(wsp(r.ws, r.w.loss_part));
-        hl.M = r.M;
-        hl.A = g.A;
-        hl.Hl = g.H[L - 1];
-        hl.clip = hp->clip;
-        hl.value_coef = hp->value_coef;
-        hl.inv_m = 1.0f / static_cast<float>(r.M);
-        hl.clip_value = hp->clip_value;
+        const HeadLossArgs hl = head_loss_args(r.c, r.p, hp, r.w, r.ws, r.b, r.perm + static_cast<long long>(k) * r.M,
+                                               r.M);
         e = launch_head_loss(prec, hl, s);
         if (e != hipSuccess) return e;
     }
     for (int l = L - 1; l >= 1; --l) {
         std::vector<GemmArgs> launches;
         for (BatchedRun &r : runs)
-            append_problems(launches, build_dx(r.c, r.p, r.w, r.ws, r.M, l, kBatchedTile), kBatchedTile, bk);
+            append_problems(launches, build_dx(r.c, r.p, r.w, r.ws, r.M, l, bt.dx[l]), bt.dx[l], bk);
         for (const GemmArgs &a : launches) {
             e = launch_gemm(prec, 0, 1, kEpiDElu, a, s);
             if (e != hipSuccess) return e;
         }
     }
-    // weight gradients: each run keeps the split count it would use alone
     std::vector<DwPlan> plans(R);
     std::vector<GemmArgs> launches;
     for (int i = 0; i < R; ++i) {
         TileChoice tc;
-        tc.tile = kBatchedTile;
+        tc.tile = bt.dw;
         tc.rounds = 1;
-        plans[i] = build_dw(runs[i].c, runs[i].w, runs[i].ws, runs[i].M, tc);
-        for (int q = 0; q < plans[i].n_launch; ++q) append_problems(launches, plans[i].launch[q], kBatchedTile, bk);
+        plans[i] = build_dw(runs[i].c, runs[i].w, runs[i].ws, runs[i].M, tc, bt.dw_kps);
+        for (int q = 0; q < plans[i].n_launch; ++q) append_problems(launches, plans[i].launch[q], bt.dw, bk);
     }
     for (const GemmArgs &a : launches) {
         e = launch_gemm(prec, 1, 1, kEpiPartial, a, s);
@@ -1296,54 +1345,108 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
     }
     for (int i = 0; i < R; ++i) {
         BatchedRun &r = runs[i];
-        const NetLayout &g = r.c->g;
         ReduceArgs &red = plans[i].red;
-        red.grad = r.p->grad;
-        red.sumsq_partials = reinterpret_cast<double *>(wsp(r.ws, r.w.sumsq));
-        red.loss_partials = reinterpret_cast<const float *>(wsp(r.ws, r.w.loss_part));
-        red.n_loss = head_loss_blocks(r.M);
-        red.loss_width = head_loss_partial_width(g.A);
-        red.A = g.A;
-        red.logstd_offset = g.logstd;
-        red.entropy_coef = hp->entropy_coef;
-        red.loss_sums = reinterpret_cast<float *>(wsp(r.ws, r.w.loss_sums));
+        set_reduce_loss(red, r.c, r.p, hp, r.w, r.ws, r.p->grad, r.M, 1);
         e = launch_grad_reduce(red, s);
         if (e != hipSuccess) return e;
-        AdamArgs ad{};
-        ad.theta = r.p->theta;
-        ad.grad = r.p->grad;
-        ad.m = r.p->adam_m;
-        ad.v = r.p->adam_v;
-        ad.shadow = prec == kBF16 ? r.p->shadow : nullptr;
-        ad.step = r.p->step;
-        ad.step_offset = k;
-        ad.lr = r.p->lr;
-        ad.sumsq_partials = red.sumsq_partials;
-        ad.n_sumsq = reduce_blocks(red.total);
-        ad.loss_sums = red.loss_sums;
-        ad.max_grad_norm = hp->max_grad_norm;
-        ad.beta1 = hp->beta1;
-        ad.beta2 = hp->beta2;
-        ad.eps = hp->adam_eps;
-        ad.inv_m = 1.0f / static_cast<float>(r.M);
-        ad.value_coef = hp->value_coef;
-        ad.entropy_coef = hp->entropy_coef;
-        ad.stats = r.stats + k * PPO_STATS_WIDTH;
-        ad.P = g.P;
-        ad.apply = 1;
+        const AdamArgs ad = adam_args(r.c, r.p, hp, red, r.p->grad, r.stats + k * PPO_STATS_WIDTH, r.M, k, 1);
         e = launch_adam(ad, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
+// Times one grouped GEMM site over all runs for a candidate.
+template <typename Build>
+hipError_t time_grouped(const std::vector<BatchedRun> &runs, int a_mode, int b_mode, int epi, int tile,
+                        Build &&build, hipStream_t s, float &ms) {
+    const int bk = gemm_bk(runs[0].c->prec);
+    std::vector<GemmArgs> launches;
+    for (const BatchedRun &r : runs) {
+        std::vector<GemmArgs> one = build(r);
+        for (const GemmArgs &a : one) append_problems(launches, a, tile, bk);
+    }
+    return time_launch(
+        s,
+        [&] {
+            hipError_t e = hipSuccess;
+            for (const GemmArgs &a : launches)
+                if (e == hipSuccess) e = launch_gemm(runs[0].c->prec, a_mode, b_mode, epi, a, s);
+            return e;
+        },
+        3, ms);
+}
+
+int tune_batched(std::vector<BatchedRun> &runs, hipStream_t s, BatchedTuning &bt) {
+    bt = BatchedTuning{};
+    if (!autotune_enabled()) return PPO_OK;
+    const int L = runs[0].c->g.L;
+    for (int l = 0; l < L; ++l) {
+        float best = 1e30f;
+        for (int tile = 0; tile < kNumTileShapes; ++tile) {
+            float ms = 0.0f;
+            PPO_HIP(time_grouped(runs, 0, 0, kEpiBiasElu, tile,
+                                 [&](const BatchedRun &r) {
+                                     return std::vector<GemmArgs>{
+                                         build_fwd(r.c, r.p, r.w, r.ws, r.M, l, true, true, tile)};
+                                 },
+                                 s, ms),
+                    "autotune grouped forward");
+            if (ms < best) {
+                best = ms;
+                bt.fwd[l] = tile;
+            }
+        }
+    }
+    for (int l = 1; l < L; ++l) {
+        float best = 1e30f;
+        for (int tile = 0; tile < kNumTileShapes; ++tile) {
+            float ms = 0.0f;
+            PPO_HIP(time_grouped(runs, 0, 1, kEpiDElu, tile,
+                                 [&](const BatchedRun &r) {
+                                     return std::vector<GemmArgs>{build_dx(r.c, r.p, r.w, r.ws, r.M, l, tile)};
+                                 },
+                                 s, ms),
+                    "autotune grouped input gradient");
+            if (ms < best) {
+                best = ms;
+                bt.dx[l] = tile;
+            }
+        }
+    }
+    float best = 1e30f;
+    for (int tile = 0; tile < kNumTileShapes; ++tile)
+        for (int rounds : {1, 2, 4}) {
+            const int kps = batched_dw_kps(runs, tile, rounds);
+            float ms = 0.0f;
+            PPO_HIP(time_grouped(runs, 1, 1, kEpiPartial, tile,
+                                 [&](const BatchedRun &r) {
+                                     TileChoice tc;
+                                     tc.tile = tile;
+                                     DwPlan d = build_dw(r.c, r.w, r.ws, r.M, tc, kps);
+                                     return std::vector<GemmArgs>(d.launch, d.launch + d.n_launch);
+                                 },
+                                 s, ms),
+                    "autotune grouped weight gradient");
+            if (ms < best) {
+                best = ms;
+                bt.dw = tile;
+                bt.dw_kps = kps;
+            }
+        }
+    return PPO_OK;
+}
+
 std::mutex g_batched_mu;
+std::map<std::string, BatchedTuning> g_batched_tuning;
 std::map<std::vector<uint64_t>, hipGraphExec_t> g_batched_graphs;
 std::vector<std::vector<uint64_t>> g_batched_order;
 hipStream_t g_batched_capture = nullptr;
 int g_batched_dev = -1;
 
 }  // namespace
+
+extern "C" {
 
 int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_params *params,
                        const ppo_batch *batches, const int32_t *const *perms, int32_t n_minibatches,
@@ -1373,9 +1476,22 @@ int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_
     }
     PPO_CHECK(check_device());
     const hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchedTuning bt;
+    {
+        std::string key = std::string(autotune_enabled() ? "t" : "f");
+        for (const BatchedRun &r : runs) key += "|" + tune_key(r.c, r.M, true);
+        std::lock_guard<std::mutex> lk(g_batched_mu);
+        auto it = g_batched_tuning.find(key);
+        if (it != g_batched_tuning.end()) {
+            bt = it->second;
+        } else {
+            PPO_CHECK(tune_batched(runs, s, bt));
+            g_batched_tuning[key] = bt;
+        }
+    }
     auto enqueue_all = [&](hipStream_t target) -> hipError_t {
         for (int k = 0; k < n_minibatches; ++k) {
-            hipError_t e = enqueue_batched_step(runs, hp, k, target);
+            hipError_t e = enqueue_batched_step(runs, hp, k, bt, target);
             if (e != hipSuccess) return e;
         }
         for (int i = 0; i < R; ++i) {
@@ -1391,13 +1507,15 @@ int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_
     std::vector<uint64_t> key = {static_cast<uint64_t>(R), static_cast<uint64_t>(n_minibatches),
                                  fbits(hp->clip), fbits(hp->value_coef), fbits(hp->entropy_coef),
                                  fbits(hp->max_grad_norm), fbits(hp->beta1), fbits(hp->beta2), fbits(hp->adam_eps),
-                                 static_cast<uint64_t>(hp->clip_value)};
+                                 static_cast<uint64_t>(hp->clip_value), fbits(hp->desired_kl),
+                                 fbits(hp->lr_factor), fbits(hp->lr_min), fbits(hp->lr_max)};
     for (int i = 0; i < R; ++i) {
         const ppo_params &p = params[i];
         const ppo_batch &b = batches[i];
         for (uint64_t v : {u64(ctxs[i]), u64(p.theta), u64(p.grad), u64(p.adam_m), u64(p.adam_v), u64(p.shadow),
                            u64(p.step), u64(p.lr), u64(b.obs), u64(b.actions), u64(b.logp), u64(b.adv),
-                           u64(b.returns), u64(b.values), static_cast<uint64_t>(b.B), u64(perms[i]), u64(stats[i]),
+                           u64(b.returns), u64(b.values), u64(b.mu_old), u64(b.logstd_old),
+                           static_cast<uint64_t>(b.B), u64(perms[i]), u64(stats[i]),
                            u64(ws[i])})
             key.push_back(v);
     }

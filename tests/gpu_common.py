@@ -80,8 +80,30 @@ def teacher_batch(cfg, theta, B, seed, shift="near", returns="gae"):
 
 def oracle_view(batch):
     """Key names of the oracle's batch dictionary."""
-    return dict(obs=batch["obs"], actions=batch["actions"], logp_old=batch["logp"], adv=batch["adv"],
-                returns=batch["returns"], values_old=batch["values"])
+    out = dict(obs=batch["obs"], actions=batch["actions"], logp_old=batch["logp"], adv=batch["adv"],
+               returns=batch["returns"], values_old=batch["values"])
+    for k in ("mu_old", "logstd_old"):
+        if k in batch:
+            out[k] = batch[k]
+    return out
+
+
+def add_kl_inputs(cfg, theta, batch, seed, shift_scale, logstd_shift=0.03):
+    """Collection-time means and log-std for the KL: mu_old = mu(theta) +
+    shift_scale[s] * N(0, 1) per sample s (shift_scale is a scalar or a [B]
+    array) and logstd_old = logstd + logstd_shift * N(0, 1).  Returns the
+    batch with mu_old [B, A] and logstd_old [A] added (float32)."""
+    from oracle import mlp_forward, unpack
+    spec = spec_of(cfg)
+    actor, logstd, _ = unpack(theta, spec)
+    mu, _, _ = mlp_forward(actor, batch["obs"].astype(np.float64))
+    rng = np.random.default_rng(seed)
+    B, A = mu.shape
+    scale = np.broadcast_to(np.asarray(shift_scale, dtype=np.float64), (B,))
+    out = dict(batch)
+    out["mu_old"] = (mu + scale[:, None] * rng.normal(0, 1, (B, A))).astype(np.float32)
+    out["logstd_old"] = (np.asarray(logstd, np.float32) + logstd_shift * rng.normal(0, 1, A)).astype(np.float32)
+    return out
 
 
 def bf16_round(x):

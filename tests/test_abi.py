@@ -81,7 +81,7 @@ def _params(lib_ctx_bf16=True):
 
 
 def _batch(B, obs=FAKE):
-    return _abi.Batch(obs, FAKE, FAKE, FAKE, FAKE, None, B)
+    return _abi.Batch(obs, FAKE, FAKE, FAKE, FAKE, None, None, None, B)
 
 
 def test_misuse_codes():
@@ -153,7 +153,32 @@ def test_batched_rejects_mismatched_runs():
     h = ppo.UpdateHParams().abi()
     for i in range(2):
         pars[i] = _abi.Params(0x10000, 0x10000, 0x10000, 0x10000, 0x10000, 0x10000, 0x10000)
-        bats[i] = _abi.Batch(0x10000, 0x10000, 0x10000, 0x10000, 0x10000, None, 64)
+        bats[i] = _abi.Batch(0x10000, 0x10000, 0x10000, 0x10000, 0x10000, None, None, None, 64)
     rc = lib.ppo_update_batched(ctxs, 2, None, pars, bats, arr, 4, ctypes.byref(h), arr, arr, wsb)
     assert rc == ppo.PPO_E_SHAPE
     assert b"hidden layers" in lib.ppo_last_error()
+
+
+def test_adaptive_rate_validation():
+    lib = ppo.load()
+    ctx = ppo.Context(48, 12, (64, 64), "bf16")
+    p = _params()
+    ws = ctx.workspace_size(N=64, T=24, M=1536)
+    b = _batch(1536)
+    # desired_kl > 0 needs the collection-time means
+    h = ppo.UpdateHParams(desired_kl=0.01).abi()
+    assert lib.ppo_update_epoch(ctx.handle, None, ctypes.byref(p), ctypes.byref(b), FAKE, 1, ctypes.byref(h),
+                                FAKE, FAKE, ws) == ppo.PPO_E_INVAL
+    assert b"mu_old" in lib.ppo_last_error()
+    # mu_old without logstd_old
+    b2 = _abi.Batch(FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, None, 1536)
+    assert lib.ppo_update_epoch(ctx.handle, None, ctypes.byref(p), ctypes.byref(b2), FAKE, 1, ctypes.byref(h),
+                                FAKE, FAKE, ws) == ppo.PPO_E_INVAL
+    # bad rule parameters
+    b3 = _abi.Batch(FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, 1536)
+    for bad in (ppo.UpdateHParams(desired_kl=-1.0), ppo.UpdateHParams(desired_kl=0.01, lr_factor=0.5),
+                ppo.UpdateHParams(desired_kl=0.01, lr_min=0.0), ppo.UpdateHParams(desired_kl=0.01, lr_max=1e-6),
+                ppo.UpdateHParams(desired_kl=float("nan"))):
+        hb = bad.abi()
+        assert lib.ppo_update_epoch(ctx.handle, None, ctypes.byref(p), ctypes.byref(b3), FAKE, 1, ctypes.byref(hb),
+                                    FAKE, FAKE, ws) == ppo.PPO_E_INVAL, bad

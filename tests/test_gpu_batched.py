@@ -11,7 +11,7 @@ import torch
 
 import paper_2109_11978_amd as ppo
 import synth
-from tests.gpu_common import dev, require_gpu, teacher_batch
+from tests.gpu_common import add_kl_inputs, dev, require_gpu, teacher_batch
 
 pytestmark = pytest.mark.gpu
 
@@ -28,6 +28,9 @@ def _runs(prec):
                                       epochs=1, minibatches=K, seed=r)
         theta = synth.xavier_theta(cfg.net, seed=r, logstd=-0.3)
         batch = teacher_batch(cfg, theta, cfg.batch, seed=10 + r, shift="mixed")
+        # collection-time means: KL well above, below and inside the adaptive band per run
+        batch = add_kl_inputs(cfg, theta, batch, seed=30 + r, shift_scale=(0.08, 0.004, 0.033, 0.08)[r],
+                              logstd_shift=0.01)
         perm = np.random.default_rng(20 + r).permutation(cfg.batch).astype(np.int32)
         out.append((cfg, theta, batch, perm))
     return out
@@ -35,7 +38,7 @@ def _runs(prec):
 
 def _state(params):
     return [params.theta.cpu().numpy().copy(), params.adam_m.cpu().numpy().copy(),
-            params.adam_v.cpu().numpy().copy(), int(params.step[0].item())]
+            params.adam_v.cpu().numpy().copy(), params.lr.cpu().numpy().copy(), int(params.step[0].item())]
 
 
 @pytest.fixture
@@ -43,12 +46,12 @@ def fixed_tiles(monkeypatch):
     monkeypatch.setenv("PPO_AUTOTUNE", "0")
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_batched_equals_solo(prec, fixed_tiles):
+@pytest.mark.parametrize("prec,desired_kl", [("fp32", 0.0), ("bf16", 0.0), ("bf16", 0.01)])
+def test_batched_equals_solo(prec, desired_kl, fixed_tiles):
     d = require_gpu()
     runs = _runs(prec)
-    print(f"[gpu-case] batched vs solo {prec} runs={RUNS}", flush=True)
-    hp = ppo.UpdateHParams()
+    print(f"[gpu-case] batched vs solo {prec} desired_kl={desired_kl} runs={RUNS}", flush=True)
+    hp = ppo.UpdateHParams(desired_kl=desired_kl)
     ctxs, solo_state, solo_stats = [], [], []
     for cfg, theta, batch, perm in runs:
         ctx = ppo.Context(cfg.net.obs_dim, cfg.net.act_dim, cfg.net.hidden, prec)
@@ -61,6 +64,10 @@ def test_batched_equals_solo(prec, fixed_tiles):
         solo_state.append(_state(params))
         solo_stats.append(stats.cpu().numpy())
 
+    if desired_kl > 0:
+        # run 0 starts far above the band (rate divided), run 1 far below (multiplied)
+        assert solo_stats[0][0, 9] == pytest.approx(1e-3 / 1.5, rel=1e-6)
+        assert solo_stats[1][0, 9] == pytest.approx(1e-3 * 1.5, rel=1e-6)
     for use_graph in (False, True):
         params, batches, perms, stats, wss = [], [], [], [], []
         for (cfg, theta, batch, perm), ctx in zip(runs, ctxs):
@@ -69,11 +76,12 @@ def test_batched_equals_solo(prec, fixed_tiles):
             perms.append(dev(perm, d))
             stats.append(torch.zeros(K, ppo.PPO_STATS_WIDTH, device=d))
             wss.append(ctx.new_workspace(M=cfg.minibatch))
-        ppo.ppo_update_batched(ctxs, params, batches, perms, K, ppo.UpdateHParams(use_graph=use_graph), stats, wss)
+        ppo.ppo_update_batched(ctxs, params, batches, perms, K,
+                               ppo.UpdateHParams(use_graph=use_graph, desired_kl=desired_kl), stats, wss)
         torch.cuda.synchronize()
         for r in range(len(runs)):
             got = _state(params[r])
-            for a, b in zip(got[:3], solo_state[r][:3]):
+            for a, b in zip(got[:4], solo_state[r][:4]):
                 np.testing.assert_array_equal(a, b)
-            assert got[3] == solo_state[r][3] == K
+            assert got[4] == solo_state[r][4] == K
             np.testing.assert_array_equal(stats[r].cpu().numpy(), solo_stats[r])
