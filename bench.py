@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--fp32-steps", type=int, default=3)
     ap.add_argument("--quick", action="store_true",
                     help="only the timed steps (for profiler runs): no parts, roofline, fp32 or CPU legs")
+    ap.add_argument("--sweep-mode", default="both", choices=["both", "batched", "serial"],
+                    help="sweep config: time the batched update, the run-after-run update, or both")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -300,6 +302,15 @@ def sweep_bench(args, dev):
         for w in runs:
             w.iteration += 1
 
+    if args.sweep_mode == "serial":
+        def step():  # noqa: F811 -- the same iteration with run-after-run updates
+            for w in runs:
+                w.collect()
+                w.advantages()
+            for w in runs:
+                w.update()
+                w.iteration += 1
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -318,8 +329,8 @@ def sweep_bench(args, dev):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / reps
 
-    t_batched = timed(batched_update)
-    t_serial = timed(lambda: [w.update() for w in runs])
+    t_batched = timed(batched_update) if args.sweep_mode != "serial" else float("nan")
+    t_serial = timed(lambda: [w.update() for w in runs]) if args.sweep_mode != "batched" else float("nan")
     out = {
         "metric": "PPO update samples/s, 8 uneven sweep runs updated together",
         "value": round(total_b / s_step, 1), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
@@ -329,6 +340,7 @@ def sweep_bench(args, dev):
         "update_samples_per_s_batched": round(total_b / t_batched, 1),
         "update_samples_per_s_run_after_run": round(total_b / t_serial, 1),
         "batched_speedup": round(t_serial / t_batched, 3),
+        "sweep_mode": args.sweep_mode,
     }
     print(json.dumps(out), flush=True)
 

@@ -135,6 +135,13 @@ __device__ inline u32x4 transpose_col(const u32x4 *in, int i) {
     return o;
 }
 
+// Buffer resource over [base, base + bytes) (raw buffer, no swizzle): loads
+// past the end return zeros instead of touching memory.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, long long bytes) {
+    const int n = bytes > 0x7FFFFFFFLL ? 0x7FFFFFFF : static_cast<int>(bytes < 0 ? 0 : bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), static_cast<short>(0), n, 0x00020000);
+}
+
 template <typename T, int MODE, int ROWS, int BK>
 struct TileLoader {
     static constexpr int VEC = 16 / sizeof(T);
@@ -146,9 +153,62 @@ struct TileLoader {
     static constexpr int REGS = MODE == 0 ? PER : PER * VEC;
     static_assert(UNITS % NT == 0, "tile units must divide evenly");
     u32x4 r[REGS];
+    int voff[PER];  // fast path: byte offset of each load at k = 0
+    int kofs[PER];  // fast path, MODE 0: k of each load within the slab
+
+    // Fast path set-up for a tile starting at row r0.  The operand must be
+    // 16-byte aligned with ld % VEC == 0 and kend % VEC == 0; its buffer
+    // resource ends at the last valid byte (MODE 0: R rows of ld; MODE 1:
+    // kend rows of ld), so rows past R (MODE 0) and k past kend (MODE 1)
+    // read as zeros.  MODE 1 rows past R read neighbouring features, which
+    // only reach outputs the epilogue discards.
+    __device__ inline void setup(int ld, int r0, int t) {
+        if (NT < kThreads && (t < 0 || t >= NT)) return;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int u = t + p * NT;
+            if constexpr (MODE == 0) {
+                const int row = u / (BK / VEC);
+                const int kv = (u % (BK / VEC)) * VEC;
+                voff[p] = ((r0 + row) * ld + kv) * static_cast<int>(sizeof(T));
+                kofs[p] = kv;
+            } else {
+                const int kb = u % (BK / VEC);
+                const int rb = u / (BK / VEC);
+                voff[p] = (kb * VEC * ld + r0 + rb * VEC) * static_cast<int>(sizeof(T));
+                kofs[p] = 0;
+            }
+        }
+    }
+
+    // Fast path: one buffer load per 16-byte vector, k0 folded into the
+    // scalar offset, nothing done to the loaded registers (so the loads stay
+    // in flight until the LDS store).  MODE 0 vectors at or past kend (a
+    // partial last slab) get an offset past the resource's end and read as
+    // zeros.
+    static constexpr int kOutside = 0x7FFFFFF0;
+    __device__ inline void load_fast(__amdgpu_buffer_rsrc_t rs, int ld, int k0, int kend, int t) {
+        if (NT < kThreads && (t < 0 || t >= NT)) return;
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            // k0 and ld are uniform; readfirstlane keeps the scalar offset in an
+            // SGPR (the compiler cannot always prove uniformity by itself)
+            if constexpr (MODE == 0) {
+                const int so = __builtin_amdgcn_readfirstlane(k0 * static_cast<int>(sizeof(T)));
+                const int vo = k0 + kofs[p] < kend ? voff[p] : kOutside;
+                r[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    const int so = __builtin_amdgcn_readfirstlane((k0 + e) * ld * static_cast<int>(sizeof(T)));
+                    r[p * VEC + e] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[p], so, 0);
+                }
+            }
+        }
+    }
 
     __device__ inline void load(const T *src, int ld, int R, int r0, int k0, int kend, int t, bool vec_ok) {
-        if (t < 0 || t >= NT) return;
+        if (NT < kThreads && (t < 0 || t >= NT)) return;
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int u = t + p * NT;
@@ -169,7 +229,7 @@ struct TileLoader {
     }
 
     __device__ inline void store(T *lds, int t) const {
-        if (t < 0 || t >= NT) return;
+        if (NT < kThreads && (t < 0 || t >= NT)) return;
 #pragma unroll
         for (int p = 0; p < PER; ++p) {
             const int u = t + p * NT;
@@ -200,7 +260,11 @@ __device__ inline int xcd_swizzle(int b, int n) {
     return xcd * q + min(xcd, r) + slot;
 }
 
-template <typename T, int BM, int BN, int AMODE, int BMODE, int EPI>
+// FAST: every problem of the launch has 16-byte aligned operands with
+// ld % VEC == 0 and K % VEC == 0 (checked on the host); its slabs are loaded
+// with buffer loads and nothing else, so the loads stay in flight across the
+// multiply of the previous slabs.  Otherwise every element is bounds-checked.
+template <typename T, int BM, int BN, int AMODE, int BMODE, int EPI, bool FAST>
 __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) {
     constexpr int BK = GemmTile<T>::BK;
     constexpr int WM = BM / 2, WN = BN / 2;   // per-wave tile (2 x 2 waves)
@@ -237,6 +301,12 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     const bool a_vec = (P.lda % VEC) == 0 && (reinterpret_cast<uintptr_t>(A) & 15u) == 0;
     const bool b_vec = (P.ldb % VEC) == 0 && (reinterpret_cast<uintptr_t>(B) & 15u) == 0;
 
+    // Fast (buffer-load) paths, chosen per operand for the whole tile.
+    const __amdgpu_buffer_rsrc_t a_rs =
+        make_rsrc(A, static_cast<long long>(AMODE == 0 ? P.M : kend) * P.lda * static_cast<int>(sizeof(T)));
+    const __amdgpu_buffer_rsrc_t b_rs =
+        make_rsrc(B, static_cast<long long>(BMODE == 0 ? P.N : kend) * P.ldb * static_cast<int>(sizeof(T)));
+
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -261,6 +331,31 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     // registers on its way to the other buffer and slab kt + 2 is loading.
     LA la0, la1;
     LB lb0, lb1;
+    if constexpr (FAST) {
+        la0.setup(P.lda, m0, tid);
+        lb0.setup(P.ldb, n0, tid - B_OFF);
+    }
+#pragma unroll
+    for (int p = 0; p < LA::PER; ++p) {
+        la1.voff[p] = la0.voff[p];
+        la1.kofs[p] = la0.kofs[p];
+    }
+#pragma unroll
+    for (int p = 0; p < LB::PER; ++p) {
+        lb1.voff[p] = lb0.voff[p];
+        lb1.kofs[p] = lb0.kofs[p];
+    }
+    // Loads slab kt into a staging set.
+    auto load_slab = [&](LA &la, LB &lb, int kt) {
+        const int k0 = kbeg + kt * BK;
+        if constexpr (FAST) {
+            la.load_fast(a_rs, P.lda, k0, kend, tid);
+            lb.load_fast(b_rs, P.ldb, k0, kend, tid - B_OFF);
+        } else {
+            la.load(A, P.lda, P.M, m0, k0, kend, tid, a_vec);
+            lb.load(B, P.ldb, P.N, n0, k0, kend, tid - B_OFF, b_vec);
+        }
+    };
     auto compute = [&](int buf) {
         const T *As = &lds[0][0] + buf * ((BM + BN) * PITCH);
         const T *Bs = As + BM * PITCH;
@@ -287,26 +382,25 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
         }
     };
 
-    // The bf16 128 x 128 input-gradient variant does not fit two staging
-    // sets into the 256 registers of two waves per SIMD (it would spill):
-    // it keeps one slab of lookahead.
-    constexpr bool kTwoAhead = !(sizeof(T) == 2 && BM == 128 && BN == 128 && AMODE == 0 && BMODE == 1);
+    // The bf16 128 x 128 variants with a transposed operand (input and
+    // weight gradients) do not fit two staging sets into the 256 registers
+    // of two waves per SIMD (they would spill): they keep one slab of
+    // lookahead.
+    constexpr bool kTwoAhead = !(sizeof(T) == 2 && BM == 128 && BN == 128 && BMODE == 1);
 
-    if (nk > 0) {
-        la0.load(A, P.lda, P.M, m0, kbeg, kend, tid, a_vec);
-        lb0.load(B, P.ldb, P.N, n0, kbeg, kend, tid - B_OFF, b_vec);
-        la0.store(&lds[0][0], tid);
-        lb0.store(&lds[0][BM * PITCH], tid - B_OFF);
-    }
+    // On the FAST path every load and LDS store of the loop is unconditional:
+    // slabs past the end read as zeros (their offsets fall outside the buffer
+    // resources) and land in a buffer nobody reads again.  Conditional loads
+    // would make the compiler wait for them before the next LDS store.
+    load_slab(la0, lb0, 0);
+    la0.store(&lds[0][0], tid);
+    lb0.store(&lds[0][BM * PITCH], tid - B_OFF);
     if constexpr (!kTwoAhead) {
         __syncthreads();
         for (int kt = 0; kt < nk; ++kt) {
             const int cur = kt & 1;
-            const bool more = kt + 1 < nk;
-            if (more) {
-                la0.load(A, P.lda, P.M, m0, kbeg + (kt + 1) * BK, kend, tid, a_vec);
-                lb0.load(B, P.ldb, P.N, n0, kbeg + (kt + 1) * BK, kend, tid - B_OFF, b_vec);
-            }
+            const bool more = FAST || kt + 1 < nk;
+            if (more) load_slab(la0, lb0, kt + 1);
             compute(cur);
             if (more) {
                 la0.store(&lds[cur ^ 1][0], tid);
@@ -315,37 +409,27 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
             __syncthreads();
         }
     } else {
-    if (nk > 1) {
-        la1.load(A, P.lda, P.M, m0, kbeg + BK, kend, tid, a_vec);
-        lb1.load(B, P.ldb, P.N, n0, kbeg + BK, kend, tid - B_OFF, b_vec);
-    }
-    __syncthreads();
-
-    for (int kt = 0; kt < nk; kt += 2) {
-        // even slab kt in buffer 0
-        if (kt + 2 < nk) {
-            la0.load(A, P.lda, P.M, m0, kbeg + (kt + 2) * BK, kend, tid, a_vec);
-            lb0.load(B, P.ldb, P.N, n0, kbeg + (kt + 2) * BK, kend, tid - B_OFF, b_vec);
-        }
-        compute(0);
-        if (kt + 1 < nk) {
-            la1.store(&lds[1][0], tid);
-            lb1.store(&lds[1][BM * PITCH], tid - B_OFF);
-        }
+        if (FAST || nk > 1) load_slab(la1, lb1, 1);
         __syncthreads();
-        if (kt + 1 >= nk) break;
-        // odd slab kt + 1 in buffer 1
-        if (kt + 3 < nk) {
-            la1.load(A, P.lda, P.M, m0, kbeg + (kt + 3) * BK, kend, tid, a_vec);
-            lb1.load(B, P.ldb, P.N, n0, kbeg + (kt + 3) * BK, kend, tid - B_OFF, b_vec);
+        for (int kt = 0; kt < nk; kt += 2) {
+            // even slab kt in buffer 0
+            if (FAST || kt + 2 < nk) load_slab(la0, lb0, kt + 2);
+            compute(0);
+            if (FAST || kt + 1 < nk) {
+                la1.store(&lds[1][0], tid);
+                lb1.store(&lds[1][BM * PITCH], tid - B_OFF);
+            }
+            __syncthreads();
+            if (kt + 1 >= nk) break;
+            // odd slab kt + 1 in buffer 1
+            if (FAST || kt + 3 < nk) load_slab(la1, lb1, kt + 3);
+            compute(1);
+            if (FAST || kt + 2 < nk) {
+                la0.store(&lds[0][0], tid);
+                lb0.store(&lds[0][BM * PITCH], tid - B_OFF);
+            }
+            __syncthreads();
         }
-        compute(1);
-        if (kt + 2 < nk) {
-            la0.store(&lds[0][0], tid);
-            lb0.store(&lds[0][BM * PITCH], tid - B_OFF);
-        }
-        __syncthreads();
-    }
     }
 
     if constexpr (EPI == kEpiPartial) {
@@ -449,18 +533,37 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     }
 }
 
-template <typename T, int BM, int BN>
+// Whether every problem qualifies for the buffer-load path.
+template <typename T>
+bool all_fast(const GemmArgs &args) {
+    constexpr int VEC = 16 / sizeof(T);
+    auto ok = [](const void *p, int ld) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0 && ld % VEC == 0; };
+    for (int i = 0; i < args.count; ++i) {
+        const GemmProblem &q = args.p[i];
+        if (!ok(q.A, q.lda) || !ok(q.B, q.ldb) || q.K % VEC != 0) return false;
+        if (q.splits > 1 && q.kps % VEC != 0) return false;
+    }
+    return true;
+}
+
+template <typename T, int BM, int BN, bool FAST>
 hipError_t launch_tiled(int a_mode, int b_mode, int epi, const GemmArgs &args, hipStream_t s) {
     dim3 grid(args.total_tiles), block(kThreads);
     if (a_mode == 0 && b_mode == 0 && epi == kEpiBiasElu)
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 0, kEpiBiasElu>), grid, block, 0, s, args);
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 0, kEpiBiasElu, FAST>), grid, block, 0, s, args);
     else if (a_mode == 0 && b_mode == 1 && epi == kEpiDElu)
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 1, kEpiDElu>), grid, block, 0, s, args);
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 1, kEpiDElu, FAST>), grid, block, 0, s, args);
     else if (a_mode == 1 && b_mode == 1 && epi == kEpiPartial)
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 1, 1, kEpiPartial>), grid, block, 0, s, args);
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 1, 1, kEpiPartial, FAST>), grid, block, 0, s, args);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+template <typename T, int BM, int BN>
+hipError_t launch_tiled(int a_mode, int b_mode, int epi, const GemmArgs &args, hipStream_t s) {
+    return all_fast<T>(args) ? launch_tiled<T, BM, BN, true>(a_mode, b_mode, epi, args, s)
+                             : launch_tiled<T, BM, BN, false>(a_mode, b_mode, epi, args, s);
 }
 
 template <typename T>

@@ -422,16 +422,16 @@ struct DwPlan {
     ReduceArgs red{};
 };
 
-DwPlan build_dw(const ppo_ctx *c, const WsPlan &w, void *ws, int M, const TileChoice &tc, int kps_override = 0) {
+// kps_layer (optional, per layer 0..L, both networks): samples per split in
+// place of the run's own choice where positive.  Problems are added network
+// by network, layer by layer: problem net * (L + 1) + l.
+DwPlan build_dw(const ppo_ctx *c, const WsPlan &w, void *ws, int M, const TileChoice &tc,
+                const int *kps_layer = nullptr) {
     const NetLayout &g = c->g;
     const int L = g.L;
     DwPlan d;
-    int splits, kps;
-    dw_splits(g, c->prec, M, tc.tile, tc.rounds, splits, kps);
-    if (kps_override > 0) {
-        kps = kps_override;
-        splits = cdiv(M, kps);
-    }
+    int splits0, kps0;
+    dw_splits(g, c->prec, M, tc.tile, tc.rounds, splits0, kps0);
     long long pos = 0;
     float *part = reinterpret_cast<float *>(wsp(ws, w.part));
     float *rows_part = reinterpret_cast<float *>(wsp(ws, w.rowsum));
@@ -442,6 +442,11 @@ DwPlan build_dw(const ppo_ctx *c, const WsPlan &w, void *ws, int M, const TileCh
         for (int l = 0; l <= L; ++l) {
             int r, cc;
             dw_shape(g, net == 0, l, r, cc);
+            int kps = kps0, splits = splits0;
+            if (kps_layer && kps_layer[l] > 0) {
+                kps = kps_layer[l];
+                splits = cdiv(M, kps);
+            }
             GemmProblem q{};
             if (l == L) {
                 q.A = wsp(ws, net == 0 ? w.dzh_a : w.dzh_c);
@@ -1273,22 +1278,52 @@ struct BatchedTuning {
     int fwd[kMaxHidden] = {kTile128x128, kTile128x128, kTile128x128, kTile128x128};
     int dx[kMaxHidden] = {kTile128x128, kTile128x128, kTile128x128, kTile128x128};
     int dw = kTile128x128;
-    int dw_kps = 0;   // 0: each run's own split count
+    int dw_kps[kMaxHidden + 1] = {0, 0, 0, 0, 0};   // per layer; 0: each run's own split count
 };
 
-// Common k-length for `rounds` rounds of resident workgroups over all runs.
-int batched_dw_kps(const std::vector<BatchedRun> &runs, int tile, int rounds) {
-    long long work = 0;  // tile-samples
-    for (const BatchedRun &r : runs) work += static_cast<long long>(dw_tiles(r.c->g, tile)) * r.M;
+// Per-layer common k-length: the weight-gradient problems of layer l of all
+// runs share one launch, sized to `rounds` rounds of resident workgroups.
+void batched_dw_kps(const std::vector<BatchedRun> &runs, int tile, int rounds, int *kps_out) {
+    const int L = runs[0].c->g.L;
     const int bk = gemm_bk(runs[0].c->prec);
-    long long kps = (work + static_cast<long long>(rounds) * kResidentSlots - 1) / (rounds * kResidentSlots);
-    kps = std::max<long long>(kps, 2 * bk);
-    for (const BatchedRun &r : runs) {
-        // never more splits than the workspace holds for that run
-        const int min_kps = cdiv(cdiv(r.M, r.w.max_splits), bk) * bk;
-        kps = std::max<long long>(kps, min_kps);
+    for (int l = 0; l <= L; ++l) {
+        long long work = 0;  // tile-samples
+        for (const BatchedRun &r : runs)
+            for (int net = 0; net < 2; ++net) {
+                int rows, cols;
+                dw_shape(r.c->g, net == 0, l, rows, cols);
+                work += static_cast<long long>(cdiv(rows, tile_rows(tile))) * cdiv(cols, tile_cols(tile)) * r.M;
+            }
+        long long kps = (work + static_cast<long long>(rounds) * kResidentSlots - 1) / (rounds * kResidentSlots);
+        kps = std::max<long long>(kps, 2 * bk);
+        for (const BatchedRun &r : runs) {
+            // never more splits than the workspace holds for that run
+            const int min_kps = cdiv(cdiv(r.M, r.w.max_splits), bk) * bk;
+            kps = std::max<long long>(kps, min_kps);
+        }
+        kps_out[l] = static_cast<int>(cdiv(kps, bk) * bk);
     }
-    return static_cast<int>(cdiv(kps, bk) * bk);
+}
+
+// Weight-gradient launches of all runs, one group per layer (both networks
+// of every run), so each launch holds like-sized work from every run.
+std::vector<GemmArgs> batched_dw_launches(const std::vector<DwPlan> &plans, int L, int tile, int bk) {
+    std::vector<GemmArgs> out;
+    for (int l = 0; l <= L; ++l) {
+        out.push_back(GemmArgs{});  // each layer starts a launch of its own
+        out.back().tile = tile;
+        for (const DwPlan &d : plans)
+            for (int net = 0; net < 2; ++net) {
+                const int i = net * (L + 1) + l;
+                const GemmProblem &q = d.launch[i / kGemmMaxProblems].p[i % kGemmMaxProblems];
+                if (out.back().count == kGemmMaxProblems) {
+                    out.push_back(GemmArgs{});
+                    out.back().tile = tile;
+                }
+                add_problem(out.back(), q, bk);
+            }
+    }
+    return out;
 }
 
 // Step k of every run: per-run gathers, then one grouped launch per GEMM
@@ -1331,14 +1366,13 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
         }
     }
     std::vector<DwPlan> plans(R);
-    std::vector<GemmArgs> launches;
     for (int i = 0; i < R; ++i) {
         TileChoice tc;
         tc.tile = bt.dw;
         tc.rounds = 1;
         plans[i] = build_dw(runs[i].c, runs[i].w, runs[i].ws, runs[i].M, tc, bt.dw_kps);
-        for (int q = 0; q < plans[i].n_launch; ++q) append_problems(launches, plans[i].launch[q], bt.dw, bk);
     }
+    const std::vector<GemmArgs> launches = batched_dw_launches(plans, L, bt.dw, bk);
     for (const GemmArgs &a : launches) {
         e = launch_gemm(prec, 1, 1, kEpiPartial, a, s);
         if (e != hipSuccess) return e;
@@ -1415,23 +1449,34 @@ int tune_batched(std::vector<BatchedRun> &runs, hipStream_t s, BatchedTuning &bt
         }
     }
     float best = 1e30f;
+    const Precision prec = runs[0].c->prec;
+    const int bk = gemm_bk(prec);
     for (int tile = 0; tile < kNumTileShapes; ++tile)
         for (int rounds : {1, 2, 4}) {
-            const int kps = batched_dw_kps(runs, tile, rounds);
+            int kps[kMaxHidden + 1] = {0, 0, 0, 0, 0};
+            batched_dw_kps(runs, tile, rounds, kps);
+            std::vector<DwPlan> plans;
+            for (const BatchedRun &r : runs) {
+                TileChoice tc;
+                tc.tile = tile;
+                plans.push_back(build_dw(r.c, r.w, r.ws, r.M, tc, kps));
+            }
+            const std::vector<GemmArgs> launches = batched_dw_launches(plans, L, tile, bk);
             float ms = 0.0f;
-            PPO_HIP(time_grouped(runs, 1, 1, kEpiPartial, tile,
-                                 [&](const BatchedRun &r) {
-                                     TileChoice tc;
-                                     tc.tile = tile;
-                                     DwPlan d = build_dw(r.c, r.w, r.ws, r.M, tc, kps);
-                                     return std::vector<GemmArgs>(d.launch, d.launch + d.n_launch);
-                                 },
-                                 s, ms),
+            PPO_HIP(time_launch(
+                        s,
+                        [&] {
+                            hipError_t e = hipSuccess;
+                            for (const GemmArgs &a : launches)
+                                if (e == hipSuccess) e = launch_gemm(prec, 1, 1, kEpiPartial, a, s);
+                            return e;
+                        },
+                        3, ms),
                     "autotune grouped weight gradient");
             if (ms < best) {
                 best = ms;
                 bt.dw = tile;
-                bt.dw_kps = kps;
+                for (int l = 0; l <= L; ++l) bt.dw_kps[l] = kps[l];
             }
         }
     return PPO_OK;
