@@ -196,6 +196,26 @@ struct AdamArgs {
 int adam_blocks(long long P);
 hipError_t launch_adam(const AdamArgs &a, hipStream_t s);
 hipError_t launch_step_advance(int32_t *step, int k, hipStream_t s);
+
+// Per-step copies of weight matrices in the layouts the GEMMs load fastest:
+// the first layer zero-padded to a vector-multiple width, and the hidden
+// layers transposed for the input-gradient chain.  Elements of the GEMM
+// operand type (bf16 or float32).
+struct StageJob {
+    const void *src;   // rows x cols, row pitch src_ld
+    void *dst;         // transpose ? cols x rows : rows x dst_ld (cols..dst_ld zero-filled)
+    int rows, cols, src_ld, dst_ld;
+    int transpose;
+    int tile_begin;    // first 64 x 64 tile of this job
+};
+constexpr int kMaxStageJobs = 16;
+struct StageArgs {
+    StageJob job[kMaxStageJobs];
+    int count;
+    int total_tiles;
+};
+void add_stage_job(StageArgs &a, const StageJob &j);
+hipError_t launch_stage_weights(Precision prec, const StageArgs &a, hipStream_t s);
 hipError_t launch_pack_bf16(const float *theta, uint16_t *shadow, long long n, hipStream_t s);
 
 }  // namespace ppo

@@ -551,6 +551,8 @@ hipError_t launch_tiled(int a_mode, int b_mode, int epi, const GemmArgs &args, h
     dim3 grid(args.total_tiles), block(kThreads);
     if (a_mode == 0 && b_mode == 0 && epi == kEpiBiasElu)
         hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 0, kEpiBiasElu, FAST>), grid, block, 0, s, args);
+    else if (a_mode == 0 && b_mode == 0 && epi == kEpiDElu)
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 0, kEpiDElu, FAST>), grid, block, 0, s, args);
     else if (a_mode == 0 && b_mode == 1 && epi == kEpiDElu)
         hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 1, kEpiDElu, FAST>), grid, block, 0, s, args);
     else if (a_mode == 1 && b_mode == 1 && epi == kEpiPartial)

@@ -582,6 +582,44 @@ __global__ __launch_bounds__(kAdamThreads) void adam_kernel(const AdamArgs a) {
     }
 }
 
+// ------------------------------------------------------- weight staging
+// One 64 x 64 tile of one job per block: coalesced reads of source rows into
+// LDS, coalesced writes of destination rows (transposed or padded).
+constexpr int kStageTile = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void stage_weights_kernel(const StageArgs a) {
+    __shared__ T tile[kStageTile][kStageTile + 1];
+    int ji = 0;
+    while (ji + 1 < a.count && static_cast<int>(blockIdx.x) >= a.job[ji + 1].tile_begin) ++ji;
+    const StageJob &j = a.job[ji];
+    const int local = blockIdx.x - j.tile_begin;
+    // tiles cover the source (transpose) or the padded destination (copy)
+    const int cols_t = j.transpose ? j.cols : j.dst_ld;
+    const int tiles_c = (cols_t + kStageTile - 1) / kStageTile;
+    const int r0 = (local / tiles_c) * kStageTile;
+    const int c0 = (local % tiles_c) * kStageTile;
+    const T *src = static_cast<const T *>(j.src);
+    T *dst = static_cast<T *>(j.dst);
+    for (int e = threadIdx.x; e < kStageTile * kStageTile; e += blockDim.x) {
+        const int r = e / kStageTile, c = e % kStageTile;
+        const int gr = r0 + r, gc = c0 + c;
+        tile[r][c] = (gr < j.rows && gc < j.cols) ? src[static_cast<long long>(gr) * j.src_ld + gc] : T(0);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kStageTile * kStageTile; e += blockDim.x) {
+        const int r = e / kStageTile, c = e % kStageTile;
+        if (j.transpose) {
+            // destination row c0 + r holds source column c0 + r
+            const int dr = c0 + r, dc = r0 + c;
+            if (dr < j.cols && dc < j.rows) dst[static_cast<long long>(dr) * j.dst_ld + dc] = tile[c][r];
+        } else {
+            const int dr = r0 + r, dc = c0 + c;
+            if (dr < j.rows && dc < j.dst_ld) dst[static_cast<long long>(dr) * j.dst_ld + dc] = tile[r][c];
+        }
+    }
+}
+
 __global__ void step_advance_kernel(int32_t *step, int k) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *step += k;
 }
@@ -634,6 +672,24 @@ hipError_t launch_head_sample(Precision prec, const HeadSampleArgs &a, hipStream
         hipLaunchKernelGGL(head_sample_kernel<uint16_t>, grid, block, shm, s, a, shm > 0 ? 1 : 0);
     else
         hipLaunchKernelGGL(head_sample_kernel<float>, grid, block, shm, s, a, shm > 0 ? 1 : 0);
+    return hipGetLastError();
+}
+
+void add_stage_job(StageArgs &a, const StageJob &j) {
+    StageJob q = j;
+    const int cols_t = q.transpose ? q.cols : q.dst_ld;
+    q.tile_begin = a.total_tiles;
+    a.job[a.count++] = q;
+    a.total_tiles += ((q.rows + kStageTile - 1) / kStageTile) * ((cols_t + kStageTile - 1) / kStageTile);
+}
+
+hipError_t launch_stage_weights(Precision prec, const StageArgs &a, hipStream_t s) {
+    if (a.count == 0 || a.total_tiles == 0) return hipSuccess;
+    const dim3 grid(a.total_tiles), block(256);
+    if (prec == kBF16)
+        hipLaunchKernelGGL(stage_weights_kernel<uint16_t>, grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL(stage_weights_kernel<float>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 

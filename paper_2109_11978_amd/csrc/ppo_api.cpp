@@ -134,6 +134,12 @@ struct WsPlan {
     Region dz_a[kMaxHidden], dz_c[kMaxHidden];
     Region dzh_a, dzh_c;
     Region part, rowsum, loss_part, loss_sums, sumsq, gae_part;
+    // staged weights (elements of the operand type): the first layer padded
+    // to kpad columns when D is not a multiple of 8, and W_l^T for l >= 1
+    Region wt;
+    bool pad_w0 = false;
+    size_t wt_w0[2] = {0, 0};
+    size_t wt_t[2][kMaxHidden] = {{0}};
     int max_splits = 1;
     size_t total = 0;
 };
@@ -229,6 +235,19 @@ WsPlan plan_workspace(const NetLayout &g, Precision prec, int N, int T, int M) {
     w.loss_sums = a.take(8 * 4);
     w.sumsq = a.take(static_cast<size_t>(1024) * 8);
     w.gae_part = a.take(static_cast<size_t>(gae_blocks(std::max(N, 1))) * 3 * 8);
+    w.pad_w0 = g.D != w.kpad;
+    size_t wt_elems = 0;
+    for (int net = 0; net < 2; ++net) {
+        if (w.pad_w0) {
+            w.wt_w0[net] = wt_elems;
+            wt_elems += align_up(static_cast<size_t>(g.H[0]) * w.kpad, 64);
+        }
+        for (int l = 1; l < g.L; ++l) {
+            w.wt_t[net][l] = wt_elems;
+            wt_elems += align_up(static_cast<size_t>(g.H[l - 1]) * g.H[l], 64);
+        }
+    }
+    w.wt = a.take(std::max<size_t>(wt_elems, 1) * w.esz);
     (void)T;
     w.total = a.cur;
     return w;
@@ -364,6 +383,41 @@ void add_problem(GemmArgs &args, const GemmProblem &proto, int bk) {
     args.total_tiles += p.tiles_m * p.tiles_n * p.splits;
 }
 
+// Staged copies of the weights: the padded first layer (rollout and update)
+// and, for the update, the transposed hidden layers W_1 .. W_{L-1}.
+StageArgs build_stage(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *ws, bool transposes) {
+    const NetLayout &g = c->g;
+    const Weights W = gemm_weights(c, p);
+    StageArgs a{};
+    char *base = static_cast<char *>(wsp(ws, w.wt));
+    for (int net = 0; net < 2; ++net) {
+        if (w.pad_w0) {
+            StageJob j{};
+            j.src = W.W[net][0];
+            j.dst = base + w.wt_w0[net] * w.esz;
+            j.rows = g.H[0];
+            j.cols = g.D;
+            j.src_ld = g.D;
+            j.dst_ld = w.kpad;
+            j.transpose = 0;
+            add_stage_job(a, j);
+        }
+        if (!transposes) continue;
+        for (int l = 1; l < g.L; ++l) {
+            StageJob j{};
+            j.src = W.W[net][l];
+            j.dst = base + w.wt_t[net][l] * w.esz;
+            j.rows = g.H[l];        // W_l is [H_l, H_{l-1}]
+            j.cols = g.H[l - 1];
+            j.src_ld = g.H[l - 1];
+            j.dst_ld = g.H[l];      // W_l^T is [H_{l-1}, H_l]
+            j.transpose = 1;
+            add_stage_job(a, j);
+        }
+    }
+    return a;
+}
+
 // Forward GEMM of hidden layer l for `rows` rows (input gathered in xg).
 GemmArgs build_fwd(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *ws, int rows, int l, bool actor,
                    bool critic, int tile) {
@@ -380,6 +434,12 @@ GemmArgs build_fwd(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void 
         q.K = l == 0 ? g.D : g.H[l - 1];
         q.B = W.W[net][l];
         q.ldb = q.K;
+        if (l == 0 && w.pad_w0) {
+            // zero-padded copy: K runs over the padded width (zeros on both sides)
+            q.B = static_cast<char *>(wsp(ws, w.wt)) + w.wt_w0[net] * w.esz;
+            q.K = w.kpad;
+            q.ldb = w.kpad;
+        }
         q.C = wsp(ws, net == 0 ? w.h_a[l] : w.h_c[l]);
         q.ldc = g.H[l];
         q.bias = p->theta + (net == 0 ? g.ba[l] : g.bc[l]);
@@ -390,10 +450,11 @@ GemmArgs build_fwd(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void 
     return args;
 }
 
-// Input-gradient GEMM: dz_{l-1} = (dz_l W_l) * ELU'(z_{l-1}) for both networks.
+// Input-gradient GEMM: dz_{l-1} = (dz_l W_l) * ELU'(z_{l-1}) for both
+// networks, with W_l^T staged row-major (both operands k-contiguous).
 GemmArgs build_dx(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *ws, int M, int l, int tile) {
     const NetLayout &g = c->g;
-    const Weights W = gemm_weights(c, p);
+    (void)p;
     GemmArgs args{};
     args.tile = tile;
     for (int net = 0; net < 2; ++net) {
@@ -401,8 +462,8 @@ GemmArgs build_dx(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *
         q.A = wsp(ws, net == 0 ? w.dz_a[l] : w.dz_c[l]);
         q.lda = g.H[l];
         q.K = g.H[l];
-        q.B = W.W[net][l];
-        q.ldb = g.H[l - 1];
+        q.B = static_cast<char *>(wsp(ws, w.wt)) + w.wt_t[net][l] * w.esz;
+        q.ldb = g.H[l];
         q.C = wsp(ws, net == 0 ? w.dz_a[l - 1] : w.dz_c[l - 1]);
         q.ldc = g.H[l - 1];
         q.H = wsp(ws, net == 0 ? w.h_a[l - 1] : w.h_c[l - 1]);
@@ -622,7 +683,7 @@ int ensure_tuned(const ppo_ctx *cc, const ppo_params *p, const WsPlan &w, void *
                 for (int tile = 0; tile < kNumTileShapes; ++tile) {
                     GemmArgs a = build_dx(c, p, w, ws, rows, l, tile);
                     float ms = 0.0f;
-                    PPO_HIP(time_launch(s, [&] { return launch_gemm(prec, 0, 1, kEpiDElu, a, s); }, reps, ms),
+                    PPO_HIP(time_launch(s, [&] { return launch_gemm(prec, 0, 0, kEpiDElu, a, s); }, reps, ms),
                             "autotune input gradient");
                     if (ms < best) {
                         best = ms;
@@ -779,6 +840,7 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
     const int L = g.L;
     hipError_t e;
 
+    PROFILED(prof, PPO_PHASE_GATHER, launch_stage_weights(prec, build_stage(c, p, w, ws, true), s));
     PROFILED(prof, PPO_PHASE_GATHER, launch_gather_obs(prec, s, sb.b->obs, sb.idx, sb.b->B, M, g.D, w.kpad,
                                                        wsp(ws, w.xg)));
     e = enqueue_forward(c, p, w, ws, M, true, true, t, s, prof);
@@ -789,7 +851,7 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
 
     for (int l = L - 1; l >= 1; --l) {
         const GemmArgs args = build_dx(c, p, w, ws, M, l, t.site[kSiteDx + l].tile);
-        PROFILED(prof, PPO_PHASE_INPUT_GRAD, launch_gemm(prec, 0, 1, kEpiDElu, args, s));
+        PROFILED(prof, PPO_PHASE_INPUT_GRAD, launch_gemm(prec, 0, 0, kEpiDElu, args, s));
     }
 
     DwPlan d = build_dw(c, w, ws, M, t.site[kSiteDw]);
@@ -981,6 +1043,7 @@ int ppo_rollout_infer(const ppo_ctx *c, void *stream, const ppo_params *p, const
     const WsPlan w = plan_workspace(g, c->prec, N, 0, 0);
     Tuning tune;
     PPO_CHECK(ensure_tuned(c, p, w, ws, N, false, s, tune));
+    PPO_HIP(launch_stage_weights(c->prec, build_stage(c, p, w, ws, false), s), "stage_weights");
     PPO_HIP(launch_gather_obs(c->prec, s, obs, nullptr, N, N, g.D, w.kpad, wsp(ws, w.xg)), "gather_obs");
     PPO_HIP(enqueue_forward(c, p, w, ws, N, !value_only, values != nullptr, tune, s), "forward GEMM");
     HeadSampleArgs a{};
@@ -1195,6 +1258,7 @@ int ppo_gemm_check(void *stream, int32_t precision, int32_t a_mode, int32_t b_mo
     if (precision != PPO_FP32 && precision != PPO_BF16) return fail(PPO_E_INVAL, "precision %d", precision);
     if (tile < 0 || tile >= kNumTileShapes) return fail(PPO_E_INVAL, "tile %d", tile);
     const bool combo_ok = (a_mode == 0 && b_mode == 0 && epilogue == kEpiBiasElu) ||
+                          (a_mode == 0 && b_mode == 0 && epilogue == kEpiDElu) ||
                           (a_mode == 0 && b_mode == 1 && epilogue == kEpiDElu) ||
                           (a_mode == 1 && b_mode == 1 && epilogue == kEpiPartial);
     if (!combo_ok) return fail(PPO_E_INVAL, "unsupported operand modes / epilogue combination");
@@ -1338,6 +1402,8 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
     hipError_t e;
     for (BatchedRun &r : runs) {
         const int32_t *idx = r.perm + static_cast<long long>(k) * r.M;
+        e = launch_stage_weights(prec, build_stage(r.c, r.p, r.w, r.ws, true), s);
+        if (e != hipSuccess) return e;
         e = launch_gather_obs(prec, s, r.b->obs, idx, r.b->B, r.M, r.c->g.D, r.w.kpad, wsp(r.ws, r.w.xg));
         if (e != hipSuccess) return e;
     }
@@ -1361,7 +1427,7 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
         for (BatchedRun &r : runs)
             append_problems(launches, build_dx(r.c, r.p, r.w, r.ws, r.M, l, bt.dx[l]), bt.dx[l], bk);
         for (const GemmArgs &a : launches) {
-            e = launch_gemm(prec, 0, 1, kEpiDElu, a, s);
+            e = launch_gemm(prec, 0, 0, kEpiDElu, a, s);
             if (e != hipSuccess) return e;
         }
     }
@@ -1436,7 +1502,7 @@ int tune_batched(std::vector<BatchedRun> &runs, hipStream_t s, BatchedTuning &bt
         float best = 1e30f;
         for (int tile = 0; tile < kNumTileShapes; ++tile) {
             float ms = 0.0f;
-            PPO_HIP(time_grouped(runs, 0, 1, kEpiDElu, tile,
+            PPO_HIP(time_grouped(runs, 0, 0, kEpiDElu, tile,
                                  [&](const BatchedRun &r) {
                                      return std::vector<GemmArgs>{build_dx(r.c, r.p, r.w, r.ws, r.M, l, tile)};
                                  },

@@ -82,10 +82,12 @@ def test_forward_bias_elu(prec, M, N, K, tile):
 DX = [(1, 16, 16), (300, 48, 64), (1536, 64, 64), (4100, 256, 128), (777, 512, 256), (200, 64, 192)]
 
 
+@pytest.mark.parametrize("b_mode", [0, 1])
 @pytest.mark.parametrize("tile", TILES)
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("M,N,K", DX)
-def test_input_grad_delu(prec, M, N, K, tile):
+def test_input_grad_delu(prec, M, N, K, tile, b_mode):
+    """b_mode 1: W [out=K, in=N] read transposed; b_mode 0: the staged W^T [N, K]."""
     require_gpu()
     rng = np.random.default_rng(M + 11 * N + K)
     a, ta = operand((M, K), prec, rng)
@@ -100,7 +102,11 @@ def test_input_grad_delu(prec, M, N, K, tile):
         hv = hval.astype(np.float64)
         th = torch.as_tensor(hval).cuda()
     C = torch.zeros(M, N, dtype=ta.dtype, device="cuda")
-    ppo.ppo_gemm_check(prec, 0, 1, 1, M, N, K, ta, K, tw, N, C, N, H=th, ldh=N, tile=tile)
+    if b_mode == 1:
+        ppo.ppo_gemm_check(prec, 0, 1, 1, M, N, K, ta, K, tw, N, C, N, H=th, ldh=N, tile=tile)
+    else:
+        twt = tw.t().contiguous()   # [N, K]
+        ppo.ppo_gemm_check(prec, 0, 0, 1, M, N, K, ta, K, twt, K, C, N, H=th, ldh=N, tile=tile)
     torch.cuda.synchronize()
     ref = (a @ w) * np.where(hv > 0, 1.0, hv + 1.0)
     check(output_values(C, prec), ref, prec, "input_grad", K)
