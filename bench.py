@@ -144,62 +144,102 @@ def time_parts(wl, reps=5):
     return out
 
 
-def gemm_flops(cfg):
-    """Useful GEMM FLOPs per mini-batch step, by phase (both networks)."""
+def phase_model(cfg, precision, P):
+    """Algorithmic work of one mini-batch step, per phase: useful FLOPs and
+    compulsory HBM bytes (every input read once, every output written once,
+    at the operand width; split partials and re-reads are not counted)."""
     net, M = cfg.net, cfg.minibatch
-    dims = [net.obs_dim, *net.hidden]
-    fwd = sum(2 * M * dims[l] * dims[l + 1] for l in range(len(net.hidden))) * 2
-    dx = sum(2 * M * dims[l] * dims[l + 1] for l in range(1, len(net.hidden))) * 2
-    dw = fwd + 2 * M * net.hidden[-1] * (net.act_dim + 1)
-    return {"forward": fwd, "input_grad": dx, "weight_grad": dw}
+    e = 2 if precision == "bf16" else 4
+    D, A = net.obs_dim, net.act_dim
+    kpad = -(-D // 8) * 8
+    H = list(net.hidden)
+    L = len(H)
+    ins = [D, *H[:-1]]          # useful K of each hidden layer
+    ins_pad = [kpad, *H[:-1]]   # stored width of each layer's input
+    fwd_f = sum(2 * M * ins[l] * H[l] for l in range(L)) * 2
+    fwd_b = (M * kpad * e                                      # gathered input, shared by both nets
+             + sum(M * ins_pad[l] * e * 2 for l in range(1, L))  # hidden inputs
+             + sum(M * H[l] * e * 2 for l in range(L))           # outputs
+             + sum((H[l] * ins_pad[l] * e + H[l] * 4) * 2 for l in range(L)))  # weights, biases
+    dx_f = sum(2 * M * H[l] * H[l - 1] for l in range(1, L)) * 2
+    dx_b = sum((M * H[l] * e + 2 * M * H[l - 1] * e + H[l] * H[l - 1] * e) * 2 for l in range(1, L))
+    dw_f = (sum(2 * M * H[l] * ins[l] for l in range(L)) * 2 + 2 * M * H[-1] * (A + 1))
+    dw_b = (M * sum(H) * e * 2 + M * 16 * e * 2                # pre-activation gradients, output-layer gradients
+            + M * kpad * e + M * sum(H) * e * 2                 # layer inputs
+            + 4 * P)                                            # the gradient
+    head_b = M * H[-1] * e * 2 * 2 + M * 16 * e * 2 + M * 4 * (A + 5)
+    return {
+        "forward": (fwd_f, fwd_b),
+        "input_grad": (dx_f, dx_b),
+        "weight_grad": (dw_f, dw_b),
+        "head_loss": (M * H[-1] * (A + 1) * 4.0, head_b),
+        "gather": (0.0, M * D * 4.0 + M * kpad * e + M * 4.0),
+        "grad_reduce": (0.0, 4.0 * P),
+        "adam": (0.0, (30.0 if precision == "bf16" else 28.0) * P),
+    }
+
+
+def recorded_traffic(kernel_phase, workload):
+    """HBM bytes per launch of a phase from the committed rocprofv3 counter
+    summary, or None when the summary is missing or was taken on another
+    version of the GEMM source."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", f"traffic_{workload}.txt")
+    src = os.path.join(here, "paper_2109_11978_amd", "csrc", "k_gemm.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("k_gemm_sha256") != sha:
+        return None
+    v = fields.get(f"hbm_bytes_per_launch.{kernel_phase}")
+    return float(v) if v else None
 
 
 def roofline(wl, precision):
-    """Per-phase HIP-event durations of one eager epoch; roofline of the dominant kernel."""
+    """Per-phase HIP-event durations of one eager epoch and each phase's
+    place under the roofline: t_roof = max(FLOPs / MFMA peak, bytes / HBM
+    peak); the binding roof names the bound and frac = t_roof / t."""
     import torch
     cfg = wl.cfg
     prof = wl.ppo.ppo_update_epoch_profiled(wl.ctx, wl.params, wl.batch, wl.perms[0], cfg.minibatches,
                                             wl.hp, wl.stats[0], wl.ws)
     torch.cuda.synchronize()
-    flops = gemm_flops(cfg)
-    P = wl.ctx.param_count
-    M, D = cfg.minibatch, cfg.net.obs_dim
-    esz = 2 if precision == "bf16" else 4
-    kpad = -(-D // 8) * 8
-    algo_bytes = {  # per mini-batch step
-        "adam": 30.0 * P if precision == "bf16" else 28.0 * P,
-        "gather": M * D * 4.0 + M * kpad * esz + M * 4.0,
-        "grad_reduce": 4.0 * P,
-    }
+    model = phase_model(cfg, precision, wl.ctx.param_count)
+    steps = cfg.minibatches
     phases = {}
     for name, (ms, launches) in prof.items():
         if launches == 0:
             continue
-        phases[name] = {"ms_per_epoch": round(ms, 4), "launches": launches,
-                        "us_per_launch": round(ms * 1e3 / launches, 2)}
+        t = ms * 1e-3 / launches
+        f, b = model.get(name, (0.0, 0.0))
+        f, b = f * steps / launches, b * steps / launches
+        t_f = f / (MFMA_PEAK_TFLOPS[precision] * 1e12)
+        t_b = b / (HBM_PEAK_GBS * 1e9)
+        phases[name] = {"ms_per_epoch": round(ms, 4), "launches": launches, "us_per_launch": round(t * 1e6, 2),
+                        "tflops": round(f / t / 1e12, 2), "gbs": round(b / t / 1e9, 1),
+                        "bound": "mfma" if t_f >= t_b else "hbm", "frac": round(max(t_f, t_b) / t, 4)}
     dominant = max(phases, key=lambda k: phases[k]["ms_per_epoch"])
+    ph = phases[dominant]
     ms, launches = prof[dominant]
-    steps = cfg.minibatches
-    avg_s = ms / launches * 1e-3
-    if dominant in flops:
-        per_launch = flops[dominant] * steps / launches
-        achieved = per_launch / avg_s / 1e12
-        peak = MFMA_PEAK_TFLOPS[precision]
-        roof = {"kernel": dominant, "bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "algorithmic_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
+    t = ms * 1e-3 / launches
+    f, b = model[dominant]
+    f, b = f * steps / launches, b * steps / launches
+    if ph["bound"] == "mfma":
+        roof = {"kernel": dominant, "bound": "mfma", "achieved": ph["tflops"],
+                "peak": MFMA_PEAK_TFLOPS[precision], "unit": "TFLOP/s", "frac": ph["frac"]}
     else:
-        per_launch = algo_bytes.get(dominant, 0.0) * steps / launches
-        achieved = per_launch / avg_s / 1e9
-        roof = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "algorithmic_per_launch": per_launch, "avg_launch_us": round(avg_s * 1e6, 2)}
-    # every GEMM phase, for context
-    gemm = {}
-    for name in flops:
-        if name in prof and prof[name][1]:
-            t = prof[name][0] * 1e-3
-            gemm[name] = round(flops[name] * steps / t / 1e12, 2)
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": ph["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ph["frac"]}
+    roof.update({"traffic": recorded_traffic(dominant, cfg.name.split("_")[0]),
+                 "algorithmic_flops_per_launch": f, "algorithmic_bytes_per_launch": b,
+                 "avg_launch_us": round(t * 1e6, 2)})
+    gemm = {k: phases[k]["tflops"] for k in ("forward", "input_grad", "weight_grad") if k in phases}
     return roof, phases, gemm
 
 

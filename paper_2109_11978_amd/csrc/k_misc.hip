@@ -115,9 +115,23 @@ __device__ inline HeadWeights stage_head_weights(float *s_w, bool in_lds, const 
                                                  int Hl) {
     if (!in_lds) return HeadWeights{nullptr, 0};
     const int pitch = Hl + kWPad;
-    for (int q = threadIdx.x; q < (A + 1) * Hl; q += blockDim.x) {
-        const int j = q / Hl, k = q - (q / Hl) * Hl;
-        s_w[j * pitch + k] = j < A ? Wa[static_cast<long long>(j) * Hl + k] : Wc[k];
+    const int n = (A + 1) * Hl;
+    // eight loads in flight per thread before any store
+    constexpr int U = 8;
+    for (int q0 = threadIdx.x; q0 < n; q0 += U * blockDim.x) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + u * blockDim.x;
+            const int j = q / Hl, k = q - (q / Hl) * Hl;
+            v[u] = q < n ? (j < A ? Wa[static_cast<long long>(j) * Hl + k] : Wc[k]) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + u * blockDim.x;
+            const int j = q / Hl, k = q - (q / Hl) * Hl;
+            if (q < n) s_w[j * pitch + k] = v[u];
+        }
     }
     __syncthreads();
     return HeadWeights{s_w, pitch};
@@ -142,11 +156,17 @@ __device__ inline void output_layers(const T *ha, const T *hc, const HeadWeights
         const T *h = (j < A ? ha : hc) + static_cast<long long>(r0 + i) * Hl;
         const float *w = head_row(hw, Wa, Wc, A, Hl, j);
         float acc = j < A ? ba[j] : bc[0];
-        for (int k = 0; k < Hl; k += 8) {
-            float x[8];
-            load8<T>(h + k, x);
+        // 64 activations (eight 8-wide loads) in flight per step; Hl is a multiple of 16
+        for (int k0 = 0; k0 < Hl; k0 += 64) {
+            float x[8][8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) acc += x[e] * w[k + e];
+            for (int u = 0; u < 8; ++u)
+                if (k0 + 8 * u < Hl) load8<T>(h + k0 + 8 * u, x[u]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + 8 * u < Hl)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) acc += x[u][e] * w[k0 + 8 * u + e];
         }
         out[i][j] = acc;
     }
@@ -320,15 +340,31 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
 
     // gradient into the last hidden pre-activations, both networks
     const int chunks = Hl / 8;
-    for (int q = tid; q < 2 * kLossRows * chunks; q += kHeadThreads) {
+    const int n_q = 2 * kLossRows * chunks;
+    // four 8-wide activation loads in flight per thread before the arithmetic
+    constexpr int U = 4;
+    for (int q0 = tid; q0 < n_q; q0 += U * kHeadThreads) {
+        float xs[U][8];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + u * kHeadThreads;
+            const int net = q / (kLossRows * chunks);
+            const int rem = q - net * kLossRows * chunks;
+            const int i = rem / chunks;
+            const int k = (rem - i * chunks) * 8;
+            if (q < n_q && i < rows) load8<T>((net == 0 ? ha : hc) + static_cast<long long>(r0 + i) * Hl + k, xs[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+        const int q = q0 + u * kHeadThreads;
         const int net = q / (kLossRows * chunks);
         const int rem = q - net * kLossRows * chunks;
         const int i = rem / chunks;
         const int k = (rem - i * chunks) * 8;
-        if (i >= rows) continue;
+        if (q >= n_q || i >= rows) continue;
         const long long off = static_cast<long long>(r0 + i) * Hl + k;
-        float x[8], g[8];
-        load8<T>((net == 0 ? ha : hc) + off, x);
+        const float *x = xs[u];
+        float g[8];
         if (net == 0) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) g[e] = 0.0f;
@@ -353,6 +389,7 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
         } else {
             reinterpret_cast<u32x4 *>(dst)[0] = reinterpret_cast<const u32x4 *>(o)[0];
             reinterpret_cast<u32x4 *>(dst)[1] = reinterpret_cast<const u32x4 *>(o)[1];
+        }
         }
     }
 }
@@ -463,8 +500,16 @@ __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(const Reduc
             const int r = static_cast<int>(local / S.cols);
             const int c = static_cast<int>(local - static_cast<long long>(r) * S.cols);
             const float *src = S.src + static_cast<long long>(r) * S.ld + c;
+            // eight partials in flight at a time, added in split order
             float sum = 0.0f;
-            for (int s = 0; s < S.splits; ++s) sum += src[s * S.split_stride];
+            for (int s0 = 0; s0 < S.splits; s0 += 8) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = s0 + u < S.splits ? src[(s0 + u) * S.split_stride] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (s0 + u < S.splits) sum += v[u];
+            }
             sum += S.add;
             a.grad[S.dst_offset + local] = sum;
             ss += static_cast<double>(sum) * sum;
