@@ -32,6 +32,7 @@ import numpy as np
 
 METRIC = "PPO update samples/s at 4096 envs x 24 steps, BF16 vs FP32, at stated tol"
 HBM_PEAK_GBS = 8000.0
+PROFILE_REPS = 10
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 
 
@@ -179,26 +180,40 @@ def phase_model(cfg, precision, P):
     }
 
 
-def recorded_traffic(kernel_phase, workload):
-    """HBM bytes per launch of a phase from the committed rocprofv3 counter
-    summary, or None when the summary is missing or was taken on another
-    version of the GEMM source."""
+def recorded_traffic(wl, phase, workload):
+    """HBM bytes per launch of the forward or input-gradient phase, from the
+    committed rocprofv3 counter summary (per kernel and grid, at the tiles
+    this run chose), or None when the summary is missing, lacks one of those
+    launches, or was taken on another version of the GEMM source."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", f"traffic_{workload}.txt")
     src = os.path.join(here, "paper_2109_11978_amd", "csrc", "k_gemm.hip")
-    if not os.path.exists(path):
+    if phase not in ("forward", "input_grad") or not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
+            k, v = line.rsplit(":", 1)
             fields[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("k_gemm_sha256") != sha:
+    if fields.get("k_gemm_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
-    v = fields.get(f"hbm_bytes_per_launch.{kernel_phase}")
-    return float(v) if v else None
+    cfg = wl.cfg
+    M, H = cfg.minibatch, list(cfg.net.hidden)
+    tiles = wl.ctx.tuning(M, True)
+    keys = []
+    if phase == "forward":
+        sites = [(tiles[f"forward_{l + 1}"], H[l], 0) for l in range(len(H))]
+    else:
+        sites = [(tiles[f"input_grad_{l + 1}"], H[l - 1], 1) for l in range(len(H) - 1, 0, -1)]
+    for tile, cols, epi in sites:
+        bm, bn = (int(x) for x in tile.split("x"))
+        grid = -(-M // bm) * -(-cols // bn) * 2
+        keys.append(f"hbm_bytes.gemm_kernel<bf16,{bm},{bn},0,0,{epi},true>.{grid}")
+    vals = [fields.get(k) for k in keys]
+    if any(v is None for v in vals):
+        return None
+    return sum(float(v) for v in vals) / len(vals)
 
 
 def roofline(wl, precision):
@@ -207,8 +222,10 @@ def roofline(wl, precision):
     peak); the binding roof names the bound and frac = t_roof / t."""
     import torch
     cfg = wl.cfg
+    # repeatable launches run PROFILE_REPS times back to back inside their
+    # event pair, so the event overhead does not inflate the per-launch time
     prof = wl.ppo.ppo_update_epoch_profiled(wl.ctx, wl.params, wl.batch, wl.perms[0], cfg.minibatches,
-                                            wl.hp, wl.stats[0], wl.ws)
+                                            wl.hp, wl.stats[0], wl.ws, reps=PROFILE_REPS)
     torch.cuda.synchronize()
     model = phase_model(cfg, precision, wl.ctx.param_count)
     steps = cfg.minibatches
@@ -236,7 +253,7 @@ def roofline(wl, precision):
     else:
         roof = {"kernel": dominant, "bound": "hbm", "achieved": ph["gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ph["frac"]}
-    roof.update({"traffic": recorded_traffic(dominant, cfg.name.split("_")[0]),
+    roof.update({"traffic": recorded_traffic(wl, dominant, cfg.name.split("_")[0]),
                  "algorithmic_flops_per_launch": f, "algorithmic_bytes_per_launch": b,
                  "avg_launch_us": round(t * 1e6, 2)})
     gemm = {k: phases[k]["tflops"] for k in ("forward", "input_grad", "weight_grad") if k in phases}

@@ -261,13 +261,18 @@ int ppo_loss_grad(const ppo_ctx *ctx, void *stream, const ppo_params *p, const p
 #define PPO_N_PHASES           7
 
 /* Same computation as ppo_update_epoch, launched eagerly with a HIP event
- * pair recorded on `stream` around every kernel launch.  Synchronises the
- * stream before returning, then writes phase_ms[PPO_N_PHASES] (summed
+ * pair recorded on `stream` around every kernel launch.  Launches that only
+ * read what earlier launches wrote (all but Adam, and the gradient reduction
+ * when the rate adapts) are enqueued `reps` (1..1000) times back to back
+ * inside their event pair, which leaves the results unchanged and spreads
+ * the event overhead; phase_ms then reports one repetition.  Synchronises
+ * the stream before returning, then writes phase_ms[PPO_N_PHASES] (summed
  * event-measured milliseconds per phase over the epoch) and
- * phase_launches[PPO_N_PHASES] (launch counts).  For measurement only. */
+ * phase_launches[PPO_N_PHASES] (launch counts of one repetition).  For
+ * measurement only. */
 int ppo_update_epoch_profiled(ppo_ctx *ctx, void *stream, const ppo_params *p, const ppo_batch *b,
                               const int32_t *perm, int32_t n_minibatches, const ppo_hparams *hp,
-                              float *stats, void *ws, size_t ws_bytes, float *phase_ms,
+                              float *stats, void *ws, size_t ws_bytes, int32_t reps, float *phase_ms,
                               int32_t *phase_launches);
 
 /* Verification: one launch of the library's GEMM kernel on caller data.

@@ -261,8 +261,9 @@ def ppo_loss_grad(ctx: Context, params: Params, batch: Dict[str, torch.Tensor], 
 
 def ppo_update_epoch_profiled(ctx: Context, params: Params, batch: Dict[str, torch.Tensor], perm: torch.Tensor,
                               n_minibatches: int, hp: UpdateHParams, stats: torch.Tensor, ws: torch.Tensor,
-                              stream=None) -> Dict[str, tuple]:
-    """Eager epoch with HIP events around each launch; returns {phase: (ms, launches)}."""
+                              stream=None, reps: int = 1) -> Dict[str, tuple]:
+    """Eager epoch with HIP events around each launch (repeatable launches
+    enqueued `reps` times inside their events); returns {phase: (ms, launches)}."""
     b = batch_abi(batch)
     p = params.abi()
     h = hp.abi()
@@ -272,7 +273,7 @@ def ppo_update_epoch_profiled(ctx: Context, params: Params, batch: Dict[str, tor
     check(_lib().ppo_update_epoch_profiled(ctx.handle, _stream(stream), ctypes.byref(p), ctypes.byref(b),
                                            _ptr(perm, torch.int32, "perm"), n_minibatches, ctypes.byref(h),
                                            _ptr(stats, torch.float32, "stats"), _ptr(ws, torch.uint8, "ws"),
-                                           ws.numel(), ms, cnt))
+                                           ws.numel(), reps, ms, cnt))
     return {name: (ms[i], cnt[i]) for i, name in enumerate(_abi.PHASES)}
 
 

@@ -335,6 +335,15 @@ struct Profiler {
     std::vector<hipEvent_t> ev;
     std::vector<int> phase;
     size_t used = 0;
+    int reps = 1;               // back-to-back repetitions of each repeatable launch
+    bool reduce_repeatable = true;
+    // Launches that only read what earlier launches wrote give the same
+    // result when repeated; Adam (and the reduction when it adapts the rate)
+    // change state and run once.
+    int reps_for(int ph) const {
+        if (ph == PPO_PHASE_ADAM || (ph == PPO_PHASE_GRAD_REDUCE && !reduce_repeatable)) return 1;
+        return reps;
+    }
     hipError_t begin(int ph) {
         while (ev.size() < used + 2) {
             hipEvent_t e;
@@ -358,12 +367,15 @@ struct Profiler {
 // Wraps one launch expression with profiling events when a profiler is set.
 #define PROFILED(prof, ph, expr)                                  \
     do {                                                          \
+        const int _reps = (prof) ? (prof)->reps_for(ph) : 1;      \
         if (prof) {                                               \
             hipError_t _pe = (prof)->begin(ph);                   \
             if (_pe != hipSuccess) return _pe;                    \
         }                                                         \
-        hipError_t _le = (expr);                                  \
-        if (_le != hipSuccess) return _le;                        \
+        for (int _r = 0; _r < _reps; ++_r) {                      \
+            hipError_t _le = (expr);                              \
+            if (_le != hipSuccess) return _le;                    \
+        }                                                         \
         if (prof) {                                               \
             hipError_t _pe = (prof)->end();                       \
             if (_pe != hipSuccess) return _pe;                    \
@@ -1210,9 +1222,10 @@ int ppo_update_epoch(ppo_ctx *c, void *stream, const ppo_params *p, const ppo_ba
 
 int ppo_update_epoch_profiled(ppo_ctx *c, void *stream, const ppo_params *p, const ppo_batch *b,
                               const int32_t *perm, int32_t n_minibatches, const ppo_hparams *hp, float *stats,
-                              void *ws, size_t ws_bytes, float *phase_ms, int32_t *phase_launches) {
+                              void *ws, size_t ws_bytes, int32_t reps, float *phase_ms, int32_t *phase_launches) {
     if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
     if (!phase_ms || !phase_launches) return fail(PPO_E_INVAL, "phase_ms and phase_launches are required");
+    if (reps < 1 || reps > 1000) return fail(PPO_E_INVAL, "reps = %d outside 1..1000", reps);
     PPO_CHECK(validate_hparams(hp));
     PPO_CHECK(validate_params(c, p, true));
     PPO_CHECK(validate_batch(c, b, hp));
@@ -1232,6 +1245,8 @@ int ppo_update_epoch_profiled(ppo_ctx *c, void *stream, const ppo_params *p, con
     PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, s, tune));
     Profiler prof;
     prof.s = s;
+    prof.reps = reps;
+    prof.reduce_repeatable = !(hp->desired_kl > 0.0f);
     for (int k = 0; k < n_minibatches; ++k) {
         StepBuffers sb{b, perm + static_cast<long long>(k) * M, M, p->grad, stats + k * PPO_STATS_WIDTH, 1, k};
         PPO_HIP(enqueue_step(c, p, hp, w, ws, sb, tune, s, &prof), "update_epoch (profiled)");
@@ -1245,7 +1260,7 @@ int ppo_update_epoch_profiled(ppo_ctx *c, void *stream, const ppo_params *p, con
     for (size_t i = 0; i < prof.phase.size(); ++i) {
         float ms = 0.0f;
         PPO_HIP(hipEventElapsedTime(&ms, prof.ev[2 * i], prof.ev[2 * i + 1]), "hipEventElapsedTime");
-        phase_ms[prof.phase[i]] += ms;
+        phase_ms[prof.phase[i]] += ms / prof.reps_for(prof.phase[i]);
         phase_launches[prof.phase[i]] += 1;
     }
     return PPO_OK;

@@ -339,3 +339,35 @@ def test_update_epoch_multi_step_tracks_oracle():
         assert st[k, 6] == pytest.approx(rec[k]["grad_norm"], rel=1e-4)
     nw, _ = rel_errors(params.theta.cpu().numpy() - theta, th - theta)
     assert nw < 1e-3, nw
+
+
+@pytest.mark.parametrize("desired_kl", [0.0, 0.01])
+def test_profiled_epoch_with_repeats_matches_plain_epoch(desired_kl):
+    """The measurement entry point repeats idempotent launches inside its
+    event pairs; the epoch's results must equal the plain eager epoch's."""
+    d = require_gpu()
+    cfg = synth.get_config("tiny")
+    _announce(f"profiled epoch reps=3 desired_kl={desired_kl}")
+    from tests.gpu_common import add_kl_inputs
+    theta = synth.xavier_theta(cfg.net, seed=21)
+    B, K = cfg.batch, 4
+    batch = add_kl_inputs(cfg, theta, teacher_batch(cfg, theta, B, seed=22, shift="mixed"), seed=23,
+                          shift_scale=0.05)
+    perm = np.random.default_rng(24).permutation(B).astype(np.int32)
+    ctx = ppo.Context(cfg.net.obs_dim, cfg.net.act_dim, cfg.net.hidden, "bf16")
+    tb = {k: dev(v, d) for k, v in batch.items()}
+    hp = ppo.UpdateHParams(use_graph=False, desired_kl=desired_kl)
+    out = []
+    for reps in (None, 3):
+        params = ppo.Params(ctx, theta, device=d)
+        stats = torch.zeros(K, ppo.PPO_STATS_WIDTH, device=d)
+        ws = ctx.new_workspace(M=B // K)
+        if reps is None:
+            ppo.ppo_update_epoch(ctx, params, tb, dev(perm, d), K, hp, stats, ws)
+        else:
+            ph = ppo.ppo_update_epoch_profiled(ctx, params, tb, dev(perm, d), K, hp, stats, ws, reps=reps)
+            assert ph["forward"][1] == K * len(cfg.net.hidden) and ph["adam"][1] == K
+        torch.cuda.synchronize()
+        out.append((params.theta.cpu().numpy().copy(), params.lr.cpu().numpy().copy(), stats.cpu().numpy().copy()))
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
