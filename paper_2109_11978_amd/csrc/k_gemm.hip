@@ -18,6 +18,8 @@
 // 16-byte vector per row of an 8 x 8 (bf16) or 4 x 4 (float32) block.
 #include "common.hpp"
 
+#include <type_traits>
+
 namespace ppo {
 namespace {
 
@@ -446,6 +448,61 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     // writes them with one 8-byte (bf16) or 16-byte (float32) store.  Rows are
     // padded to EP = WN + 8 floats (EP = 8 mod 16), so the two lane halves of
     // the scattered accumulator writes (rows 4 apart) hit disjoint banks.
+    // WN / 4 lanes cover one staged row (4 floats each): for WN = 64 every
+    // 16-lane group of a 16-byte LDS read touches all 64 banks once.
+    constexpr int CW = 4;
+    constexpr int LPR = WN / CW;         // lanes per staged row
+    constexpr int RPI = 64 / LPR;        // rows per iteration
+    constexpr int ITS = WM / RPI;        // epilogue iterations per lane
+    const int sub_r = lane / LPR;
+    const int sub_c = (lane % LPR) * CW;
+    const int col = n0 + wn * WN + sub_c;
+    const bool full_cols = col + CW <= P.N;
+
+    // ELU' input: every activation this lane needs is loaded before the
+    // accumulators go through LDS, all loads in flight at once (the output
+    // stores that follow could alias them as far as the compiler knows, so
+    // loads inside the store loop would each wait for the previous store).
+    T hreg[ITS][CW];
+    if constexpr (EPI == kEpiDElu && FAST) {
+        // buffer loads: rows past M read as zeros, no branches, one scalar
+        // offset per iteration
+        const __amdgpu_buffer_rsrc_t h_rs =
+            make_rsrc(P.H, static_cast<long long>(P.M) * P.ldh * static_cast<int>(sizeof(T)));
+        const int vo = ((m0 + wm * WM + sub_r) * P.ldh + col) * static_cast<int>(sizeof(T));
+#pragma unroll
+        for (int it = 0; it < ITS; ++it) {
+            const int so = __builtin_amdgcn_readfirstlane(it * RPI * P.ldh * static_cast<int>(sizeof(T)));
+            if constexpr (sizeof(T) == 2) {
+                typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(h_rs, vo, so, 0);
+                *reinterpret_cast<u32x2 *>(hreg[it]) = v;
+            } else {
+                *reinterpret_cast<u32x4 *>(hreg[it]) = __builtin_amdgcn_raw_buffer_load_b128(h_rs, vo, so, 0);
+            }
+        }
+    } else if constexpr (EPI == kEpiDElu) {
+        const bool h_vec = full_cols && (P.ldh % CW) == 0 && (reinterpret_cast<uintptr_t>(P.H) & 15u) == 0;
+#pragma unroll
+        for (int it = 0; it < ITS; ++it) {
+            const int row = m0 + wm * WM + it * RPI + sub_r;
+#pragma unroll
+            for (int e = 0; e < CW; ++e) hreg[it][e] = T(0);
+            if (row >= P.M || col >= P.N) continue;
+            const T *hsrc = static_cast<const T *>(P.H) + static_cast<long long>(row) * P.ldh + col;
+            if (h_vec) {
+                if constexpr (sizeof(T) == 2) {
+                    *reinterpret_cast<uint2 *>(hreg[it]) = *reinterpret_cast<const uint2 *>(hsrc);
+                } else {
+                    *reinterpret_cast<u32x4 *>(hreg[it]) = *reinterpret_cast<const u32x4 *>(hsrc);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < CW; ++e) hreg[it][e] = (col + e < P.N) ? hsrc[e] : T(0);
+            }
+        }
+    }
+
     constexpr int EP = WN + 8;
     static_assert(4 * WM * EP * 4 <= sizeof(lds), "epilogue staging must fit in the tile buffers");
     float *stage = reinterpret_cast<float *>(&lds[0][0]) + wave * WM * EP;
@@ -458,15 +515,6 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
                 stage[(i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * EP + j * 32 + lrow] = acc[i][j][r];
     __syncthreads();
 
-    // WN / 4 lanes cover one staged row (4 floats each): for WN = 64 every
-    // 16-lane group of a 16-byte LDS read touches all 64 banks once.
-    constexpr int CW = 4;
-    constexpr int LPR = WN / CW;         // lanes per staged row
-    constexpr int RPI = 64 / LPR;        // rows per iteration
-    const int sub_r = lane / LPR;
-    const int sub_c = (lane % LPR) * CW;
-    const int col = n0 + wn * WN + sub_c;
-    const bool full_cols = col + CW <= P.N;
     if (col >= P.N) return;
     float bias[CW];
     if constexpr (EPI == kEpiBiasElu) {
@@ -474,61 +522,52 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
         for (int e = 0; e < CW; ++e) bias[e] = (col + e < P.N) ? P.bias[col + e] : 0.0f;
     }
     const bool c_vec = full_cols && (P.ldc % CW) == 0 && (reinterpret_cast<uintptr_t>(P.C) & 15u) == 0;
-    const bool h_vec = full_cols && (P.ldh % CW) == 0 && (reinterpret_cast<uintptr_t>(P.H) & 15u) == 0;
-#pragma unroll 4
-    for (int it = 0; it < WM / RPI; ++it) {
+    // Full 4-column segments go out as one buffer store each (rows past M
+    // fall outside the resource and are dropped); ragged column edges take
+    // element stores.  Keeping the two paths on different instructions stops
+    // the compiler from merging them into split partial-width stores.
+    using OutT = typename std::conditional<EPI == kEpiPartial, float, T>::type;
+    OutT *cbase = static_cast<OutT *>(P.C) + (EPI == kEpiPartial ? split * P.c_split_stride : 0);
+    const __amdgpu_buffer_rsrc_t c_rs =
+        make_rsrc(cbase, static_cast<long long>(P.M) * P.ldc * static_cast<int>(sizeof(OutT)));
+    const int c_vo = ((m0 + wm * WM + sub_r) * P.ldc + col) * static_cast<int>(sizeof(OutT));
+#pragma unroll
+    for (int it = 0; it < ITS; ++it) {
         const int lr = it * RPI + sub_r;
         const int row = m0 + wm * WM + lr;
-        if (row >= P.M) break;
+        const int c_so = __builtin_amdgcn_readfirstlane(it * RPI * P.ldc * static_cast<int>(sizeof(OutT)));
         float v[CW];
         *reinterpret_cast<float4 *>(&v[0]) = *reinterpret_cast<const float4 *>(stage + lr * EP + sub_c);
+        OutT out[CW];
         if constexpr (EPI == kEpiPartial) {
-            float *dst = static_cast<float *>(P.C) + split * P.c_split_stride + static_cast<long long>(row) * P.ldc + col;
-            if (c_vec) {
-                *reinterpret_cast<float4 *>(dst) = *reinterpret_cast<const float4 *>(&v[0]);
-            } else {
 #pragma unroll
-                for (int e = 0; e < CW; ++e)
-                    if (col + e < P.N) dst[e] = v[e];
-            }
+            for (int e = 0; e < CW; ++e) out[e] = v[e];
         } else {
             if constexpr (EPI == kEpiBiasElu) {
 #pragma unroll
                 for (int e = 0; e < CW; ++e) v[e] = Act<T>::elu(v[e] + bias[e]);
             } else {
-                const T *hsrc = static_cast<const T *>(P.H) + static_cast<long long>(row) * P.ldh + col;
-                T h[CW];
-                if (h_vec) {
-                    if constexpr (sizeof(T) == 2) {
-                        *reinterpret_cast<uint2 *>(h) = *reinterpret_cast<const uint2 *>(hsrc);
-                    } else {
-                        *reinterpret_cast<u32x4 *>(h) = *reinterpret_cast<const u32x4 *>(hsrc);
-                    }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < CW; ++e) h[e] = (col + e < P.N) ? hsrc[e] : T(0);
-                }
 #pragma unroll
                 for (int e = 0; e < CW; ++e) {
-                    const float hv = Elem<T>::to_f(h[e]);
+                    const float hv = Elem<T>::to_f(hreg[it][e]);
                     v[e] *= hv > 0.0f ? 1.0f : hv + 1.0f;
                 }
             }
-            T out[CW];
 #pragma unroll
             for (int e = 0; e < CW; ++e) out[e] = Act<T>::store(v[e]);
-            T *dst = static_cast<T *>(P.C) + static_cast<long long>(row) * P.ldc + col;
-            if (c_vec) {
-                if constexpr (sizeof(T) == 2) {
-                    *reinterpret_cast<uint2 *>(dst) = *reinterpret_cast<const uint2 *>(out);
-                } else {
-                    *reinterpret_cast<u32x4 *>(dst) = *reinterpret_cast<const u32x4 *>(out);
-                }
+        }
+        if (c_vec) {
+            if constexpr (sizeof(OutT) == 2) {
+                typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                __builtin_amdgcn_raw_buffer_store_b64(*reinterpret_cast<const u32x2 *>(out), c_rs, c_vo, c_so, 0);
             } else {
-#pragma unroll
-                for (int e = 0; e < CW; ++e)
-                    if (col + e < P.N) dst[e] = out[e];
+                __builtin_amdgcn_raw_buffer_store_b128(*reinterpret_cast<const u32x4 *>(out), c_rs, c_vo, c_so, 0);
             }
+        } else if (row < P.M) {
+            OutT *dst = cbase + static_cast<long long>(row) * P.ldc + col;
+#pragma unroll
+            for (int e = 0; e < CW; ++e)
+                if (col + e < P.N) dst[e] = out[e];
         }
     }
 }
