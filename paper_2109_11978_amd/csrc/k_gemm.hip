@@ -144,19 +144,51 @@ __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, long long b
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), static_cast<short>(0), n, 0x00020000);
 }
 
+// bf16 operands stored transposed (MODE 1) are staged without any register
+// transpose: each 16-byte global vector (8 consecutive rows at one k) goes to
+// LDS as is, in a k-major tile [BK][ROWS] whose 16-byte columns are XOR-
+// swizzled per k-row, and the MFMA fragments are read back with the LDS
+// transpose load (see frag_tr).  The swizzle keeps both the stores and the
+// transposed reads of a half-wave on distinct banks.
+template <int ROWS>
+__device__ inline int tr_swz(int k) {
+    return ROWS == 128 ? ((k & 3) << 2) : (((k >> 1) & 1) << 2);
+}
+template <int ROWS>
+__device__ inline int tr_index(int k, int r) {  // element (k, r) of a k-major tile
+    return k * ROWS + ((((r >> 3) ^ tr_swz<ROWS>(k))) << 3) + (r & 7);
+}
+
 template <typename T, int MODE, int ROWS, int BK>
 struct TileLoader {
     static constexpr int VEC = 16 / sizeof(T);
     static constexpr int PITCH = BK + VEC;
-    // MODE 0: units are 16-byte vectors along k; MODE 1: VEC x VEC blocks.
-    static constexpr int UNITS = MODE == 0 ? ROWS * BK / VEC : (ROWS / VEC) * (BK / VEC);
+    // TR: bf16 transposed operand staged k-major (no register transpose).
+    static constexpr bool TR = MODE == 1 && sizeof(T) == 2;
+    static_assert(!TR || ROWS == 64 || ROWS == 128, "k-major tiles have 64 or 128 rows");
+    // Elements of one LDS tile of this operand.
+    static constexpr int ELEMS = TR ? BK * ROWS : ROWS * PITCH;
+    // MODE 0 and TR: units are 16-byte vectors (along k, resp. along rows);
+    // float32 MODE 1: VEC x VEC blocks transposed in registers.
+    static constexpr int UNITS = (MODE == 0 || TR) ? ROWS * BK / VEC : (ROWS / VEC) * (BK / VEC);
     static constexpr int NT = UNITS < kThreads ? UNITS : kThreads;
     static constexpr int PER = UNITS / NT;
-    static constexpr int REGS = MODE == 0 ? PER : PER * VEC;
+    static constexpr int REGS = (MODE == 0 || TR) ? PER : PER * VEC;
     static_assert(UNITS % NT == 0, "tile units must divide evenly");
     u32x4 r[REGS];
     int voff[PER];  // fast path: byte offset of each load at k = 0
     int kofs[PER];  // fast path, MODE 0: k of each load within the slab
+
+    // Position of unit u: MODE 0 (row, k) of a k-vector; TR (k, row) of a
+    // row-vector.
+    __device__ static inline void unit0(int u, int &row, int &kv) {
+        row = u / (BK / VEC);
+        kv = (u % (BK / VEC)) * VEC;
+    }
+    __device__ static inline void unit_tr(int u, int &kk, int &rv) {
+        kk = u / (ROWS / VEC);
+        rv = (u % (ROWS / VEC)) * VEC;
+    }
 
     // Fast path set-up for a tile starting at row r0.  The operand must be
     // 16-byte aligned with ld % VEC == 0 and kend % VEC == 0; its buffer
@@ -170,10 +202,15 @@ struct TileLoader {
         for (int p = 0; p < PER; ++p) {
             const int u = t + p * NT;
             if constexpr (MODE == 0) {
-                const int row = u / (BK / VEC);
-                const int kv = (u % (BK / VEC)) * VEC;
+                int row, kv;
+                unit0(u, row, kv);
                 voff[p] = ((r0 + row) * ld + kv) * static_cast<int>(sizeof(T));
                 kofs[p] = kv;
+            } else if constexpr (TR) {
+                int kk, rv;
+                unit_tr(u, kk, rv);
+                voff[p] = (kk * ld + r0 + rv) * static_cast<int>(sizeof(T));
+                kofs[p] = 0;
             } else {
                 const int kb = u % (BK / VEC);
                 const int rb = u / (BK / VEC);
@@ -199,6 +236,9 @@ struct TileLoader {
                 const int so = __builtin_amdgcn_readfirstlane(k0 * static_cast<int>(sizeof(T)));
                 const int vo = k0 + kofs[p] < kend ? voff[p] : kOutside;
                 r[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0);
+            } else if constexpr (TR) {
+                const int so = __builtin_amdgcn_readfirstlane(k0 * ld * static_cast<int>(sizeof(T)));
+                r[p] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff[p], so, 0);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e) {
@@ -215,9 +255,13 @@ struct TileLoader {
         for (int p = 0; p < PER; ++p) {
             const int u = t + p * NT;
             if constexpr (MODE == 0) {
-                const int row = u / (BK / VEC);
-                const int kv = (u % (BK / VEC)) * VEC;
+                int row, kv;
+                unit0(u, row, kv);
                 r[p] = load_rowmajor<T>(src, ld, r0 + row, k0 + kv, R, kend, vec_ok);
+            } else if constexpr (TR) {
+                int kk, rv;
+                unit_tr(u, kk, rv);
+                r[p] = load_transposed<T>(src, ld, r0 + rv, k0 + kk, R, kend, vec_ok);
             } else {
                 // k-block fastest across lanes: the transposed LDS rows written by
                 // neighbouring lanes then fall on disjoint banks (see store()).
@@ -236,9 +280,13 @@ struct TileLoader {
         for (int p = 0; p < PER; ++p) {
             const int u = t + p * NT;
             if constexpr (MODE == 0) {
-                const int row = u / (BK / VEC);
-                const int kv = (u % (BK / VEC)) * VEC;
+                int row, kv;
+                unit0(u, row, kv);
                 *reinterpret_cast<u32x4 *>(lds + row * PITCH + kv) = r[p];
+            } else if constexpr (TR) {
+                int kk, rv;
+                unit_tr(u, kk, rv);
+                *reinterpret_cast<u32x4 *>(lds + tr_index<ROWS>(kk, rv)) = r[p];
             } else {
                 const int kb = u % (BK / VEC);
                 const int rb = u / (BK / VEC);
@@ -249,7 +297,45 @@ struct TileLoader {
             }
         }
     }
+
+    // TR only: add this thread's staged vectors (8 rows each, the same 8
+    // rows for every unit of the thread) to its per-row partial sums.
+    __device__ inline void accumulate_rows(float (&acc)[VEC], int t) const {
+        if (NT < kThreads && (t < 0 || t >= NT)) return;
+#pragma unroll
+        for (int p = 0; p < PER; ++p)
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                acc[2 * w] += __uint_as_float(r[p][w] << 16);
+                acc[2 * w + 1] += __uint_as_float(r[p][w] & 0xFFFF0000u);
+            }
+    }
 };
+
+// MFMA fragment (32 rows x 16 k, bf16) from a k-major swizzled tile with the
+// gfx950 LDS transpose load.  Within each 16-lane group, lane i receives
+// element (i mod 4) of the 8-byte chunks addressed by lanes i/4, i/4+4,
+// i/4+8 and i/4+12 of its group; so lane s of a group addresses the chunk
+// (k = kb + s/4, rows 4 (s mod 4) .. +3) and receives row s at k = kb .. kb+3.
+// Two loads (k and k + 4) give the 8 consecutive k of the MFMA operand.
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+template <int ROWS>
+__device__ inline u32x4 frag_tr(const uint16_t *tile, int frow0, int kc, int lane) {
+    const int g = lane >> 4, sl = lane & 15;
+    const int r = frow0 + 16 * (g & 1) + 4 * (sl & 3);
+    const int k = kc * 16 + 8 * (g >> 1) + (sl >> 2);
+    typedef __attribute__((address_space(3))) v4i16 lds_v4i16;
+    const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+        (lds_v4i16 *)(const_cast<uint16_t *>(tile) + tr_index<ROWS>(k, r)));
+    const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+        (lds_v4i16 *)(const_cast<uint16_t *>(tile) + tr_index<ROWS>(k + 4, r)));
+    u32x4 o;
+    o.x = static_cast<uint16_t>(lo.x) | (static_cast<uint32_t>(static_cast<uint16_t>(lo.y)) << 16);
+    o.y = static_cast<uint16_t>(lo.z) | (static_cast<uint32_t>(static_cast<uint16_t>(lo.w)) << 16);
+    o.z = static_cast<uint16_t>(hi.x) | (static_cast<uint32_t>(static_cast<uint16_t>(hi.y)) << 16);
+    o.w = static_cast<uint16_t>(hi.z) | (static_cast<uint32_t>(static_cast<uint16_t>(hi.w)) << 16);
+    return o;
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Give XCD x a contiguous range of logical tiles, so neighbouring
@@ -279,7 +365,15 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     // Split the threads between the two operands when neither needs all of them.
     constexpr int B_OFF = (LA::NT + LB::NT <= kThreads) ? LA::NT : 0;
 
-    __shared__ __attribute__((aligned(16))) T lds[2][(BM + BN) * PITCH];
+    // Two buffers of both operand tiles; the epilogue reuses the same memory
+    // to stage the float32 accumulators (WM rows of WN + 8 floats per wave).
+    constexpr int BUF = LA::ELEMS + LB::ELEMS;
+    constexpr int EP = WN + 8;
+    constexpr size_t TILE_BYTES = 2 * BUF * sizeof(T);
+    constexpr size_t STAGE_BYTES = 4 * WM * EP * sizeof(float);
+    constexpr size_t LDS_BYTES = TILE_BYTES > STAGE_BYTES ? TILE_BYTES : STAGE_BYTES;
+    __shared__ __attribute__((aligned(16))) unsigned char lds_mem[LDS_BYTES];
+    T *const lds0 = reinterpret_cast<T *>(lds_mem);
 
     const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
     int pi = 0;
@@ -327,6 +421,9 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     const bool do_rowsum = (EPI == kEpiPartial) && tn == 0;
     constexpr int TPR = kThreads / BM;
     float rowsum = 0.0f;
+    float rows8[VEC];  // k-major A tiles: per-thread partial sums of its 8 rows
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) rows8[e] = 0.0f;
 
     // Two k-slabs in flight: staging set 0 holds even slabs, set 1 odd ones.
     // While slab kt is multiplied out of one LDS buffer, slab kt + 1 sits in
@@ -358,24 +455,41 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
             lb.load(B, P.ldb, P.N, n0, k0, kend, tid - B_OFF, b_vec);
         }
     };
+    // Stores a staging set into LDS buffer `buf`; k-major A tiles also feed
+    // the row sums of the bias gradient from the staged registers.
+    auto store_slab = [&](LA &la, LB &lb, int buf) {
+        la.store(lds0 + buf * BUF, tid);
+        lb.store(lds0 + buf * BUF + LA::ELEMS, tid - B_OFF);
+        if constexpr (LA::TR && EPI == kEpiPartial) {
+            if (do_rowsum) la.accumulate_rows(rows8, tid);
+        }
+    };
     auto compute = [&](int buf) {
-        const T *As = &lds[0][0] + buf * ((BM + BN) * PITCH);
-        const T *Bs = As + BM * PITCH;
+        const T *As = lds0 + buf * BUF;
+        const T *Bs = As + LA::ELEMS;
 #pragma unroll
         for (int kc = 0; kc < BK / KC; ++kc) {
             u32x4 a[MI], b[NJ];
 #pragma unroll
-            for (int i = 0; i < MI; ++i)
-                a[i] = *reinterpret_cast<const u32x4 *>(As + (wm * WM + i * 32 + lrow) * PITCH + kc * KC + lk);
+            for (int i = 0; i < MI; ++i) {
+                if constexpr (LA::TR)
+                    a[i] = frag_tr<BM>(reinterpret_cast<const uint16_t *>(As), wm * WM + i * 32, kc, lane);
+                else
+                    a[i] = *reinterpret_cast<const u32x4 *>(As + (wm * WM + i * 32 + lrow) * PITCH + kc * KC + lk);
+            }
 #pragma unroll
-            for (int j = 0; j < NJ; ++j)
-                b[j] = *reinterpret_cast<const u32x4 *>(Bs + (wn * WN + j * 32 + lrow) * PITCH + kc * KC + lk);
+            for (int j = 0; j < NJ; ++j) {
+                if constexpr (LB::TR)
+                    b[j] = frag_tr<BN>(reinterpret_cast<const uint16_t *>(Bs), wn * WN + j * 32, kc, lane);
+                else
+                    b[j] = *reinterpret_cast<const u32x4 *>(Bs + (wn * WN + j * 32 + lrow) * PITCH + kc * KC + lk);
+            }
 #pragma unroll
             for (int i = 0; i < MI; ++i)
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) Mma<T>::mac(acc[i][j], a[i], b[j]);
         }
-        if (do_rowsum) {
+        if (!LA::TR && do_rowsum) {
             // TPR adjacent threads per row of A, each summing a part of the slab.
             const int row = tid / TPR;
             const T *src = As + row * PITCH + (tid % TPR) * (BK / TPR);
@@ -384,19 +498,14 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
         }
     };
 
-    // The bf16 128 x 128 variants with a transposed operand (input and
-    // weight gradients) do not fit two staging sets into the 256 registers
-    // of two waves per SIMD (they would spill): they keep one slab of
-    // lookahead.
-    constexpr bool kTwoAhead = !(sizeof(T) == 2 && BM == 128 && BN == 128 && BMODE == 1);
+    constexpr bool kTwoAhead = true;
 
     // On the FAST path every load and LDS store of the loop is unconditional:
     // slabs past the end read as zeros (their offsets fall outside the buffer
     // resources) and land in a buffer nobody reads again.  Conditional loads
     // would make the compiler wait for them before the next LDS store.
     load_slab(la0, lb0, 0);
-    la0.store(&lds[0][0], tid);
-    lb0.store(&lds[0][BM * PITCH], tid - B_OFF);
+    store_slab(la0, lb0, 0);
     if constexpr (!kTwoAhead) {
         __syncthreads();
         for (int kt = 0; kt < nk; ++kt) {
@@ -404,10 +513,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
             const bool more = FAST || kt + 1 < nk;
             if (more) load_slab(la0, lb0, kt + 1);
             compute(cur);
-            if (more) {
-                la0.store(&lds[cur ^ 1][0], tid);
-                lb0.store(&lds[cur ^ 1][BM * PITCH], tid - B_OFF);
-            }
+            if (more) store_slab(la0, lb0, cur ^ 1);
             __syncthreads();
         }
     } else {
@@ -417,24 +523,37 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
             // even slab kt in buffer 0
             if (FAST || kt + 2 < nk) load_slab(la0, lb0, kt + 2);
             compute(0);
-            if (FAST || kt + 1 < nk) {
-                la1.store(&lds[1][0], tid);
-                lb1.store(&lds[1][BM * PITCH], tid - B_OFF);
-            }
+            if (FAST || kt + 1 < nk) store_slab(la1, lb1, 1);
             __syncthreads();
             if (kt + 1 >= nk) break;
             // odd slab kt + 1 in buffer 1
             if (FAST || kt + 3 < nk) load_slab(la1, lb1, kt + 3);
             compute(1);
-            if (FAST || kt + 2 < nk) {
-                la0.store(&lds[0][0], tid);
-                lb0.store(&lds[0][BM * PITCH], tid - B_OFF);
-            }
+            if (FAST || kt + 2 < nk) store_slab(la0, lb0, 0);
             __syncthreads();
         }
     }
 
-    if constexpr (EPI == kEpiPartial) {
+    if constexpr (EPI == kEpiPartial && LA::TR) {
+        // every thread summed the same 8 rows in every slab: combine the
+        // threads of each row group through LDS, in thread order
+        if (do_rowsum) {
+            constexpr int GROUPS = BM / VEC;            // row groups of 8
+            constexpr int PER_GROUP = kThreads / GROUPS;
+            float *red = reinterpret_cast<float *>(lds_mem);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) red[tid * VEC + e] = rows8[e];
+            __syncthreads();
+            if (tid < BM) {
+                const int gq = tid / VEC, e = tid % VEC;
+                float v = 0.0f;
+                for (int q = 0; q < PER_GROUP; ++q) v += red[(gq + GROUPS * q) * VEC + e];
+                const int row = m0 + tid;
+                if (row < P.M) P.rowsum[static_cast<long long>(split) * P.M + row] = v;
+            }
+            __syncthreads();
+        }
+    } else if constexpr (EPI == kEpiPartial) {
         if (do_rowsum) {
 #pragma unroll
             for (int o = 1; o < TPR; o <<= 1) rowsum += __shfl_xor(rowsum, o);
@@ -503,9 +622,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
         }
     }
 
-    constexpr int EP = WN + 8;
-    static_assert(4 * WM * EP * 4 <= sizeof(lds), "epilogue staging must fit in the tile buffers");
-    float *stage = reinterpret_cast<float *>(&lds[0][0]) + wave * WM * EP;
+    float *stage = reinterpret_cast<float *>(lds_mem) + wave * WM * EP;
 #pragma unroll
     for (int i = 0; i < MI; ++i)
 #pragma unroll
