@@ -18,6 +18,7 @@
 // 16-byte vector per row of an 8 x 8 (bf16) or 4 x 4 (float32) block.
 #include "common.hpp"
 
+#include <cstdlib>
 #include <type_traits>
 
 namespace ppo {
@@ -352,6 +353,31 @@ __device__ inline int xcd_swizzle(int b, int n) {
 // ld % VEC == 0 and K % VEC == 0 (checked on the host); its slabs are loaded
 // with buffer loads and nothing else, so the loads stay in flight across the
 // multiply of the previous slabs.  Otherwise every element is bounds-checked.
+// Decodes dispatch index d into the tile it computes: problem pi, tile
+// origin (m0, n0), split and column-tile index, and the split's k-range.
+template <int BM, int BN, int BK>
+__device__ inline void decode_tile(const GemmArgs &args, int d, int &pi, int &m0, int &n0, int &split, int &tn,
+                                   int &kbeg, int &kend) {
+    const int bid = xcd_swizzle(d, args.total_tiles);
+    pi = 0;
+    while (pi + 1 < args.count && bid >= args.p[pi + 1].tile_begin) ++pi;
+    const GemmProblem &P = args.p[pi];
+    const int local = bid - P.tile_begin;
+    const int per_split = P.tiles_m * P.tiles_n;
+    split = local / per_split;
+    const int rem = local - split * per_split;
+    const int tm = rem / P.tiles_n;
+    tn = rem - tm * P.tiles_n;
+    m0 = tm * BM;
+    n0 = tn * BN;
+    kbeg = split * P.kps;
+    kend = min(P.K, kbeg + P.kps);
+}
+
+// Persistent on the FAST path: workgroup b takes dispatch indices b, b + G,
+// b + 2G, ... (G = gridDim.x, a multiple of 8, so every index of a workgroup
+// maps to the same XCD range) and loads the first slab of its next tile while
+// it runs the current tile's epilogue.
 template <typename T, int BM, int BN, int AMODE, int BMODE, int EPI, bool FAST>
 __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) {
     constexpr int BK = GemmTile<T>::BK;
@@ -375,34 +401,6 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     __shared__ __attribute__((aligned(16))) unsigned char lds_mem[LDS_BYTES];
     T *const lds0 = reinterpret_cast<T *>(lds_mem);
 
-    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
-    int pi = 0;
-    while (pi + 1 < args.count && bid >= args.p[pi + 1].tile_begin) ++pi;
-    const GemmProblem &P = args.p[pi];
-
-    const int local = bid - P.tile_begin;
-    const int per_split = P.tiles_m * P.tiles_n;
-    const int split = local / per_split;
-    const int rem = local - split * per_split;
-    const int tm = rem / P.tiles_n;
-    const int tn = rem - tm * P.tiles_n;
-    const int m0 = tm * BM, n0 = tn * BN;
-    const int kbeg = split * P.kps;
-    const int kend = min(P.K, kbeg + P.kps);
-    const int nk = (kend - kbeg + BK - 1) / BK;
-
-    const T *A = static_cast<const T *>(P.A);
-    const T *B = static_cast<const T *>(P.B);
-    // 16-byte vector loads need a 16-byte aligned base and row pitch.
-    const bool a_vec = (P.lda % VEC) == 0 && (reinterpret_cast<uintptr_t>(A) & 15u) == 0;
-    const bool b_vec = (P.ldb % VEC) == 0 && (reinterpret_cast<uintptr_t>(B) & 15u) == 0;
-
-    // Fast (buffer-load) paths, chosen per operand for the whole tile.
-    const __amdgpu_buffer_rsrc_t a_rs =
-        make_rsrc(A, static_cast<long long>(AMODE == 0 ? P.M : kend) * P.lda * static_cast<int>(sizeof(T)));
-    const __amdgpu_buffer_rsrc_t b_rs =
-        make_rsrc(B, static_cast<long long>(BMODE == 0 ? P.N : kend) * P.ldb * static_cast<int>(sizeof(T)));
-
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -411,60 +409,60 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     const int lk = (lane >> 5) * VEC;
 
     floatx16 acc[MI][NJ];
-#pragma unroll
-    for (int i = 0; i < MI; ++i)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-
-    const bool do_rowsum = (EPI == kEpiPartial) && tn == 0;
     constexpr int TPR = kThreads / BM;
     float rowsum = 0.0f;
     float rows8[VEC];  // k-major A tiles: per-thread partial sums of its 8 rows
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) rows8[e] = 0.0f;
 
     // Two k-slabs in flight: staging set 0 holds even slabs, set 1 odd ones.
     // While slab kt is multiplied out of one LDS buffer, slab kt + 1 sits in
     // registers on its way to the other buffer and slab kt + 2 is loading.
     LA la0, la1;
     LB lb0, lb1;
-    if constexpr (FAST) {
-        la0.setup(P.lda, m0, tid);
-        lb0.setup(P.ldb, n0, tid - B_OFF);
-    }
+    auto setup_loaders = [&](int pi, int m0, int n0) {
+        if constexpr (FAST) {
+            la0.setup(args.p[pi].lda, m0, tid);
+            lb0.setup(args.p[pi].ldb, n0, tid - B_OFF);
 #pragma unroll
-    for (int p = 0; p < LA::PER; ++p) {
-        la1.voff[p] = la0.voff[p];
-        la1.kofs[p] = la0.kofs[p];
-    }
+            for (int p = 0; p < LA::PER; ++p) {
+                la1.voff[p] = la0.voff[p];
+                la1.kofs[p] = la0.kofs[p];
+            }
 #pragma unroll
-    for (int p = 0; p < LB::PER; ++p) {
-        lb1.voff[p] = lb0.voff[p];
-        lb1.kofs[p] = lb0.kofs[p];
-    }
-    // Loads slab kt into a staging set.
-    auto load_slab = [&](LA &la, LB &lb, int kt) {
+            for (int p = 0; p < LB::PER; ++p) {
+                lb1.voff[p] = lb0.voff[p];
+                lb1.kofs[p] = lb0.kofs[p];
+            }
+        }
+    };
+    // Loads slab kt of a tile into a staging set.
+    auto load_slab = [&](int pi, int m0, int n0, int kbeg, int kend, LA &la, LB &lb, int kt) {
+        const GemmProblem &Q = args.p[pi];
         const int k0 = kbeg + kt * BK;
         if constexpr (FAST) {
-            la.load_fast(a_rs, P.lda, k0, kend, tid);
-            lb.load_fast(b_rs, P.ldb, k0, kend, tid - B_OFF);
+            const __amdgpu_buffer_rsrc_t a_rs =
+                make_rsrc(Q.A, static_cast<long long>(AMODE == 0 ? Q.M : kend) * Q.lda * static_cast<int>(sizeof(T)));
+            const __amdgpu_buffer_rsrc_t b_rs =
+                make_rsrc(Q.B, static_cast<long long>(BMODE == 0 ? Q.N : kend) * Q.ldb * static_cast<int>(sizeof(T)));
+            la.load_fast(a_rs, Q.lda, k0, kend, tid);
+            lb.load_fast(b_rs, Q.ldb, k0, kend, tid - B_OFF);
         } else {
-            la.load(A, P.lda, P.M, m0, k0, kend, tid, a_vec);
-            lb.load(B, P.ldb, P.N, n0, k0, kend, tid - B_OFF, b_vec);
+            // 16-byte vector loads need a 16-byte aligned base and row pitch.
+            const bool a_vec = (Q.lda % VEC) == 0 && (reinterpret_cast<uintptr_t>(Q.A) & 15u) == 0;
+            const bool b_vec = (Q.ldb % VEC) == 0 && (reinterpret_cast<uintptr_t>(Q.B) & 15u) == 0;
+            la.load(static_cast<const T *>(Q.A), Q.lda, Q.M, m0, k0, kend, tid, a_vec);
+            lb.load(static_cast<const T *>(Q.B), Q.ldb, Q.N, n0, k0, kend, tid - B_OFF, b_vec);
         }
     };
     // Stores a staging set into LDS buffer `buf`; k-major A tiles also feed
     // the row sums of the bias gradient from the staged registers.
-    auto store_slab = [&](LA &la, LB &lb, int buf) {
+    auto store_slab = [&](bool do_rowsum, LA &la, LB &lb, int buf) {
         la.store(lds0 + buf * BUF, tid);
         lb.store(lds0 + buf * BUF + LA::ELEMS, tid - B_OFF);
         if constexpr (LA::TR && EPI == kEpiPartial) {
             if (do_rowsum) la.accumulate_rows(rows8, tid);
         }
     };
-    auto compute = [&](int buf) {
+    auto compute = [&](bool do_rowsum, int buf) {
         const T *As = lds0 + buf * BUF;
         const T *Bs = As + LA::ELEMS;
 #pragma unroll
@@ -498,194 +496,232 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
         }
     };
 
-    constexpr bool kTwoAhead = true;
-
-    // On the FAST path every load and LDS store of the loop is unconditional:
-    // slabs past the end read as zeros (their offsets fall outside the buffer
-    // resources) and land in a buffer nobody reads again.  Conditional loads
-    // would make the compiler wait for them before the next LDS store.
-    load_slab(la0, lb0, 0);
-    store_slab(la0, lb0, 0);
-    if constexpr (!kTwoAhead) {
-        __syncthreads();
-        for (int kt = 0; kt < nk; ++kt) {
-            const int cur = kt & 1;
-            const bool more = FAST || kt + 1 < nk;
-            if (more) load_slab(la0, lb0, kt + 1);
-            compute(cur);
-            if (more) store_slab(la0, lb0, cur ^ 1);
-            __syncthreads();
-        }
-    } else {
-        if (FAST || nk > 1) load_slab(la1, lb1, 1);
-        __syncthreads();
-        for (int kt = 0; kt < nk; kt += 2) {
-            // even slab kt in buffer 0
-            if (FAST || kt + 2 < nk) load_slab(la0, lb0, kt + 2);
-            compute(0);
-            if (FAST || kt + 1 < nk) store_slab(la1, lb1, 1);
-            __syncthreads();
-            if (kt + 1 >= nk) break;
-            // odd slab kt + 1 in buffer 1
-            if (FAST || kt + 3 < nk) load_slab(la1, lb1, kt + 3);
-            compute(1);
-            if (FAST || kt + 2 < nk) store_slab(la0, lb0, 0);
-            __syncthreads();
-        }
-    }
-
-    if constexpr (EPI == kEpiPartial && LA::TR) {
-        // every thread summed the same 8 rows in every slab: combine the
-        // threads of each row group through LDS, in thread order
-        if (do_rowsum) {
-            constexpr int GROUPS = BM / VEC;            // row groups of 8
-            constexpr int PER_GROUP = kThreads / GROUPS;
-            float *red = reinterpret_cast<float *>(lds_mem);
-#pragma unroll
-            for (int e = 0; e < VEC; ++e) red[tid * VEC + e] = rows8[e];
-            __syncthreads();
-            if (tid < BM) {
-                const int gq = tid / VEC, e = tid % VEC;
-                float v = 0.0f;
-                for (int q = 0; q < PER_GROUP; ++q) v += red[(gq + GROUPS * q) * VEC + e];
-                const int row = m0 + tid;
-                if (row < P.M) P.rowsum[static_cast<long long>(split) * P.M + row] = v;
-            }
-            __syncthreads();
-        }
-    } else if constexpr (EPI == kEpiPartial) {
-        if (do_rowsum) {
-#pragma unroll
-            for (int o = 1; o < TPR; o <<= 1) rowsum += __shfl_xor(rowsum, o);
-            const int row = m0 + tid / TPR;
-            if (tid % TPR == 0 && row < P.M) P.rowsum[static_cast<long long>(split) * P.M + row] = rowsum;
-        }
-    }
-
-    // Epilogue: accumulators -> LDS (float32, per-wave WM x WN tile) -> each
-    // lane takes 4 consecutive columns of a row, applies the epilogue and
-    // writes them with one 8-byte (bf16) or 16-byte (float32) store.  Rows are
-    // padded to EP = WN + 8 floats (EP = 8 mod 16), so the two lane halves of
-    // the scattered accumulator writes (rows 4 apart) hit disjoint banks.
-    // WN / 4 lanes cover one staged row (4 floats each): for WN = 64 every
-    // 16-lane group of a 16-byte LDS read touches all 64 banks once.
+    // Epilogue constants: WN / 4 lanes cover one staged row (4 floats each);
+    // for WN = 64 every 16-lane group of a 16-byte LDS read touches all 64
+    // banks once.
     constexpr int CW = 4;
     constexpr int LPR = WN / CW;         // lanes per staged row
     constexpr int RPI = 64 / LPR;        // rows per iteration
     constexpr int ITS = WM / RPI;        // epilogue iterations per lane
     const int sub_r = lane / LPR;
     const int sub_c = (lane % LPR) * CW;
-    const int col = n0 + wn * WN + sub_c;
-    const bool full_cols = col + CW <= P.N;
 
-    // ELU' input: every activation this lane needs is loaded before the
-    // accumulators go through LDS, all loads in flight at once (the output
-    // stores that follow could alias them as far as the compiler knows, so
-    // loads inside the store loop would each wait for the previous store).
-    T hreg[ITS][CW];
-    if constexpr (EPI == kEpiDElu && FAST) {
-        // buffer loads: rows past M read as zeros, no branches, one scalar
-        // offset per iteration
-        const __amdgpu_buffer_rsrc_t h_rs =
-            make_rsrc(P.H, static_cast<long long>(P.M) * P.ldh * static_cast<int>(sizeof(T)));
-        const int vo = ((m0 + wm * WM + sub_r) * P.ldh + col) * static_cast<int>(sizeof(T));
+    const int total = args.total_tiles;
+    const int G = gridDim.x;
+    int d = blockIdx.x;
+    int pi, m0, n0, split, tn, kbeg, kend;
+    decode_tile<BM, BN, BK>(args, d, pi, m0, n0, split, tn, kbeg, kend);
+    setup_loaders(pi, m0, n0);
+    // On the FAST path every load and LDS store of the loop is unconditional:
+    // slabs past the end read as zeros (their offsets fall outside the buffer
+    // resources) and land in a buffer nobody reads again.  Conditional loads
+    // would make the compiler wait for them before the next LDS store.
+    load_slab(pi, m0, n0, kbeg, kend, la0, lb0, 0);
+    if (FAST || kend - kbeg > BK) load_slab(pi, m0, n0, kbeg, kend, la1, lb1, 1);
+
+    while (true) {
+        const GemmProblem &P = args.p[pi];
+        const int nk = (kend - kbeg + BK - 1) / BK;
+        const bool do_rowsum = (EPI == kEpiPartial) && tn == 0;
 #pragma unroll
-        for (int it = 0; it < ITS; ++it) {
-            const int so = __builtin_amdgcn_readfirstlane(it * RPI * P.ldh * static_cast<int>(sizeof(T)));
-            if constexpr (sizeof(T) == 2) {
-                typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-                const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(h_rs, vo, so, 0);
-                *reinterpret_cast<u32x2 *>(hreg[it]) = v;
-            } else {
-                *reinterpret_cast<u32x4 *>(hreg[it]) = __builtin_amdgcn_raw_buffer_load_b128(h_rs, vo, so, 0);
-            }
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+        rowsum = 0.0f;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) rows8[e] = 0.0f;
+
+        store_slab(do_rowsum, la0, lb0, 0);
+        __syncthreads();
+        for (int kt = 0; kt < nk; kt += 2) {
+            // even slab kt in buffer 0
+            if (FAST || kt + 2 < nk) load_slab(pi, m0, n0, kbeg, kend, la0, lb0, kt + 2);
+            compute(do_rowsum, 0);
+            if (FAST || kt + 1 < nk) store_slab(do_rowsum, la1, lb1, 1);
+            __syncthreads();
+            if (kt + 1 >= nk) break;
+            // odd slab kt + 1 in buffer 1
+            if (FAST || kt + 3 < nk) load_slab(pi, m0, n0, kbeg, kend, la1, lb1, kt + 3);
+            compute(do_rowsum, 1);
+            if (FAST || kt + 2 < nk) store_slab(do_rowsum, la0, lb0, 0);
+            __syncthreads();
         }
-    } else if constexpr (EPI == kEpiDElu) {
-        const bool h_vec = full_cols && (P.ldh % CW) == 0 && (reinterpret_cast<uintptr_t>(P.H) & 15u) == 0;
+
+        if constexpr (EPI == kEpiPartial && LA::TR) {
+            // every thread summed the same 8 rows in every slab: combine the
+            // threads of each row group through LDS, in thread order
+            if (do_rowsum) {
+                constexpr int GROUPS = BM / VEC;            // row groups of 8
+                constexpr int PER_GROUP = kThreads / GROUPS;
+                float *red = reinterpret_cast<float *>(lds_mem);
 #pragma unroll
-        for (int it = 0; it < ITS; ++it) {
-            const int row = m0 + wm * WM + it * RPI + sub_r;
-#pragma unroll
-            for (int e = 0; e < CW; ++e) hreg[it][e] = T(0);
-            if (row >= P.M || col >= P.N) continue;
-            const T *hsrc = static_cast<const T *>(P.H) + static_cast<long long>(row) * P.ldh + col;
-            if (h_vec) {
-                if constexpr (sizeof(T) == 2) {
-                    *reinterpret_cast<uint2 *>(hreg[it]) = *reinterpret_cast<const uint2 *>(hsrc);
-                } else {
-                    *reinterpret_cast<u32x4 *>(hreg[it]) = *reinterpret_cast<const u32x4 *>(hsrc);
+                for (int e = 0; e < VEC; ++e) red[tid * VEC + e] = rows8[e];
+                __syncthreads();
+                if (tid < BM) {
+                    const int gq = tid / VEC, e = tid % VEC;
+                    float v = 0.0f;
+                    for (int q = 0; q < PER_GROUP; ++q) v += red[(gq + GROUPS * q) * VEC + e];
+                    const int row = m0 + tid;
+                    if (row < P.M) P.rowsum[static_cast<long long>(split) * P.M + row] = v;
                 }
-            } else {
+                __syncthreads();
+            }
+        } else if constexpr (EPI == kEpiPartial) {
+            if (do_rowsum) {
 #pragma unroll
-                for (int e = 0; e < CW; ++e) hreg[it][e] = (col + e < P.N) ? hsrc[e] : T(0);
+                for (int o = 1; o < TPR; o <<= 1) rowsum += __shfl_xor(rowsum, o);
+                const int row = m0 + tid / TPR;
+                if (tid % TPR == 0 && row < P.M) P.rowsum[static_cast<long long>(split) * P.M + row] = rowsum;
             }
         }
-    }
 
-    float *stage = reinterpret_cast<float *>(lds_mem) + wave * WM * EP;
-#pragma unroll
-    for (int i = 0; i < MI; ++i)
-#pragma unroll
-        for (int j = 0; j < NJ; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                stage[(i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * EP + j * 32 + lrow] = acc[i][j][r];
-    __syncthreads();
+        // Epilogue: accumulators -> LDS (float32, per-wave WM x WN tile) -> each
+        // lane takes 4 consecutive columns of a row, applies the epilogue and
+        // writes them with one 8-byte (bf16) or 16-byte (float32) store.  Rows are
+        // padded to EP = WN + 8 floats (EP = 8 mod 16), so the two lane halves of
+        // the scattered accumulator writes (rows 4 apart) hit disjoint banks.
+        const int col = n0 + wn * WN + sub_c;
+        const bool full_cols = col + CW <= P.N;
 
-    if (col >= P.N) return;
-    float bias[CW];
-    if constexpr (EPI == kEpiBiasElu) {
+        // ELU' input: every activation this lane needs is loaded before the
+        // accumulators go through LDS, all loads in flight at once (the output
+        // stores that follow could alias them as far as the compiler knows, so
+        // loads inside the store loop would each wait for the previous store).
+        T hreg[ITS][CW];
+        if constexpr (EPI == kEpiDElu && FAST) {
+            // buffer loads: rows past M read as zeros, no branches, one scalar
+            // offset per iteration
+            const __amdgpu_buffer_rsrc_t h_rs =
+                make_rsrc(P.H, static_cast<long long>(P.M) * P.ldh * static_cast<int>(sizeof(T)));
+            const int vo = ((m0 + wm * WM + sub_r) * P.ldh + col) * static_cast<int>(sizeof(T));
 #pragma unroll
-        for (int e = 0; e < CW; ++e) bias[e] = (col + e < P.N) ? P.bias[col + e] : 0.0f;
-    }
-    const bool c_vec = full_cols && (P.ldc % CW) == 0 && (reinterpret_cast<uintptr_t>(P.C) & 15u) == 0;
-    // Full 4-column segments go out as one buffer store each (rows past M
-    // fall outside the resource and are dropped); ragged column edges take
-    // element stores.  Keeping the two paths on different instructions stops
-    // the compiler from merging them into split partial-width stores.
-    using OutT = typename std::conditional<EPI == kEpiPartial, float, T>::type;
-    OutT *cbase = static_cast<OutT *>(P.C) + (EPI == kEpiPartial ? split * P.c_split_stride : 0);
-    const __amdgpu_buffer_rsrc_t c_rs =
-        make_rsrc(cbase, static_cast<long long>(P.M) * P.ldc * static_cast<int>(sizeof(OutT)));
-    const int c_vo = ((m0 + wm * WM + sub_r) * P.ldc + col) * static_cast<int>(sizeof(OutT));
+            for (int it = 0; it < ITS; ++it) {
+                const int so = __builtin_amdgcn_readfirstlane(it * RPI * P.ldh * static_cast<int>(sizeof(T)));
+                if constexpr (sizeof(T) == 2) {
+                    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(h_rs, vo, so, 0);
+                    *reinterpret_cast<u32x2 *>(hreg[it]) = v;
+                } else {
+                    *reinterpret_cast<u32x4 *>(hreg[it]) = __builtin_amdgcn_raw_buffer_load_b128(h_rs, vo, so, 0);
+                }
+            }
+        } else if constexpr (EPI == kEpiDElu) {
+            const bool h_vec = full_cols && (P.ldh % CW) == 0 && (reinterpret_cast<uintptr_t>(P.H) & 15u) == 0;
 #pragma unroll
-    for (int it = 0; it < ITS; ++it) {
-        const int lr = it * RPI + sub_r;
-        const int row = m0 + wm * WM + lr;
-        const int c_so = __builtin_amdgcn_readfirstlane(it * RPI * P.ldc * static_cast<int>(sizeof(OutT)));
-        float v[CW];
-        *reinterpret_cast<float4 *>(&v[0]) = *reinterpret_cast<const float4 *>(stage + lr * EP + sub_c);
-        OutT out[CW];
-        if constexpr (EPI == kEpiPartial) {
+            for (int it = 0; it < ITS; ++it) {
+                const int row = m0 + wm * WM + it * RPI + sub_r;
 #pragma unroll
-            for (int e = 0; e < CW; ++e) out[e] = v[e];
-        } else {
+                for (int e = 0; e < CW; ++e) hreg[it][e] = T(0);
+                if (row >= P.M || col >= P.N) continue;
+                const T *hsrc = static_cast<const T *>(P.H) + static_cast<long long>(row) * P.ldh + col;
+                if (h_vec) {
+                    if constexpr (sizeof(T) == 2) {
+                        *reinterpret_cast<uint2 *>(hreg[it]) = *reinterpret_cast<const uint2 *>(hsrc);
+                    } else {
+                        *reinterpret_cast<u32x4 *>(hreg[it]) = *reinterpret_cast<const u32x4 *>(hsrc);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < CW; ++e) hreg[it][e] = (col + e < P.N) ? hsrc[e] : T(0);
+                }
+            }
+        }
+
+        float *stage = reinterpret_cast<float *>(lds_mem) + wave * WM * EP;
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    stage[(i * 32 + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3)) * EP + j * 32 + lrow] = acc[i][j][r];
+        __syncthreads();
+
+        // the next tile's first slab loads while this tile's epilogue runs
+        const int dn = d + G;
+        const bool has_next = FAST && dn < total;
+        int npi = pi, nm0 = m0, nn0 = n0, nsplit = split, ntn = tn, nkbeg = kbeg, nkend = kend;
+        if (has_next) {
+            decode_tile<BM, BN, BK>(args, dn, npi, nm0, nn0, nsplit, ntn, nkbeg, nkend);
+            setup_loaders(npi, nm0, nn0);
+            load_slab(npi, nm0, nn0, nkbeg, nkend, la0, lb0, 0);
+        }
+
+        if (col < P.N) {
+            float bias[CW];
             if constexpr (EPI == kEpiBiasElu) {
 #pragma unroll
-                for (int e = 0; e < CW; ++e) v[e] = Act<T>::elu(v[e] + bias[e]);
-            } else {
+                for (int e = 0; e < CW; ++e) bias[e] = (col + e < P.N) ? P.bias[col + e] : 0.0f;
+            }
+            const bool c_vec = full_cols && (P.ldc % CW) == 0 && (reinterpret_cast<uintptr_t>(P.C) & 15u) == 0;
+            // Full 4-column segments go out as one buffer store each (rows past
+            // M fall outside the resource and are dropped); ragged column edges
+            // take element stores.  Keeping the two paths on different
+            // instructions stops the compiler from merging them into split
+            // partial-width stores.
+            using OutT = typename std::conditional<EPI == kEpiPartial, float, T>::type;
+            OutT *cbase = static_cast<OutT *>(P.C) + (EPI == kEpiPartial ? split * P.c_split_stride : 0);
+            const __amdgpu_buffer_rsrc_t c_rs =
+                make_rsrc(cbase, static_cast<long long>(P.M) * P.ldc * static_cast<int>(sizeof(OutT)));
+            const int c_vo = ((m0 + wm * WM + sub_r) * P.ldc + col) * static_cast<int>(sizeof(OutT));
 #pragma unroll
-                for (int e = 0; e < CW; ++e) {
-                    const float hv = Elem<T>::to_f(hreg[it][e]);
-                    v[e] *= hv > 0.0f ? 1.0f : hv + 1.0f;
+            for (int it = 0; it < ITS; ++it) {
+                const int lr = it * RPI + sub_r;
+                const int row = m0 + wm * WM + lr;
+                const int c_so = __builtin_amdgcn_readfirstlane(it * RPI * P.ldc * static_cast<int>(sizeof(OutT)));
+                float v[CW];
+                *reinterpret_cast<float4 *>(&v[0]) = *reinterpret_cast<const float4 *>(stage + lr * EP + sub_c);
+                OutT out[CW];
+                if constexpr (EPI == kEpiPartial) {
+#pragma unroll
+                    for (int e = 0; e < CW; ++e) out[e] = v[e];
+                } else {
+                    if constexpr (EPI == kEpiBiasElu) {
+#pragma unroll
+                        for (int e = 0; e < CW; ++e) v[e] = Act<T>::elu(v[e] + bias[e]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < CW; ++e) {
+                            const float hv = Elem<T>::to_f(hreg[it][e]);
+                            v[e] *= hv > 0.0f ? 1.0f : hv + 1.0f;
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < CW; ++e) out[e] = Act<T>::store(v[e]);
+                }
+                if (c_vec) {
+                    if constexpr (sizeof(OutT) == 2) {
+                        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                        __builtin_amdgcn_raw_buffer_store_b64(*reinterpret_cast<const u32x2 *>(out), c_rs, c_vo, c_so,
+                                                              0);
+                    } else {
+                        __builtin_amdgcn_raw_buffer_store_b128(*reinterpret_cast<const u32x4 *>(out), c_rs, c_vo, c_so,
+                                                               0);
+                    }
+                } else if (row < P.M) {
+                    OutT *dst = cbase + static_cast<long long>(row) * P.ldc + col;
+#pragma unroll
+                    for (int e = 0; e < CW; ++e)
+                        if (col + e < P.N) dst[e] = out[e];
                 }
             }
-#pragma unroll
-            for (int e = 0; e < CW; ++e) out[e] = Act<T>::store(v[e]);
         }
-        if (c_vec) {
-            if constexpr (sizeof(OutT) == 2) {
-                typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-                __builtin_amdgcn_raw_buffer_store_b64(*reinterpret_cast<const u32x2 *>(out), c_rs, c_vo, c_so, 0);
-            } else {
-                __builtin_amdgcn_raw_buffer_store_b128(*reinterpret_cast<const u32x4 *>(out), c_rs, c_vo, c_so, 0);
-            }
-        } else if (row < P.M) {
-            OutT *dst = cbase + static_cast<long long>(row) * P.ldc + col;
-#pragma unroll
-            for (int e = 0; e < CW; ++e)
-                if (col + e < P.N) dst[e] = out[e];
-        }
+
+        if (!has_next) break;
+        d = dn;
+        pi = npi;
+        m0 = nm0;
+        n0 = nn0;
+        split = nsplit;
+        tn = ntn;
+        kbeg = nkbeg;
+        kend = nkend;
+        load_slab(pi, m0, n0, kbeg, kend, la1, lb1, 1);
+        // the staged accumulators are read before the next tile's slab 0 goes
+        // into the same memory
+        __syncthreads();
     }
 }
 
@@ -702,20 +738,60 @@ bool all_fast(const GemmArgs &args) {
     return true;
 }
 
+// Workgroups of a persistent FAST kernel: as many as can be resident at
+// once (occupancy per CU times the CU count, rounded down to a multiple of
+// 8), queried once per kernel.  PPO_GEMM_GRID_CAP=0 turns persistence off
+// (one tile per workgroup).  Launched non-persistently, the same kernel runs
+// exactly one tile per workgroup.
+int persistence_enabled() {
+    static const int on = [] {
+        const char *e = std::getenv("PPO_GEMM_GRID_CAP");
+        return e && std::atoi(e) <= 0 ? 0 : 1;
+    }();
+    return on;
+}
+
+template <typename K>
+int resident_grid(K kernel) {
+    static int grid = -1;
+    if (grid < 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, 0) != hipSuccess) {
+            grid = 0;
+        } else {
+            grid = (cus * per_cu) / 8 * 8;
+        }
+    }
+    return grid;
+}
+
+template <typename T, int BM, int BN, int AMODE, int BMODE, int EPI, bool FAST>
+hipError_t launch_one(const GemmArgs &args, hipStream_t s) {
+    auto kernel = gemm_kernel<T, BM, BN, AMODE, BMODE, EPI, FAST>;
+    int g = args.total_tiles;
+    // measured: persistence pays off for the 128 x 128 tiles only (smaller
+    // tiles already overlap through more resident workgroups per CU)
+    if (FAST && BM == 128 && BN == 128 && persistence_enabled()) {
+        const int cap = resident_grid(kernel);
+        if (cap > 0 && g > cap) g = cap;
+    }
+    hipLaunchKernelGGL(kernel, dim3(g), dim3(kThreads), 0, s, args);
+    return hipGetLastError();
+}
+
 template <typename T, int BM, int BN, bool FAST>
 hipError_t launch_tiled(int a_mode, int b_mode, int epi, const GemmArgs &args, hipStream_t s) {
-    dim3 grid(args.total_tiles), block(kThreads);
     if (a_mode == 0 && b_mode == 0 && epi == kEpiBiasElu)
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 0, kEpiBiasElu, FAST>), grid, block, 0, s, args);
-    else if (a_mode == 0 && b_mode == 0 && epi == kEpiDElu)
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 0, kEpiDElu, FAST>), grid, block, 0, s, args);
-    else if (a_mode == 0 && b_mode == 1 && epi == kEpiDElu)
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 0, 1, kEpiDElu, FAST>), grid, block, 0, s, args);
-    else if (a_mode == 1 && b_mode == 1 && epi == kEpiPartial)
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, 1, 1, kEpiPartial, FAST>), grid, block, 0, s, args);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+        return launch_one<T, BM, BN, 0, 0, kEpiBiasElu, FAST>(args, s);
+    if (a_mode == 0 && b_mode == 0 && epi == kEpiDElu)
+        return launch_one<T, BM, BN, 0, 0, kEpiDElu, FAST>(args, s);
+    if (a_mode == 0 && b_mode == 1 && epi == kEpiDElu)
+        return launch_one<T, BM, BN, 0, 1, kEpiDElu, FAST>(args, s);
+    if (a_mode == 1 && b_mode == 1 && epi == kEpiPartial)
+        return launch_one<T, BM, BN, 1, 1, kEpiPartial, FAST>(args, s);
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int BM, int BN>

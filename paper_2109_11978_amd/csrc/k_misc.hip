@@ -145,15 +145,60 @@ __device__ inline const float *head_row(const HeadWeights &hw, const float *Wa, 
 
 // out[i][j] = b_j + h_i . W_j for the A actor outputs (j < A) and the critic
 // value (j == A); one dot product per thread.  Hl is a multiple of 16.
+// The block's rows of both last hidden layers, staged in LDS (pitch Hl + 8
+// elements) with coalesced 16-byte loads, four in flight per thread.
+template <typename T>
+__device__ inline void stage_hidden_rows(T *ha_l, T *hc_l, const T *ha, const T *hc, int r0, int rows, int Hl,
+                                         bool actor, bool critic) {
+    constexpr int VEC = 16 / sizeof(T);
+    const int pitch = Hl + 8;
+    const int per_row = Hl / VEC;
+    const int n = 2 * rows * per_row;
+    constexpr int U = 4;
+    for (int q0 = threadIdx.x; q0 < n; q0 += U * blockDim.x) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + u * blockDim.x;
+            const int net = q / (rows * per_row);
+            const int rem = q - net * rows * per_row;
+            const int i = rem / per_row, c = (rem - i * per_row) * VEC;
+            const bool want = q < n && (net == 0 ? actor : critic);
+            if (want)
+                v[u] = *reinterpret_cast<const u32x4 *>((net == 0 ? ha : hc) + static_cast<long long>(r0 + i) * Hl + c);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int q = q0 + u * blockDim.x;
+            const int net = q / (rows * per_row);
+            const int rem = q - net * rows * per_row;
+            const int i = rem / per_row, c = (rem - i * per_row) * VEC;
+            const bool want = q < n && (net == 0 ? actor : critic);
+            if (want) *reinterpret_cast<u32x4 *>((net == 0 ? ha_l : hc_l) + i * pitch + c) = v[u];
+        }
+    }
+    __syncthreads();
+}
+
+// Bytes of dynamic LDS for `rows` staged rows of both last hidden layers,
+// 0 when they do not fit next to the output-layer weights.
+template <typename T>
+size_t head_rows_lds(int rows, int Hl, size_t weight_bytes) {
+    const size_t bytes = 2 * static_cast<size_t>(rows) * (Hl + 8) * sizeof(T);
+    return weight_bytes + bytes <= 48 * 1024 ? bytes : 0;
+}
+
 template <typename T, int ROWS>
-__device__ inline void output_layers(const T *ha, const T *hc, const HeadWeights &hw, const float *Wa,
+__device__ inline void output_layers(const T *ha, const T *hc, const T *ha_l, const T *hc_l,
+                                     const HeadWeights &hw, const float *Wa,
                                      const float *ba, const float *Wc, const float *bc, int r0, int rows, int A,
                                      int Hl, bool actor, float (*out)[kMaxAct + 1]) {
     const int n_out = A + 1;
     for (int q = threadIdx.x; q < ROWS * n_out; q += kHeadThreads) {
         const int i = q / n_out, j = q - (q / n_out) * n_out;
         if (i >= rows || (j < A && !actor)) continue;
-        const T *h = (j < A ? ha : hc) + static_cast<long long>(r0 + i) * Hl;
+        const T *h = ha_l ? (j < A ? ha_l : hc_l) + i * (Hl + 8)
+                          : (j < A ? ha : hc) + static_cast<long long>(r0 + i) * Hl;
         const float *w = head_row(hw, Wa, Wc, A, Hl, j);
         float acc = j < A ? ba[j] : bc[0];
         // 64 activations (eight 8-wide loads) in flight per step; Hl is a multiple of 16
@@ -178,15 +223,24 @@ __device__ inline void output_layers(const T *ha, const T *hc, const HeadWeights
 // a = mu + sigma * eps with Philox noise and its log-density
 // sum_j(-eps_j^2 / 2 - log sigma_j) - (A/2) log(2 pi).
 template <typename T>
-__global__ __launch_bounds__(kHeadThreads) void head_sample_kernel(const HeadSampleArgs a, int w_in_lds) {
+__global__ __launch_bounds__(kHeadThreads) void head_sample_kernel(const HeadSampleArgs a, int w_in_lds,
+                                                                    int rows_lds_offset) {
     extern __shared__ float s_w[];
     __shared__ float s_out[kSampleRows][kMaxAct + 1];
     const int r0 = blockIdx.x * kSampleRows;
     const int rows = min(kSampleRows, a.N - r0);
     const int A = a.A;
     const HeadWeights hw = stage_head_weights(s_w, w_in_lds, a.Wa, a.Wc, A, a.Hl);
-    output_layers<T, kSampleRows>(static_cast<const T *>(a.ha), static_cast<const T *>(a.hc), hw, a.Wa, a.ba, a.Wc,
-                                  a.bc, r0, rows, A, a.Hl, !a.value_only, s_out);
+    const T *ha = static_cast<const T *>(a.ha);
+    const T *hc = static_cast<const T *>(a.hc);
+    T *ha_l = nullptr, *hc_l = nullptr;
+    if (rows_lds_offset >= 0) {
+        ha_l = reinterpret_cast<T *>(reinterpret_cast<char *>(s_w) + rows_lds_offset);
+        hc_l = ha_l + kSampleRows * (a.Hl + 8);
+        stage_hidden_rows<T>(ha_l, hc_l, ha, hc, r0, rows, a.Hl, !a.value_only, true);
+    }
+    output_layers<T, kSampleRows>(ha, hc, ha_l, hc_l, hw, a.Wa, a.ba, a.Wc, a.bc, r0, rows, A, a.Hl,
+                                  !a.value_only, s_out);
     __syncthreads();
     const int i = threadIdx.x;
     if (i >= rows) return;
@@ -224,7 +278,8 @@ __global__ __launch_bounds__(kHeadThreads) void head_sample_kernel(const HeadSam
 // the loss terms and of the log-std gradient go to `partials` (wave-0
 // shuffle reduction, fixed order).
 template <typename T>
-__global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossArgs a, int w_in_lds) {
+__global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossArgs a, int w_in_lds,
+                                                                  int rows_lds_offset) {
     extern __shared__ float s_w[];
     __shared__ float s_out[kLossRows][kMaxAct + 1];
     const int r0 = blockIdx.x * kLossRows;
@@ -234,7 +289,15 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
     const T *ha = static_cast<const T *>(a.ha);
     const T *hc = static_cast<const T *>(a.hc);
     const HeadWeights hw = stage_head_weights(s_w, w_in_lds, a.Wa, a.Wc, A, Hl);
-    output_layers<T, kLossRows>(ha, hc, hw, a.Wa, a.ba, a.Wc, a.bc, r0, rows, A, Hl, true, s_out);
+    // the block's activation rows, read once from HBM and reused by the
+    // output layers and the backward below
+    T *ha_l = nullptr, *hc_l = nullptr;
+    if (rows_lds_offset >= 0) {
+        ha_l = reinterpret_cast<T *>(reinterpret_cast<char *>(s_w) + rows_lds_offset);
+        hc_l = ha_l + kLossRows * (Hl + 8);
+        stage_hidden_rows<T>(ha_l, hc_l, ha, hc, r0, rows, Hl, true, true);
+    }
+    output_layers<T, kLossRows>(ha, hc, ha_l, hc_l, hw, a.Wa, a.ba, a.Wc, a.bc, r0, rows, A, Hl, true, s_out);
     __syncthreads();
 
     const int tid = threadIdx.x;
@@ -352,7 +415,12 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
             const int rem = q - net * kLossRows * chunks;
             const int i = rem / chunks;
             const int k = (rem - i * chunks) * 8;
-            if (q < n_q && i < rows) load8<T>((net == 0 ? ha : hc) + static_cast<long long>(r0 + i) * Hl + k, xs[u]);
+            if (q < n_q && i < rows) {
+                if (ha_l)
+                    load8<T>((net == 0 ? ha_l : hc_l) + i * (Hl + 8) + k, xs[u]);
+                else
+                    load8<T>((net == 0 ? ha : hc) + static_cast<long long>(r0 + i) * Hl + k, xs[u]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -712,11 +780,16 @@ size_t head_weight_lds(int A, int Hl) {
 
 hipError_t launch_head_sample(Precision prec, const HeadSampleArgs &a, hipStream_t s) {
     const dim3 grid((a.N + kSampleRows - 1) / kSampleRows), block(kHeadThreads);
-    const size_t shm = head_weight_lds(a.A, a.Hl);
-    if (prec == kBF16)
-        hipLaunchKernelGGL(head_sample_kernel<uint16_t>, grid, block, shm, s, a, shm > 0 ? 1 : 0);
-    else
-        hipLaunchKernelGGL(head_sample_kernel<float>, grid, block, shm, s, a, shm > 0 ? 1 : 0);
+    const size_t wsh = head_weight_lds(a.A, a.Hl);
+    if (prec == kBF16) {
+        const size_t rsh = head_rows_lds<uint16_t>(kSampleRows, a.Hl, wsh);
+        hipLaunchKernelGGL(head_sample_kernel<uint16_t>, grid, block, wsh + rsh, s, a, wsh > 0 ? 1 : 0,
+                           rsh > 0 ? static_cast<int>(wsh) : -1);
+    } else {
+        const size_t rsh = head_rows_lds<float>(kSampleRows, a.Hl, wsh);
+        hipLaunchKernelGGL(head_sample_kernel<float>, grid, block, wsh + rsh, s, a, wsh > 0 ? 1 : 0,
+                           rsh > 0 ? static_cast<int>(wsh) : -1);
+    }
     return hipGetLastError();
 }
 
@@ -743,11 +816,16 @@ int head_loss_partial_width(int A) { return A + 8; }
 
 hipError_t launch_head_loss(Precision prec, const HeadLossArgs &a, hipStream_t s) {
     const dim3 grid(head_loss_blocks(a.M)), block(kHeadThreads);
-    const size_t shm = head_weight_lds(a.A, a.Hl);
-    if (prec == kBF16)
-        hipLaunchKernelGGL(head_loss_kernel<uint16_t>, grid, block, shm, s, a, shm > 0 ? 1 : 0);
-    else
-        hipLaunchKernelGGL(head_loss_kernel<float>, grid, block, shm, s, a, shm > 0 ? 1 : 0);
+    const size_t wsh = head_weight_lds(a.A, a.Hl);
+    if (prec == kBF16) {
+        const size_t rsh = head_rows_lds<uint16_t>(kLossRows, a.Hl, wsh);
+        hipLaunchKernelGGL(head_loss_kernel<uint16_t>, grid, block, wsh + rsh, s, a, wsh > 0 ? 1 : 0,
+                           rsh > 0 ? static_cast<int>(wsh) : -1);
+    } else {
+        const size_t rsh = head_rows_lds<float>(kLossRows, a.Hl, wsh);
+        hipLaunchKernelGGL(head_loss_kernel<float>, grid, block, wsh + rsh, s, a, wsh > 0 ? 1 : 0,
+                           rsh > 0 ? static_cast<int>(wsh) : -1);
+    }
     return hipGetLastError();
 }
 
