@@ -1405,23 +1405,78 @@ std::vector<GemmArgs> batched_dw_launches(const std::vector<DwPlan> &plans, int 
     return out;
 }
 
+// Side streams for the per-run kernels of a batched step: the runs' small
+// launches (gather, loss, reduction, Adam) are independent of each other, so
+// they fork from the caller's stream onto these streams and join back
+// before the next grouped GEMM launch.  Captured into the epoch's graph they
+// become parallel branches.  Default priority, library-owned, per device.
+constexpr int kSideStreams = 4;
+struct SideStreams {
+    int dev = -1;
+    hipStream_t st[kSideStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSideStreams] = {};
+};
+
+int ensure_side_streams(SideStreams &ss, int dev) {
+    if (ss.dev == dev) return PPO_OK;
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (ss.st[i]) (void)hipStreamDestroy(ss.st[i]);
+        if (ss.join[i]) (void)hipEventDestroy(ss.join[i]);
+        ss.st[i] = nullptr;
+        ss.join[i] = nullptr;
+    }
+    if (ss.fork) (void)hipEventDestroy(ss.fork);
+    ss.fork = nullptr;
+    ss.dev = -1;
+    for (int i = 0; i < kSideStreams; ++i) {
+        PPO_HIP(hipStreamCreateWithFlags(&ss.st[i], hipStreamNonBlocking), "hipStreamCreate (side)");
+        PPO_HIP(hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming), "hipEventCreate");
+    }
+    PPO_HIP(hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming), "hipEventCreate");
+    ss.dev = dev;
+    return PPO_OK;
+}
+
+hipError_t fork_to(const SideStreams &ss, hipStream_t s, int n) {
+    hipError_t e = hipEventRecord(ss.fork, s);
+    for (int i = 0; i < n && e == hipSuccess; ++i) e = hipStreamWaitEvent(ss.st[i], ss.fork, 0);
+    return e;
+}
+
+hipError_t join_from(const SideStreams &ss, hipStream_t s, int n) {
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        e = hipEventRecord(ss.join[i], ss.st[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ss.join[i], 0);
+    }
+    return e;
+}
+
 // Step k of every run: per-run gathers, then one grouped launch per GEMM
-// site covering all runs, per-run loss, reduce and Adam kernels.
+// site covering all runs, per-run loss, reduce and Adam kernels (on side
+// streams when given).
 hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams *hp, int k,
-                                const BatchedTuning &bt, hipStream_t s) {
+                                const BatchedTuning &bt, hipStream_t s, const SideStreams *side) {
     const int R = static_cast<int>(runs.size());
     const NetLayout &g0 = runs[0].c->g;
     const Precision prec = runs[0].c->prec;
     const int bk = gemm_bk(prec);
     const int L = g0.L;
+    const int n_side = side ? std::min(R, kSideStreams) : 0;
+    auto run_stream = [&](int i) { return n_side > 0 ? side->st[i % n_side] : s; };
     hipError_t e;
-    for (BatchedRun &r : runs) {
+    if (n_side > 0 && (e = fork_to(*side, s, n_side)) != hipSuccess) return e;
+    for (int i = 0; i < R; ++i) {
+        BatchedRun &r = runs[i];
         const int32_t *idx = r.perm + static_cast<long long>(k) * r.M;
-        e = launch_stage_weights(prec, build_stage(r.c, r.p, r.w, r.ws, true), s);
+        e = launch_stage_weights(prec, build_stage(r.c, r.p, r.w, r.ws, true), run_stream(i));
         if (e != hipSuccess) return e;
-        e = launch_gather_obs(prec, s, r.b->obs, idx, r.b->B, r.M, r.c->g.D, r.w.kpad, wsp(r.ws, r.w.xg));
+        e = launch_gather_obs(prec, run_stream(i), r.b->obs, idx, r.b->B, r.M, r.c->g.D, r.w.kpad,
+                              wsp(r.ws, r.w.xg));
         if (e != hipSuccess) return e;
     }
+    if (n_side > 0 && (e = join_from(*side, s, n_side)) != hipSuccess) return e;
     for (int l = 0; l < L; ++l) {
         std::vector<GemmArgs> launches;
         for (BatchedRun &r : runs)
@@ -1431,12 +1486,15 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
             if (e != hipSuccess) return e;
         }
     }
-    for (BatchedRun &r : runs) {
+    if (n_side > 0 && (e = fork_to(*side, s, n_side)) != hipSuccess) return e;
+    for (int i = 0; i < R; ++i) {
+        BatchedRun &r = runs[i];
         const HeadLossArgs hl = head_loss_args(r.c, r.p, hp, r.w, r.ws, r.b, r.perm + static_cast<long long>(k) * r.M,
                                                r.M);
-        e = launch_head_loss(prec, hl, s);
+        e = launch_head_loss(prec, hl, run_stream(i));
         if (e != hipSuccess) return e;
     }
+    if (n_side > 0 && (e = join_from(*side, s, n_side)) != hipSuccess) return e;
     for (int l = L - 1; l >= 1; --l) {
         std::vector<GemmArgs> launches;
         for (BatchedRun &r : runs)
@@ -1458,16 +1516,18 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
         e = launch_gemm(prec, 1, 1, kEpiPartial, a, s);
         if (e != hipSuccess) return e;
     }
+    if (n_side > 0 && (e = fork_to(*side, s, n_side)) != hipSuccess) return e;
     for (int i = 0; i < R; ++i) {
         BatchedRun &r = runs[i];
         ReduceArgs &red = plans[i].red;
         set_reduce_loss(red, r.c, r.p, hp, r.w, r.ws, r.p->grad, r.M, 1);
-        e = launch_grad_reduce(red, s);
+        e = launch_grad_reduce(red, run_stream(i));
         if (e != hipSuccess) return e;
         const AdamArgs ad = adam_args(r.c, r.p, hp, red, r.p->grad, r.stats + k * PPO_STATS_WIDTH, r.M, k, 1);
-        e = launch_adam(ad, s);
+        e = launch_adam(ad, run_stream(i));
         if (e != hipSuccess) return e;
     }
+    if (n_side > 0 && (e = join_from(*side, s, n_side)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -1569,6 +1629,7 @@ std::map<std::vector<uint64_t>, hipGraphExec_t> g_batched_graphs;
 std::vector<std::vector<uint64_t>> g_batched_order;
 hipStream_t g_batched_capture = nullptr;
 int g_batched_dev = -1;
+SideStreams g_side;
 
 }  // namespace
 
@@ -1617,7 +1678,7 @@ int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_
     }
     auto enqueue_all = [&](hipStream_t target) -> hipError_t {
         for (int k = 0; k < n_minibatches; ++k) {
-            hipError_t e = enqueue_batched_step(runs, hp, k, bt, target);
+            hipError_t e = enqueue_batched_step(runs, hp, k, bt, target, R > 1 ? &g_side : nullptr);
             if (e != hipSuccess) return e;
         }
         for (int i = 0; i < R; ++i) {
@@ -1626,6 +1687,10 @@ int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_
         }
         return hipSuccess;
     };
+    std::lock_guard<std::mutex> lk(g_batched_mu);
+    int dev = 0;
+    PPO_HIP(hipGetDevice(&dev), "hipGetDevice");
+    PPO_CHECK(ensure_side_streams(g_side, dev));
     if (!hp->use_graph) {
         PPO_HIP(enqueue_all(s), "update_batched");
         return PPO_OK;
@@ -1645,9 +1710,6 @@ int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_
                            u64(ws[i])})
             key.push_back(v);
     }
-    std::lock_guard<std::mutex> lk(g_batched_mu);
-    int dev = 0;
-    PPO_HIP(hipGetDevice(&dev), "hipGetDevice");
     if (g_batched_capture && g_batched_dev != dev) {
         for (auto &kv : g_batched_graphs) (void)hipGraphExecDestroy(kv.second);
         g_batched_graphs.clear();
