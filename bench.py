@@ -169,7 +169,18 @@ def phase_model(cfg, precision, P):
             + M * kpad * e + M * sum(H) * e * 2                 # layer inputs
             + 4 * P)                                            # the gradient
     head_b = M * H[-1] * e * 2 * 2 + M * 16 * e * 2 + M * 4 * (A + 5)
+    head_f = M * H[-1] * (A + 1) * 4.0
+    # the fused per-sample pass (bf16): the forward, output-layer and
+    # input-gradient arithmetic of both networks; it reads the observation
+    # rows, the loss inputs and every weight once, and writes only the
+    # weight-gradient operands (gathered inputs, activations, pre-activation
+    # and output gradients) and the loss partials
+    fused_b = (M * D * 4.0 + M * 4.0 + M * 4.0 * (A + 4)
+               + M * kpad * e + M * sum(H) * e * 2 * 2 + M * 16 * e * 2
+               + sum(H[l] * ins_pad[l] * e + H[l] * 4 for l in range(L)) * 2
+               + sum(H[l] * H[l - 1] * e for l in range(1, L)) * 2)
     return {
+        "fused": (fwd_f + dx_f + head_f, fused_b),
         "forward": (fwd_f, fwd_b),
         "input_grad": (dx_f, dx_b),
         "weight_grad": (dw_f, dw_b),
@@ -181,35 +192,41 @@ def phase_model(cfg, precision, P):
 
 
 def recorded_traffic(wl, phase, workload):
-    """HBM bytes per launch of the forward or input-gradient phase, from the
-    committed rocprofv3 counter summary (per kernel and grid, at the tiles
+    """HBM bytes per launch of the fused, forward or input-gradient phase, from
+    the committed rocprofv3 counter summary (per kernel and grid, at the tiles
     this run chose), or None when the summary is missing, lacks one of those
-    launches, or was taken on another version of the GEMM source."""
+    launches, or was taken on another version of the kernel's source."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", f"traffic_{workload}.txt")
-    src = os.path.join(here, "paper_2109_11978_amd", "csrc", "k_gemm.hip")
-    if phase not in ("forward", "input_grad") or not os.path.exists(path):
+    if phase not in ("fused", "forward", "input_grad") or not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.rsplit(":", 1)
             fields[k.strip()] = v.strip()
-    if fields.get("k_gemm_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    src_name = "k_fused.hip" if phase == "fused" else "k_gemm.hip"
+    src = os.path.join(here, "paper_2109_11978_amd", "csrc", src_name)
+    sha_key = src_name.replace(".hip", "_sha256")
+    if fields.get(sha_key) != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
     cfg = wl.cfg
     M, H = cfg.minibatch, list(cfg.net.hidden)
-    tiles = wl.ctx.tuning(M, True)
     keys = []
-    if phase == "forward":
-        sites = [(tiles[f"forward_{l + 1}"], H[l], 0) for l in range(len(H))]
+    if phase == "fused":
+        rows = 64 if max(H) <= 512 else 32
+        keys.append(f"hbm_bytes.fused_update_kernel<{rows}>.{2 * -(-M // rows)}")
     else:
-        sites = [(tiles[f"input_grad_{l + 1}"], H[l - 1], 1) for l in range(len(H) - 1, 0, -1)]
-    for tile, cols, epi in sites:
-        bm, bn = (int(x) for x in tile.split("x"))
-        grid = -(-M // bm) * -(-cols // bn) * 2
-        keys.append(f"hbm_bytes.gemm_kernel<bf16,{bm},{bn},0,0,{epi},true>.{grid}")
+        tiles = wl.ctx.tuning(M, True)
+        if phase == "forward":
+            sites = [(tiles[f"forward_{l + 1}"], H[l], 0) for l in range(len(H))]
+        else:
+            sites = [(tiles[f"input_grad_{l + 1}"], H[l - 1], 1) for l in range(len(H) - 1, 0, -1)]
+        for tile, cols, epi in sites:
+            bm, bn = (int(x) for x in tile.split("x"))
+            grid = -(-M // bm) * -(-cols // bn) * 2
+            keys.append(f"hbm_bytes.gemm_kernel<bf16,{bm},{bn},0,0,{epi},true>.{grid}")
     vals = [fields.get(k) for k in keys]
     if any(v is None for v in vals):
         return None

@@ -42,6 +42,15 @@
  *     host synchronisation outside ctx create/destroy); the choice is cached
  *     in the context, and in the file named by the environment variable
  *     PPO_TUNE_CACHE if set.  PPO_AUTOTUNE=0 keeps 128 x 128 tiles.
+ *   - bf16 update steps of networks whose hidden widths are 128, 256, 512 or
+ *     1024 (input width a multiple of 16) run everything that is independent
+ *     per sample (gather, hidden layers, output layers with the loss,
+ *     input-gradient chain) as one fused launch with the activations in LDS,
+ *     then the split-sample weight-gradient GEMMs; other shapes, and the fp32
+ *     path, run the layer-by-layer kernels.  The results agree to float32
+ *     rounding (bf16 ulps downstream of it).  PPO_FUSED=0 forces the
+ *     layer-by-layer kernels; PPO_FUSED_ROWS=32 or 64 overrides the fused
+ *     pass's samples per workgroup.
  */
 #ifndef PPO_MI355X_PPO_H
 #define PPO_MI355X_PPO_H
@@ -258,7 +267,11 @@ int ppo_loss_grad(const ppo_ctx *ctx, void *stream, const ppo_params *p, const p
 #define PPO_PHASE_WEIGHT_GRAD  4  /* split-sample weight-gradient GEMMs         */
 #define PPO_PHASE_GRAD_REDUCE  5  /* split sums, flat gradient, float64 norm^2  */
 #define PPO_PHASE_ADAM         6  /* clip coefficient + Adam + bf16 shadow      */
-#define PPO_N_PHASES           7
+#define PPO_PHASE_FUSED        7  /* bf16: gather, forward, loss and input
+                                     gradients of both networks in one launch
+                                     (replaces phases 0-3 except the weight
+                                     staging, which stays in phase 0)         */
+#define PPO_N_PHASES           8
 
 /* Same computation as ppo_update_epoch, launched eagerly with a HIP event
  * pair recorded on `stream` around every kernel launch.  Launches that only

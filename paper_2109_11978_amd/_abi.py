@@ -17,7 +17,7 @@ PPO_FP32 = 0
 PPO_BF16 = 1
 PPO_MAX_HIDDEN = 4
 PPO_STATS_WIDTH = 10
-PHASES = ("gather", "forward", "head_loss", "input_grad", "weight_grad", "grad_reduce", "adam")
+PHASES = ("gather", "forward", "head_loss", "input_grad", "weight_grad", "grad_reduce", "adam", "fused")
 
 ERROR_NAMES = {
     PPO_E_INVAL: "PPO_E_INVAL", PPO_E_SHAPE: "PPO_E_SHAPE", PPO_E_UNSUPPORTED: "PPO_E_UNSUPPORTED",

@@ -89,6 +89,73 @@ template <> struct GemmTile<float> { static constexpr int BK = 32; };
 hipError_t launch_gemm(Precision prec, int a_mode, int b_mode, int epi, const GemmArgs &args,
                        hipStream_t stream);
 
+// ------------------------------------------------ fused per-sample pass ---
+// One launch per bf16 mini-batch step for everything independent per
+// sample: the gather of the observation rows, every hidden layer, the output
+// layers with the PPO loss and their gradients, and the input-gradient chain.
+// Its outputs are exactly the operands of the weight-gradient GEMMs and the
+// loss partials of the head kernel.
+constexpr int kFusedThreads = 256;
+constexpr int kFusedMaxAct = 16;
+
+// Weights of the fused pass in MFMA A-fragment order (pack_frags): for a
+// matrix with `rows` output features (a multiple of 32) and K inputs, S =
+// ceil(K / 16) k-steps; fragment (fb, s) is 64 lanes x 8 bf16 at element
+// ((fb * S + s) * 64) * 8, lane l holding row 32 fb + l % 32 and inputs
+// 16 s + 8 (l / 32) .. + 7 (zero past K).
+struct FragJob {
+    const uint16_t *src;   // row-major bf16 W [out][in] with row pitch ld
+    uint16_t *dst;
+    int rows, K, S, ld;
+    int transpose;         // 1: pack W^T (rows = in, K = out)
+    int begin;             // first lane chunk of this job
+};
+constexpr int kMaxFragJobs = 16;
+struct FragArgs {
+    FragJob job[kMaxFragJobs];
+    int count;
+    int total;             // lane chunks (8 elements each)
+};
+void add_frag_job(FragArgs &a, const FragJob &j);
+hipError_t launch_pack_frags(const FragArgs &a, hipStream_t s);
+
+struct FusedNet {
+    const uint16_t *W[kMaxHidden];    // layer l weights, fragment order, K = kpad for l = 0
+    const uint16_t *WT[kMaxHidden];   // W_l^T, fragment order ([H_{l-1}] x H_l), l >= 1
+    const float *bias[kMaxHidden];    // [H_l], 16-byte aligned
+    const float *Wout, *bout;         // output layer (float32) [n_out][H_{L-1}], [n_out]
+    uint16_t *h[kMaxHidden];          // [M][H_l] activations
+    uint16_t *dz[kMaxHidden];         // [M][H_l] gradients wrt the pre-activations
+    uint16_t *dzh;                    // [M][kHeadPad] gradient wrt the output layer
+};
+
+struct FusedArgs {
+    FusedNet net[2];                  // actor, critic (n_out = A, 1)
+    int L, D, kpad, A;
+    int H[kMaxHidden];
+    const float *obs;                 // [B][D]
+    const int32_t *idx;               // [M] rows of the batch (clamped to [0, B)), or null
+    int B, M;
+    const float *actions, *logp_old, *adv, *returns, *values_old, *mu_old, *logstd_old, *logstd;
+    uint16_t *xg;                     // [M][kpad] gathered inputs (written by the actor blocks)
+    float *partials;                  // [blocks][A + 8], the layout of HeadLossArgs::partials
+    float clip, value_coef, inv_m;
+    int clip_value;
+    int R;                            // samples per workgroup (fused_rows)
+    // filled in by launch_fused_update
+    int blocks;
+    int lds_region[kMaxHidden], lds_x, lds_w, lds_sum, lds_in, lds_rows, lds_bias, lds_head;
+    int bias_off[kMaxHidden];         // floats into the staged biases
+};
+// Samples per workgroup for this network shape (64 or 32), 0 when the fused
+// pass does not apply (hidden widths not 128, 256, 512 or 1024, input width
+// not a multiple of 16, or the activations do not fit in LDS).
+// prefer = 32 or 64 picks that block size where it applies (0: the default,
+// 32 rows when two workgroups then share a CU, else 64).
+int fused_rows(int L, const int *H, int kpad, int A, int prefer = 0);
+int fused_blocks(int M, int R);
+hipError_t launch_fused_update(FusedArgs a, hipStream_t s);
+
 // -------------------------------------------------------- other kernels ---
 hipError_t launch_philox_blocks(hipStream_t s, uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
                                 uint32_t c3, long long n, uint32_t *out);

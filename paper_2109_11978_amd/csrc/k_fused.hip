@@ -1,0 +1,788 @@
+// Fused per-sample pass of the bf16 PPO update for gfx950 (CDNA4).
+//
+// Everything in a mini-batch step that is independent per sample runs in
+// one launch: one workgroup takes R samples of one network (actor or critic)
+// through the gather of their observation rows, every hidden layer
+// (z = h W^T + b, h = ELU(z)), the output layer with the PPO loss of Sec. 3
+// and App. A (clipped surrogate, value loss, log-std gradient, KL statistic),
+// and the input-gradient chain dz_{l-1} = (dz_l W_l) * ELU'(z_{l-1}) back to
+// the first hidden layer.  The activations of all layers stay in LDS for the
+// whole pass; what leaves the chip is only what the split-sample weight
+// gradients read (gathered inputs, hidden activations, pre-activation and
+// output gradients), in the layouts of the layer-by-layer path, each written
+// once with coalesced 16-byte stores.
+//
+// MFMA layout: every layer is computed transposed, C[feature][sample] =
+// W[feature, :] . act[sample, :], with v_mfma_f32_32x32x16_bf16.  The weights
+// are the A operand (lane l: feature row l % 32, k = 8 (l / 32) .. + 7, one
+// 16-byte buffer load from the row-major weight matrix), the activations the
+// B operand (lane l: sample l % 32, the same 8 k, one 16-byte LDS read).  A
+// lane's accumulators then hold, per group of four registers, 4 consecutive
+// features of one sample: one 8-byte LDS write each.  The four waves split
+// the output features and each covers all R samples, so every weight element
+// is read from L2 once per workgroup; PF k-steps of weight fragments are in
+// flight ahead of the MFMAs.
+#include "common.hpp"
+
+namespace ppo {
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kWaves = kFusedThreads / 64;
+constexpr int kOutside = 0x7FFFFFF0;   // buffer offset past any resource: loads read zero
+constexpr int kMaxLdsBytes = 160 * 1024;
+constexpr float kLog2Pi = 1.8378770664093453f;
+// per-sample loss terms: policy, value, clipped, ratio-KL, mean-shift KL,
+// log-std gradient [kFusedMaxAct]
+constexpr int kSums = 5 + kFusedMaxAct;
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, long long bytes) {
+    const int n = bytes > 0x7FFFFFFFLL ? 0x7FFFFFFF : static_cast<int>(bytes < 0 ? 0 : bytes);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), static_cast<short>(0), n, 0x00020000);
+}
+
+__device__ inline uint32_t bf16_bits(float v) {
+    return __builtin_bit_cast(uint16_t, static_cast<__bf16>(v));
+}
+__device__ inline uint32_t pack2(float lo, float hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
+__device__ inline float lo_f(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float hi_f(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+// ELU and its derivative recovered from the activation h = ELU(z), with the
+// values of the layer-by-layer GEMM epilogues in fewer instructions:
+// e^z - 1 >= z everywhere and both sides share the sign of z, so ELU(z) is the
+// median of (e^z - 1, z, 0); ELU'(z) is 1 for h > 0 and h + 1 = e^z otherwise,
+// i.e. min(h + 1, 1).
+__device__ inline float elu(float v) { return __builtin_amdgcn_fmed3f(__expf(v) - 1.0f, v, 0.0f); }
+__device__ inline float delu(float h) { return fminf(h + 1.0f, 1.0f); }
+
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// acc[f][j] = sum_k W[f0 + 32 f + (l % 32), k] * act[32 j + (l % 32), k] over
+// K = 16 S in k-steps of 16.  W is stored in MFMA fragment order (see
+// pack_frags_kernel): the A fragment of feature block fb at k-step s is 1 KB
+// at ((fb * S + s) * 64 + lane) * 16 bytes, so each load instruction reads
+// one contiguous kilobyte.  act: LDS rows of `pitch` elements.  Weight
+// fragments are loaded PF k-steps ahead and activation fragments one step
+// ahead; scheduling barriers keep every step's loads behind its MFMAs, so
+// the loads retire in issue order and each step waits only for its own
+// fragments.  The loop runs whole groups of PF steps; steps past K multiply
+// zero weight fragments (loaded from outside the buffer) with a clamped,
+// finite activation fragment.
+template <int FBW, int SB, int PF>
+__device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16_t *W, int rows_w, int S, int f0,
+                                 const uint16_t *act, int pitch, int lane) {
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(W, static_cast<long long>(rows_w / 32) * S * 1024);
+    const int kh = (lane >> 5) * 8;
+    // per-block lane offsets in VGPRs, one scalar step offset per load
+    int vo[FBW];
+#pragma unroll
+    for (int f = 0; f < FBW; ++f) vo[f] = (f0 / 32 + f) * S * 1024 + lane * 16;
+    const uint16_t *bp = act + (lane & 31) * pitch + kh;
+#pragma unroll
+    for (int f = 0; f < FBW; ++f)
+#pragma unroll
+        for (int j = 0; j < SB; ++j) acc[f][j] = floatx16{};
+    u32x4 w[PF][FBW];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+        const int so = __builtin_amdgcn_readfirstlane(p * 1024);
+#pragma unroll
+        for (int f = 0; f < FBW; ++f)
+            w[p][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, p < S ? vo[f] : kOutside, so, 0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    u32x4 b[SB];
+#pragma unroll
+    for (int j = 0; j < SB; ++j) b[j] = *reinterpret_cast<const u32x4 *>(bp + 32 * j * pitch);
+    for (int s0 = 0; s0 < S; s0 += PF) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int s = s0 + u;
+            const int s1 = s + 1 < S ? s + 1 : S - 1;
+            u32x4 bn[SB];
+#pragma unroll
+            for (int j = 0; j < SB; ++j) bn[j] = *reinterpret_cast<const u32x4 *>(bp + 32 * j * pitch + 16 * s1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int f = 0; f < FBW; ++f)
+#pragma unroll
+                for (int j = 0; j < SB; ++j)
+                    acc[f][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, w[u][f]),
+                                                                      __builtin_bit_cast(bf16x8_t, b[j]), acc[f][j],
+                                                                      0, 0, 0);
+            const int sn = s + PF;
+            const int so = __builtin_amdgcn_readfirstlane(sn * 1024);
+#pragma unroll
+            for (int f = 0; f < FBW; ++f)
+                w[u][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, sn < S ? vo[f] : kOutside, so, 0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < SB; ++j) b[j] = bn[j];
+        }
+    }
+}
+
+// Forward epilogue: out[sample][feature] = bf16(ELU(acc + bias)).
+template <int FBW, int SB>
+__device__ __forceinline__ void epi_forward(const floatx16 (&acc)[FBW][SB], const float *bias, int f0, uint16_t *out,
+                                   int pitch, int lane) {
+    const int h4 = (lane >> 5) * 4;
+    const int i0 = lane & 31;
+#pragma unroll
+    for (int f = 0; f < FBW; ++f)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int fr = f0 + 32 * f + 8 * g + h4;
+            const float4 b = *reinterpret_cast<const float4 *>(bias + fr);
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                const float v0 = elu(acc[f][j][4 * g + 0] + b.x);
+                const float v1 = elu(acc[f][j][4 * g + 1] + b.y);
+                const float v2 = elu(acc[f][j][4 * g + 2] + b.z);
+                const float v3 = elu(acc[f][j][4 * g + 3] + b.w);
+                *reinterpret_cast<u32x2 *>(out + (i0 + 32 * j) * pitch + fr) = u32x2{pack2(v0, v1), pack2(v2, v3)};
+            }
+        }
+}
+
+// Backward epilogue, in place: hz holds h_{l-1}[sample][feature] on entry and
+// dz_{l-1} = bf16(acc * ELU'(h_{l-1})) on exit.  Each element is read and
+// written by the same lane.
+template <int FBW, int SB>
+__device__ __forceinline__ void epi_backward(const floatx16 (&acc)[FBW][SB], int f0, uint16_t *hz, int pitch, int lane) {
+    const int h4 = (lane >> 5) * 4;
+    const int i0 = lane & 31;
+#pragma unroll
+    for (int f = 0; f < FBW; ++f)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int fr = f0 + 32 * f + 8 * g + h4;
+#pragma unroll
+            for (int j = 0; j < SB; ++j) {
+                u32x2 *p = reinterpret_cast<u32x2 *>(hz + (i0 + 32 * j) * pitch + fr);
+                const u32x2 h = *p;
+                const float v0 = acc[f][j][4 * g + 0] * delu(lo_f(h.x));
+                const float v1 = acc[f][j][4 * g + 1] * delu(hi_f(h.x));
+                const float v2 = acc[f][j][4 * g + 2] * delu(lo_f(h.y));
+                const float v3 = acc[f][j][4 * g + 3] * delu(hi_f(h.y));
+                *p = u32x2{pack2(v0, v1), pack2(v2, v3)};
+            }
+        }
+}
+
+template <int FBW, int SB, int PF, bool BWD>
+__device__ __forceinline__ void layer_impl(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
+                                  int in_pitch, uint16_t *out, int out_pitch, int wave, int lane) {
+    const int f0 = wave * FBW * 32;
+    floatx16 acc[FBW][SB];
+    mma_layer<FBW, SB, PF>(acc, W, nout, K >> 4, f0, in, in_pitch, lane);
+    if constexpr (BWD)
+        epi_backward<FBW, SB>(acc, f0, out, out_pitch, lane);
+    else
+        epi_forward<FBW, SB>(acc, bias, f0, out, out_pitch, lane);
+}
+
+// One layer for all R samples of the block: nout output features (a multiple
+// of 128) split over the four waves.  Weight fragments in flight per lane:
+// PF k-steps x FBW blocks, up to 32, with PF no larger than the layer's
+// k-step count S (K / 16) rounded up to a power of two (S is a power of two
+// for hidden layers; a first layer of 3 or 15 steps takes PF = 4).
+template <int FBW, int SB, bool BWD, int PFMAX>
+__device__ __forceinline__ void layer_pf(int S, const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
+                                int in_pitch, uint16_t *out, int out_pitch, int wave, int lane) {
+    if (PFMAX >= 32 && S >= 32)
+        layer_impl<FBW, SB, (PFMAX >= 32 ? 32 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane);
+    else if (PFMAX >= 16 && S >= 16)
+        layer_impl<FBW, SB, (PFMAX >= 16 ? 16 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane);
+    else if (PFMAX >= 8 && S >= 8)
+        layer_impl<FBW, SB, (PFMAX >= 8 ? 8 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane);
+    else
+        layer_impl<FBW, SB, 4, BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane);
+}
+
+template <int R, int OCC, bool BWD>
+__device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
+                                 int in_pitch, uint16_t *out, int out_pitch, int wave, int lane) {
+    constexpr int SB = R / 32;
+    const int S = K >> 4;
+    switch (nout / (32 * kWaves)) {
+    case 1: layer_pf<1, SB, BWD, 32>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane); break;
+    case 2: layer_pf<2, SB, BWD, 16>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane); break;
+    case 4: layer_pf<4, SB, BWD, 8>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane); break;
+    default:
+        if constexpr (SB == 1 && OCC == 1)
+            layer_pf<8, 1, BWD, 4>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane);
+        break;
+    }
+}
+
+// rows x cols bf16 from LDS (row pitch `pitch`) to global rows of `ld`
+// elements; cols is a multiple of 8 and at most 8 * kFusedThreads.  Each
+// thread keeps one 16-byte column chunk and strides over the rows; four LDS
+// reads go out before their stores, and stores past the last row fall
+// outside the buffer and are dropped.
+__device__ inline void copy_out(const uint16_t *src, int pitch, uint16_t *dst, int ld, int cols, int rows) {
+    constexpr int U = 4;
+    const int cpr = cols >> 3;
+    const int rpp = kFusedThreads / cpr;   // rows per pass
+    const int r0 = threadIdx.x / cpr;
+    const int c = (threadIdx.x - r0 * cpr) * 8;
+    if (r0 >= rpp) return;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(dst, static_cast<long long>(rows) * ld * 2);
+    for (int i0 = r0; i0 < rows; i0 += U * rpp) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = min(i0 + u * rpp, rows - 1);
+            v[u] = *reinterpret_cast<const u32x4 *>(src + i * pitch + c);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * rpp;
+            __builtin_amdgcn_raw_buffer_store_b128(v[u], rs, i < rows ? (i * ld + c) * 2 : kOutside, 0, 0);
+        }
+    }
+}
+
+// Observation rows of the block (batch rows s_rows[0 .. R)) as bf16 into
+// LDS, zero-padded to kpad columns and zero past the last valid row.  Each
+// wave takes every fourth row; a row's elements are spread over the lanes
+// (coalesced), and sixteen buffer loads are in flight per lane (out-of-range
+// ones read zero).
+template <int R>
+__device__ inline void gather_rows(const FusedArgs &a, const int *s_rows, int rows, uint16_t *x, int pitch,
+                                   int wave, int lane) {
+    constexpr int U = 16;
+    constexpr int PER_WAVE = R / kWaves;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.obs, static_cast<long long>(a.B) * a.D * 4);
+    const int cpr = (a.kpad + 63) >> 6;     // 64-element chunks per row
+    const int total = PER_WAVE * cpr;       // loads per lane
+    for (int t0 = 0; t0 < total; t0 += U) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = min(t0 + u, total - 1);
+            const int il = t / cpr;
+            const int k = 64 * (t - il * cpr) + lane;
+            const int i = wave + kWaves * il;
+            const bool ok = t0 + u < total && i < rows && k < a.D;
+            const int row = __builtin_amdgcn_readfirstlane(s_rows[i]);
+            v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, ok ? k * 4 : kOutside, row * a.D * 4, 0));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u;
+            const int il = t / cpr;
+            const int k = 64 * (t - il * cpr) + lane;
+            const int i = wave + kWaves * il;
+            if (t < total && k < a.kpad) x[i * pitch + k] = static_cast<uint16_t>(bf16_bits(v[u]));
+        }
+    }
+}
+
+// Sum over the KP adjacent lanes of a sample (KP = 4 or 8) with DPP lane
+// swaps: xor 1 and xor 2 inside each quad, then the two quads of an 8-lane
+// row half exchanged by the half-row mirror.  Every lane ends with the same
+// value (each step adds a value and its partner's in commuted order).
+template <int KP>
+__device__ inline float kpart_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));   // quad [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad [2,3,0,1]
+    if constexpr (KP == 8)
+        v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));  // half mirror
+    return v;
+}
+
+template <int R, int OCC>
+__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
+void fused_update_kernel(const FusedArgs a) {
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    constexpr int KP = kFusedThreads / R;  // k-parts per sample in the output layer
+    const int net = blockIdx.x & 1;
+    const int m0 = (blockIdx.x >> 1) * R;
+    const int rows = min(R, a.M - m0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int L = a.L, A = a.A;
+    const int Hl = a.H[L - 1];
+    const int n_out = net == 0 ? A : 1;
+    const int WP = Hl + 4;                 // row pitch of the staged output-layer weights
+    float *w_out = reinterpret_cast<float *>(lds + a.lds_w);
+    float *s_sum = reinterpret_cast<float *>(lds + a.lds_sum);    // [R][kSums] per-sample loss terms
+    float *s_in = reinterpret_cast<float *>(lds + a.lds_in);      // [R][2 A + 4] per-sample loss inputs
+    float *s_bias = reinterpret_cast<float *>(lds + a.lds_bias);  // hidden-layer biases
+    int *s_rows = reinterpret_cast<int *>(lds + a.lds_rows);      // [R] batch rows of the block
+    const FusedNet &N = a.net[net];
+    const int IW = 2 * A + 4;
+
+    // ------------------------------------------------------- prologue
+    // batch rows of the block (rows past the end repeat the last one; their
+    // results are discarded), then every global input of the block in one
+    // round of loads: observations, loss inputs, output-layer weights and
+    // hidden biases
+    if (tid < R) {
+        int r = m0 + min(tid, rows - 1);
+        if (a.idx) r = min(max(a.idx[r], 0), a.B - 1);
+        s_rows[tid] = r;
+    }
+    float *s_head = reinterpret_cast<float *>(lds + a.lds_head);  // output biases [n_out], log-std [A]
+    {
+        // every float input of the block in one round of buffer loads (out of
+        // range ones read zero), then the LDS stores: output-layer weights
+        // (pitch WP), output biases, log-std, hidden-layer biases
+        constexpr int UW = 16, UB = 4;
+        const int nw = n_out * Hl;
+        const __amdgpu_buffer_rsrc_t rw = make_rsrc(N.Wout, static_cast<long long>(nw) * 4);
+        float vw[UW], vb[kMaxHidden][UB];
+#pragma unroll
+        for (int u = 0; u < UW; ++u) {
+            const int q = tid + u * kFusedThreads;
+            vw[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, q < nw ? q * 4 : kOutside, 0, 0));
+        }
+#pragma unroll
+        for (int l = 0; l < kMaxHidden; ++l) {
+            const int H = l < L ? a.H[l] : 0;
+            const __amdgpu_buffer_rsrc_t rb = make_rsrc(N.bias[l], static_cast<long long>(H) * 4);
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int q = tid + u * kFusedThreads;
+                vb[l][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, q < H ? q * 4 : kOutside, 0, 0));
+            }
+        }
+        const __amdgpu_buffer_rsrc_t ro = make_rsrc(N.bout, static_cast<long long>(n_out) * 4);
+        const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.logstd, static_cast<long long>(A) * 4);
+        const float vo = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ro, tid < n_out ? tid * 4 : kOutside, 0, 0));
+        const float vl = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rl, tid < A ? tid * 4 : kOutside, 0, 0));
+#pragma unroll
+        for (int u = 0; u < UW; ++u) {
+            const int q = tid + u * kFusedThreads;
+            const int j = q / Hl;
+            if (q < nw) w_out[j * WP + (q - j * Hl)] = vw[u];
+        }
+#pragma unroll
+        for (int l = 0; l < kMaxHidden; ++l) {
+            if (l >= L) continue;
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int q = tid + u * kFusedThreads;
+                if (q < a.H[l]) s_bias[a.bias_off[l] + q] = vb[l][u];
+            }
+        }
+        if (tid < n_out) s_head[tid] = vo;
+        if (tid < A) s_head[kFusedMaxAct + tid] = vl;
+        // output layers wider than UW loads per thread (not the paper's shapes)
+        for (int q = tid + UW * kFusedThreads; q < nw; q += kFusedThreads) {
+            const int j = q / Hl;
+            w_out[j * WP + (q - j * Hl)] = N.Wout[q];
+        }
+    }
+    __syncthreads();
+    uint16_t *x = reinterpret_cast<uint16_t *>(lds + a.lds_x);
+    const int xp = a.kpad + 8;
+    {
+        // loss inputs: TPS threads per sample, columns part, part + TPS, ...
+        constexpr int TPS = kFusedThreads / R;
+        const int i = tid / TPS, part = tid - (tid / TPS) * TPS;
+        const long long row = s_rows[i];
+        float v[2 * (kFusedMaxAct / TPS) + 1];
+#pragma unroll
+        for (int u = 0; u < kFusedMaxAct / TPS; ++u) {
+            const int j = part + TPS * u;
+            v[2 * u] = net == 0 && j < A ? a.actions[row * A + j] : 0.0f;
+            v[2 * u + 1] = net == 0 && j < A && a.mu_old ? a.mu_old[row * A + j] : 0.0f;
+        }
+        const float *sc = part == 0 ? a.logp_old : part == 1 ? a.adv : part == 2 ? a.returns : a.values_old;
+        const bool want = part < 4 && (part < 2 ? net == 0 : net == 1) && (part != 3 || a.clip_value);
+        v[2 * (kFusedMaxAct / TPS)] = want ? sc[row] : 0.0f;
+        gather_rows<R>(a, s_rows, rows, x, xp, wave, lane);
+#pragma unroll
+        for (int u = 0; u < kFusedMaxAct / TPS; ++u) {
+            const int j = part + TPS * u;
+            if (j < A) {
+                s_in[i * IW + j] = v[2 * u];
+                s_in[i * IW + A + j] = v[2 * u + 1];
+            }
+        }
+        if (part < 4) s_in[i * IW + 2 * A + part] = v[2 * (kFusedMaxAct / TPS)];
+    }
+    __syncthreads();
+    if (net == 0) copy_out(x, xp, a.xg + static_cast<long long>(m0) * a.kpad, a.kpad, a.kpad, rows);
+
+    // --------------------------------------------------------- forward
+    const uint16_t *in = x;
+    int in_pitch = xp, K = a.kpad;
+    for (int l = 0; l < L; ++l) {
+        const int H = a.H[l];
+        uint16_t *out = reinterpret_cast<uint16_t *>(lds + a.lds_region[l]);
+        run_layer<R, OCC, false>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave, lane);
+        __syncthreads();
+        copy_out(out, H + 8, N.h[l] + static_cast<long long>(m0) * H, H, H, rows);
+        in = out;
+        in_pitch = H + 8;
+        K = H;
+    }
+
+    // ----------------------------------------- output layer and PPO loss
+    // KP adjacent lanes per sample, each with CK consecutive activations of
+    // the last hidden layer; partial dot products are combined with DPP lane
+    // swaps that leave the same value in every lane of the sample, so all of
+    // them compute the same loss terms and output gradients (the block sums
+    // take the first lane's).
+    uint16_t *hl = reinterpret_cast<uint16_t *>(lds + a.lds_region[L - 1]);
+    const int PL = Hl + 8;
+    const int si = tid / KP, kq = tid - (tid / KP) * KP;
+    const int CK = Hl / KP;               // activations per lane (multiple of 8, <= 64)
+    const int nck = CK >> 3;
+    const bool valid = si < rows;
+    const bool lead = valid && kq == 0;
+    const float *in_s = s_in + si * IW;
+    u32x4 hx[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (c < nck) hx[c] = *reinterpret_cast<const u32x4 *>(hl + si * PL + kq * CK + 8 * c);
+    float o[kFusedMaxAct];
+    {
+#pragma unroll
+        for (int j = 0; j < kFusedMaxAct; ++j) o[j] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (c >= nck) continue;
+            float xv[8];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                xv[2 * e] = lo_f(hx[c][e]);
+                xv[2 * e + 1] = hi_f(hx[c][e]);
+            }
+#pragma unroll
+            for (int j = 0; j < kFusedMaxAct; ++j) {
+                if (j >= n_out) continue;
+                const float *w = w_out + j * WP + kq * CK + 8 * c;
+                const float4 w0 = *reinterpret_cast<const float4 *>(w);
+                const float4 w1 = *reinterpret_cast<const float4 *>(w + 4);
+                o[j] += xv[0] * w0.x + xv[1] * w0.y + xv[2] * w0.z + xv[3] * w0.w + xv[4] * w1.x +
+                        xv[5] * w1.y + xv[6] * w1.z + xv[7] * w1.w;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kFusedMaxAct; ++j) {
+            if (j >= n_out) continue;
+            o[j] = kpart_sum<KP>(o[j]) + s_head[j];
+        }
+    }
+
+    float g[kFusedMaxAct];
+#pragma unroll
+    for (int j = 0; j < kFusedMaxAct; ++j) g[j] = 0.0f;
+    // per-sample loss terms: policy, value, clipped, ratio-KL, mean-shift KL, log-std gradient
+    float sums[kSums];
+#pragma unroll
+    for (int q = 0; q < kSums; ++q) sums[q] = 0.0f;
+    if (net == 0) {
+        // log-probability of the stored action in float64 (a sum of A terms of
+        // order 1 whose float32 rounding would dominate the ratio's error)
+        float z[kFusedMaxAct], inv_sig[kFusedMaxAct];
+        double logp = -0.5 * A * 1.8378770664093453;
+        float kl_mu = 0.0f;
+#pragma unroll
+        for (int j = 0; j < kFusedMaxAct; ++j) {
+            z[j] = 0.0f;
+            inv_sig[j] = 0.0f;
+            if (j >= A) continue;
+            const float ls = s_head[kFusedMaxAct + j];
+            const float inv_sigma = expf(-ls);
+            inv_sig[j] = inv_sigma;
+            z[j] = (in_s[j] - o[j]) * inv_sigma;
+            logp += -0.5 * static_cast<double>(z[j]) * z[j] - ls;
+            const float dm = (in_s[A + j] - o[j]) * inv_sigma;
+            kl_mu += 0.5f * dm * dm;
+        }
+        const float adv = in_s[2 * A + 1];
+        const float ratio = static_cast<float>(exp(logp - static_cast<double>(in_s[2 * A])));
+        const float lo = 1.0f - a.clip, hi = 1.0f + a.clip;
+        const bool active = adv >= 0.0f ? (ratio <= hi) : (ratio >= lo);
+        const float g_lp = valid && active ? -a.inv_m * adv * ratio : 0.0f;
+        if (lead) {
+            sums[0] = -fminf(ratio * adv, fminf(fmaxf(ratio, lo), hi) * adv);
+            sums[2] = fabsf(ratio - 1.0f) > a.clip ? 1.0f : 0.0f;
+            sums[3] = (ratio - 1.0f) - logf(ratio);
+            sums[4] = a.mu_old ? kl_mu : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < kFusedMaxAct; ++j) {
+            if (j >= A) continue;
+            g[j] = g_lp * z[j] * inv_sig[j];
+            if (lead) sums[5 + j] = g_lp * (z[j] * z[j] - 1.0f);
+        }
+    } else {
+        const float V = o[0];
+        const float ret = in_s[2 * A + 2], v_old = in_s[2 * A + 3];
+        const float diff = V - ret;
+        float pass = 1.0f, vl = diff * diff;
+        if (a.clip_value) {
+            const float vc = v_old + fminf(fmaxf(V - v_old, -a.clip), a.clip);
+            const float sqc = (vc - ret) * (vc - ret);
+            pass = vl >= sqc ? 1.0f : 0.0f;
+            vl = fmaxf(vl, sqc);
+        }
+        g[0] = valid ? 2.0f * a.value_coef * a.inv_m * diff * pass : 0.0f;
+        if (lead) sums[1] = vl;
+    }
+    if (lead) {
+        // output-layer gradient row, zero-padded to kHeadPad columns
+        uint32_t pk[kHeadPad / 2];
+#pragma unroll
+        for (int e = 0; e < kHeadPad / 2; ++e) pk[e] = pack2(g[2 * e], g[2 * e + 1]);
+        u32x4 *dst = reinterpret_cast<u32x4 *>(N.dzh + static_cast<long long>(m0 + si) * kHeadPad);
+        dst[0] = u32x4{pk[0], pk[1], pk[2], pk[3]};
+        dst[1] = u32x4{pk[4], pk[5], pk[6], pk[7]};
+    }
+    if (lead)
+#pragma unroll
+        for (int q = 0; q < kSums; ++q) s_sum[si * kSums + q] = sums[q];
+
+    // gradient into the last hidden pre-activations, in place over h_{L-1}
+    // (after every thread's copy of h_{L-1} to global memory has read it)
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (c >= nck) continue;
+        float dh[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dh[e] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < kFusedMaxAct; ++j) {
+            if (j >= n_out) continue;
+            const float *w = w_out + j * WP + kq * CK + 8 * c;
+            const float4 w0 = *reinterpret_cast<const float4 *>(w);
+            const float4 w1 = *reinterpret_cast<const float4 *>(w + 4);
+            dh[0] += g[j] * w0.x; dh[1] += g[j] * w0.y; dh[2] += g[j] * w0.z; dh[3] += g[j] * w0.w;
+            dh[4] += g[j] * w1.x; dh[5] += g[j] * w1.y; dh[6] += g[j] * w1.z; dh[7] += g[j] * w1.w;
+        }
+        u32x4 ov;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            ov[e] = pack2(dh[2 * e] * delu(lo_f(hx[c][e])), dh[2 * e + 1] * delu(hi_f(hx[c][e])));
+        *reinterpret_cast<u32x4 *>(hl + si * PL + kq * CK + 8 * c) = ov;
+    }
+    __syncthreads();
+    // block sums over the samples in order, one thread per term
+    if (tid < kSums) {
+        float v = 0.0f;
+        for (int i0 = 0; i0 < rows; i0 += 8) {
+            float t8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t8[u] = s_sum[min(i0 + u, R - 1) * kSums + tid];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i0 + u < rows) v += t8[u];
+        }
+        s_sum[R * kSums + tid] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const float *t = s_sum + R * kSums;
+        float *out = a.partials + static_cast<long long>(m0 / R) * (A + 8);
+        if (net == 0) {
+            out[0] = t[0];
+            out[2] = t[2];
+            out[3] = t[3];
+            for (int j = 0; j < A; ++j) out[4 + j] = t[5 + j];
+            float ent = 0.0f, kl_ls = 0.0f;
+            if (m0 == 0) {
+                // entropy of the state-independent policy, and the
+                // sample-independent part of KL(pi_old || pi):
+                //   sum_j log(sigma / sigma_old) + sigma_old^2 / (2 sigma^2) - 1/2
+                ent = 0.5f * A * (1.0f + kLog2Pi);
+                for (int j = 0; j < A; ++j) ent += a.logstd[j];
+                if (a.mu_old)
+                    for (int j = 0; j < A; ++j) {
+                        const float d = a.logstd_old[j] - a.logstd[j];
+                        kl_ls += -d + 0.5f * expf(2.0f * d) - 0.5f;
+                    }
+            }
+            out[4 + A] = ent;
+            out[5 + A] = t[4];
+            out[6 + A] = kl_ls;
+        } else {
+            out[1] = t[1];
+        }
+    }
+    copy_out(hl, PL, N.dz[L - 1] + static_cast<long long>(m0) * Hl, Hl, Hl, rows);
+
+    // ------------------------------------------------ input-gradient chain
+    for (int l = L - 1; l >= 1; --l) {
+        const int Hin = a.H[l], Hout = a.H[l - 1];
+        const uint16_t *dz = reinterpret_cast<const uint16_t *>(lds + a.lds_region[l]);
+        uint16_t *hz = reinterpret_cast<uint16_t *>(lds + a.lds_region[l - 1]);
+        run_layer<R, OCC, true>(N.WT[l], Hin, Hout, nullptr, dz, Hin + 8, hz, Hout + 8, wave, lane);
+        __syncthreads();
+        copy_out(hz, Hout + 8, N.dz[l - 1] + static_cast<long long>(m0) * Hout, Hout, Hout, rows);
+    }
+}
+
+// Weights in MFMA A-fragment order.  For a matrix with `rows` output
+// features and K inputs (zero-padded to 16 S), fragment (fb, s) holds, for
+// lane l, the 8 elements W[32 fb + l % 32][16 s + 8 (l / 32) .. + 7]; fragment
+// (fb, s) starts at element ((fb * S + s) * 64) * 8.  transpose = 1 packs
+// W^T from the row-major W: element (r, k) = src[k * ld + r].
+__global__ __launch_bounds__(256) void pack_frags_kernel(const FragArgs a) {
+    const int t = blockIdx.x * 256 + threadIdx.x;   // one 8-element lane chunk per thread
+    if (t >= a.total) return;
+    int j = 0;
+#pragma unroll 1
+    for (int q = 1; q < a.count; ++q)
+        if (t >= a.job[q].begin) j = q;
+    const FragJob &J = a.job[j];
+    const int local = t - J.begin;
+    const int lane = local & 63;
+    const int frag = local >> 6;
+    const int fb = frag / J.S, s = frag - (frag / J.S) * J.S;
+    const int r = 32 * fb + (lane & 31);
+    const int k0 = 16 * s + 8 * (lane >> 5);
+    uint32_t v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        uint32_t lo = 0, hi = 0;
+        const int k = k0 + 2 * e;
+        if (J.transpose) {
+            if (k < J.K) lo = J.src[static_cast<long long>(k) * J.ld + r];
+            if (k + 1 < J.K) hi = J.src[static_cast<long long>(k + 1) * J.ld + r];
+        } else {
+            if (k < J.K) lo = J.src[static_cast<long long>(r) * J.ld + k];
+            if (k + 1 < J.K) hi = J.src[static_cast<long long>(r) * J.ld + k + 1];
+        }
+        v[e] = lo | (hi << 16);
+    }
+    *reinterpret_cast<u32x4 *>(J.dst + static_cast<long long>(local) * 8) = u32x4{v[0], v[1], v[2], v[3]};
+}
+
+size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
+
+// LDS layout for R rows; returns the total bytes (0 if a constraint fails).
+size_t fused_layout(int L, const int *H, int kpad, int A, int R, FusedArgs *a) {
+    const int KP = kFusedThreads / R;
+    const int Hl = H[L - 1];
+    if (Hl % KP != 0 || (Hl / KP) % 8 != 0 || Hl / KP > 64) return 0;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const int at = static_cast<int>(off);
+        off += align16(bytes);
+        return at;
+    };
+    const int lds_w = take(static_cast<size_t>(A) * (Hl + 4) * 4);
+    const int lds_sum = take(static_cast<size_t>(R + 1) * kSums * 4);
+    const int lds_in = take(static_cast<size_t>(R) * (2 * A + 4) * 4);
+    const int lds_rows = take(static_cast<size_t>(R) * 4);
+    const int lds_head = take(static_cast<size_t>(2 * kFusedMaxAct) * 4);
+    int bias_off[kMaxHidden] = {0};
+    size_t nb = 0;
+    for (int l = 0; l < L; ++l) {
+        bias_off[l] = static_cast<int>(nb);
+        nb += (H[l] + 3) & ~3;
+    }
+    const int lds_bias = take(nb * 4);
+    int region[kMaxHidden] = {0};
+    for (int l = 0; l < L; ++l) region[l] = take(static_cast<size_t>(R) * (H[l] + 8) * 2);
+    int lds_x;
+    if (L >= 2 && kpad <= H[1])
+        lds_x = region[1];   // the inputs are dead once the first layer has run
+    else
+        lds_x = take(static_cast<size_t>(R) * (kpad + 8) * 2);
+    if (off > static_cast<size_t>(kMaxLdsBytes)) return 0;
+    if (a) {
+        a->lds_w = lds_w;
+        a->lds_sum = lds_sum;
+        a->lds_in = lds_in;
+        a->lds_rows = lds_rows;
+        a->lds_head = lds_head;
+        a->lds_bias = lds_bias;
+        a->lds_x = lds_x;
+        for (int l = 0; l < L; ++l) {
+            a->lds_region[l] = region[l];
+            a->bias_off[l] = bias_off[l];
+        }
+    }
+    return off;
+}
+
+}  // namespace
+
+// Two workgroups share a CU when 32-row blocks fit in half the LDS and the
+// layers are at most 512 wide (accumulators within a 256-register budget).
+bool fused_two_per_cu(int L, const int *H, int kpad, int A, int R) {
+    if (R != 32) return false;
+    for (int l = 0; l < L; ++l)
+        if (H[l] > 4 * 32 * kWaves) return false;
+    return fused_layout(L, H, kpad, A, 32, nullptr) <= static_cast<size_t>(kMaxLdsBytes / 2);
+}
+
+int fused_rows(int L, const int *H, int kpad, int A, int prefer) {
+    if (L < 1 || L > kMaxHidden || A < 1 || A > kFusedMaxAct || kpad < 16 || kpad % 16 != 0) return 0;
+    int maxh = 0;
+    for (int l = 0; l < L; ++l) {
+        const int f = H[l] / (32 * kWaves);
+        if (H[l] % (32 * kWaves) != 0 || (f != 1 && f != 2 && f != 4 && f != 8)) return 0;
+        maxh = H[l] > maxh ? H[l] : maxh;
+    }
+    const bool ok64 = maxh <= 4 * 32 * kWaves && fused_layout(L, H, kpad, A, 64, nullptr) > 0;
+    const bool ok32 = maxh <= 8 * 32 * kWaves && fused_layout(L, H, kpad, A, 32, nullptr) > 0;
+    if (prefer == 64 && ok64) return 64;
+    if (prefer == 32 && ok32) return 32;
+    // two 32-row workgroups per CU hide each other's latencies better than
+    // one 64-row workgroup, which reads each weight half as often
+    if (ok32 && fused_two_per_cu(L, H, kpad, A, 32)) return 32;
+    if (ok64) return 64;
+    return ok32 ? 32 : 0;
+}
+
+int fused_blocks(int M, int R) { return R > 0 ? (M + R - 1) / R : 0; }
+
+void add_frag_job(FragArgs &a, const FragJob &j) {
+    FragJob q = j;
+    q.begin = a.total;
+    a.job[a.count++] = q;
+    a.total += (q.rows / 32) * q.S * 64;
+}
+
+hipError_t launch_pack_frags(const FragArgs &a, hipStream_t s) {
+    if (a.total == 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_frags_kernel, dim3((a.total + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_update(FusedArgs a, hipStream_t s) {
+    const int R = a.R;
+    if ((R != 32 && R != 64) || a.M < 1) return hipErrorInvalidValue;
+    const size_t bytes = fused_layout(a.L, a.H, a.kpad, a.A, R, &a);
+    if (bytes == 0) return hipErrorInvalidValue;
+    a.blocks = fused_blocks(a.M, R);
+    static bool attr_set = false;
+    if (!attr_set) {
+        const void *fns[3] = {reinterpret_cast<const void *>(&fused_update_kernel<64, 1>),
+                              reinterpret_cast<const void *>(&fused_update_kernel<32, 1>),
+                              reinterpret_cast<const void *>(&fused_update_kernel<32, 2>)};
+        for (const void *fn : fns) {
+            const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
+            if (e != hipSuccess) return e;
+        }
+        attr_set = true;
+    }
+    const dim3 grid(2 * a.blocks), block(kFusedThreads);
+    if (R == 64)
+        hipLaunchKernelGGL((fused_update_kernel<64, 1>), grid, block, bytes, s, a);
+    else if (fused_two_per_cu(a.L, a.H, a.kpad, a.A, R))
+        hipLaunchKernelGGL((fused_update_kernel<32, 2>), grid, block, bytes, s, a);
+    else
+        hipLaunchKernelGGL((fused_update_kernel<32, 1>), grid, block, bytes, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ppo

@@ -137,6 +137,10 @@ struct WsPlan {
     // staged weights (elements of the operand type): the first layer padded
     // to kpad columns when D is not a multiple of 8, and W_l^T for l >= 1
     Region wt;
+    // bf16 weights of the fused pass in MFMA fragment order: W_l for every
+    // hidden layer and W_l^T for l >= 1 (elements)
+    Region frag;
+    size_t frag_w[2][kMaxHidden] = {{0}}, frag_wt[2][kMaxHidden] = {{0}};
     bool pad_w0 = false;
     size_t wt_w0[2] = {0, 0};
     size_t wt_t[2][kMaxHidden] = {{0}};
@@ -248,6 +252,19 @@ WsPlan plan_workspace(const NetLayout &g, Precision prec, int N, int T, int M) {
         }
     }
     w.wt = a.take(std::max<size_t>(wt_elems, 1) * w.esz);
+    size_t frag_elems = 0;
+    if (prec == kBF16 && w.kpad % 16 == 0) {
+        for (int net = 0; net < 2; ++net)
+            for (int l = 0; l < g.L; ++l) {
+                w.frag_w[net][l] = frag_elems;
+                frag_elems += static_cast<size_t>(g.H[l]) * (l == 0 ? w.kpad : g.H[l - 1]);
+                if (l >= 1) {
+                    w.frag_wt[net][l] = frag_elems;
+                    frag_elems += static_cast<size_t>(g.H[l - 1]) * g.H[l];
+                }
+            }
+    }
+    w.frag = a.take(std::max<size_t>(frag_elems, 1) * 2);
     (void)T;
     w.total = a.cur;
     return w;
@@ -796,12 +813,12 @@ HeadLossArgs head_loss_args(const ppo_ctx *c, const ppo_params *p, const ppo_hpa
 // The loss-partial half of the gradient assembly (the segments come from
 // build_dw).  The learning rate adapts only in an optimiser step.
 void set_reduce_loss(ReduceArgs &red, const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp,
-                     const WsPlan &w, void *ws, float *grad, int M, int apply) {
+                     const WsPlan &w, void *ws, float *grad, int M, int apply, int fused_r = 0) {
     const NetLayout &g = c->g;
     red.grad = grad;
     red.sumsq_partials = reinterpret_cast<double *>(wsp(ws, w.sumsq));
     red.loss_partials = reinterpret_cast<const float *>(wsp(ws, w.loss_part));
-    red.n_loss = head_loss_blocks(M);
+    red.n_loss = fused_r > 0 ? fused_blocks(M, fused_r) : head_loss_blocks(M);
     red.loss_width = head_loss_partial_width(g.A);
     red.A = g.A;
     red.logstd_offset = g.logstd;
@@ -842,6 +859,106 @@ AdamArgs adam_args(const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp,
     return ad;
 }
 
+bool fused_env_enabled() {
+    const char *v = std::getenv("PPO_FUSED");
+    return !(v && std::strcmp(v, "0") == 0);
+}
+
+
+// Samples per workgroup of the fused per-sample pass for this step, or 0 for
+// the layer-by-layer kernels: bf16 only, a network shape the fused kernel
+// covers, 16-byte aligned weights and biases, and offsets that fit its
+// 32-bit buffer addressing.  PPO_FUSED=0 forces the layer-by-layer path.
+int fused_rows_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, const ppo_batch *b) {
+    if (c->prec != kBF16 || !fused_env_enabled()) return 0;
+    const NetLayout &g = c->g;
+    const char *pref = std::getenv("PPO_FUSED_ROWS");
+    const int R = fused_rows(g.L, g.H, w.kpad, g.A, pref ? std::atoi(pref) : 0);
+    if (R == 0) return 0;
+    if (static_cast<long long>(b->B) * g.D * 4 > 0x7FFFFFF0LL - 0x100000LL) return 0;
+    for (int net = 0; net < 2; ++net)
+        for (int l = 0; l < g.L; ++l)
+            if (!aligned16(p->theta + (net == 0 ? g.ba[l] : g.bc[l]))) return 0;
+    return R;
+}
+
+// Packing of the bf16 shadow weights into fragment order for the fused pass.
+FragArgs build_frags(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *ws) {
+    const NetLayout &g = c->g;
+    const Weights W = gemm_weights(c, p);
+    uint16_t *base = reinterpret_cast<uint16_t *>(wsp(ws, w.frag));
+    FragArgs a{};
+    for (int net = 0; net < 2; ++net)
+        for (int l = 0; l < g.L; ++l) {
+            const int K = l == 0 ? g.D : g.H[l - 1];
+            FragJob j{};
+            j.src = static_cast<const uint16_t *>(W.W[net][l]);
+            j.dst = base + w.frag_w[net][l];
+            j.rows = g.H[l];
+            j.K = K;
+            j.S = (l == 0 ? w.kpad : K) / 16;
+            j.ld = K;
+            j.transpose = 0;
+            add_frag_job(a, j);
+            if (l >= 1) {
+                FragJob t{};
+                t.src = static_cast<const uint16_t *>(W.W[net][l]);
+                t.dst = base + w.frag_wt[net][l];
+                t.rows = g.H[l - 1];
+                t.K = g.H[l];
+                t.S = g.H[l] / 16;
+                t.ld = g.H[l - 1];
+                t.transpose = 1;
+                add_frag_job(a, t);
+            }
+        }
+    return a;
+}
+
+FusedArgs fused_args(const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp, const WsPlan &w, void *ws,
+                     const ppo_batch *b, const int32_t *idx, int M) {
+    const NetLayout &g = c->g;
+    const uint16_t *frag = reinterpret_cast<const uint16_t *>(wsp(ws, w.frag));
+    FusedArgs a{};
+    for (int net = 0; net < 2; ++net) {
+        FusedNet &n = a.net[net];
+        for (int l = 0; l < g.L; ++l) {
+            n.W[l] = frag + w.frag_w[net][l];
+            n.WT[l] = l >= 1 ? frag + w.frag_wt[net][l] : nullptr;
+            n.bias[l] = p->theta + (net == 0 ? g.ba[l] : g.bc[l]);
+            n.h[l] = reinterpret_cast<uint16_t *>(wsp(ws, net == 0 ? w.h_a[l] : w.h_c[l]));
+            n.dz[l] = reinterpret_cast<uint16_t *>(wsp(ws, net == 0 ? w.dz_a[l] : w.dz_c[l]));
+        }
+        n.dzh = reinterpret_cast<uint16_t *>(wsp(ws, net == 0 ? w.dzh_a : w.dzh_c));
+        n.Wout = p->theta + (net == 0 ? g.Wa[g.L] : g.Wc[g.L]);
+        n.bout = p->theta + (net == 0 ? g.ba[g.L] : g.bc[g.L]);
+    }
+    a.L = g.L;
+    a.D = g.D;
+    a.kpad = w.kpad;
+    a.A = g.A;
+    for (int l = 0; l < g.L; ++l) a.H[l] = g.H[l];
+    a.obs = b->obs;
+    a.idx = idx;
+    a.B = b->B;
+    a.M = M;
+    a.actions = b->actions;
+    a.logp_old = b->logp;
+    a.adv = b->adv;
+    a.returns = b->returns;
+    a.values_old = b->values;
+    a.mu_old = b->mu_old;
+    a.logstd_old = b->mu_old ? b->logstd_old : nullptr;
+    a.logstd = p->theta + g.logstd;
+    a.xg = reinterpret_cast<uint16_t *>(wsp(ws, w.xg));
+    a.partials = reinterpret_cast<float *>(wsp(ws, w.loss_part));
+    a.clip = hp->clip;
+    a.value_coef = hp->value_coef;
+    a.inv_m = 1.0f / static_cast<float>(M);
+    a.clip_value = hp->clip_value;
+    return a;
+}
+
 // One mini-batch step: gather, forward, head+loss, input-gradient chain,
 // weight gradients, gradient assembly with the float64 norm, Adam.
 hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp, const WsPlan &w, void *ws,
@@ -852,18 +969,28 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
     const int L = g.L;
     hipError_t e;
 
-    PROFILED(prof, PPO_PHASE_GATHER, launch_stage_weights(prec, build_stage(c, p, w, ws, true), s));
-    PROFILED(prof, PPO_PHASE_GATHER, launch_gather_obs(prec, s, sb.b->obs, sb.idx, sb.b->B, M, g.D, w.kpad,
-                                                       wsp(ws, w.xg)));
-    e = enqueue_forward(c, p, w, ws, M, true, true, t, s, prof);
-    if (e != hipSuccess) return e;
+    const int fused_r = fused_rows_for(c, p, w, sb.b);
+    if (fused_r > 0) {
+        // weights into fragment order, then gather, forward, loss and input
+        // gradients of both networks in one launch
+        PROFILED(prof, PPO_PHASE_GATHER, launch_pack_frags(build_frags(c, p, w, ws), s));
+        FusedArgs fa = fused_args(c, p, hp, w, ws, sb.b, sb.idx, M);
+        fa.R = fused_r;
+        PROFILED(prof, PPO_PHASE_FUSED, launch_fused_update(fa, s));
+    } else {
+        PROFILED(prof, PPO_PHASE_GATHER, launch_stage_weights(prec, build_stage(c, p, w, ws, true), s));
+        PROFILED(prof, PPO_PHASE_GATHER, launch_gather_obs(prec, s, sb.b->obs, sb.idx, sb.b->B, M, g.D, w.kpad,
+                                                           wsp(ws, w.xg)));
+        e = enqueue_forward(c, p, w, ws, M, true, true, t, s, prof);
+        if (e != hipSuccess) return e;
 
-    const HeadLossArgs hl = head_loss_args(c, p, hp, w, ws, sb.b, sb.idx, M);
-    PROFILED(prof, PPO_PHASE_HEAD_LOSS, launch_head_loss(prec, hl, s));
+        const HeadLossArgs hl = head_loss_args(c, p, hp, w, ws, sb.b, sb.idx, M);
+        PROFILED(prof, PPO_PHASE_HEAD_LOSS, launch_head_loss(prec, hl, s));
 
-    for (int l = L - 1; l >= 1; --l) {
-        const GemmArgs args = build_dx(c, p, w, ws, M, l, t.site[kSiteDx + l].tile);
-        PROFILED(prof, PPO_PHASE_INPUT_GRAD, launch_gemm(prec, 0, 0, kEpiDElu, args, s));
+        for (int l = L - 1; l >= 1; --l) {
+            const GemmArgs args = build_dx(c, p, w, ws, M, l, t.site[kSiteDx + l].tile);
+            PROFILED(prof, PPO_PHASE_INPUT_GRAD, launch_gemm(prec, 0, 0, kEpiDElu, args, s));
+        }
     }
 
     DwPlan d = build_dw(c, w, ws, M, t.site[kSiteDw]);
@@ -871,7 +998,7 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
         PROFILED(prof, PPO_PHASE_WEIGHT_GRAD, launch_gemm(prec, 1, 1, kEpiPartial, d.launch[i], s));
 
     ReduceArgs &red = d.red;
-    set_reduce_loss(red, c, p, hp, w, ws, sb.grad, M, sb.apply);
+    set_reduce_loss(red, c, p, hp, w, ws, sb.grad, M, sb.apply, fused_r);
     PROFILED(prof, PPO_PHASE_GRAD_REDUCE, launch_grad_reduce(red, s));
 
     const AdamArgs ad = adam_args(c, p, hp, red, sb.grad, sb.stats, M, sb.step_offset, sb.apply);

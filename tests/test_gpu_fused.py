@@ -1,0 +1,139 @@
+"""The fused per-sample pass of the bf16 update (gather, every hidden layer,
+output layers with the PPO loss, input-gradient chain in one launch) on an
+MI355X: it must be the path the bf16 step takes for the paper's network
+shapes, agree with the layer-by-layer kernels it replaces, and keep the
+update deterministic.  Its parity with the FP64 oracle is gated by the loss
+and gradient cases of test_gpu_parity (bf16 rows of the flat, rough and large
+shapes, including ragged row blocks)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2109_11978_amd as ppo
+import synth
+from tests.gpu_common import dev, require_gpu, teacher_batch
+from tests.parity import rel_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+class _Fused:
+    """Sets PPO_FUSED for the duration of a block (read at every call)."""
+
+    def __init__(self, on):
+        self.on = on
+
+    def __enter__(self):
+        self.old = os.environ.get("PPO_FUSED")
+        os.environ["PPO_FUSED"] = "1" if self.on else "0"
+
+    def __exit__(self, *exc):
+        if self.old is None:
+            os.environ.pop("PPO_FUSED", None)
+        else:
+            os.environ["PPO_FUSED"] = self.old
+
+
+def _setup(name, M, seed=1):
+    d = require_gpu()
+    cfg = synth.get_config(name)
+    theta = synth.xavier_theta(cfg.net, seed=seed, logstd=-0.2)
+    B = 2 * M
+    batch = teacher_batch(cfg, theta, B, seed=seed + 4, shift="mixed")
+    idx = np.random.default_rng(seed + 5).permutation(B)[:M].astype(np.int32)
+    ctx = ppo.Context(cfg.net.obs_dim, cfg.net.act_dim, cfg.net.hidden, "bf16")
+    return d, cfg, theta, batch, idx, ctx
+
+
+def _loss_grad(ctx, theta, batch, idx, d, fused, hp=None):
+    params = ppo.Params(ctx, theta, device=d)
+    tb = {k: dev(v, d) for k, v in batch.items()}
+    stats = torch.zeros(ppo.PPO_STATS_WIDTH, device=d)
+    grad = torch.zeros(ctx.param_count, device=d)
+    ws = ctx.new_workspace(M=len(idx))
+    with _Fused(fused):
+        ppo.ppo_loss_grad(ctx, params, tb, dev(idx, d), hp or ppo.UpdateHParams(), stats, grad, ws)
+    torch.cuda.synchronize()
+    return grad.cpu().numpy(), stats.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,M", [("flat", 24576), ("flat", 1000), ("rough", 777), ("large", 333),
+                                    ("flat", 10), ("large", 31)])
+def test_fused_matches_layered(name, M):
+    """Same inputs through both paths: the hidden layers round to bf16 at the
+    same points and accumulate in the same k order; the output layers sum in a
+    different order, so the two differ by float32 rounding, magnified by the
+    bf16 rounding of the gradients downstream of it (a few bf16 ulps)."""
+    d, cfg, theta, batch, idx, ctx = _setup(name, M)
+    _announce(f"fused vs layered {name} M={M}")
+    gf, sf = _loss_grad(ctx, theta, batch, idx, d, True)
+    gl, sl = _loss_grad(ctx, theta, batch, idx, d, False)
+    nw, ew = rel_errors(gf, gl)
+    print(f"grad fused vs layered: normwise {nw:.2e}, worst element {ew:.2e}")
+    assert np.all(np.isfinite(gf))
+    assert nw < 4e-3, nw
+    stf, stl = ppo.stats_dict(sf), ppo.stats_dict(sl)
+    for key in ("policy_loss", "value_loss", "entropy", "loss", "approx_kl", "grad_norm"):
+        assert abs(stf[key] - stl[key]) <= 2e-3 * (abs(stl[key]) + 1e-3), (key, stf[key], stl[key])
+    assert stf["clip_frac"] == stl["clip_frac"]
+
+
+def test_fused_is_the_bf16_path_and_deterministic():
+    d, cfg, theta, batch, idx, ctx = _setup("flat", 4096)
+    _announce("fused phase accounting and determinism")
+    g1, s1 = _loss_grad(ctx, theta, batch, idx, d, True)
+    g2, s2 = _loss_grad(ctx, theta, batch, idx, d, True)
+    np.testing.assert_array_equal(g1, g2)
+    np.testing.assert_array_equal(s1, s2)
+    # the profiled epoch names the launches: one fused launch per mini-batch
+    params = ppo.Params(ctx, theta, device=d)
+    tb = {k: dev(v, d) for k, v in batch.items()}
+    perm = dev(np.random.default_rng(3).permutation(len(batch["adv"])).astype(np.int32), d)
+    K = 2
+    ws = ctx.new_workspace(M=len(batch["adv"]) // K)
+    stats = torch.zeros(K, ppo.PPO_STATS_WIDTH, device=d)
+    with _Fused(True):
+        ph = ppo.ppo_update_epoch_profiled(ctx, params, tb, perm, K, ppo.UpdateHParams(), stats, ws)
+    assert ph["fused"][1] == K
+    assert ph["forward"][1] == 0 and ph["head_loss"][1] == 0 and ph["input_grad"][1] == 0
+    with _Fused(False):
+        ph = ppo.ppo_update_epoch_profiled(ctx, params, tb, perm, K, ppo.UpdateHParams(), stats, ws)
+    assert ph["fused"][1] == 0 and ph["forward"][1] == K * len(cfg.net.hidden)
+
+
+@pytest.mark.parametrize("name", ["flat", "large"])
+def test_fused_epoch_graph_matches_eager_and_layered(name):
+    """A four-mini-batch epoch: the captured graph replays the eager launches
+    bit for bit, and the parameters track the layer-by-layer epoch."""
+    d = require_gpu()
+    cfg = synth.get_config(name)
+    _announce(f"fused epoch graph vs eager vs layered {name}")
+    theta = synth.xavier_theta(cfg.net, seed=21, logstd=-0.2)
+    B = 4096
+    batch = teacher_batch(cfg, theta, B, seed=22, shift="mixed")
+    perm = np.random.default_rng(23).permutation(B).astype(np.int32)
+    ctx = ppo.Context(cfg.net.obs_dim, cfg.net.act_dim, cfg.net.hidden, "bf16")
+    K = 4
+    tb = {k: dev(v, d) for k, v in batch.items()}
+    ws = ctx.new_workspace(M=B // K)
+    out = {}
+    for label, fused, graph in (("eager", True, False), ("graph", True, True), ("layered", False, False)):
+        params = ppo.Params(ctx, theta, lr=1e-3, device=d)
+        stats = torch.zeros(K, ppo.PPO_STATS_WIDTH, device=d)
+        with _Fused(fused):
+            for _ in range(2):   # the second graph call replays the captured epoch
+                ppo.ppo_update_epoch(ctx, params, tb, dev(perm, d), K, ppo.UpdateHParams(use_graph=graph), stats,
+                                     ws)
+        torch.cuda.synchronize()
+        out[label] = (params.theta.cpu().numpy().copy(), stats.cpu().numpy().copy())
+    np.testing.assert_array_equal(out["eager"][0], out["graph"][0])
+    np.testing.assert_array_equal(out["eager"][1], out["graph"][1])
+    nw, _ = rel_errors(out["eager"][0] - theta, out["layered"][0] - theta)
+    print(f"parameter change fused vs layered: normwise {nw:.2e}")
+    assert nw < 2e-2, nw

@@ -165,7 +165,9 @@ def test_rollout_infer(name, prec, N):
 LOSS_CASES = [("tiny", "fp32", 1536, "near"), ("tiny", "fp32", 1536, "mixed"), ("tiny", "bf16", 1536, "mixed"),
               ("tiny", "fp32", 1000, "mixed"), ("flat", "fp32", 24576, "mixed"), ("flat", "bf16", 24576, "mixed"),
               ("rough", "bf16", 4096, "mixed"), ("rough", "fp32", 2000, "near"),
-              ("large", "bf16", 8192, "mixed")]
+              ("large", "bf16", 8192, "mixed"),
+              # ragged row blocks of the fused bf16 pass (64 rows; 32 for the large widths)
+              ("flat", "bf16", 1000, "mixed"), ("rough", "bf16", 777, "near"), ("large", "bf16", 333, "mixed")]
 
 
 @pytest.mark.parametrize("name,prec,M,shift", LOSS_CASES)
