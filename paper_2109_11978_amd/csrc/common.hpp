@@ -95,7 +95,6 @@ hipError_t launch_gemm(Precision prec, int a_mode, int b_mode, int epi, const Ge
 // layers with the PPO loss and their gradients, and the input-gradient chain.
 // Its outputs are exactly the operands of the weight-gradient GEMMs and the
 // loss partials of the head kernel.
-constexpr int kFusedThreads = 256;
 constexpr int kFusedMaxAct = 16;
 
 // Weights of the fused pass in MFMA A-fragment order (pack_frags): for a
@@ -141,18 +140,21 @@ struct FusedArgs {
     float *partials;                  // [blocks][A + 8], the layout of HeadLossArgs::partials
     float clip, value_coef, inv_m;
     int clip_value;
-    int R;                            // samples per workgroup (fused_rows)
+    int R, NT;                        // samples and threads per workgroup (a fused_shape)
     // filled in by launch_fused_update
     int blocks;
     int lds_region[kMaxHidden], lds_x, lds_w, lds_sum, lds_in, lds_rows, lds_bias, lds_head;
     int bias_off[kMaxHidden];         // floats into the staged biases
 };
-// Samples per workgroup for this network shape (64 or 32), 0 when the fused
-// pass does not apply (hidden widths not 128, 256, 512 or 1024, input width
-// not a multiple of 16, or the activations do not fit in LDS).
-// prefer = 32 or 64 picks that block size where it applies (0: the default,
-// 32 rows when two workgroups then share a CU, else 64).
-int fused_rows(int L, const int *H, int kpad, int A, int prefer = 0);
+// Samples per workgroup and threads per workgroup of the fused pass for this
+// network shape ({0, 0} when it does not apply: hidden widths that do not
+// split over the waves, an input width that is not a multiple of 16, or
+// activations that do not fit in LDS); per_cu = workgroups sharing a CU.
+// Nonzero prefer_rows / prefer_threads restrict the candidates.
+struct FusedShape {
+    int rows, threads, per_cu;
+};
+FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows = 0, int prefer_threads = 0);
 int fused_blocks(int M, int R);
 hipError_t launch_fused_update(FusedArgs a, hipStream_t s);
 

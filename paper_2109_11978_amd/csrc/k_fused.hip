@@ -32,13 +32,16 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kWaves = kFusedThreads / 64;
 constexpr int kOutside = 0x7FFFFFF0;   // buffer offset past any resource: loads read zero
 constexpr int kMaxLdsBytes = 160 * 1024;
 constexpr float kLog2Pi = 1.8378770664093453f;
 // per-sample loss terms: policy, value, clipped, ratio-KL, mean-shift KL,
 // log-std gradient [kFusedMaxAct]
 constexpr int kSums = 5 + kFusedMaxAct;
+// per-sample loss inputs in LDS: actions [kFusedMaxAct], collection-time
+// means [kFusedMaxAct] (both zero past A), old log-prob, advantage, return,
+// old value
+constexpr int kInW = 2 * kFusedMaxAct + 4;
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, long long bytes) {
     const int n = bytes > 0x7FFFFFFFLL ? 0x7FFFFFFF : static_cast<int>(bytes < 0 ? 0 : bytes);
@@ -66,7 +69,7 @@ __device__ inline float wave_sum(float v) {
     return v;
 }
 
-// acc[f][j] = sum_k W[f0 + 32 f + (l % 32), k] * act[32 j + (l % 32), k] over
+// acc[f][j] = sum_k W[f0 + 32 f + (l % 32), k] * act[32 (sb0 + j) + (l % 32), k] over
 // K = 16 S in k-steps of 16.  W is stored in MFMA fragment order (see
 // pack_frags_kernel): the A fragment of feature block fb at k-step s is 1 KB
 // at ((fb * S + s) * 64 + lane) * 16 bytes, so each load instruction reads
@@ -79,14 +82,14 @@ __device__ inline float wave_sum(float v) {
 // finite activation fragment.
 template <int FBW, int SB, int PF>
 __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16_t *W, int rows_w, int S, int f0,
-                                 const uint16_t *act, int pitch, int lane) {
+                                          int sb0, const uint16_t *act, int pitch, int lane) {
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(W, static_cast<long long>(rows_w / 32) * S * 1024);
     const int kh = (lane >> 5) * 8;
     // per-block lane offsets in VGPRs, one scalar step offset per load
     int vo[FBW];
 #pragma unroll
     for (int f = 0; f < FBW; ++f) vo[f] = (f0 / 32 + f) * S * 1024 + lane * 16;
-    const uint16_t *bp = act + (lane & 31) * pitch + kh;
+    const uint16_t *bp = act + (32 * sb0 + (lane & 31)) * pitch + kh;
 #pragma unroll
     for (int f = 0; f < FBW; ++f)
 #pragma unroll
@@ -133,10 +136,10 @@ __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16
 
 // Forward epilogue: out[sample][feature] = bf16(ELU(acc + bias)).
 template <int FBW, int SB>
-__device__ __forceinline__ void epi_forward(const floatx16 (&acc)[FBW][SB], const float *bias, int f0, uint16_t *out,
-                                   int pitch, int lane) {
+__device__ __forceinline__ void epi_forward(const floatx16 (&acc)[FBW][SB], const float *bias, int f0, int sb0,
+                                            uint16_t *out, int pitch, int lane) {
     const int h4 = (lane >> 5) * 4;
-    const int i0 = lane & 31;
+    const int i0 = 32 * sb0 + (lane & 31);
 #pragma unroll
     for (int f = 0; f < FBW; ++f)
 #pragma unroll
@@ -158,9 +161,10 @@ __device__ __forceinline__ void epi_forward(const floatx16 (&acc)[FBW][SB], cons
 // dz_{l-1} = bf16(acc * ELU'(h_{l-1})) on exit.  Each element is read and
 // written by the same lane.
 template <int FBW, int SB>
-__device__ __forceinline__ void epi_backward(const floatx16 (&acc)[FBW][SB], int f0, uint16_t *hz, int pitch, int lane) {
+__device__ __forceinline__ void epi_backward(const floatx16 (&acc)[FBW][SB], int f0, int sb0, uint16_t *hz, int pitch,
+                                             int lane) {
     const int h4 = (lane >> 5) * 4;
-    const int i0 = lane & 31;
+    const int i0 = 32 * sb0 + (lane & 31);
 #pragma unroll
     for (int f = 0; f < FBW; ++f)
 #pragma unroll
@@ -181,59 +185,105 @@ __device__ __forceinline__ void epi_backward(const floatx16 (&acc)[FBW][SB], int
 
 template <int FBW, int SB, int PF, bool BWD>
 __device__ __forceinline__ void layer_impl(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
-                                  int in_pitch, uint16_t *out, int out_pitch, int wave, int lane) {
-    const int f0 = wave * FBW * 32;
+                                           int in_pitch, uint16_t *out, int out_pitch, int f0, int sb0, int lane) {
     floatx16 acc[FBW][SB];
-    mma_layer<FBW, SB, PF>(acc, W, nout, K >> 4, f0, in, in_pitch, lane);
+    mma_layer<FBW, SB, PF>(acc, W, nout, K >> 4, f0, sb0, in, in_pitch, lane);
     if constexpr (BWD)
-        epi_backward<FBW, SB>(acc, f0, out, out_pitch, lane);
+        epi_backward<FBW, SB>(acc, f0, sb0, out, out_pitch, lane);
     else
-        epi_forward<FBW, SB>(acc, bias, f0, out, out_pitch, lane);
+        epi_forward<FBW, SB>(acc, bias, f0, sb0, out, out_pitch, lane);
 }
 
-// One layer for all R samples of the block: nout output features (a multiple
-// of 128) split over the four waves.  Weight fragments in flight per lane:
-// PF k-steps x FBW blocks, up to 32, with PF no larger than the layer's
-// k-step count S (K / 16) rounded up to a power of two (S is a power of two
+// Weight fragments in flight per lane: PF k-steps x FBW blocks, up to 32,
+// with PF no larger than the layer's k-step count S = K / 16 (a power of two
 // for hidden layers; a first layer of 3 or 15 steps takes PF = 4).
 template <int FBW, int SB, bool BWD, int PFMAX>
-__device__ __forceinline__ void layer_pf(int S, const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
-                                int in_pitch, uint16_t *out, int out_pitch, int wave, int lane) {
+__device__ __forceinline__ void layer_pf(int S, const uint16_t *W, int K, int nout, const float *bias,
+                                         const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
+                                         int sb0, int lane) {
     if (PFMAX >= 32 && S >= 32)
-        layer_impl<FBW, SB, (PFMAX >= 32 ? 32 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane);
+        layer_impl<FBW, SB, (PFMAX >= 32 ? 32 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane);
     else if (PFMAX >= 16 && S >= 16)
-        layer_impl<FBW, SB, (PFMAX >= 16 ? 16 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane);
+        layer_impl<FBW, SB, (PFMAX >= 16 ? 16 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane);
     else if (PFMAX >= 8 && S >= 8)
-        layer_impl<FBW, SB, (PFMAX >= 8 ? 8 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane);
+        layer_impl<FBW, SB, (PFMAX >= 8 ? 8 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane);
     else
-        layer_impl<FBW, SB, 4, BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane);
+        layer_impl<FBW, SB, 4, BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane);
 }
 
-template <int R, int OCC, bool BWD>
-__device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
-                                 int in_pitch, uint16_t *out, int out_pitch, int wave, int lane) {
-    constexpr int SB = R / 32;
-    const int S = K >> 4;
-    switch (nout / (32 * kWaves)) {
-    case 1: layer_pf<1, SB, BWD, 32>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane); break;
-    case 2: layer_pf<2, SB, BWD, 16>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane); break;
-    case 4: layer_pf<4, SB, BWD, 8>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane); break;
+// Deepest weight prefetch (k-steps) that keeps the accumulators (FBW x SBW
+// blocks of 16 registers) and the fragment ring (PF x FBW x 4 registers)
+// within REGS registers, at most 32 fragments, at least 4 steps.
+template <int FBW, int SBW, int REGS>
+constexpr int pf_max() {
+    int pf = 32 / FBW;
+    while (pf > 4 && FBW * SBW * 16 + pf * FBW * 4 > REGS) pf /= 2;
+    return pf;
+}
+
+template <int SBW, bool BWD, bool WIDE, int REGS>
+__device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int K, int nout, const float *bias,
+                                         const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
+                                         int sb0, int lane) {
+    switch (fbw) {
+    case 1:
+        layer_pf<1, SBW, BWD, pf_max<1, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0,
+                                                      lane);
+        break;
+    case 2:
+        layer_pf<2, SBW, BWD, pf_max<2, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0,
+                                                      lane);
+        break;
+    case 4:
+        layer_pf<4, SBW, BWD, pf_max<4, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0,
+                                                      lane);
+        break;
     default:
-        if constexpr (SB == 1 && OCC == 1)
-            layer_pf<8, 1, BWD, 4>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave, lane);
+        if constexpr (WIDE)
+            layer_pf<8, SBW, BWD, pf_max<8, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
+                                                          sb0, lane);
         break;
     }
 }
 
+// One layer for all R samples of the block.  The layer's 32-feature blocks
+// are split over the NT / 64 waves; when there are fewer blocks than waves,
+// the waves sharing a block split the sample blocks instead (each weight
+// fragment is then read by two waves, the second time from L1).
+template <int R, int NT, int WPE, bool BWD>
+__device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
+                                          int in_pitch, uint16_t *out, int out_pitch, int wave, int lane) {
+    constexpr int NW = NT / 64;
+    constexpr int SB = R / 32;
+    // registers for accumulators and fragments: 512 / WPE per lane, less
+    // what the addresses, activation fragments and epilogue keep live
+    constexpr int REGS = WPE == 1 ? 320 : 192;
+    // eight feature blocks per wave only with one sample block and a full
+    // register file
+    constexpr bool WIDE = SB == 1 && WPE == 1;
+    const int S = K >> 4;
+    const int fb = nout / 32;
+    if (fb >= NW) {
+        const int fbw = fb / NW;
+        layer_fb<SB, BWD, WIDE, REGS>(fbw, S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave * fbw * 32, 0,
+                                      lane);
+    } else if constexpr (SB >= 2) {
+        // two waves per feature block, each with half the sample blocks
+        layer_fb<SB / 2, BWD, false, REGS>(1, S, W, K, nout, bias, in, in_pitch, out, out_pitch, (wave % fb) * 32,
+                                           (wave / fb) * (SB / 2), lane);
+    }
+}
+
 // rows x cols bf16 from LDS (row pitch `pitch`) to global rows of `ld`
-// elements; cols is a multiple of 8 and at most 8 * kFusedThreads.  Each
+// elements; cols is a multiple of 8 and at most 8 * NT.  Each
 // thread keeps one 16-byte column chunk and strides over the rows; four LDS
 // reads go out before their stores, and stores past the last row fall
 // outside the buffer and are dropped.
+template <int NT>
 __device__ inline void copy_out(const uint16_t *src, int pitch, uint16_t *dst, int ld, int cols, int rows) {
     constexpr int U = 4;
     const int cpr = cols >> 3;
-    const int rpp = kFusedThreads / cpr;   // rows per pass
+    const int rpp = NT / cpr;   // rows per pass
     const int r0 = threadIdx.x / cpr;
     const int c = (threadIdx.x - r0 * cpr) * 8;
     if (r0 >= rpp) return;
@@ -254,15 +304,16 @@ __device__ inline void copy_out(const uint16_t *src, int pitch, uint16_t *dst, i
 }
 
 // Observation rows of the block (batch rows s_rows[0 .. R)) as bf16 into
-// LDS, zero-padded to kpad columns and zero past the last valid row.  Each
-// wave takes every fourth row; a row's elements are spread over the lanes
+// LDS, zero-padded to kpad columns and zero past the last valid row.  Wave w
+// takes rows w, w + NW, ...; a row's elements are spread over the lanes
 // (coalesced), and sixteen buffer loads are in flight per lane (out-of-range
 // ones read zero).
-template <int R>
+template <int R, int NT>
 __device__ inline void gather_rows(const FusedArgs &a, const int *s_rows, int rows, uint16_t *x, int pitch,
                                    int wave, int lane) {
     constexpr int U = 16;
-    constexpr int PER_WAVE = R / kWaves;
+    constexpr int NW = NT / 64;
+    constexpr int PER_WAVE = R / NW;
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.obs, static_cast<long long>(a.B) * a.D * 4);
     const int cpr = (a.kpad + 63) >> 6;     // 64-element chunks per row
     const int total = PER_WAVE * cpr;       // loads per lane
@@ -273,7 +324,7 @@ __device__ inline void gather_rows(const FusedArgs &a, const int *s_rows, int ro
             const int t = min(t0 + u, total - 1);
             const int il = t / cpr;
             const int k = 64 * (t - il * cpr) + lane;
-            const int i = wave + kWaves * il;
+            const int i = wave + NW * il;
             const bool ok = t0 + u < total && i < rows && k < a.D;
             const int row = __builtin_amdgcn_readfirstlane(s_rows[i]);
             v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, ok ? k * 4 : kOutside, row * a.D * 4, 0));
@@ -283,30 +334,170 @@ __device__ inline void gather_rows(const FusedArgs &a, const int *s_rows, int ro
             const int t = t0 + u;
             const int il = t / cpr;
             const int k = 64 * (t - il * cpr) + lane;
-            const int i = wave + kWaves * il;
+            const int i = wave + NW * il;
             if (t < total && k < a.kpad) x[i * pitch + k] = static_cast<uint16_t>(bf16_bits(v[u]));
         }
     }
 }
 
-// Sum over the KP adjacent lanes of a sample (KP = 4 or 8) with DPP lane
-// swaps: xor 1 and xor 2 inside each quad, then the two quads of an 8-lane
-// row half exchanged by the half-row mirror.  Every lane ends with the same
-// value (each step adds a value and its partner's in commuted order).
+// Sum over the KP adjacent lanes of a sample (KP = 4, 8 or 16) with DPP lane
+// swaps: xor 1 and xor 2 inside each quad, then the quads of an 8-lane half
+// row exchanged by the half-row mirror, then the halves of a 16-lane row by
+// the row mirror.  Every lane ends with the same value (each step adds a
+// value and its partner's in commuted order).
 template <int KP>
 __device__ inline float kpart_sum(float v) {
     v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));   // quad [1,0,3,2]
     v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad [2,3,0,1]
-    if constexpr (KP == 8)
+    if constexpr (KP >= 8)
         v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));  // half mirror
+    if constexpr (KP >= 16)
+        v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, true));  // row mirror
     return v;
 }
 
-template <int R, int OCC>
-__global__ __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
+// Output layer, PPO loss terms and output gradients of the block's samples.
+// KP = NT / R adjacent lanes per sample, NCK 8-element chunks of
+// the last hidden layer per lane; the actor computes kFusedMaxAct outputs
+// (weights, biases, log-std and loss inputs zero past A, which makes the
+// extra terms vanish), the critic one.  Partial dot products are combined
+// with DPP lane swaps that leave the same value in every lane of a sample,
+// so all of them compute the same loss terms and output gradients; the
+// sample's first lane stores its output-gradient row and loss terms.  On
+// return the last hidden layer in LDS holds the gradient wrt its
+// pre-activations (after a barrier: every thread's copy of h_{L-1} to global
+// memory has read it).
+template <int R, int NT, int NCK, bool ACTOR>
+__device__ __forceinline__ void head_pass(const FusedArgs &a, const FusedNet &N, uint16_t *hl, int PL,
+                                          const float *w_out, int WP, const float *s_head, const float *s_in,
+                                          float *s_sum, int m0, int rows) {
+    constexpr int KP = NT / R;
+    constexpr int CK = NCK * 8;
+    constexpr int NO = ACTOR ? kFusedMaxAct : 1;
+    const int tid = threadIdx.x;
+    const int si = tid / KP, kq = tid % KP;
+    const bool valid = si < rows;
+    const bool lead = valid && kq == 0;
+    const float *in_s = s_in + si * kInW;
+    uint16_t *hrow = hl + si * PL + kq * CK;
+    const float *wl = w_out + kq * CK;
+    u32x4 hx[NCK];
+#pragma unroll
+    for (int c = 0; c < NCK; ++c) hx[c] = *reinterpret_cast<const u32x4 *>(hrow + 8 * c);
+    float o[NO];
+#pragma unroll
+    for (int j = 0; j < NO; ++j) o[j] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < NCK; ++c) {
+        float xv[8];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            xv[2 * e] = lo_f(hx[c][e]);
+            xv[2 * e + 1] = hi_f(hx[c][e]);
+        }
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            const float4 w0 = *reinterpret_cast<const float4 *>(wl + j * WP + 8 * c);
+            const float4 w1 = *reinterpret_cast<const float4 *>(wl + j * WP + 8 * c + 4);
+            o[j] += xv[0] * w0.x + xv[1] * w0.y + xv[2] * w0.z + xv[3] * w0.w + xv[4] * w1.x + xv[5] * w1.y +
+                    xv[6] * w1.z + xv[7] * w1.w;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NO; ++j) o[j] = kpart_sum<KP>(o[j]) + s_head[j];
+
+    float g[NO];
+    float sums[kSums];
+#pragma unroll
+    for (int q = 0; q < kSums; ++q) sums[q] = 0.0f;
+    if constexpr (ACTOR) {
+        const int A = a.A;
+        // log-probability of the stored action in float64 (a sum of A terms of
+        // order 1 whose float32 rounding would dominate the ratio's error)
+        float z[NO], inv_sig[NO];
+        double logp = -0.5 * A * 1.8378770664093453;
+        float kl_mu = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            const float ls = s_head[kFusedMaxAct + j];
+            inv_sig[j] = expf(-ls);
+            z[j] = (in_s[j] - o[j]) * inv_sig[j];
+            logp += -0.5 * static_cast<double>(z[j]) * z[j] - ls;
+            const float dm = (in_s[kFusedMaxAct + j] - o[j]) * inv_sig[j];
+            kl_mu += 0.5f * dm * dm;
+        }
+        const float adv = in_s[2 * kFusedMaxAct + 1];
+        const float ratio = static_cast<float>(exp(logp - static_cast<double>(in_s[2 * kFusedMaxAct])));
+        const float lo = 1.0f - a.clip, hi = 1.0f + a.clip;
+        const bool active = adv >= 0.0f ? (ratio <= hi) : (ratio >= lo);
+        const float g_lp = valid && active ? -a.inv_m * adv * ratio : 0.0f;
+        sums[0] = -fminf(ratio * adv, fminf(fmaxf(ratio, lo), hi) * adv);
+        sums[2] = fabsf(ratio - 1.0f) > a.clip ? 1.0f : 0.0f;
+        sums[3] = (ratio - 1.0f) - logf(ratio);
+        sums[4] = kl_mu;
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            g[j] = g_lp * z[j] * inv_sig[j];
+            sums[5 + j] = g_lp * (z[j] * z[j] - 1.0f);
+        }
+    } else {
+        const float V = o[0];
+        const float ret = in_s[2 * kFusedMaxAct + 2], v_old = in_s[2 * kFusedMaxAct + 3];
+        const float diff = V - ret;
+        float pass = 1.0f, vl = diff * diff;
+        if (a.clip_value) {
+            const float vc = v_old + fminf(fmaxf(V - v_old, -a.clip), a.clip);
+            const float sqc = (vc - ret) * (vc - ret);
+            pass = vl >= sqc ? 1.0f : 0.0f;
+            vl = fmaxf(vl, sqc);
+        }
+        g[0] = valid ? 2.0f * a.value_coef * a.inv_m * diff * pass : 0.0f;
+        sums[1] = vl;
+    }
+    if (lead) {
+        // output-layer gradient row, zero-padded to kHeadPad columns
+        float gp[kHeadPad];
+#pragma unroll
+        for (int e = 0; e < kHeadPad; ++e) gp[e] = e < NO ? g[e < NO ? e : 0] : 0.0f;
+        uint32_t pk[kHeadPad / 2];
+#pragma unroll
+        for (int e = 0; e < kHeadPad / 2; ++e) pk[e] = pack2(gp[2 * e], gp[2 * e + 1]);
+        u32x4 *dst = reinterpret_cast<u32x4 *>(N.dzh + static_cast<long long>(m0 + si) * kHeadPad);
+        dst[0] = u32x4{pk[0], pk[1], pk[2], pk[3]};
+        dst[1] = u32x4{pk[4], pk[5], pk[6], pk[7]};
+#pragma unroll
+        for (int q = 0; q < kSums; ++q) s_sum[si * kSums + q] = sums[q];
+    }
+
+    // gradient into the last hidden pre-activations, in place over h_{L-1}
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NCK; ++c) {
+        float dh[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dh[e] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            const float4 w0 = *reinterpret_cast<const float4 *>(wl + j * WP + 8 * c);
+            const float4 w1 = *reinterpret_cast<const float4 *>(wl + j * WP + 8 * c + 4);
+            dh[0] += g[j] * w0.x; dh[1] += g[j] * w0.y; dh[2] += g[j] * w0.z; dh[3] += g[j] * w0.w;
+            dh[4] += g[j] * w1.x; dh[5] += g[j] * w1.y; dh[6] += g[j] * w1.z; dh[7] += g[j] * w1.w;
+        }
+        u32x4 ov;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            ov[e] = pack2(dh[2 * e] * delu(lo_f(hx[c][e])), dh[2 * e + 1] * delu(hi_f(hx[c][e])));
+        *reinterpret_cast<u32x4 *>(hrow + 8 * c) = ov;
+    }
+}
+
+// R samples per workgroup of NT threads; WPE waves per SIMD (the NT / 256
+// waves of one workgroup times the workgroups that share a CU).
+template <int R, int NT, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void fused_update_kernel(const FusedArgs a) {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    constexpr int KP = kFusedThreads / R;  // k-parts per sample in the output layer
+    constexpr int KP = NT / R;  // lanes per sample in the output layer
     const int net = blockIdx.x & 1;
     const int m0 = (blockIdx.x >> 1) * R;
     const int rows = min(R, a.M - m0);
@@ -317,11 +508,10 @@ void fused_update_kernel(const FusedArgs a) {
     const int WP = Hl + 4;                 // row pitch of the staged output-layer weights
     float *w_out = reinterpret_cast<float *>(lds + a.lds_w);
     float *s_sum = reinterpret_cast<float *>(lds + a.lds_sum);    // [R][kSums] per-sample loss terms
-    float *s_in = reinterpret_cast<float *>(lds + a.lds_in);      // [R][2 A + 4] per-sample loss inputs
+    float *s_in = reinterpret_cast<float *>(lds + a.lds_in);      // [R][kInW] per-sample loss inputs
     float *s_bias = reinterpret_cast<float *>(lds + a.lds_bias);  // hidden-layer biases
     int *s_rows = reinterpret_cast<int *>(lds + a.lds_rows);      // [R] batch rows of the block
     const FusedNet &N = a.net[net];
-    const int IW = 2 * A + 4;
 
     // ------------------------------------------------------- prologue
     // batch rows of the block (rows past the end repeat the last one; their
@@ -344,7 +534,7 @@ void fused_update_kernel(const FusedArgs a) {
         float vw[UW], vb[kMaxHidden][UB];
 #pragma unroll
         for (int u = 0; u < UW; ++u) {
-            const int q = tid + u * kFusedThreads;
+            const int q = tid + u * NT;
             vw[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, q < nw ? q * 4 : kOutside, 0, 0));
         }
 #pragma unroll
@@ -353,7 +543,7 @@ void fused_update_kernel(const FusedArgs a) {
             const __amdgpu_buffer_rsrc_t rb = make_rsrc(N.bias[l], static_cast<long long>(H) * 4);
 #pragma unroll
             for (int u = 0; u < UB; ++u) {
-                const int q = tid + u * kFusedThreads;
+                const int q = tid + u * NT;
                 vb[l][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, q < H ? q * 4 : kOutside, 0, 0));
             }
         }
@@ -363,7 +553,7 @@ void fused_update_kernel(const FusedArgs a) {
         const float vl = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rl, tid < A ? tid * 4 : kOutside, 0, 0));
 #pragma unroll
         for (int u = 0; u < UW; ++u) {
-            const int q = tid + u * kFusedThreads;
+            const int q = tid + u * NT;
             const int j = q / Hl;
             if (q < nw) w_out[j * WP + (q - j * Hl)] = vw[u];
         }
@@ -372,14 +562,22 @@ void fused_update_kernel(const FusedArgs a) {
             if (l >= L) continue;
 #pragma unroll
             for (int u = 0; u < UB; ++u) {
-                const int q = tid + u * kFusedThreads;
+                const int q = tid + u * NT;
                 if (q < a.H[l]) s_bias[a.bias_off[l] + q] = vb[l][u];
             }
         }
-        if (tid < n_out) s_head[tid] = vo;
-        if (tid < A) s_head[kFusedMaxAct + tid] = vl;
+        if (tid < kFusedMaxAct) {
+            s_head[tid] = tid < n_out ? vo : 0.0f;
+            s_head[kFusedMaxAct + tid] = tid < A ? vl : 0.0f;
+        }
+        // zero rows of the output-layer weights past n_out (read by the
+        // actor's kFusedMaxAct-wide head)
+        for (int q = nw + tid; q < kFusedMaxAct * Hl; q += NT) {
+            const int j = q / Hl;
+            w_out[j * WP + (q - j * Hl)] = 0.0f;
+        }
         // output layers wider than UW loads per thread (not the paper's shapes)
-        for (int q = tid + UW * kFusedThreads; q < nw; q += kFusedThreads) {
+        for (int q = tid + UW * NT; q < nw; q += NT) {
             const int j = q / Hl;
             w_out[j * WP + (q - j * Hl)] = N.Wout[q];
         }
@@ -389,7 +587,7 @@ void fused_update_kernel(const FusedArgs a) {
     const int xp = a.kpad + 8;
     {
         // loss inputs: TPS threads per sample, columns part, part + TPS, ...
-        constexpr int TPS = kFusedThreads / R;
+        constexpr int TPS = NT / R;
         const int i = tid / TPS, part = tid - (tid / TPS) * TPS;
         const long long row = s_rows[i];
         float v[2 * (kFusedMaxAct / TPS) + 1];
@@ -402,19 +600,17 @@ void fused_update_kernel(const FusedArgs a) {
         const float *sc = part == 0 ? a.logp_old : part == 1 ? a.adv : part == 2 ? a.returns : a.values_old;
         const bool want = part < 4 && (part < 2 ? net == 0 : net == 1) && (part != 3 || a.clip_value);
         v[2 * (kFusedMaxAct / TPS)] = want ? sc[row] : 0.0f;
-        gather_rows<R>(a, s_rows, rows, x, xp, wave, lane);
+        gather_rows<R, NT>(a, s_rows, rows, x, xp, wave, lane);
 #pragma unroll
         for (int u = 0; u < kFusedMaxAct / TPS; ++u) {
             const int j = part + TPS * u;
-            if (j < A) {
-                s_in[i * IW + j] = v[2 * u];
-                s_in[i * IW + A + j] = v[2 * u + 1];
-            }
+            s_in[i * kInW + j] = v[2 * u];
+            s_in[i * kInW + kFusedMaxAct + j] = v[2 * u + 1];
         }
-        if (part < 4) s_in[i * IW + 2 * A + part] = v[2 * (kFusedMaxAct / TPS)];
+        if (part < 4) s_in[i * kInW + 2 * kFusedMaxAct + part] = v[2 * (kFusedMaxAct / TPS)];
     }
     __syncthreads();
-    if (net == 0) copy_out(x, xp, a.xg + static_cast<long long>(m0) * a.kpad, a.kpad, a.kpad, rows);
+    if (net == 0) copy_out<NT>(x, xp, a.xg + static_cast<long long>(m0) * a.kpad, a.kpad, a.kpad, rows);
 
     // --------------------------------------------------------- forward
     const uint16_t *in = x;
@@ -422,155 +618,30 @@ void fused_update_kernel(const FusedArgs a) {
     for (int l = 0; l < L; ++l) {
         const int H = a.H[l];
         uint16_t *out = reinterpret_cast<uint16_t *>(lds + a.lds_region[l]);
-        run_layer<R, OCC, false>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave, lane);
+        run_layer<R, NT, WPE, false>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave, lane);
         __syncthreads();
-        copy_out(out, H + 8, N.h[l] + static_cast<long long>(m0) * H, H, H, rows);
+        copy_out<NT>(out, H + 8, N.h[l] + static_cast<long long>(m0) * H, H, H, rows);
         in = out;
         in_pitch = H + 8;
         K = H;
     }
 
     // ----------------------------------------- output layer and PPO loss
-    // KP adjacent lanes per sample, each with CK consecutive activations of
-    // the last hidden layer; partial dot products are combined with DPP lane
-    // swaps that leave the same value in every lane of the sample, so all of
-    // them compute the same loss terms and output gradients (the block sums
-    // take the first lane's).
     uint16_t *hl = reinterpret_cast<uint16_t *>(lds + a.lds_region[L - 1]);
     const int PL = Hl + 8;
-    const int si = tid / KP, kq = tid - (tid / KP) * KP;
-    const int CK = Hl / KP;               // activations per lane (multiple of 8, <= 64)
-    const int nck = CK >> 3;
-    const bool valid = si < rows;
-    const bool lead = valid && kq == 0;
-    const float *in_s = s_in + si * IW;
-    u32x4 hx[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-        if (c < nck) hx[c] = *reinterpret_cast<const u32x4 *>(hl + si * PL + kq * CK + 8 * c);
-    float o[kFusedMaxAct];
-    {
-#pragma unroll
-        for (int j = 0; j < kFusedMaxAct; ++j) o[j] = 0.0f;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            if (c >= nck) continue;
-            float xv[8];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                xv[2 * e] = lo_f(hx[c][e]);
-                xv[2 * e + 1] = hi_f(hx[c][e]);
-            }
-#pragma unroll
-            for (int j = 0; j < kFusedMaxAct; ++j) {
-                if (j >= n_out) continue;
-                const float *w = w_out + j * WP + kq * CK + 8 * c;
-                const float4 w0 = *reinterpret_cast<const float4 *>(w);
-                const float4 w1 = *reinterpret_cast<const float4 *>(w + 4);
-                o[j] += xv[0] * w0.x + xv[1] * w0.y + xv[2] * w0.z + xv[3] * w0.w + xv[4] * w1.x +
-                        xv[5] * w1.y + xv[6] * w1.z + xv[7] * w1.w;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kFusedMaxAct; ++j) {
-            if (j >= n_out) continue;
-            o[j] = kpart_sum<KP>(o[j]) + s_head[j];
-        }
-    }
-
-    float g[kFusedMaxAct];
-#pragma unroll
-    for (int j = 0; j < kFusedMaxAct; ++j) g[j] = 0.0f;
-    // per-sample loss terms: policy, value, clipped, ratio-KL, mean-shift KL, log-std gradient
-    float sums[kSums];
-#pragma unroll
-    for (int q = 0; q < kSums; ++q) sums[q] = 0.0f;
-    if (net == 0) {
-        // log-probability of the stored action in float64 (a sum of A terms of
-        // order 1 whose float32 rounding would dominate the ratio's error)
-        float z[kFusedMaxAct], inv_sig[kFusedMaxAct];
-        double logp = -0.5 * A * 1.8378770664093453;
-        float kl_mu = 0.0f;
-#pragma unroll
-        for (int j = 0; j < kFusedMaxAct; ++j) {
-            z[j] = 0.0f;
-            inv_sig[j] = 0.0f;
-            if (j >= A) continue;
-            const float ls = s_head[kFusedMaxAct + j];
-            const float inv_sigma = expf(-ls);
-            inv_sig[j] = inv_sigma;
-            z[j] = (in_s[j] - o[j]) * inv_sigma;
-            logp += -0.5 * static_cast<double>(z[j]) * z[j] - ls;
-            const float dm = (in_s[A + j] - o[j]) * inv_sigma;
-            kl_mu += 0.5f * dm * dm;
-        }
-        const float adv = in_s[2 * A + 1];
-        const float ratio = static_cast<float>(exp(logp - static_cast<double>(in_s[2 * A])));
-        const float lo = 1.0f - a.clip, hi = 1.0f + a.clip;
-        const bool active = adv >= 0.0f ? (ratio <= hi) : (ratio >= lo);
-        const float g_lp = valid && active ? -a.inv_m * adv * ratio : 0.0f;
-        if (lead) {
-            sums[0] = -fminf(ratio * adv, fminf(fmaxf(ratio, lo), hi) * adv);
-            sums[2] = fabsf(ratio - 1.0f) > a.clip ? 1.0f : 0.0f;
-            sums[3] = (ratio - 1.0f) - logf(ratio);
-            sums[4] = a.mu_old ? kl_mu : 0.0f;
-        }
-#pragma unroll
-        for (int j = 0; j < kFusedMaxAct; ++j) {
-            if (j >= A) continue;
-            g[j] = g_lp * z[j] * inv_sig[j];
-            if (lead) sums[5 + j] = g_lp * (z[j] * z[j] - 1.0f);
-        }
-    } else {
-        const float V = o[0];
-        const float ret = in_s[2 * A + 2], v_old = in_s[2 * A + 3];
-        const float diff = V - ret;
-        float pass = 1.0f, vl = diff * diff;
-        if (a.clip_value) {
-            const float vc = v_old + fminf(fmaxf(V - v_old, -a.clip), a.clip);
-            const float sqc = (vc - ret) * (vc - ret);
-            pass = vl >= sqc ? 1.0f : 0.0f;
-            vl = fmaxf(vl, sqc);
-        }
-        g[0] = valid ? 2.0f * a.value_coef * a.inv_m * diff * pass : 0.0f;
-        if (lead) sums[1] = vl;
-    }
-    if (lead) {
-        // output-layer gradient row, zero-padded to kHeadPad columns
-        uint32_t pk[kHeadPad / 2];
-#pragma unroll
-        for (int e = 0; e < kHeadPad / 2; ++e) pk[e] = pack2(g[2 * e], g[2 * e + 1]);
-        u32x4 *dst = reinterpret_cast<u32x4 *>(N.dzh + static_cast<long long>(m0 + si) * kHeadPad);
-        dst[0] = u32x4{pk[0], pk[1], pk[2], pk[3]};
-        dst[1] = u32x4{pk[4], pk[5], pk[6], pk[7]};
-    }
-    if (lead)
-#pragma unroll
-        for (int q = 0; q < kSums; ++q) s_sum[si * kSums + q] = sums[q];
-
-    // gradient into the last hidden pre-activations, in place over h_{L-1}
-    // (after every thread's copy of h_{L-1} to global memory has read it)
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        if (c >= nck) continue;
-        float dh[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) dh[e] = 0.0f;
-#pragma unroll
-        for (int j = 0; j < kFusedMaxAct; ++j) {
-            if (j >= n_out) continue;
-            const float *w = w_out + j * WP + kq * CK + 8 * c;
-            const float4 w0 = *reinterpret_cast<const float4 *>(w);
-            const float4 w1 = *reinterpret_cast<const float4 *>(w + 4);
-            dh[0] += g[j] * w0.x; dh[1] += g[j] * w0.y; dh[2] += g[j] * w0.z; dh[3] += g[j] * w0.w;
-            dh[4] += g[j] * w1.x; dh[5] += g[j] * w1.y; dh[6] += g[j] * w1.z; dh[7] += g[j] * w1.w;
-        }
-        u32x4 ov;
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            ov[e] = pack2(dh[2 * e] * delu(lo_f(hx[c][e])), dh[2 * e + 1] * delu(hi_f(hx[c][e])));
-        *reinterpret_cast<u32x4 *>(hl + si * PL + kq * CK + 8 * c) = ov;
+    switch ((Hl / KP) / 8) {
+    case 2:
+        if (net == 0) head_pass<R, NT, 2, true>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
+        else head_pass<R, NT, 2, false>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
+        break;
+    case 4:
+        if (net == 0) head_pass<R, NT, 4, true>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
+        else head_pass<R, NT, 4, false>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
+        break;
+    default:
+        if (net == 0) head_pass<R, NT, 8, true>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
+        else head_pass<R, NT, 8, false>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
+        break;
     }
     __syncthreads();
     // block sums over the samples in order, one thread per term
@@ -615,16 +686,16 @@ void fused_update_kernel(const FusedArgs a) {
             out[1] = t[1];
         }
     }
-    copy_out(hl, PL, N.dz[L - 1] + static_cast<long long>(m0) * Hl, Hl, Hl, rows);
+    copy_out<NT>(hl, PL, N.dz[L - 1] + static_cast<long long>(m0) * Hl, Hl, Hl, rows);
 
     // ------------------------------------------------ input-gradient chain
     for (int l = L - 1; l >= 1; --l) {
         const int Hin = a.H[l], Hout = a.H[l - 1];
         const uint16_t *dz = reinterpret_cast<const uint16_t *>(lds + a.lds_region[l]);
         uint16_t *hz = reinterpret_cast<uint16_t *>(lds + a.lds_region[l - 1]);
-        run_layer<R, OCC, true>(N.WT[l], Hin, Hout, nullptr, dz, Hin + 8, hz, Hout + 8, wave, lane);
+        run_layer<R, NT, WPE, true>(N.WT[l], Hin, Hout, nullptr, dz, Hin + 8, hz, Hout + 8, wave, lane);
         __syncthreads();
-        copy_out(hz, Hout + 8, N.dz[l - 1] + static_cast<long long>(m0) * Hout, Hout, Hout, rows);
+        copy_out<NT>(hz, Hout + 8, N.dz[l - 1] + static_cast<long long>(m0) * Hout, Hout, Hout, rows);
     }
 }
 
@@ -667,19 +738,19 @@ __global__ __launch_bounds__(256) void pack_frags_kernel(const FragArgs a) {
 size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
 
 // LDS layout for R rows; returns the total bytes (0 if a constraint fails).
-size_t fused_layout(int L, const int *H, int kpad, int A, int R, FusedArgs *a) {
-    const int KP = kFusedThreads / R;
+size_t fused_layout(int L, const int *H, int kpad, int A, int R, int NT, FusedArgs *a) {
+    const int KP = NT / R;
     const int Hl = H[L - 1];
-    if (Hl % KP != 0 || (Hl / KP) % 8 != 0 || Hl / KP > 64) return 0;
+    if (Hl % KP != 0 || (Hl / KP != 16 && Hl / KP != 32 && Hl / KP != 64)) return 0;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const int at = static_cast<int>(off);
         off += align16(bytes);
         return at;
     };
-    const int lds_w = take(static_cast<size_t>(A) * (Hl + 4) * 4);
+    const int lds_w = take(static_cast<size_t>(kFusedMaxAct) * (Hl + 4) * 4);
     const int lds_sum = take(static_cast<size_t>(R + 1) * kSums * 4);
-    const int lds_in = take(static_cast<size_t>(R) * (2 * A + 4) * 4);
+    const int lds_in = take(static_cast<size_t>(R) * kInW * 4);
     const int lds_rows = take(static_cast<size_t>(R) * 4);
     const int lds_head = take(static_cast<size_t>(2 * kFusedMaxAct) * 4);
     int bias_off[kMaxHidden] = {0};
@@ -713,34 +784,44 @@ size_t fused_layout(int L, const int *H, int kpad, int A, int R, FusedArgs *a) {
     return off;
 }
 
-}  // namespace
-
-// Two workgroups share a CU when 32-row blocks fit in half the LDS and the
-// layers are at most 512 wide (accumulators within a 256-register budget).
-bool fused_two_per_cu(int L, const int *H, int kpad, int A, int R) {
-    if (R != 32) return false;
-    for (int l = 0; l < L; ++l)
-        if (H[l] > 4 * 32 * kWaves) return false;
-    return fused_layout(L, H, kpad, A, 32, nullptr) <= static_cast<size_t>(kMaxLdsBytes / 2);
+// Whether R rows per workgroup of NT threads cover this network: every
+// layer width splits over the waves as run_layer does, the output layer's
+// per-lane slice is 16 to 64 activations, and the LDS layout fits (in half
+// of it for two workgroups per CU).
+bool fused_fits(int L, const int *H, int kpad, int A, int R, int NT, bool two_per_cu) {
+    const int NW = NT / 64, SB = R / 32;
+    const bool wide_ok = SB == 1 && NT == 256 && !two_per_cu;   // the WIDE case of run_layer
+    for (int l = 0; l < L; ++l) {
+        const int fb = H[l] / 32;
+        if (H[l] % 32 != 0) return false;
+        if (fb >= NW) {
+            const int fbw = fb / NW;
+            if (fb % NW != 0 || (fbw != 1 && fbw != 2 && fbw != 4 && !(fbw == 8 && wide_ok))) return false;
+        } else if (!(SB >= 2 && 2 * fb == NW)) {
+            return false;
+        }
+    }
+    const size_t bytes = fused_layout(L, H, kpad, A, R, NT, nullptr);
+    return bytes > 0 && bytes <= static_cast<size_t>(two_per_cu ? kMaxLdsBytes / 2 : kMaxLdsBytes);
 }
 
-int fused_rows(int L, const int *H, int kpad, int A, int prefer) {
-    if (L < 1 || L > kMaxHidden || A < 1 || A > kFusedMaxAct || kpad < 16 || kpad % 16 != 0) return 0;
-    int maxh = 0;
-    for (int l = 0; l < L; ++l) {
-        const int f = H[l] / (32 * kWaves);
-        if (H[l] % (32 * kWaves) != 0 || (f != 1 && f != 2 && f != 4 && f != 8)) return 0;
-        maxh = H[l] > maxh ? H[l] : maxh;
+}  // namespace
+
+FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows, int prefer_threads) {
+    FusedShape none{0, 0, 0};
+    if (L < 1 || L > kMaxHidden || A < 1 || A > kFusedMaxAct || kpad < 16 || kpad % 16 != 0) return none;
+    // candidates in order of preference: 32 rows x 4 waves with two
+    // workgroups per CU (one hides the other's prologue, head and barrier
+    // latencies); 64 rows x 8 waves (each weight fragment feeds two MFMAs,
+    // two waves per SIMD, one workgroup per CU); 32 rows x 8 waves; 64 rows x
+    // 4 waves
+    const FusedShape cand[4] = {{32, 256, 2}, {64, 512, 1}, {32, 512, 1}, {64, 256, 1}};
+    for (const FusedShape &c : cand) {
+        if (prefer_rows && c.rows != prefer_rows) continue;
+        if (prefer_threads && c.threads != prefer_threads) continue;
+        if (fused_fits(L, H, kpad, A, c.rows, c.threads, c.per_cu == 2)) return c;
     }
-    const bool ok64 = maxh <= 4 * 32 * kWaves && fused_layout(L, H, kpad, A, 64, nullptr) > 0;
-    const bool ok32 = maxh <= 8 * 32 * kWaves && fused_layout(L, H, kpad, A, 32, nullptr) > 0;
-    if (prefer == 64 && ok64) return 64;
-    if (prefer == 32 && ok32) return 32;
-    // two 32-row workgroups per CU hide each other's latencies better than
-    // one 64-row workgroup, which reads each weight half as often
-    if (ok32 && fused_two_per_cu(L, H, kpad, A, 32)) return 32;
-    if (ok64) return 64;
-    return ok32 ? 32 : 0;
+    return none;
 }
 
 int fused_blocks(int M, int R) { return R > 0 ? (M + R - 1) / R : 0; }
@@ -759,29 +840,32 @@ hipError_t launch_pack_frags(const FragArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_fused_update(FusedArgs a, hipStream_t s) {
-    const int R = a.R;
-    if ((R != 32 && R != 64) || a.M < 1) return hipErrorInvalidValue;
-    const size_t bytes = fused_layout(a.L, a.H, a.kpad, a.A, R, &a);
+    const FusedShape sh = fused_shape(a.L, a.H, a.kpad, a.A, a.R, a.NT);
+    if (sh.rows == 0 || a.M < 1) return hipErrorInvalidValue;
+    const size_t bytes = fused_layout(a.L, a.H, a.kpad, a.A, sh.rows, sh.threads, &a);
     if (bytes == 0) return hipErrorInvalidValue;
-    a.blocks = fused_blocks(a.M, R);
+    a.blocks = fused_blocks(a.M, sh.rows);
     static bool attr_set = false;
     if (!attr_set) {
-        const void *fns[3] = {reinterpret_cast<const void *>(&fused_update_kernel<64, 1>),
-                              reinterpret_cast<const void *>(&fused_update_kernel<32, 1>),
-                              reinterpret_cast<const void *>(&fused_update_kernel<32, 2>)};
+        const void *fns[4] = {reinterpret_cast<const void *>(&fused_update_kernel<64, 512, 2>),
+                              reinterpret_cast<const void *>(&fused_update_kernel<32, 256, 2>),
+                              reinterpret_cast<const void *>(&fused_update_kernel<32, 512, 2>),
+                              reinterpret_cast<const void *>(&fused_update_kernel<64, 256, 1>)};
         for (const void *fn : fns) {
             const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
             if (e != hipSuccess) return e;
         }
         attr_set = true;
     }
-    const dim3 grid(2 * a.blocks), block(kFusedThreads);
-    if (R == 64)
-        hipLaunchKernelGGL((fused_update_kernel<64, 1>), grid, block, bytes, s, a);
-    else if (fused_two_per_cu(a.L, a.H, a.kpad, a.A, R))
-        hipLaunchKernelGGL((fused_update_kernel<32, 2>), grid, block, bytes, s, a);
+    const dim3 grid(2 * a.blocks), block(sh.threads);
+    if (sh.rows == 64 && sh.threads == 512)
+        hipLaunchKernelGGL((fused_update_kernel<64, 512, 2>), grid, block, bytes, s, a);
+    else if (sh.rows == 32 && sh.threads == 256)
+        hipLaunchKernelGGL((fused_update_kernel<32, 256, 2>), grid, block, bytes, s, a);
+    else if (sh.rows == 32)
+        hipLaunchKernelGGL((fused_update_kernel<32, 512, 2>), grid, block, bytes, s, a);
     else
-        hipLaunchKernelGGL((fused_update_kernel<32, 1>), grid, block, bytes, s, a);
+        hipLaunchKernelGGL((fused_update_kernel<64, 256, 1>), grid, block, bytes, s, a);
     return hipGetLastError();
 }
 

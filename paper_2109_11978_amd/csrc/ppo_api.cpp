@@ -865,21 +865,25 @@ bool fused_env_enabled() {
 }
 
 
-// Samples per workgroup of the fused per-sample pass for this step, or 0 for
-// the layer-by-layer kernels: bf16 only, a network shape the fused kernel
-// covers, 16-byte aligned weights and biases, and offsets that fit its
-// 32-bit buffer addressing.  PPO_FUSED=0 forces the layer-by-layer path.
-int fused_rows_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, const ppo_batch *b) {
-    if (c->prec != kBF16 || !fused_env_enabled()) return 0;
+// Shape of the fused per-sample pass for this step, or rows = 0 for the
+// layer-by-layer kernels: bf16 only, a network shape the fused kernel
+// covers, 16-byte aligned biases, and observation offsets that fit its
+// 32-bit buffer addressing.  PPO_FUSED=0 forces the layer-by-layer path;
+// PPO_FUSED_ROWS and PPO_FUSED_THREADS restrict the block shape.
+FusedShape fused_shape_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, const ppo_batch *b) {
+    const FusedShape none{0, 0, 0};
+    if (c->prec != kBF16 || !fused_env_enabled()) return none;
     const NetLayout &g = c->g;
-    const char *pref = std::getenv("PPO_FUSED_ROWS");
-    const int R = fused_rows(g.L, g.H, w.kpad, g.A, pref ? std::atoi(pref) : 0);
-    if (R == 0) return 0;
-    if (static_cast<long long>(b->B) * g.D * 4 > 0x7FFFFFF0LL - 0x100000LL) return 0;
+    const char *rows = std::getenv("PPO_FUSED_ROWS");
+    const char *threads = std::getenv("PPO_FUSED_THREADS");
+    const FusedShape sh = fused_shape(g.L, g.H, w.kpad, g.A, rows ? std::atoi(rows) : 0,
+                                      threads ? std::atoi(threads) : 0);
+    if (sh.rows == 0) return none;
+    if (static_cast<long long>(b->B) * g.D * 4 > 0x7FFFFFF0LL - 0x100000LL) return none;
     for (int net = 0; net < 2; ++net)
         for (int l = 0; l < g.L; ++l)
-            if (!aligned16(p->theta + (net == 0 ? g.ba[l] : g.bc[l]))) return 0;
-    return R;
+            if (!aligned16(p->theta + (net == 0 ? g.ba[l] : g.bc[l]))) return none;
+    return sh;
 }
 
 // Packing of the bf16 shadow weights into fragment order for the fused pass.
@@ -969,13 +973,15 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
     const int L = g.L;
     hipError_t e;
 
-    const int fused_r = fused_rows_for(c, p, w, sb.b);
+    const FusedShape fsh = fused_shape_for(c, p, w, sb.b);
+    const int fused_r = fsh.rows;
     if (fused_r > 0) {
         // weights into fragment order, then gather, forward, loss and input
         // gradients of both networks in one launch
         PROFILED(prof, PPO_PHASE_GATHER, launch_pack_frags(build_frags(c, p, w, ws), s));
         FusedArgs fa = fused_args(c, p, hp, w, ws, sb.b, sb.idx, M);
-        fa.R = fused_r;
+        fa.R = fsh.rows;
+        fa.NT = fsh.threads;
         PROFILED(prof, PPO_PHASE_FUSED, launch_fused_update(fa, s));
     } else {
         PROFILED(prof, PPO_PHASE_GATHER, launch_stage_weights(prec, build_stage(c, p, w, ws, true), s));
