@@ -215,8 +215,10 @@ def recorded_traffic(wl, phase, workload):
     M, H = cfg.minibatch, list(cfg.net.hidden)
     keys = []
     if phase == "fused":
-        rows = 64 if max(H) <= 512 else 32
-        keys.append(f"hbm_bytes.fused_update_kernel<{rows}>.{2 * -(-M // rows)}")
+        rows, _ = wl.ctx.fused_shape()
+        if rows == 0:
+            return None
+        keys.append(f"hbm_bytes.fused_update_kernel.{2 * -(-M // rows)}")
     else:
         tiles = wl.ctx.tuning(M, True)
         if phase == "forward":

@@ -311,6 +311,14 @@ int ppo_gemm_check(void *stream, int32_t precision, int32_t a_mode, int32_t b_mo
  * gradients.  capacity >= 18.  PPO_E_SHAPE if nothing was tuned yet. */
 int ppo_ctx_tuning(const ppo_ctx *ctx, int32_t rows, int32_t update, int32_t *choices, int32_t capacity);
 
+/* Block shape of the fused per-sample pass that bf16 update steps of this
+ * network take: *rows samples per workgroup of *threads threads (both 0 when
+ * the layer-by-layer kernels run: fp32, PPO_FUSED=0, or a network shape the
+ * fused kernel does not cover).  Reflects PPO_FUSED, PPO_FUSED_ROWS and
+ * PPO_FUSED_THREADS as set now; a step also falls back for batches of more
+ * than 2^31 bytes of observations or misaligned biases.  Host only. */
+int ppo_fused_shape(const ppo_ctx *ctx, int32_t *rows, int32_t *threads);
+
 /* Debug/verification: raw Philox4x32-10 blocks.  out[4 i + w] = word w of
  * Philox(counter = (c0_base + i mod 2^32, c1, c2, c3), key = (seed mod 2^32,
  * seed >> 32)) for i in [0, n).  n in 1..2^28. */

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 from dataclasses import dataclass
-from typing import Dict, Optional, Sequence
+from typing import Dict, Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -136,6 +136,13 @@ class Context:
                 out[f"input_grad_{l + 1}"] = self.TILE_NAMES[arr[2 * (4 + l)]]
             out["weight_grad"] = f"{self.TILE_NAMES[arr[16]]} x {arr[17]} round(s) of splits"
         return out
+
+    def fused_shape(self) -> Tuple[int, int]:
+        """(samples, threads) per workgroup of the fused bf16 update pass, or
+        (0, 0) when update steps run the layer-by-layer kernels."""
+        r, t = ctypes.c_int32(0), ctypes.c_int32(0)
+        check(_lib().ppo_fused_shape(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        return r.value, t.value
 
     def new_workspace(self, N: int = 0, T: int = 0, M: int = 0, device="cuda") -> torch.Tensor:
         nbytes = self.workspace_size(N, T, M)

@@ -1901,6 +1901,21 @@ int ppo_ctx_tuning(const ppo_ctx *c, int32_t rows, int32_t update, int32_t *choi
     return PPO_OK;
 }
 
+int ppo_fused_shape(const ppo_ctx *c, int32_t *rows, int32_t *threads) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    if (!rows || !threads) return fail(PPO_E_INVAL, "rows or threads is NULL");
+    *rows = 0;
+    *threads = 0;
+    if (c->prec != kBF16 || !fused_env_enabled()) return PPO_OK;
+    const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, 1);
+    const char *r = std::getenv("PPO_FUSED_ROWS");
+    const char *t = std::getenv("PPO_FUSED_THREADS");
+    const FusedShape sh = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, r ? std::atoi(r) : 0, t ? std::atoi(t) : 0);
+    *rows = sh.rows;
+    *threads = sh.threads;
+    return PPO_OK;
+}
+
 int ppo_philox_blocks(void *stream, uint64_t seed, uint32_t c0_base, uint32_t c1, uint32_t c2, uint32_t c3,
                       int64_t n, uint32_t *out) {
     if (n < 1 || n > (static_cast<int64_t>(1) << 28)) return fail(PPO_E_SHAPE, "n = %lld outside 1..2^28", (long long)n);

@@ -182,3 +182,29 @@ def test_adaptive_rate_validation():
         hb = bad.abi()
         assert lib.ppo_update_epoch(ctx.handle, None, ctypes.byref(p), ctypes.byref(b3), FAKE, 1, ctypes.byref(hb),
                                     FAKE, FAKE, ws) == ppo.PPO_E_INVAL, bad
+
+
+@pytest.mark.parametrize("shape,prec,env,expect", [
+    ((48, 12, (512, 256, 128)), "bf16", {}, (32, 256)),
+    ((235, 12, (512, 256, 128)), "bf16", {}, (32, 256)),
+    ((235, 12, (1024, 512, 256)), "bf16", {}, (32, 512)),
+    ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "64"}, (64, 512)),
+    ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "64", "PPO_FUSED_THREADS": "256"}, (64, 256)),
+    ((235, 12, (1024, 512, 256)), "bf16", {"PPO_FUSED_ROWS": "64"}, (0, 0)),
+    ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED": "0"}, (0, 0)),
+    ((48, 12, (512, 256, 128)), "fp32", {}, (0, 0)),
+    ((48, 12, (64, 64)), "bf16", {}, (64, 256)),        # two waves per feature block
+    ((48, 12, (32, 32)), "bf16", {}, (0, 0)),           # one feature block for four waves
+    ((40, 12, (512, 256, 128)), "bf16", {}, (0, 0)),    # input width not a multiple of 16
+    ((48, 12, (384, 256, 128)), "bf16", {}, (0, 0)),    # 12 feature blocks over 4 waves: 3 per wave
+])
+def test_fused_shape_selection(monkeypatch, shape, prec, env, expect):
+    """Which bf16 update steps take the fused per-sample pass, and its block
+    shape (host-side rule; no GPU needed)."""
+    for k in ("PPO_FUSED", "PPO_FUSED_ROWS", "PPO_FUSED_THREADS"):
+        monkeypatch.delenv(k, raising=False)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    D, A, H = shape
+    ctx = ppo.Context(D, A, H, prec)
+    assert ctx.fused_shape() == expect
