@@ -140,6 +140,11 @@ struct FusedArgs {
     float *partials;                  // [blocks][A + 8], the layout of HeadLossArgs::partials
     float clip, value_coef, inv_m;
     int clip_value;
+    // rollout inference (launch_fused_infer): outputs for the M environments
+    // of obs (each may be null), Philox key and counter words, networks to run
+    float *act_out, *logp_out, *val_out, *mu_out;
+    uint32_t key0, key1, t_step, iteration;
+    int net_mask;                     // bit 0: actor, bit 1: critic
     int R, NT;                        // samples and threads per workgroup (a fused_shape)
     // filled in by launch_fused_update
     int blocks;
@@ -157,6 +162,8 @@ struct FusedShape {
 FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows = 0, int prefer_threads = 0);
 int fused_blocks(int M, int R);
 hipError_t launch_fused_update(FusedArgs a, hipStream_t s);
+// Forward pass and sampling head for M environments (rows of obs in order).
+hipError_t launch_fused_infer(FusedArgs a, hipStream_t s);
 
 // -------------------------------------------------------- other kernels ---
 hipError_t launch_philox_blocks(hipStream_t s, uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,

@@ -23,6 +23,7 @@
 // is read from L2 once per workgroup; PF k-steps of weight fragments are in
 // flight ahead of the MFMAs.
 #include "common.hpp"
+#include "philox.hpp"
 
 namespace ppo {
 namespace {
@@ -356,6 +357,38 @@ __device__ inline float kpart_sum(float v) {
     return v;
 }
 
+// Output-layer values o[j] = b_j + h . W_j (j < NO) of one sample: each of
+// its KP lanes loads NCK 8-element chunks of h (kept in hx for the caller)
+// and multiplies them with its slice of the staged float32 weights; the
+// partial sums are combined with DPP lane swaps that leave the same value in
+// every lane of the sample.
+template <int KP, int NCK, int NO>
+__device__ __forceinline__ void head_dots(const uint16_t *hrow, const float *wl, int WP, const float *s_head,
+                                          u32x4 (&hx)[NCK], float (&o)[NO]) {
+#pragma unroll
+    for (int c = 0; c < NCK; ++c) hx[c] = *reinterpret_cast<const u32x4 *>(hrow + 8 * c);
+#pragma unroll
+    for (int j = 0; j < NO; ++j) o[j] = 0.0f;
+#pragma unroll
+    for (int c = 0; c < NCK; ++c) {
+        float xv[8];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            xv[2 * e] = lo_f(hx[c][e]);
+            xv[2 * e + 1] = hi_f(hx[c][e]);
+        }
+#pragma unroll
+        for (int j = 0; j < NO; ++j) {
+            const float4 w0 = *reinterpret_cast<const float4 *>(wl + j * WP + 8 * c);
+            const float4 w1 = *reinterpret_cast<const float4 *>(wl + j * WP + 8 * c + 4);
+            o[j] += xv[0] * w0.x + xv[1] * w0.y + xv[2] * w0.z + xv[3] * w0.w + xv[4] * w1.x + xv[5] * w1.y +
+                    xv[6] * w1.z + xv[7] * w1.w;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NO; ++j) o[j] = kpart_sum<KP>(o[j]) + s_head[j];
+}
+
 // Output layer, PPO loss terms and output gradients of the block's samples.
 // KP = NT / R adjacent lanes per sample, NCK 8-element chunks of
 // the last hidden layer per lane; the actor computes kFusedMaxAct outputs
@@ -382,29 +415,8 @@ __device__ __forceinline__ void head_pass(const FusedArgs &a, const FusedNet &N,
     uint16_t *hrow = hl + si * PL + kq * CK;
     const float *wl = w_out + kq * CK;
     u32x4 hx[NCK];
-#pragma unroll
-    for (int c = 0; c < NCK; ++c) hx[c] = *reinterpret_cast<const u32x4 *>(hrow + 8 * c);
     float o[NO];
-#pragma unroll
-    for (int j = 0; j < NO; ++j) o[j] = 0.0f;
-#pragma unroll
-    for (int c = 0; c < NCK; ++c) {
-        float xv[8];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            xv[2 * e] = lo_f(hx[c][e]);
-            xv[2 * e + 1] = hi_f(hx[c][e]);
-        }
-#pragma unroll
-        for (int j = 0; j < NO; ++j) {
-            const float4 w0 = *reinterpret_cast<const float4 *>(wl + j * WP + 8 * c);
-            const float4 w1 = *reinterpret_cast<const float4 *>(wl + j * WP + 8 * c + 4);
-            o[j] += xv[0] * w0.x + xv[1] * w0.y + xv[2] * w0.z + xv[3] * w0.w + xv[4] * w1.x + xv[5] * w1.y +
-                    xv[6] * w1.z + xv[7] * w1.w;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < NO; ++j) o[j] = kpart_sum<KP>(o[j]) + s_head[j];
+    head_dots<KP, NCK, NO>(hrow, wl, WP, s_head, hx, o);
 
     float g[NO];
     float sums[kSums];
@@ -735,6 +747,153 @@ __global__ __launch_bounds__(256) void pack_frags_kernel(const FragArgs a) {
     *reinterpret_cast<u32x4 *>(J.dst + static_cast<long long>(local) * 8) = u32x4{v[0], v[1], v[2], v[3]};
 }
 
+// Rollout inference for R environments of one network per workgroup: the
+// observation rows, every hidden layer with the activations in LDS, the
+// output layer, then for the actor the diagonal-Gaussian action
+// a = mu + sigma eps with Philox noise (counter (n * groups + g, t,
+// iteration, 1) for the g-th group of four actions of environment n, two
+// Box-Muller pairs per draw) and its log-density
+// sum_j (-eps_j^2 / 2 - log sigma_j) - (A / 2) log(2 pi); for the critic the
+// value.  Same draws, formulas and float64 log-density as the
+// layer-by-layer sampling kernel; only the output layer's summation order
+// differs.
+template <int R, int NT, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
+void fused_infer_kernel(const FusedArgs a) {
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    constexpr int KP = NT / R;
+    const bool both = a.net_mask == 3;
+    const int net = both ? static_cast<int>(blockIdx.x & 1) : (a.net_mask == 1 ? 0 : 1);
+    const int m0 = static_cast<int>(both ? blockIdx.x >> 1 : blockIdx.x) * R;
+    const int rows = min(R, a.M - m0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int L = a.L, A = a.A;
+    const int Hl = a.H[L - 1];
+    const int n_out = net == 0 ? A : 1;
+    const int WP = Hl + 4;
+    float *w_out = reinterpret_cast<float *>(lds + a.lds_w);
+    float *s_bias = reinterpret_cast<float *>(lds + a.lds_bias);
+    float *s_head = reinterpret_cast<float *>(lds + a.lds_head);
+    int *s_rows = reinterpret_cast<int *>(lds + a.lds_rows);
+    const FusedNet &N = a.net[net];
+
+    if (tid < R) s_rows[tid] = m0 + min(tid, rows - 1);
+    {
+        // output-layer weights, output biases, log-std and hidden biases in one
+        // round of buffer loads, then the LDS stores (as in the update pass)
+        constexpr int UW = 16, UB = 4;
+        const int nw = n_out * Hl;
+        const __amdgpu_buffer_rsrc_t rw = make_rsrc(N.Wout, static_cast<long long>(nw) * 4);
+        float vw[UW], vb[kMaxHidden][UB];
+#pragma unroll
+        for (int u = 0; u < UW; ++u) {
+            const int q = tid + u * NT;
+            vw[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, q < nw ? q * 4 : kOutside, 0, 0));
+        }
+#pragma unroll
+        for (int l = 0; l < kMaxHidden; ++l) {
+            const int H = l < L ? a.H[l] : 0;
+            const __amdgpu_buffer_rsrc_t rb = make_rsrc(N.bias[l], static_cast<long long>(H) * 4);
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int q = tid + u * NT;
+                vb[l][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, q < H ? q * 4 : kOutside, 0, 0));
+            }
+        }
+        const __amdgpu_buffer_rsrc_t ro = make_rsrc(N.bout, static_cast<long long>(n_out) * 4);
+        const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.logstd, static_cast<long long>(A) * 4);
+        const float vo = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ro, tid < n_out ? tid * 4 : kOutside, 0, 0));
+        const float vl = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rl, tid < A ? tid * 4 : kOutside, 0, 0));
+#pragma unroll
+        for (int u = 0; u < UW; ++u) {
+            const int q = tid + u * NT;
+            const int j = q / Hl;
+            if (q < nw) w_out[j * WP + (q - j * Hl)] = vw[u];
+        }
+#pragma unroll
+        for (int l = 0; l < kMaxHidden; ++l) {
+            if (l >= L) continue;
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int q = tid + u * NT;
+                if (q < a.H[l]) s_bias[a.bias_off[l] + q] = vb[l][u];
+            }
+        }
+        if (tid < kFusedMaxAct) {
+            s_head[tid] = tid < n_out ? vo : 0.0f;
+            s_head[kFusedMaxAct + tid] = tid < A ? vl : 0.0f;
+        }
+        for (int q = nw + tid; q < kFusedMaxAct * Hl; q += NT) {
+            const int j = q / Hl;
+            w_out[j * WP + (q - j * Hl)] = 0.0f;
+        }
+        for (int q = tid + UW * NT; q < nw; q += NT) {
+            const int j = q / Hl;
+            w_out[j * WP + (q - j * Hl)] = N.Wout[q];
+        }
+    }
+    __syncthreads();
+    uint16_t *x = reinterpret_cast<uint16_t *>(lds + a.lds_x);
+    const int xp = a.kpad + 8;
+    gather_rows<R, NT>(a, s_rows, rows, x, xp, wave, lane);
+    __syncthreads();
+
+    const uint16_t *in = x;
+    int in_pitch = xp, K = a.kpad;
+    for (int l = 0; l < L; ++l) {
+        const int H = a.H[l];
+        uint16_t *out = reinterpret_cast<uint16_t *>(lds + a.lds_region[l]);
+        run_layer<R, NT, WPE, false>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave, lane);
+        __syncthreads();
+        in = out;
+        in_pitch = H + 8;
+        K = H;
+    }
+
+    const uint16_t *hl = reinterpret_cast<const uint16_t *>(lds + a.lds_region[L - 1]);
+    const int si = tid / KP, kq = tid % KP;
+    const bool lead = si < rows && kq == 0;
+    const int n = m0 + si;
+    const int nck = (Hl / KP) / 8;
+    const uint16_t *hrow = hl + si * (Hl + 8) + kq * (Hl / KP);
+    const float *wl = w_out + kq * (Hl / KP);
+    if (net == 1) {
+        float o[1];
+        if (nck == 2) { u32x4 hx[2]; head_dots<KP, 2, 1>(hrow, wl, WP, s_head, hx, o); }
+        else if (nck == 4) { u32x4 hx[4]; head_dots<KP, 4, 1>(hrow, wl, WP, s_head, hx, o); }
+        else { u32x4 hx[8]; head_dots<KP, 8, 1>(hrow, wl, WP, s_head, hx, o); }
+        if (lead && a.val_out) a.val_out[n] = o[0];
+        return;
+    }
+    float o[kFusedMaxAct];
+    if (nck == 2) { u32x4 hx[2]; head_dots<KP, 2, kFusedMaxAct>(hrow, wl, WP, s_head, hx, o); }
+    else if (nck == 4) { u32x4 hx[4]; head_dots<KP, 4, kFusedMaxAct>(hrow, wl, WP, s_head, hx, o); }
+    else { u32x4 hx[8]; head_dots<KP, 8, kFusedMaxAct>(hrow, wl, WP, s_head, hx, o); }
+    if (!lead) return;
+    const int groups = (A + 3) / 4;
+    double logp = -0.5 * A * 1.8378770664093453;
+#pragma unroll
+    for (int g = 0; g < kFusedMaxAct / 4; ++g) {
+        if (g >= groups) break;
+        uint32_t c[4] = {static_cast<uint32_t>(n) * groups + g, a.t_step, a.iteration, 1u};
+        philox4x32_10(c, a.key0, a.key1);
+        float eps[4];
+        box_muller(c[0], c[1], eps[0], eps[1]);
+        box_muller(c[2], c[3], eps[2], eps[3]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * g + q;
+            if (j >= A) break;
+            const float m = o[j];
+            const float ls = s_head[kFusedMaxAct + j];
+            logp += -0.5 * static_cast<double>(eps[q]) * eps[q] - ls;
+            if (a.act_out) a.act_out[static_cast<long long>(n) * A + j] = m + expf(ls) * eps[q];
+            if (a.mu_out) a.mu_out[static_cast<long long>(n) * A + j] = m;
+        }
+    }
+    if (a.logp_out) a.logp_out[n] = static_cast<float>(logp);
+}
+
 size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
 
 // LDS layout for R rows; returns the total bytes (0 if a constraint fails).
@@ -836,6 +995,36 @@ void add_frag_job(FragArgs &a, const FragJob &j) {
 hipError_t launch_pack_frags(const FragArgs &a, hipStream_t s) {
     if (a.total == 0) return hipSuccess;
     hipLaunchKernelGGL(pack_frags_kernel, dim3((a.total + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_infer(FusedArgs a, hipStream_t s) {
+    const FusedShape sh = fused_shape(a.L, a.H, a.kpad, a.A, a.R, a.NT);
+    if (sh.rows == 0 || a.M < 1 || a.net_mask < 1 || a.net_mask > 3) return hipErrorInvalidValue;
+    const size_t bytes = fused_layout(a.L, a.H, a.kpad, a.A, sh.rows, sh.threads, &a);
+    if (bytes == 0) return hipErrorInvalidValue;
+    a.blocks = fused_blocks(a.M, sh.rows);
+    static bool attr_set = false;
+    if (!attr_set) {
+        const void *fns[4] = {reinterpret_cast<const void *>(&fused_infer_kernel<64, 512, 2>),
+                              reinterpret_cast<const void *>(&fused_infer_kernel<32, 256, 2>),
+                              reinterpret_cast<const void *>(&fused_infer_kernel<32, 512, 2>),
+                              reinterpret_cast<const void *>(&fused_infer_kernel<64, 256, 1>)};
+        for (const void *fn : fns) {
+            const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
+            if (e != hipSuccess) return e;
+        }
+        attr_set = true;
+    }
+    const dim3 grid((a.net_mask == 3 ? 2 : 1) * a.blocks), block(sh.threads);
+    if (sh.rows == 64 && sh.threads == 512)
+        hipLaunchKernelGGL((fused_infer_kernel<64, 512, 2>), grid, block, bytes, s, a);
+    else if (sh.rows == 32 && sh.threads == 256)
+        hipLaunchKernelGGL((fused_infer_kernel<32, 256, 2>), grid, block, bytes, s, a);
+    else if (sh.rows == 32)
+        hipLaunchKernelGGL((fused_infer_kernel<32, 512, 2>), grid, block, bytes, s, a);
+    else
+        hipLaunchKernelGGL((fused_infer_kernel<64, 256, 1>), grid, block, bytes, s, a);
     return hipGetLastError();
 }
 

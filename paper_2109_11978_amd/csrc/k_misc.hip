@@ -3,6 +3,7 @@
 // PPO loss and its output gradients (update), GAE with the float64 advantage
 // statistics, gradient assembly with the float64 global norm, and Adam.
 #include "common.hpp"
+#include "philox.hpp"
 
 namespace ppo {
 namespace {
@@ -13,34 +14,6 @@ constexpr float kLog2Pi = 1.8378770664093453f;
 constexpr int kMaxAct = 16;
 
 // ------------------------------------------------------------------ Philox
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
-// multiplies with key bumps by the Weyl constants between rounds.
-__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint32_t a = c[0], b = c[2];
-        const uint32_t hi_a = __umulhi(0xD2511F53u, a), lo_a = 0xD2511F53u * a;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, b), lo_b = 0xCD9E8D57u * b;
-        c[0] = hi_b ^ c[1] ^ k0;
-        c[1] = lo_b;
-        c[2] = hi_a ^ c[3] ^ k1;
-        c[3] = lo_a;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-// Top 23 bits plus half a step: exact in float32, strictly inside (0, 1).
-__device__ inline float uniform23(uint32_t x) { return (static_cast<float>(x >> 9) + 0.5f) * 1.1920928955078125e-07f; }
-
-__device__ inline void box_muller(uint32_t xa, uint32_t xb, float &ea, float &eb) {
-    const float r = sqrtf(-2.0f * logf(uniform23(xa)));
-    float s, c;
-    sincospif(2.0f * uniform23(xb), &s, &c);
-    ea = r * c;
-    eb = r * s;
-}
-
 __global__ void philox_blocks_kernel(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
                                      uint32_t c3, long long n, uint32_t *out) {
     for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;

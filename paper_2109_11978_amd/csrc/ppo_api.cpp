@@ -870,7 +870,7 @@ bool fused_env_enabled() {
 // covers, 16-byte aligned biases, and observation offsets that fit its
 // 32-bit buffer addressing.  PPO_FUSED=0 forces the layer-by-layer path;
 // PPO_FUSED_ROWS and PPO_FUSED_THREADS restrict the block shape.
-FusedShape fused_shape_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, const ppo_batch *b) {
+FusedShape fused_shape_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, int obs_rows) {
     const FusedShape none{0, 0, 0};
     if (c->prec != kBF16 || !fused_env_enabled()) return none;
     const NetLayout &g = c->g;
@@ -879,7 +879,7 @@ FusedShape fused_shape_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &
     const FusedShape sh = fused_shape(g.L, g.H, w.kpad, g.A, rows ? std::atoi(rows) : 0,
                                       threads ? std::atoi(threads) : 0);
     if (sh.rows == 0) return none;
-    if (static_cast<long long>(b->B) * g.D * 4 > 0x7FFFFFF0LL - 0x100000LL) return none;
+    if (static_cast<long long>(obs_rows) * g.D * 4 > 0x7FFFFFF0LL - 0x100000LL) return none;
     for (int net = 0; net < 2; ++net)
         for (int l = 0; l < g.L; ++l)
             if (!aligned16(p->theta + (net == 0 ? g.ba[l] : g.bc[l]))) return none;
@@ -887,7 +887,7 @@ FusedShape fused_shape_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &
 }
 
 // Packing of the bf16 shadow weights into fragment order for the fused pass.
-FragArgs build_frags(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *ws) {
+FragArgs build_frags(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void *ws, bool transposes = true) {
     const NetLayout &g = c->g;
     const Weights W = gemm_weights(c, p);
     uint16_t *base = reinterpret_cast<uint16_t *>(wsp(ws, w.frag));
@@ -904,7 +904,7 @@ FragArgs build_frags(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, voi
             j.ld = K;
             j.transpose = 0;
             add_frag_job(a, j);
-            if (l >= 1) {
+            if (l >= 1 && transposes) {
                 FragJob t{};
                 t.src = static_cast<const uint16_t *>(W.W[net][l]);
                 t.dst = base + w.frag_wt[net][l];
@@ -973,7 +973,7 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
     const int L = g.L;
     hipError_t e;
 
-    const FusedShape fsh = fused_shape_for(c, p, w, sb.b);
+    const FusedShape fsh = fused_shape_for(c, p, w, sb.b->B);
     const int fused_r = fsh.rows;
     if (fused_r > 0) {
         // weights into fragment order, then gather, forward, loss and input
@@ -1186,6 +1186,45 @@ int ppo_rollout_infer(const ppo_ctx *c, void *stream, const ppo_params *p, const
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const NetLayout &g = c->g;
     const WsPlan w = plan_workspace(g, c->prec, N, 0, 0);
+    const FusedShape fsh = fused_shape_for(c, p, w, N);
+    if (fsh.rows > 0) {
+        // forward weights into fragment order, then one launch for the whole
+        // forward pass and the sampling head
+        PPO_HIP(launch_pack_frags(build_frags(c, p, w, ws, false), s), "pack_frags");
+        const uint16_t *frag = reinterpret_cast<const uint16_t *>(wsp(ws, w.frag));
+        FusedArgs a{};
+        for (int net = 0; net < 2; ++net) {
+            FusedNet &n = a.net[net];
+            for (int l = 0; l < g.L; ++l) {
+                n.W[l] = frag + w.frag_w[net][l];
+                n.bias[l] = p->theta + (net == 0 ? g.ba[l] : g.bc[l]);
+            }
+            n.Wout = p->theta + (net == 0 ? g.Wa[g.L] : g.Wc[g.L]);
+            n.bout = p->theta + (net == 0 ? g.ba[g.L] : g.bc[g.L]);
+        }
+        a.L = g.L;
+        a.D = g.D;
+        a.kpad = w.kpad;
+        a.A = g.A;
+        for (int l = 0; l < g.L; ++l) a.H[l] = g.H[l];
+        a.obs = obs;
+        a.B = N;
+        a.M = N;
+        a.logstd = p->theta + g.logstd;
+        a.act_out = actions;
+        a.logp_out = logp;
+        a.val_out = values;
+        a.mu_out = mu;
+        a.key0 = static_cast<uint32_t>(seed);
+        a.key1 = static_cast<uint32_t>(seed >> 32);
+        a.t_step = static_cast<uint32_t>(t);
+        a.iteration = iteration;
+        a.net_mask = (value_only ? 0 : 1) | (values ? 2 : 0);
+        a.R = fsh.rows;
+        a.NT = fsh.threads;
+        PPO_HIP(launch_fused_infer(a, s), "fused inference");
+        return PPO_OK;
+    }
     Tuning tune;
     PPO_CHECK(ensure_tuned(c, p, w, ws, N, false, s, tune));
     PPO_HIP(launch_stage_weights(c->prec, build_stage(c, p, w, ws, false), s), "stage_weights");

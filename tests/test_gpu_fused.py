@@ -137,3 +137,43 @@ def test_fused_epoch_graph_matches_eager_and_layered(name):
     nw, _ = rel_errors(out["eager"][0] - theta, out["layered"][0] - theta)
     print(f"parameter change fused vs layered: normwise {nw:.2e}")
     assert nw < 2e-2, nw
+
+
+@pytest.mark.parametrize("name,N", [("flat", 4096), ("rough", 333), ("large", 31), ("flat", 1)])
+def test_fused_rollout_matches_layered(name, N):
+    """Rollout inference through the fused kernel and through the
+    layer-by-layer kernels: the Philox draws and the log-densities (functions
+    of the draws and log-std only) agree bit for bit; means and values agree
+    to float32 rounding of the output layer."""
+    d = require_gpu()
+    cfg = synth.get_config(name)
+    _announce(f"fused rollout vs layered {name} N={N}")
+    theta = synth.xavier_theta(cfg.net, seed=3, logstd=-0.4)
+    obs = synth.make_rollout(cfg)["obs"][2][:N] if cfg.heightfield else \
+        synth.rollout.gaussian_like((N, cfg.net.obs_dim), seed=4)
+    ctx = ppo.Context(cfg.net.obs_dim, cfg.net.act_dim, cfg.net.hidden, "bf16")
+    params = ppo.Params(ctx, theta, device=d)
+    A = cfg.net.act_dim
+    res = {}
+    for fused in (True, False):
+        out = dict(actions=torch.empty(N, A, device=d), logp=torch.empty(N, device=d),
+                   values=torch.empty(N, device=d), mu=torch.empty(N, A, device=d))
+        v_only = torch.empty(N, device=d)
+        a_only = torch.empty(N, A, device=d)
+        with _Fused(fused):
+            ppo.ppo_rollout_infer(ctx, params, dev(obs, d), t=5, seed=11, iteration=2, **out)
+            ppo.ppo_rollout_infer(ctx, params, dev(obs, d), t=5, seed=11, iteration=2, values=v_only)
+            ppo.ppo_rollout_infer(ctx, params, dev(obs, d), t=5, seed=11, iteration=2, actions=a_only)
+        torch.cuda.synchronize()
+        res[fused] = {k: v.cpu().numpy() for k, v in out.items()}
+        res[fused]["v_only"] = v_only.cpu().numpy()
+        res[fused]["a_only"] = a_only.cpu().numpy()
+    f, l = res[True], res[False]
+    np.testing.assert_array_equal(f["logp"], l["logp"])
+    sigma = np.float32(np.exp(np.float32(-0.4)))
+    np.testing.assert_allclose((f["actions"] - f["mu"]) / sigma, (l["actions"] - l["mu"]) / sigma, rtol=0, atol=2e-5)
+    for k in ("mu", "values"):
+        nw, _ = rel_errors(f[k], l[k])
+        assert nw < 1e-5, (k, nw)
+    np.testing.assert_array_equal(f["v_only"], f["values"])
+    np.testing.assert_array_equal(f["a_only"], f["actions"])
