@@ -972,10 +972,15 @@ FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows, in
     // candidates in order of preference: 32 rows x 4 waves with two
     // workgroups per CU (one hides the other's prologue, head and barrier
     // latencies); 64 rows x 8 waves (each weight fragment feeds two MFMAs,
-    // two waves per SIMD, one workgroup per CU); 32 rows x 8 waves; 64 rows x
-    // 4 waves
+    // two waves per SIMD, one workgroup per CU).  The shapes with one
+    // workgroup of 32 rows per CU (wider networks, e.g. [1024, 512, 256]) or of
+    // 4 waves lose to the layer-by-layer GEMMs, which those widths keep busy;
+    // they run only when asked for by rows and threads.
     const FusedShape cand[4] = {{32, 256, 2}, {64, 512, 1}, {32, 512, 1}, {64, 256, 1}};
-    for (const FusedShape &c : cand) {
+    const bool asked = prefer_rows && prefer_threads;
+    for (int i = 0; i < 4; ++i) {
+        const FusedShape &c = cand[i];
+        if (i >= 2 && !asked) break;
         if (prefer_rows && c.rows != prefer_rows) continue;
         if (prefer_threads && c.threads != prefer_threads) continue;
         if (fused_fits(L, H, kpad, A, c.rows, c.threads, c.per_cu == 2)) return c;

@@ -1638,10 +1638,29 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
     const int n_side = side ? std::min(R, kSideStreams) : 0;
     auto run_stream = [&](int i) { return n_side > 0 ? side->st[i % n_side] : s; };
     hipError_t e;
+    // every run through the fused per-sample pass when all of them can take
+    // it: one pass per run on the side streams, concurrently, then the
+    // grouped weight gradients; else the grouped layer-by-layer launches
+    std::vector<FusedShape> fsh(R);
+    bool all_fused = true;
+    for (int i = 0; i < R; ++i) {
+        fsh[i] = fused_shape_for(runs[i].c, runs[i].p, runs[i].w, runs[i].b->B);
+        all_fused = all_fused && fsh[i].rows > 0;
+    }
     if (n_side > 0 && (e = fork_to(*side, s, n_side)) != hipSuccess) return e;
     for (int i = 0; i < R; ++i) {
         BatchedRun &r = runs[i];
         const int32_t *idx = r.perm + static_cast<long long>(k) * r.M;
+        if (all_fused) {
+            e = launch_pack_frags(build_frags(r.c, r.p, r.w, r.ws), run_stream(i));
+            if (e != hipSuccess) return e;
+            FusedArgs fa = fused_args(r.c, r.p, hp, r.w, r.ws, r.b, idx, r.M);
+            fa.R = fsh[i].rows;
+            fa.NT = fsh[i].threads;
+            e = launch_fused_update(fa, run_stream(i));
+            if (e != hipSuccess) return e;
+            continue;
+        }
         e = launch_stage_weights(prec, build_stage(r.c, r.p, r.w, r.ws, true), run_stream(i));
         if (e != hipSuccess) return e;
         e = launch_gather_obs(prec, run_stream(i), r.b->obs, idx, r.b->B, r.M, r.c->g.D, r.w.kpad,
@@ -1649,7 +1668,7 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
         if (e != hipSuccess) return e;
     }
     if (n_side > 0 && (e = join_from(*side, s, n_side)) != hipSuccess) return e;
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < L && !all_fused; ++l) {
         std::vector<GemmArgs> launches;
         for (BatchedRun &r : runs)
             append_problems(launches, build_fwd(r.c, r.p, r.w, r.ws, r.M, l, true, true, bt.fwd[l]), bt.fwd[l], bk);
@@ -1658,16 +1677,18 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
             if (e != hipSuccess) return e;
         }
     }
-    if (n_side > 0 && (e = fork_to(*side, s, n_side)) != hipSuccess) return e;
-    for (int i = 0; i < R; ++i) {
-        BatchedRun &r = runs[i];
-        const HeadLossArgs hl = head_loss_args(r.c, r.p, hp, r.w, r.ws, r.b, r.perm + static_cast<long long>(k) * r.M,
-                                               r.M);
-        e = launch_head_loss(prec, hl, run_stream(i));
-        if (e != hipSuccess) return e;
+    if (!all_fused) {
+        if (n_side > 0 && (e = fork_to(*side, s, n_side)) != hipSuccess) return e;
+        for (int i = 0; i < R; ++i) {
+            BatchedRun &r = runs[i];
+            const HeadLossArgs hl = head_loss_args(r.c, r.p, hp, r.w, r.ws, r.b,
+                                                   r.perm + static_cast<long long>(k) * r.M, r.M);
+            e = launch_head_loss(prec, hl, run_stream(i));
+            if (e != hipSuccess) return e;
+        }
+        if (n_side > 0 && (e = join_from(*side, s, n_side)) != hipSuccess) return e;
     }
-    if (n_side > 0 && (e = join_from(*side, s, n_side)) != hipSuccess) return e;
-    for (int l = L - 1; l >= 1; --l) {
+    for (int l = L - 1; l >= 1 && !all_fused; --l) {
         std::vector<GemmArgs> launches;
         for (BatchedRun &r : runs)
             append_problems(launches, build_dx(r.c, r.p, r.w, r.ws, r.M, l, bt.dx[l]), bt.dx[l], bk);
@@ -1692,7 +1713,7 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
     for (int i = 0; i < R; ++i) {
         BatchedRun &r = runs[i];
         ReduceArgs &red = plans[i].red;
-        set_reduce_loss(red, r.c, r.p, hp, r.w, r.ws, r.p->grad, r.M, 1);
+        set_reduce_loss(red, r.c, r.p, hp, r.w, r.ws, r.p->grad, r.M, 1, all_fused ? fsh[i].rows : 0);
         e = launch_grad_reduce(red, run_stream(i));
         if (e != hipSuccess) return e;
         const AdamArgs ad = adam_args(r.c, r.p, hp, red, r.p->grad, r.stats + k * PPO_STATS_WIDTH, r.M, k, 1);

@@ -187,13 +187,15 @@ def test_adaptive_rate_validation():
 @pytest.mark.parametrize("shape,prec,env,expect", [
     ((48, 12, (512, 256, 128)), "bf16", {}, (32, 256)),
     ((235, 12, (512, 256, 128)), "bf16", {}, (32, 256)),
-    ((235, 12, (1024, 512, 256)), "bf16", {}, (32, 512)),
+    ((235, 12, (1024, 512, 256)), "bf16", {}, (0, 0)),  # one 32-row workgroup per CU: GEMMs win
+    ((235, 12, (1024, 512, 256)), "bf16", {"PPO_FUSED_ROWS": "32", "PPO_FUSED_THREADS": "512"}, (32, 512)),
     ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "64"}, (64, 512)),
     ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "64", "PPO_FUSED_THREADS": "256"}, (64, 256)),
     ((235, 12, (1024, 512, 256)), "bf16", {"PPO_FUSED_ROWS": "64"}, (0, 0)),
     ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED": "0"}, (0, 0)),
     ((48, 12, (512, 256, 128)), "fp32", {}, (0, 0)),
-    ((48, 12, (64, 64)), "bf16", {}, (64, 256)),        # two waves per feature block
+    ((48, 12, (64, 64)), "bf16", {}, (0, 0)),           # only 64 rows x 4 waves fits: not by default
+    ((48, 12, (64, 64)), "bf16", {"PPO_FUSED_ROWS": "64", "PPO_FUSED_THREADS": "256"}, (64, 256)),
     ((48, 12, (32, 32)), "bf16", {}, (0, 0)),           # one feature block for four waves
     ((40, 12, (512, 256, 128)), "bf16", {}, (0, 0)),    # input width not a multiple of 16
     ((48, 12, (384, 256, 128)), "bf16", {}, (0, 0)),    # 12 feature blocks over 4 waves: 3 per wave

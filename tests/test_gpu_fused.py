@@ -24,20 +24,30 @@ def _announce(msg):
 
 
 class _Fused:
-    """Sets PPO_FUSED for the duration of a block (read at every call)."""
+    """Sets PPO_FUSED (and optionally the block shape) for the duration of a
+    block; the library reads them at every call."""
 
-    def __init__(self, on):
+    KEYS = ("PPO_FUSED", "PPO_FUSED_ROWS", "PPO_FUSED_THREADS")
+
+    def __init__(self, on, shape=None):
         self.on = on
+        self.shape = shape
 
     def __enter__(self):
-        self.old = os.environ.get("PPO_FUSED")
+        self.old = {k: os.environ.get(k) for k in self.KEYS}
         os.environ["PPO_FUSED"] = "1" if self.on else "0"
+        for k in self.KEYS[1:]:
+            os.environ.pop(k, None)
+        if self.shape:
+            os.environ["PPO_FUSED_ROWS"] = str(self.shape[0])
+            os.environ["PPO_FUSED_THREADS"] = str(self.shape[1])
 
     def __exit__(self, *exc):
-        if self.old is None:
-            os.environ.pop("PPO_FUSED", None)
-        else:
-            os.environ["PPO_FUSED"] = self.old
+        for k, v in self.old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
 
 
 def _setup(name, M, seed=1):
@@ -51,28 +61,34 @@ def _setup(name, M, seed=1):
     return d, cfg, theta, batch, idx, ctx
 
 
-def _loss_grad(ctx, theta, batch, idx, d, fused, hp=None):
+def _loss_grad(ctx, theta, batch, idx, d, fused, hp=None, shape=None):
     params = ppo.Params(ctx, theta, device=d)
     tb = {k: dev(v, d) for k, v in batch.items()}
     stats = torch.zeros(ppo.PPO_STATS_WIDTH, device=d)
     grad = torch.zeros(ctx.param_count, device=d)
     ws = ctx.new_workspace(M=len(idx))
-    with _Fused(fused):
+    with _Fused(fused, shape):
+        assert (ctx.fused_shape() == tuple(shape or ctx.fused_shape())) and (ctx.fused_shape()[0] > 0) == fused
         ppo.ppo_loss_grad(ctx, params, tb, dev(idx, d), hp or ppo.UpdateHParams(), stats, grad, ws)
     torch.cuda.synchronize()
     return grad.cpu().numpy(), stats.cpu().numpy()
 
 
-@pytest.mark.parametrize("name,M", [("flat", 24576), ("flat", 1000), ("rough", 777), ("large", 333),
-                                    ("flat", 10), ("large", 31)])
-def test_fused_matches_layered(name, M):
+# every block shape the library can launch: (32, 256) and (64, 512) by default,
+# (32, 512) and (64, 256) when asked for
+SHAPES = [("flat", 24576, None), ("flat", 1000, (64, 512)), ("rough", 777, None), ("large", 333, (32, 512)),
+          ("flat", 10, (64, 256)), ("large", 31, (32, 512)), ("tiny", 1536, (64, 256)), ("rough", 4096, (64, 512))]
+
+
+@pytest.mark.parametrize("name,M,shape", SHAPES)
+def test_fused_matches_layered(name, M, shape):
     """Same inputs through both paths: the hidden layers round to bf16 at the
     same points and accumulate in the same k order; the output layers sum in a
     different order, so the two differ by float32 rounding, magnified by the
     bf16 rounding of the gradients downstream of it (a few bf16 ulps)."""
     d, cfg, theta, batch, idx, ctx = _setup(name, M)
-    _announce(f"fused vs layered {name} M={M}")
-    gf, sf = _loss_grad(ctx, theta, batch, idx, d, True)
+    _announce(f"fused vs layered {name} M={M} shape={shape}")
+    gf, sf = _loss_grad(ctx, theta, batch, idx, d, True, shape=shape)
     gl, sl = _loss_grad(ctx, theta, batch, idx, d, False)
     nw, ew = rel_errors(gf, gl)
     print(f"grad fused vs layered: normwise {nw:.2e}, worst element {ew:.2e}")
@@ -107,8 +123,8 @@ def test_fused_is_the_bf16_path_and_deterministic():
     assert ph["fused"][1] == 0 and ph["forward"][1] == K * len(cfg.net.hidden)
 
 
-@pytest.mark.parametrize("name", ["flat", "large"])
-def test_fused_epoch_graph_matches_eager_and_layered(name):
+@pytest.mark.parametrize("name,shape", [("flat", None), ("large", (32, 512))])
+def test_fused_epoch_graph_matches_eager_and_layered(name, shape):
     """A four-mini-batch epoch: the captured graph replays the eager launches
     bit for bit, and the parameters track the layer-by-layer epoch."""
     d = require_gpu()
@@ -126,7 +142,7 @@ def test_fused_epoch_graph_matches_eager_and_layered(name):
     for label, fused, graph in (("eager", True, False), ("graph", True, True), ("layered", False, False)):
         params = ppo.Params(ctx, theta, lr=1e-3, device=d)
         stats = torch.zeros(K, ppo.PPO_STATS_WIDTH, device=d)
-        with _Fused(fused):
+        with _Fused(fused, shape if fused else None):
             for _ in range(2):   # the second graph call replays the captured epoch
                 ppo.ppo_update_epoch(ctx, params, tb, dev(perm, d), K, ppo.UpdateHParams(use_graph=graph), stats,
                                      ws)
@@ -139,8 +155,9 @@ def test_fused_epoch_graph_matches_eager_and_layered(name):
     assert nw < 2e-2, nw
 
 
-@pytest.mark.parametrize("name,N", [("flat", 4096), ("rough", 333), ("large", 31), ("flat", 1)])
-def test_fused_rollout_matches_layered(name, N):
+@pytest.mark.parametrize("name,N,shape", [("flat", 4096, None), ("rough", 333, (64, 512)), ("large", 31, (32, 512)),
+                                          ("flat", 1, None), ("tiny", 64, (64, 256))])
+def test_fused_rollout_matches_layered(name, N, shape):
     """Rollout inference through the fused kernel and through the
     layer-by-layer kernels: the Philox draws and the log-densities (functions
     of the draws and log-std only) agree bit for bit; means and values agree
@@ -160,7 +177,8 @@ def test_fused_rollout_matches_layered(name, N):
                    values=torch.empty(N, device=d), mu=torch.empty(N, A, device=d))
         v_only = torch.empty(N, device=d)
         a_only = torch.empty(N, A, device=d)
-        with _Fused(fused):
+        with _Fused(fused, shape if fused else None):
+            assert (ctx.fused_shape()[0] > 0) == fused
             ppo.ppo_rollout_infer(ctx, params, dev(obs, d), t=5, seed=11, iteration=2, **out)
             ppo.ppo_rollout_infer(ctx, params, dev(obs, d), t=5, seed=11, iteration=2, values=v_only)
             ppo.ppo_rollout_infer(ctx, params, dev(obs, d), t=5, seed=11, iteration=2, actions=a_only)
