@@ -33,11 +33,16 @@ Parity status per function (what pins it; see tests/test_oracle_*.py):
   update_epoch      composition of the above (no independent pin beyond its
                     parts: parity unpinned as a whole against the paper, which
                     prints no intermediate values)
+  assemble_obs      nearest cell against a brute-force search over the whole
+                    grid; heading 0, 90 and 180 degrees against plain array
+                    slices; flat terrain; noise bounds, moments and
+                    independence of the streams
 """
 from .philox import philox4x32_10, uniforms, box_muller, action_noise
 from .layout import NetSpec, param_layout, unpack
 from .policy import elu, elu_grad, mlp_forward, gaussian_logp, gaussian_entropy, rollout_infer
 from .advantage import gae, advantage_stats, normalize_advantages
+from .observation import assemble_obs, height_scan, scan_world_points, nearest_cells, obs_noise_unit
 from .ppo import (
     PPOHyper,
     ppo_loss_grad,
@@ -53,5 +58,6 @@ __all__ = [
     "NetSpec", "param_layout", "unpack",
     "elu", "elu_grad", "mlp_forward", "gaussian_logp", "gaussian_entropy", "rollout_infer",
     "gae", "advantage_stats", "normalize_advantages",
+    "assemble_obs", "height_scan", "scan_world_points", "nearest_cells", "obs_noise_unit",
     "PPOHyper", "ppo_loss_grad", "clip_coef", "adam_step", "update_epoch", "gaussian_kl", "adaptive_lr",
 ]
