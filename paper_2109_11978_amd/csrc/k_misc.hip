@@ -441,7 +441,8 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
 //   A = delta + gamma lambda (1 - d) A_next;  R = A + V.
 // Each lane keeps a float64 Welford (count, mean, M2) of its advantages; the
 // block merges them (Chan et al.) in a fixed order into one partial.
-constexpr int kGaeThreads = 64;
+constexpr int kGaeThreads = 256;
+constexpr int kFinalizeThreads = 256;
 
 struct Welford { double n, mean, m2; };
 
@@ -490,21 +491,41 @@ __global__ __launch_bounds__(kGaeThreads) void gae_kernel(const GaeArgs a) {
         const bool lower = (threadIdx.x & o) == 0;
         w = lower ? merge(w, other) : merge(other, w);
     }
+    // then the block's waves, in wave order
+    __shared__ Welford s_wave[kGaeThreads / 64];
+    if ((threadIdx.x & 63) == 0) s_wave[threadIdx.x >> 6] = w;
+    __syncthreads();
     if (threadIdx.x == 0) {
+        w = s_wave[0];
+#pragma unroll
+        for (int i = 1; i < kGaeThreads / 64; ++i) w = merge(w, s_wave[i]);
         a.partials[3 * blockIdx.x + 0] = w.n;
         a.partials[3 * blockIdx.x + 1] = w.mean;
         a.partials[3 * blockIdx.x + 2] = w.m2;
     }
 }
 
-// Every block merges all partials in index order (identical result in each),
-// block 0 publishes (mean, unbiased std), and all blocks optionally normalise.
-__global__ void adv_finalize_kernel(const double *partials, int nparts, float *adv, long long count,
-                                    double *stats_out, int normalize) {
+// Every block merges all partials the same way, so each holds the identical
+// result: thread i merges a contiguous chunk of partials in index order, then
+// a pairwise tree over the threads in index order.  Block 0 publishes (mean,
+// unbiased std), and all blocks optionally normalise.
+__global__ __launch_bounds__(kFinalizeThreads) void adv_finalize_kernel(const double *partials, int nparts,
+                                                                        float *adv, long long count,
+                                                                        double *stats_out, int normalize) {
+    __shared__ Welford s_w[kFinalizeThreads];
     __shared__ double s_mean, s_std;
+    const int chunk = (nparts + kFinalizeThreads - 1) / kFinalizeThreads;
+    const int p0 = min(nparts, static_cast<int>(threadIdx.x) * chunk), p1 = min(nparts, p0 + chunk);
+    Welford w{0.0, 0.0, 0.0};
+    for (int p = p0; p < p1; ++p) w = merge(w, Welford{partials[3 * p], partials[3 * p + 1], partials[3 * p + 2]});
+    s_w[threadIdx.x] = w;
+    __syncthreads();
+    for (int off = 1; off < kFinalizeThreads; off <<= 1) {
+        if ((threadIdx.x & (2 * off - 1)) == 0) s_w[threadIdx.x] = merge(s_w[threadIdx.x], s_w[threadIdx.x + off]);
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        Welford w{0.0, 0.0, 0.0};
-        for (int p = 0; p < nparts; ++p) w = merge(w, Welford{partials[3 * p], partials[3 * p + 1], partials[3 * p + 2]});
+        w = s_w[0];
         s_mean = w.mean;
         s_std = w.n > 1.0 ? sqrt(w.m2 / (w.n - 1.0)) : 0.0;
         if (blockIdx.x == 0) {
@@ -811,8 +832,9 @@ hipError_t launch_gae(const GaeArgs &a, hipStream_t s) {
 
 hipError_t launch_adv_finalize(const double *partials, int nparts, float *adv, long long count, double *stats_out,
                                int normalize, hipStream_t s) {
-    const int blocks = normalize ? grid_for(count, 256, 1024) : 1;
-    hipLaunchKernelGGL(adv_finalize_kernel, dim3(blocks), dim3(256), 0, s, partials, nparts, adv, count, stats_out,
+    const int blocks = normalize ? grid_for(count, kFinalizeThreads, 1024) : 1;
+    hipLaunchKernelGGL(adv_finalize_kernel, dim3(blocks), dim3(kFinalizeThreads), 0, s, partials, nparts, adv, count,
+                       stats_out,
                        normalize);
     return hipGetLastError();
 }
