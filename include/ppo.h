@@ -7,6 +7,9 @@
  * collection and policy update both on the device; Section 2.2: a custom PPO
  * that stores every tensor on the GPU).  This library implements the learner
  * half of that loop as hand-written HIP kernels:
+ *   - ppo_assemble_obs  : observations from proprioception, a height scan
+ *                         around the base and uniform noise (Section 3.2,
+ *                         Table 4), in front of inference;
  *   - ppo_rollout_infer : actor-critic inference for every environment plus
  *                         diagonal-Gaussian action sampling (Philox4x32-10);
  *   - ppo_gae           : GAE over a [T, N] rollout with time-out
@@ -318,6 +321,41 @@ int ppo_ctx_tuning(const ppo_ctx *ctx, int32_t rows, int32_t update, int32_t *ch
  * PPO_FUSED_THREADS as set now; a step also falls back for batches of more
  * than 2^31 bytes of observations or misaligned biases.  Host only. */
 int ppo_fused_shape(const ppo_ctx *ctx, int32_t *rows, int32_t *threads);
+
+/* Terrain seen by the height scan: a height field on a uniform grid and the
+ * scan pattern.  Cell (i, j) of `height` [nx, ny] (row-major, float32) is the
+ * terrain height at world (i / inv_res, j / inv_res); `scan` [n_scan, 2] holds
+ * the body-frame (x, y) offsets of the scan points in metres (17 x 11 points at
+ * 0.1 m in the rough-terrain workloads; the paper's robot uses 108).  The
+ * library only reads these. */
+typedef struct ppo_terrain {
+    const float *height;
+    int32_t nx, ny;       /* 1..2^24 each                                     */
+    float inv_res;        /* cells per metre, positive and finite             */
+    const float *scan;
+    int32_t n_scan;       /* S >= 0                                           */
+} ppo_terrain;
+
+/* Observation assembly in front of ppo_rollout_infer (Section 3.2: what the
+ * policy observes; appendix Table 4: observation noise).  Writes obs [N, D],
+ * D = n_proprio + S (must equal the network's obs_dim):
+ *   obs[n, j]     = proprio[n, j]                              for j < n_proprio,
+ *   obs[n, P + k] = base_z - height[cell nearest to scan point k],
+ * plus noise_scale[j] * (2u - 1) on every element when noise_scale [D] is
+ * non-NULL (uniform on (-scale, scale)).  base [N, 5] = (x, y, z, cos yaw,
+ * sin yaw) of each robot; scan point k lands at world
+ * (x + (c px - s py), y + (s px + c py)), every product and sum rounded to
+ * float32 on its own, and reads cell (rint(wx inv_res), rint(wy inv_res))
+ * (round half to even) clamped to the grid; a NaN position reads cell 0.
+ * u comes from Philox4x32-10 with key (seed mod 2^32, seed >> 32) and counter
+ * (n * ceil(D/4) + g, t, iteration, 2) for column j = 4 g + i (draw i), mapped
+ * as in ppo_rollout_infer; tag 2 keeps it apart from the action noise (tag 1).
+ * terrain may be NULL when S = 0; proprio may be NULL when n_proprio = 0;
+ * base may be NULL when S = 0.  N * ceil(D/4) < 2^31.  Asynchronous on
+ * `stream`; the caller owns every buffer. */
+int ppo_assemble_obs(const ppo_ctx *ctx, void *stream, const float *proprio, int32_t n_proprio,
+                     const float *base, const ppo_terrain *terrain, const float *noise_scale,
+                     int32_t N, int32_t t, uint64_t seed, uint32_t iteration, float *obs);
 
 /* Debug/verification: raw Philox4x32-10 blocks.  out[4 i + w] = word w of
  * Philox(counter = (c0_base + i mod 2^32, c1, c2, c3), key = (seed mod 2^32,

@@ -48,6 +48,11 @@ class HParams(ctypes.Structure):
                 ("lr_min", c_float), ("lr_max", c_float)]
 
 
+class Terrain(ctypes.Structure):
+    _fields_ = [("height", c_void_p), ("nx", c_int32), ("ny", c_int32), ("inv_res", c_float),
+                ("scan", c_void_p), ("n_scan", c_int32)]
+
+
 EXPORTS = {
     "ppo_last_error": (c_char_p, []),
     "ppo_ctx_create": (c_int32, [POINTER(NetDesc), c_int32, POINTER(c_void_p)]),
@@ -75,6 +80,8 @@ EXPORTS = {
                                      POINTER(c_void_p), POINTER(c_size_t)]),
     "ppo_ctx_tuning": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), c_int32]),
     "ppo_fused_shape": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "ppo_assemble_obs": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, POINTER(Terrain), c_void_p,
+                                   c_int32, c_int32, c_uint64, c_uint32, c_void_p]),
     "ppo_philox_blocks": (c_int32, [c_void_p, c_uint64, c_uint32, c_uint32, c_uint32, c_uint32, c_int64,
                                     c_void_p]),
 }

@@ -199,6 +199,38 @@ def ppo_pack_weights(ctx: Context, theta: torch.Tensor, shadow: torch.Tensor, st
                                   _ptr(shadow, torch.int16, "shadow")))
 
 
+def ppo_assemble_obs(ctx: Context, obs: torch.Tensor, t: int, seed: int, iteration: int,
+                     proprio: Optional[torch.Tensor] = None, base: Optional[torch.Tensor] = None,
+                     height: Optional[torch.Tensor] = None, inv_res: float = 10.0,
+                     scan: Optional[torch.Tensor] = None, noise_scale: Optional[torch.Tensor] = None,
+                     stream=None) -> None:
+    """obs [N, D] <- proprio [N, P], the height scan of `height` [nx, ny] at the
+    body-frame points `scan` [S, 2] around each `base` [N, 5] (x, y, z, cos yaw,
+    sin yaw), plus uniform noise of half-width noise_scale [D] (None: none)."""
+    N, D = obs.shape
+    P = 0 if proprio is None else proprio.shape[1]
+    if proprio is not None and tuple(proprio.shape) != (N, P):
+        raise ValueError(f"proprio must be [{N}, P], got {tuple(proprio.shape)}")
+    if noise_scale is not None and tuple(noise_scale.shape) != (D,):
+        raise ValueError(f"noise_scale must be [{D}], got {tuple(noise_scale.shape)}")
+    terrain = None
+    if scan is not None and scan.shape[0] > 0:
+        if scan.dim() != 2 or scan.shape[1] != 2:
+            raise ValueError(f"scan must be [S, 2], got {tuple(scan.shape)}")
+        if base is None or tuple(base.shape) != (N, 5):
+            raise ValueError(f"base must be [{N}, 5]")
+        if height is None or height.dim() != 2:
+            raise ValueError("height must be a 2-D [nx, ny] tensor")
+        nx, ny = height.shape
+        terrain = _abi.Terrain(_ptr(height, torch.float32, "height"), nx, ny, float(inv_res),
+                               _ptr(scan, torch.float32, "scan"), scan.shape[0])
+    check(_lib().ppo_assemble_obs(ctx.handle, _stream(stream), _ptr(proprio, torch.float32, "proprio", True), P,
+                                  _ptr(base, torch.float32, "base", True),
+                                  ctypes.byref(terrain) if terrain is not None else None,
+                                  _ptr(noise_scale, torch.float32, "noise_scale", True), N, t, seed, iteration,
+                                  _ptr(obs, torch.float32, "obs")))
+
+
 def ppo_rollout_infer(ctx: Context, params: Params, obs: torch.Tensor, t: int, seed: int, iteration: int,
                       actions=None, logp=None, values=None, mu=None, ws: Optional[torch.Tensor] = None,
                       stream=None) -> None:

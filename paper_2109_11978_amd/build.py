@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libppo_mi355x.so")
-SOURCES = ["k_gemm.hip", "k_misc.hip", "k_fused.hip", "ppo_api.cpp"]
+SOURCES = ["k_gemm.hip", "k_misc.hip", "k_fused.hip", "k_obs.hip", "ppo_api.cpp"]
 ARCH = "gfx950"
 
 COMMON_FLAGS = [

@@ -166,6 +166,11 @@ hipError_t launch_fused_update(FusedArgs a, hipStream_t s);
 hipError_t launch_fused_infer(FusedArgs a, hipStream_t s);
 
 // -------------------------------------------------------- other kernels ---
+// Observation assembly: proprio [N, P], then S height-scan columns; noise_scale
+// may be null (no noise).
+hipError_t launch_assemble_obs(hipStream_t s, const float *proprio, int P, const float *base, const float *height,
+                               int nx, int ny, float inv_res, const float *scan, int S, const float *noise_scale,
+                               long long N, uint64_t seed, uint32_t t, uint32_t iteration, float *obs);
 hipError_t launch_philox_blocks(hipStream_t s, uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
                                 uint32_t c3, long long n, uint32_t *out);
 

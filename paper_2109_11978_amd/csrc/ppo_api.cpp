@@ -1976,6 +1976,39 @@ int ppo_fused_shape(const ppo_ctx *c, int32_t *rows, int32_t *threads) {
     return PPO_OK;
 }
 
+int ppo_assemble_obs(const ppo_ctx *c, void *stream, const float *proprio, int32_t n_proprio, const float *base,
+                     const ppo_terrain *terrain, const float *noise_scale, int32_t N, int32_t t, uint64_t seed,
+                     uint32_t iteration, float *obs) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    const int D = c->net.obs_dim;
+    const int S = terrain ? terrain->n_scan : 0;
+    if (n_proprio < 0 || S < 0 || static_cast<long long>(n_proprio) + S != D)
+        return fail(PPO_E_SHAPE, "n_proprio %d + n_scan %d must equal obs_dim %d", n_proprio, S, D);
+    const long long groups = (D + 3) / 4;
+    if (N < 1 || N * groups > 0x7FFFFFFFLL)
+        return fail(PPO_E_SHAPE, "N = %d outside 1..%lld", N, 0x7FFFFFFFLL / groups);
+    if (t < 0) return fail(PPO_E_SHAPE, "t = %d must be non-negative", t);
+    PPO_CHECK(check_ptr(proprio, "proprio", n_proprio == 0));
+    PPO_CHECK(check_ptr(noise_scale, "noise_scale", true));
+    PPO_CHECK(check_ptr(obs, "obs"));
+    if (S > 0) {
+        PPO_CHECK(check_ptr(base, "base"));
+        PPO_CHECK(check_ptr(terrain->height, "terrain.height"));
+        PPO_CHECK(check_ptr(terrain->scan, "terrain.scan"));
+        if (terrain->nx < 1 || terrain->ny < 1 || terrain->nx > (1 << 24) || terrain->ny > (1 << 24))
+            return fail(PPO_E_SHAPE, "height field %d x %d outside 1..2^24 per side", terrain->nx, terrain->ny);
+        if (!(terrain->inv_res > 0.0f) || !std::isfinite(terrain->inv_res))
+            return fail(PPO_E_INVAL, "terrain.inv_res must be positive and finite");
+    }
+    PPO_CHECK(check_device());
+    PPO_HIP(launch_assemble_obs(static_cast<hipStream_t>(stream), proprio, n_proprio, base,
+                                S > 0 ? terrain->height : nullptr, S > 0 ? terrain->nx : 1, S > 0 ? terrain->ny : 1,
+                                S > 0 ? terrain->inv_res : 1.0f, S > 0 ? terrain->scan : nullptr, S, noise_scale, N, seed,
+                                static_cast<uint32_t>(t), iteration, obs),
+            "assemble_obs");
+    return PPO_OK;
+}
+
 int ppo_philox_blocks(void *stream, uint64_t seed, uint32_t c0_base, uint32_t c1, uint32_t c2, uint32_t c3,
                       int64_t n, uint32_t *out) {
     if (n < 1 || n > (static_cast<int64_t>(1) << 28)) return fail(PPO_E_SHAPE, "n = %lld outside 1..2^28", (long long)n);

@@ -70,3 +70,40 @@ class HeightField:
         base_z = self.lookup(bx, by) + 0.5
         out = base_z[:, None] - self.lookup(wx, wy) - 0.5
         return out.astype(np.float32)
+
+
+# Column layout of the 48 proprioceptive observations used by the synthetic
+# workloads (Section 3.2 lists the quantities; the split is this project's):
+# base linear velocity 3, base angular velocity 3, projected gravity 3,
+# commands 3, joint positions 12, joint velocities 12, previous actions 12.
+PROPRIO_LAYOUT = (("base_lin_vel", 3), ("base_ang_vel", 3), ("gravity", 3), ("commands", 3),
+                  ("joint_pos", 12), ("joint_vel", 12), ("last_actions", 12))
+# Half-widths of the uniform observation noise per component (appendix Table 4);
+# the previous actions are not listed there and get none.
+NOISE_HALF_WIDTH = {"base_lin_vel": 0.01, "base_ang_vel": 0.2, "gravity": 0.05, "commands": 0.0,
+                    "joint_pos": 0.01, "joint_vel": 1.5, "last_actions": 0.0, "heights": 0.1}
+
+
+def noise_scales(n_scan: int = SCAN_X * SCAN_Y) -> np.ndarray:
+    """[48 + n_scan] float32 noise half-widths in observation column order."""
+    parts = [np.full(n, NOISE_HALF_WIDTH[name], dtype=np.float32) for name, n in PROPRIO_LAYOUT]
+    parts.append(np.full(n_scan, NOISE_HALF_WIDTH["heights"], dtype=np.float32))
+    return np.concatenate(parts)
+
+
+def scan_pattern(nx: int = SCAN_X, ny: int = SCAN_Y, spacing: float = SCAN_SPACING) -> np.ndarray:
+    """[nx * ny, 2] float32 body-frame (x, y) offsets on a centred grid, x-major."""
+    a, b = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    pts = np.stack([(a - (nx - 1) / 2) * spacing, (b - (ny - 1) / 2) * spacing], axis=-1)
+    return pts.reshape(-1, 2).astype(np.float32)
+
+
+def base_poses(rng: np.random.Generator, count: int, size: float, margin: float = 2.0,
+               z_range=(0.3, 0.8)) -> np.ndarray:
+    """[count, 5] float32 (x, y, z, cos yaw, sin yaw); x, y uniform over the
+    field minus `margin` (a negative margin puts some robots off the field)."""
+    x = rng.uniform(margin, size - margin, count)
+    y = rng.uniform(margin, size - margin, count)
+    z = rng.uniform(*z_range, count)
+    yaw = rng.uniform(-np.pi, np.pi, count)
+    return np.stack([x, y, z, np.cos(yaw), np.sin(yaw)], axis=1).astype(np.float32)

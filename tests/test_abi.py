@@ -210,3 +210,31 @@ def test_fused_shape_selection(monkeypatch, shape, prec, env, expect):
     D, A, H = shape
     ctx = ppo.Context(D, A, H, prec)
     assert ctx.fused_shape() == expect
+
+
+def test_assemble_obs_validation():
+    """Observation assembly rejects bad shapes and pointers before any device work."""
+    lib = ppo.load()
+    ctx = ppo.Context(235, 12, (64, 64), "bf16")
+    terr = _abi.Terrain(FAKE, 480, 480, 10.0, FAKE, 187)
+    call = lambda **kw: lib.ppo_assemble_obs(
+        ctx.handle, None, kw.get("proprio", FAKE), kw.get("P", 48), kw.get("base", FAKE),
+        ctypes.byref(kw.get("terrain", terr)) if kw.get("terrain", terr) is not None else None,
+        kw.get("noise", None), kw.get("N", 4096), kw.get("t", 0), 0, 0, kw.get("obs", FAKE))
+    assert call(P=47) == ppo.PPO_E_SHAPE                 # 47 + 187 != 235
+    assert b"obs_dim" in lib.ppo_last_error()
+    assert call(terrain=None) == ppo.PPO_E_SHAPE         # 48 + 0 != 235
+    assert call(N=0) == ppo.PPO_E_SHAPE
+    assert call(N=1 << 30) == ppo.PPO_E_SHAPE            # N * ceil(D/4) >= 2^31
+    assert call(t=-1) == ppo.PPO_E_SHAPE
+    assert call(obs=None) == ppo.PPO_E_INVAL
+    assert call(obs=FAKE + 4) == ppo.PPO_E_INVAL
+    assert call(base=None) == ppo.PPO_E_INVAL
+    assert call(proprio=None) == ppo.PPO_E_INVAL
+    assert call(noise=FAKE + 8) == ppo.PPO_E_INVAL
+    for bad in (_abi.Terrain(FAKE, 0, 480, 10.0, FAKE, 187), _abi.Terrain(FAKE, 480, (1 << 24) + 1, 10.0, FAKE, 187)):
+        assert call(terrain=bad) == ppo.PPO_E_SHAPE
+    for inv_res in (0.0, -10.0, float("inf"), float("nan")):
+        assert call(terrain=_abi.Terrain(FAKE, 480, 480, inv_res, FAKE, 187)) == ppo.PPO_E_INVAL
+    assert call(terrain=_abi.Terrain(None, 480, 480, 10.0, FAKE, 187)) == ppo.PPO_E_INVAL
+    assert call(terrain=_abi.Terrain(FAKE, 480, 480, 10.0, None, 187)) == ppo.PPO_E_INVAL

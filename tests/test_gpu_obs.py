@@ -1,0 +1,147 @@
+"""Observation assembly through the C ABI against the oracle (Section 3.2;
+Table 4): cell choices and the noise stream bit for bit, the assembled
+observations to float32 rounding, ragged shapes and robots off the field."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2109_11978_amd as ppo
+import synth
+import synth.heightfield as shf
+from oracle.observation import assemble_obs, nearest_cells, obs_noise_unit, scan_world_points
+from tests.gpu_common import dev, require_gpu
+from tests.parity import TOL, assert_close
+
+pytestmark = pytest.mark.gpu
+f32 = np.float32
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _run(ctx, d, N, proprio, base, height, scan, noise, t=3, seed=0x5EED, it=7, inv_res=10.0):
+    obs = torch.full((N, ctx.obs_dim), float("nan"), device=d)
+    ppo.ppo_assemble_obs(ctx, obs, t, seed, it,
+                         proprio=None if proprio is None else dev(proprio, d),
+                         base=None if base is None else dev(base, d),
+                         height=None if height is None else dev(height, d), inv_res=inv_res,
+                         scan=None if scan is None else dev(scan, d),
+                         noise_scale=None if noise is None else dev(noise, d))
+    torch.cuda.synchronize()
+    return obs.cpu().numpy()
+
+
+@pytest.mark.parametrize("N,P,S,margin", [(4096, 48, 187, 2.0), (333, 48, 187, -3.0), (1, 45, 190, 0.0),
+                                          (1000, 48, 108, -1.0), (65, 3, 0, 0.0)])
+def test_assemble_matches_oracle(N, P, S, margin):
+    d = require_gpu()
+    _announce(f"assemble_obs N={N} P={P} S={S} margin={margin}")
+    rng = np.random.default_rng(N * 7 + S)
+    ctx = ppo.Context(P + S, 12, (64,), "bf16")
+    hf = shf.HeightField(seed=1)
+    H = hf.h.astype(f32)
+    proprio = rng.standard_normal((N, P)).astype(f32)
+    base = shf.base_poses(rng, N, hf.size, margin=margin)
+    scan = shf.scan_pattern() if S == 187 else rng.uniform(-1.0, 1.0, (S, 2)).astype(f32)
+    # Table 4 half-widths on the 48-column layout; other widths get 0.05 per proprio column
+    noise = shf.noise_scales(S) if P == 48 else np.concatenate([np.full(P, 0.05, f32), np.full(S, 0.1, f32)])
+    scan_arg = scan if S else None
+    for with_noise in (False, True):
+        got = _run(ctx, d, N, proprio, base if S else None, H if S else None, scan_arg, noise if with_noise else None)
+        ref = assemble_obs(proprio, base, H, 10.0, scan_arg, noise if with_noise else None, 0x5EED, 3, 7)
+        assert got.shape == ref.shape
+        if not with_noise:
+            # one float32 rounding of an exact float64 value on both sides
+            np.testing.assert_array_equal(got, ref.astype(f32))
+        else:
+            assert_close(f"obs N={N} S={S}", got, ref, TOL["fp32"])
+
+
+def test_cell_choices_bit_exact():
+    """A height field whose every cell is a distinct integer, z = 0 and no
+    noise: the output names the cell each scan point read; it must be the
+    oracle's float32 decision, including exact half-cell positions (round half
+    to even), robots far off the field (clamped) and a NaN position (cell 0)."""
+    d = require_gpu()
+    _announce("assemble_obs cell choices")
+    rng = np.random.default_rng(5)
+    nx, ny = 300, 200
+    H = (np.arange(nx)[:, None] * 1024 + np.arange(ny)[None, :]).astype(f32)
+    N = 2048
+    base = shf.base_poses(rng, N, 30.0, margin=-15.0)
+    base[:, 2] = 0.0
+    # exact halves in binary on the heading-0 axis with a zero offset point
+    base[:8] = np.array([[0.25, 0.75, 0, 1, 0], [1.25, 0.25, 0, 1, 0], [2.75, 3.25, 0, 1, 0],
+                         [-0.25, 0.05, 0, 1, 0], [29.95, 19.95, 0, 1, 0], [1e9, -1e9, 0, 1, 0],
+                         [np.nan, 0.5, 0, 1, 0], [0.5, np.nan, 0, -0.0, 1]], dtype=f32)
+    scan = np.concatenate([np.zeros((1, 2), f32), shf.scan_pattern(), rng.uniform(-3, 3, (12, 2)).astype(f32)])
+    S = len(scan)
+    ctx = ppo.Context(S, 12, (64,), "bf16")
+    got = _run(ctx, d, N, None, base, H, scan, None)
+    cell = (-got).astype(np.int64)
+    gi, gj = cell // 1024, cell % 1024
+    wx, wy = scan_world_points(base, scan)
+    ri, rj = nearest_cells(wx, wy, 10.0, nx, ny)
+    np.testing.assert_array_equal(gi, ri)
+    np.testing.assert_array_equal(gj, rj)
+    assert (gi[0, 0], gj[0, 0], gi[1, 0], gj[1, 0]) == (2, 8, 12, 2)
+    assert (gi[5, 0], gj[5, 0]) == (nx - 1, 0) and gi[6, 0] == 0 and gj[7, 0] == 0
+
+
+def test_noise_stream_bit_exact_and_keyed():
+    """Zero observations and no terrain: the output is scale * (2u - 1), one
+    float32 product of exact factors, so it equals the oracle's float64 value
+    rounded once.  A different step, iteration or seed gives a different draw;
+    the same arguments the same one."""
+    d = require_gpu()
+    _announce("assemble_obs noise stream")
+    rng = np.random.default_rng(9)
+    N, D = 777, 61
+    scale = rng.uniform(0.01, 2.0, D).astype(f32)
+    ctx = ppo.Context(D, 12, (64,), "bf16")
+    zeros = np.zeros((N, D), f32)
+    got = _run(ctx, d, N, zeros, None, None, None, scale, t=11, seed=(3 << 40) | 17, it=2 ** 32 - 1)
+    ref = scale[None, :].astype(np.float64) * obs_noise_unit((3 << 40) | 17, N, D, 11, 2 ** 32 - 1)
+    np.testing.assert_array_equal(got, ref.astype(f32))
+    again = _run(ctx, d, N, zeros, None, None, None, scale, t=11, seed=(3 << 40) | 17, it=2 ** 32 - 1)
+    np.testing.assert_array_equal(got, again)
+    for kw in (dict(t=12), dict(it=0), dict(seed=(3 << 40) | 18)):
+        other = _run(ctx, d, N, zeros, None, None, None, scale, **{**dict(t=11, seed=(3 << 40) | 17, it=2 ** 32 - 1), **kw})
+        assert np.mean(other == got) < 0.01, kw
+
+
+def test_assembled_obs_feed_inference():
+    """The assembled rough-terrain observations go straight into inference on
+    the same stream; the policy outputs (float32 path, so a last-place
+    difference in an observation stays a last-place difference) match
+    inference on the oracle's observations rounded to float32."""
+    d = require_gpu()
+    _announce("assemble_obs -> rollout_infer")
+    rng = np.random.default_rng(11)
+    N = 512
+    net = synth.get_config("rough").net
+    ctx = ppo.Context(net.obs_dim, net.act_dim, net.hidden, "fp32")
+    params = ppo.Params(ctx, synth.xavier_theta(net, seed=0), device=d)
+    hf = shf.HeightField(seed=2)
+    H = hf.h.astype(f32)
+    proprio = rng.standard_normal((N, 48)).astype(f32)
+    base = shf.base_poses(rng, N, hf.size)
+    scan = shf.scan_pattern()
+    noise = shf.noise_scales()
+    obs = torch.empty(N, net.obs_dim, device=d)
+    ppo.ppo_assemble_obs(ctx, obs, 0, 1, 0, proprio=dev(proprio, d), base=dev(base, d), height=dev(H, d),
+                         scan=dev(scan, d), noise_scale=dev(noise, d))
+    out_a = {k: torch.empty(N, net.act_dim, device=d) for k in ("actions", "mu")}
+    v_a = torch.empty(N, device=d)
+    ppo.ppo_rollout_infer(ctx, params, obs, 0, 1, 0, actions=out_a["actions"], values=v_a, mu=out_a["mu"])
+    ref_obs = assemble_obs(proprio, base, H, 10.0, scan, noise, 1, 0, 0).astype(f32)
+    obs_b = dev(ref_obs, d)
+    out_b = {k: torch.empty(N, net.act_dim, device=d) for k in ("actions", "mu")}
+    v_b = torch.empty(N, device=d)
+    ppo.ppo_rollout_infer(ctx, params, obs_b, 0, 1, 0, actions=out_b["actions"], values=v_b, mu=out_b["mu"])
+    torch.cuda.synchronize()
+    assert_close("obs", obs.cpu().numpy(), ref_obs, TOL["fp32"])
+    for k in ("mu", "actions"):
+        assert_close(k, out_a[k].cpu().numpy(), out_b[k].cpu().numpy(), TOL["fp32"])
+    assert_close("values", v_a.cpu().numpy(), v_b.cpu().numpy(), TOL["fp32"])
