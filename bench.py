@@ -13,12 +13,15 @@ Table 3 batch, B = 98304):
 value = B / (time per step), in samples/s, bf16 GEMM operands with float32
 accumulation.  The float32 plain path is timed the same way for the speedup.
 Also reported: a roofline entry for the dominant kernel (HIP events around
-each launch of one eagerly launched epoch) and the FP64 CPU oracle timed on
-a bounded sample of the same workload.
+each launch of one eagerly launched epoch), the update's median and IQR over
+20 repetitions from the same state, GAE bandwidth on 2^20-environment
+rollouts, the copy and bf16-GEMM rates this GPU attains, and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp32]
        python bench.py --config large   (16384 x 24 envs, 235-dim obs, [1024, 512, 256])
        python bench.py --config sweep   (8 uneven runs, batched update vs run after run)
+       python bench.py --config fig4    (Fig. 4 shapes: fixed batch, 128 ... 16384 envs)
 """
 from __future__ import annotations
 
@@ -45,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 plain-path timing")
     ap.add_argument("--fp32-steps", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the large-GAE bandwidth sweep and the attainable-peak probes")
     ap.add_argument("--quick", action="store_true",
                     help="only the timed steps (for profiler runs): no parts, roofline, fp32 or CPU legs")
     ap.add_argument("--sweep-mode", default="both", choices=["both", "batched", "serial"],
@@ -329,12 +334,20 @@ def cpu_baseline(wl, precision):
     t_mb = time.perf_counter() - t0
 
     t_iter = (T + 1) * t_inf + t_gae + cfg.epochs * cfg.minibatches * t_mb
-    threads = None
+    threads, blas = None, []
     try:
         from threadpoolctl import threadpool_info
-        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+        pools = threadpool_info()
+        threads = max((i.get("num_threads", 1) for i in pools), default=1)
+        blas = [f"{i.get('internal_api')} {i.get('version')} x{i.get('num_threads')}" for i in pools]
     except Exception:
         threads = os.cpu_count()
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
 
     # the same mini-batch through the HIP path at the same parameters
     gstats = torch.zeros(wl.ppo.PPO_STATS_WIDTH, device=wl.params.theta.device)
@@ -349,8 +362,167 @@ def cpu_baseline(wl, precision):
                        f"[{T},{N}] ({t_gae:.3f} s), 1 mini-batch step of {M} samples ({t_mb:.2f} s); "
                        f"iteration time assembled as {T + 1} policy steps + GAE + "
                        f"{cfg.epochs * cfg.minibatches} mini-batch steps = {t_iter:.1f} s"),
-            "host_cpus": os.cpu_count(),
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model, "blas": blas,
             "gpu_grad_vs_oracle_normwise": normwise}
+
+
+def update_distribution(wl, reps=20, warmup=3):
+    """Wall time of one full update (HIP events on the launch stream), with the
+    parameters and optimiser state restored before every repetition so each
+    one sees the same ratios: median and interquartile range in ms."""
+    import torch
+    p = wl.params
+    state = (p.theta, p.adam_m, p.adam_v, p.shadow, p.step, p.lr)
+    saved = [t.clone() for t in state]
+    times = []
+    for r in range(warmup + reps):
+        for dst, src in zip(state, saved):
+            dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        wl.update()
+        e1.record()
+        e1.synchronize()
+        if r >= warmup:
+            times.append(e0.elapsed_time(e1))
+    for dst, src in zip(state, saved):
+        dst.copy_(src)
+    q25, q50, q75 = np.percentile(times, [25, 50, 75])
+    return {"median_ms": round(float(q50), 3), "iqr_ms": round(float(q75 - q25), 3), "reps": reps,
+            "samples_per_s_at_median": round(wl.cfg.batch / (q50 * 1e-3), 1)}
+
+
+def gae_bandwidth(ctx, dev, shapes=((24, 1 << 20), (256, 1 << 20)), reps=5):
+    """GAE with time-outs and normalisation on large synthetic rollouts, to show
+    how the scan's bandwidth scales once it is no longer cache-resident;
+    26 algorithmic bytes per sample."""
+    import torch
+    import paper_2109_11978_amd as ppo
+    out = {}
+    for T, N in shapes:
+        g = torch.Generator(device=dev)
+        g.manual_seed(T)
+        r = torch.randn(T, N, device=dev, generator=g) * 0.1
+        v = torch.randn(T, N, device=dev, generator=g)
+        dn = (torch.rand(T, N, device=dev, generator=g) < 1e-3).to(torch.uint8)
+        to = dn & (torch.rand(T, N, device=dev, generator=g) < 0.5).to(torch.uint8)
+        last = torch.randn(N, device=dev, generator=g)
+        adv, ret = torch.empty_like(r), torch.empty_like(r)
+        st = torch.empty(2, dtype=torch.float64, device=dev)
+        ws = ctx.new_workspace(N=N, T=T, device=dev)
+        run = lambda: ppo.ppo_gae(ctx, r, dn, v, last, 0.99, 0.95, adv, ret, st, timeouts=to,
+                                  normalize=True, ws=ws)
+        run()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        out[f"T{T}_N{N}"] = {"us": round(t * 1e6, 1), "gbs": round(26 * T * N / t / 1e9, 1)}
+        del r, v, dn, to, last, adv, ret, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def obs_assembly_rate(dev, sizes=(4096, 16384, 1 << 20), reps=20):
+    """ppo_assemble_obs on the rough-terrain layout (48 proprioceptive columns,
+    a 17 x 11 height scan of a 480 x 480 field, Table 4 noise): time per call
+    and algorithmic GB/s, 1900 B per robot (proprio 192 B, pose 20 B, 187
+    heights 748 B read; 235 floats written)."""
+    import torch
+    import paper_2109_11978_amd as ppo
+    import synth.heightfield as shf
+    ctx = ppo.Context(235, 12, (512, 256, 128), "bf16")
+    hf = shf.HeightField(seed=0)
+    height = torch.as_tensor(hf.h.astype(np.float32)).to(dev)
+    scan = torch.as_tensor(shf.scan_pattern()).to(dev)
+    noise = torch.as_tensor(shf.noise_scales()).to(dev)
+    out = {}
+    for N in sizes:
+        rng = np.random.default_rng(N)
+        proprio = torch.as_tensor(rng.standard_normal((N, 48)).astype(np.float32)).to(dev)
+        base = torch.as_tensor(shf.base_poses(rng, N, hf.size)).to(dev)
+        obs = torch.empty(N, 235, device=dev)
+        run = lambda t: ppo.ppo_assemble_obs(ctx, obs, t, 0, 0, proprio=proprio, base=base, height=height,
+                                             scan=scan, noise_scale=noise)
+        run(0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for t in range(reps):
+            run(t)
+        e1.record()
+        e1.synchronize()
+        t_call = e0.elapsed_time(e1) * 1e-3 / reps
+        out[f"N{N}"] = {"us": round(t_call * 1e6, 2), "gbs": round(1900 * N / t_call / 1e9, 1)}
+        del proprio, base, obs
+    return out
+
+
+def attainable_peaks(dev):
+    """What this GPU reaches on plain library work, next to the published
+    peaks: a 1 GiB device-to-device copy (read + write bytes) and a bf16
+    8192^3 matrix product through the vendor BLAS."""
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    a = torch.randn(8192, 8192, device=dev, dtype=torch.bfloat16)
+    b = torch.randn(8192, 8192, device=dev, dtype=torch.bfloat16)
+
+    def timed(fn, reps):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    t_copy = timed(lambda: dst.copy_(src), 10)
+    t_mm = timed(lambda: torch.mm(a, b), 10)
+    del src, dst, a, b
+    torch.cuda.empty_cache()
+    return {"hbm_copy_gbs": round(2 * n * 4 / t_copy / 1e9, 1), "bf16_gemm_tflops": round(2 * 8192 ** 3 / t_mm / 1e12, 1),
+            "published": {"hbm_gbs": HBM_PEAK_GBS, "bf16_tflops": MFMA_PEAK_TFLOPS["bf16"]}}
+
+
+def fig4_bench(args, dev):
+    """Fig. 4's shapes on the rough-terrain network: the parts of one learning
+    iteration at fixed batch size as the number of environments grows
+    (T = B / N), plus the 20000 x 50 reference point.  The update's time should
+    not depend on N at fixed B; collection time falls with T."""
+    import torch
+    import synth
+    rows = []
+    total_b, total_t = 0, 0.0
+    for cfg in synth.configs.fig4_runs():
+        print(f"[fig4] {cfg.name}", file=sys.stderr, flush=True)
+        wl = Workload(cfg, "bf16", dev)
+        parts = time_parts(wl, reps=2)
+        t_iter = sum(parts.values())
+        total_b += cfg.batch
+        total_t += t_iter * 1e-3
+        rows.append({"workload": cfg.name, "n_envs": cfg.n_envs, "n_steps": cfg.n_steps, "batch": cfg.batch,
+                     **{f"{k}_ms": round(v, 3) for k, v in parts.items()},
+                     "iteration_ms": round(t_iter, 3),
+                     "update_samples_per_s": round(cfg.batch / (parts["update"] * 1e-3), 1)})
+        del wl
+        torch.cuda.empty_cache()
+    spread = {}
+    for b in synth.configs.FIG4_BATCHES:
+        u = [r["update_ms"] for r in rows if r["batch"] == b]
+        spread[str(b)] = round(max(u) / min(u), 3)
+    out = {"metric": "PPO learning-iteration samples/s over Fig. 4 shapes (fixed batch, growing number of envs)",
+           "value": round(total_b / total_t, 1), "unit": "samples/s", "n_gpus": 1, "steps": 2, "warmup": 1,
+           "ms_per_step": round(total_t * 1e3 / len(rows), 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "fig4_shapes_d235_h512x256x128", "batches": list(synth.configs.FIG4_BATCHES),
+                      "n_envs": list(synth.configs.FIG4_ENVS)},
+           "update_time_max_over_min_at_fixed_batch": spread, "rows": rows}
+    print(json.dumps(out), flush=True)
 
 
 def sweep_bench(args, dev):
@@ -407,15 +579,34 @@ def sweep_bench(args, dev):
 
     t_batched = timed(batched_update) if args.sweep_mode != "serial" else float("nan")
     t_serial = timed(lambda: [w.update() for w in runs]) if args.sweep_mode != "batched" else float("nan")
+    t_default = float("nan")
+    if args.sweep_mode == "both":
+        # the batched update again, from fresh contexts that keep every GEMM site at its
+        # default 128 x 128 tile
+        tuned = [w.ctx for w in runs]
+        os.environ["PPO_AUTOTUNE"] = "0"
+        try:
+            for w in runs:
+                n = w.cfg.net
+                w.ctx = ppo.Context(n.obs_dim, n.act_dim, n.hidden, "bf16")
+            t_default = timed(batched_update)
+        finally:
+            del os.environ["PPO_AUTOTUNE"]
+            for w, c in zip(runs, tuned):
+                w.ctx = c
+    rate = lambda t: round(total_b / t, 1) if t == t else None      # None for a leg not timed (NaN)
+    ratio = lambda a, b: round(a / b, 3) if a == a and b == b else None
     out = {
         "metric": "PPO update samples/s, 8 uneven sweep runs updated together",
         "value": round(total_b / s_step, 1), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(s_step * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "sweep_8_uneven_runs", "runs": [w.cfg.name for w in runs], "total_batch": total_b},
-        "update_samples_per_s_batched": round(total_b / t_batched, 1),
-        "update_samples_per_s_run_after_run": round(total_b / t_serial, 1),
-        "batched_speedup": round(t_serial / t_batched, 3),
+        "update_samples_per_s_batched": rate(t_batched),
+        "update_samples_per_s_run_after_run": rate(t_serial),
+        "batched_speedup": ratio(t_serial, t_batched),
+        "update_samples_per_s_batched_default_tiles": rate(t_default),
+        "autotune_speedup": ratio(t_default, t_batched),
         "sweep_mode": args.sweep_mode,
     }
     print(json.dumps(out), flush=True)
@@ -436,6 +627,9 @@ def main():
     if args.config == "sweep":
         sweep_bench(args, dev)
         return
+    if args.config == "fig4":
+        fig4_bench(args, dev)
+        return
     cfg = synth.get_config(args.config)
 
     wl = Workload(cfg, "bf16", dev)
@@ -455,6 +649,7 @@ def main():
                           "quick": True}), flush=True)
         return
     parts = time_parts(wl)
+    upd = update_distribution(wl)
     roof, phases, gemm_tflops = roofline(wl, "bf16")
     out = {
         "metric": METRIC,
@@ -473,7 +668,13 @@ def main():
                    "obs_dim": cfg.net.obs_dim, "act_dim": cfg.net.act_dim, "hidden": list(cfg.net.hidden),
                    "epochs": cfg.epochs, "minibatches": cfg.minibatches, "minibatch": cfg.minibatch},
         "update_samples_per_s": round(B / (parts["update"] * 1e-3), 1),
+        "update_sample_passes_per_s": round(cfg.epochs * B / (parts["update"] * 1e-3), 1),
+        "rollout_env_steps_per_s": round(B / (parts["rollout_infer"] * 1e-3), 1),
+        # 26 B per sample: rewards, values, advantages and returns at 4 B, dones and
+        # time-outs at 1 B, and the normalisation's second read and write of the advantages
+        "gae_gbs": round(26 * B / (parts["gae"] * 1e-3) / 1e9, 1),
         "breakdown_ms": {k: round(v, 3) for k, v in parts.items()},
+        "update_ms_median_iqr": upd,
         "roofline": roof,
         "phases_bf16": phases,
         "gemm_tflops_bf16": gemm_tflops,
@@ -493,6 +694,10 @@ def main():
         out["bf16_speedup_vs_fp32"] = round(s32 / s_step, 2)
         out["bf16_update_speedup_vs_fp32"] = round(parts32["update"] / parts["update"], 2)
         del wl32
+    if not args.no_extras:
+        out["gae_bandwidth"] = gae_bandwidth(wl.ctx, dev)
+        out["obs_assembly"] = obs_assembly_rate(dev)
+        out["attainable_peaks"] = attainable_peaks(dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, "bf16")
     print(json.dumps(out), flush=True)

@@ -96,6 +96,24 @@ def sweep_runs() -> List[PPOConfig]:
     return runs
 
 
+# Fig. 4's shapes: at a fixed batch size the number of environments grows from
+# 128 to 16384 (T = B / N), next to the 20000 x 50 reference point.  Rough-terrain
+# network width; observations are all N(0, 1) here since only timings are taken.
+FIG4_BATCHES = (49152, 98304, 196608)
+FIG4_ENVS = (128, 256, 512, 1024, 2048, 4096, 8192, 16384)
+
+
+def fig4_runs() -> List[PPOConfig]:
+    runs = []
+    for b in FIG4_BATCHES:
+        for n in FIG4_ENVS:
+            runs.append(PPOConfig(name=f"fig4_b{b}_{n}x{b // n}_d235", n_envs=n, n_steps=b // n,
+                                  net=NetShape(235, 12, (512, 256, 128)), epochs=5, minibatches=4))
+    runs.append(PPOConfig(name="fig4_20000x50_d235", n_envs=20000, n_steps=50,
+                          net=NetShape(235, 12, (512, 256, 128)), epochs=5, minibatches=4))
+    return runs
+
+
 CONFIGS = {c.name: c for c in (TINY, FLAT, ROUGH, LARGE)}
 ALIASES = {"tiny": TINY.name, "flat": FLAT.name, "rough": ROUGH.name, "large": LARGE.name}
 

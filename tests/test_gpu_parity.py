@@ -107,7 +107,7 @@ def test_gae(name, gamma, lam, timeouts, normalize):
 def test_gae_ragged_small():
     d = require_gpu()
     ctx = ppo.Context(8, 2, (16,), "fp32")
-    for T, N in [(1, 2), (3, 1), (5, 65), (64, 130), (100, 3)]:
+    for T, N in [(1, 2), (3, 1), (5, 65), (64, 130), (100, 3), (384, 130), (1536, 128)]:
         _announce(f"gae ragged T={T} N={N}")
         rng = np.random.default_rng(T * 1000 + N)
         r = rng.normal(0, 1, (T, N)).astype(np.float32)
