@@ -91,6 +91,8 @@ class Workload:
         self.perms = torch.as_tensor(synth.make_permutations(B, cfg.epochs, seed=cfg.seed)).to(device)
         self.stats = torch.zeros(cfg.epochs, cfg.minibatches, ppo.PPO_STATS_WIDTH, dtype=f32, device=device)
         self.ws = self.ctx.new_workspace(N=N, T=T, M=M, device=device)
+        # one workspace for the whole run, written only through the library
+        self.ctx.keep_packed(True)
         self.hp = ppo.UpdateHParams(clip=cfg.clip, value_coef=cfg.value_coef, entropy_coef=cfg.entropy_coef,
                                     max_grad_norm=cfg.max_grad_norm, use_graph=True)
         self.batch = dict(obs=self.obs.view(B, D), actions=self.actions.view(B, A), logp=self.logp.view(B),
@@ -387,6 +389,7 @@ def update_distribution(wl, reps=20, warmup=3):
             times.append(e0.elapsed_time(e1))
     for dst, src in zip(state, saved):
         dst.copy_(src)
+    p.pack()      # the shadow was written outside the library: refresh it (and the packed copies)
     q25, q50, q75 = np.percentile(times, [25, 50, 75])
     return {"median_ms": round(float(q50), 3), "iqr_ms": round(float(q75 - q25), 3), "reps": reps,
             "samples_per_s_at_median": round(wl.cfg.batch / (q50 * 1e-3), 1)}

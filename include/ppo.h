@@ -187,6 +187,21 @@ int ppo_param_count(const ppo_net_desc *net, int64_t *count);
  * `capacity` is the length of `offsets`; PPO_E_SHAPE if it is too small. */
 int ppo_param_offsets(const ppo_net_desc *net, int64_t *offsets, int32_t capacity);
 
+/* Context options (ppo_ctx_set_option).
+ * PPO_OPT_KEEP_PACKED (0 or 1, default 0): bf16 inference keeps the forward
+ *   weights it packs into a workspace and reuses them on the next
+ *   ppo_rollout_infer with the same workspace and shadow, instead of packing
+ *   again on every call.  They are packed again when this library has written
+ *   the shadow since (ppo_pack_weights, ppo_update_epoch,
+ *   ppo_update_epoch_profiled, ppo_update_batched), when another call used an
+ *   overlapping workspace, and always for calls captured into a graph (a
+ *   shadow written under capture is never trusted again).  With the option
+ *   set, the caller promises that a workspace passed to ppo_rollout_infer
+ *   stays allocated and is written only by this library's calls, and that
+ *   the shadow is written only by them or followed by ppo_pack_weights. */
+#define PPO_OPT_KEEP_PACKED 1
+int ppo_ctx_set_option(ppo_ctx *ctx, int32_t option, int32_t value);
+
 /* Bytes of device workspace the calls below need for N environments per
  * rollout step, T steps and mini-batch size M.  One workspace of this size
  * serves ppo_rollout_infer (N rows), ppo_gae (T x N) and
@@ -205,7 +220,9 @@ int ppo_pack_weights(const ppo_ctx *ctx, void *stream, const float *theta, uint1
  * 1) for action group g; uniforms ((x >> 9) + 1/2) 2^-23; Box-Muller pairs.
  * With actions == NULL only the critic runs (value-only mode, e.g. for the
  * bootstrap values of the observation after the last step); values must be
- * non-NULL.  `ws` must hold ppo_workspace_size(ctx, N, *, *) bytes. */
+ * non-NULL.  `ws` must hold ppo_workspace_size(ctx, N, *, *) bytes.
+ * bf16 networks run from forward weights packed into `ws` at every call,
+ * unless the context has PPO_OPT_KEEP_PACKED set (see ppo_ctx_set_option). */
 int ppo_rollout_infer(const ppo_ctx *ctx, void *stream, const ppo_params *p,
                       const float *obs, int32_t N, int32_t t, uint64_t seed,
                       uint32_t iteration, float *actions, float *logp,

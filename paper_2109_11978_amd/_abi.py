@@ -17,6 +17,7 @@ PPO_FP32 = 0
 PPO_BF16 = 1
 PPO_MAX_HIDDEN = 4
 PPO_STATS_WIDTH = 10
+PPO_OPT_KEEP_PACKED = 1
 PHASES = ("gather", "forward", "head_loss", "input_grad", "weight_grad", "grad_reduce", "adam", "fused")
 
 ERROR_NAMES = {
@@ -57,6 +58,7 @@ EXPORTS = {
     "ppo_last_error": (c_char_p, []),
     "ppo_ctx_create": (c_int32, [POINTER(NetDesc), c_int32, POINTER(c_void_p)]),
     "ppo_ctx_destroy": (c_int32, [c_void_p]),
+    "ppo_ctx_set_option": (c_int32, [c_void_p, c_int32, c_int32]),
     "ppo_param_count": (c_int32, [POINTER(NetDesc), POINTER(c_int64)]),
     "ppo_param_offsets": (c_int32, [POINTER(NetDesc), POINTER(c_int64), c_int32]),
     "ppo_workspace_size": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_size_t)]),

@@ -144,6 +144,13 @@ class Context:
         check(_lib().ppo_fused_shape(self.handle, ctypes.byref(r), ctypes.byref(t)))
         return r.value, t.value
 
+    def keep_packed(self, enable: bool = True) -> None:
+        """PPO_OPT_KEEP_PACKED: reuse the forward weights packed into a workspace
+        across inference calls.  Only for workspaces kept alive and written by
+        this library alone (not the per-call workspaces the binding allocates
+        when none is passed)."""
+        check(_lib().ppo_ctx_set_option(self.handle, _abi.PPO_OPT_KEEP_PACKED, int(bool(enable))))
+
     def new_workspace(self, N: int = 0, T: int = 0, M: int = 0, device="cuda") -> torch.Tensor:
         nbytes = self.workspace_size(N, T, M)
         return torch.empty(max(nbytes, 16), dtype=torch.uint8, device=device)

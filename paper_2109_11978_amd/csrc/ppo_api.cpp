@@ -270,6 +270,87 @@ WsPlan plan_workspace(const NetLayout &g, Precision prec, int N, int T, int M) {
     return w;
 }
 
+// -------------------------------------------------- packed-weight cache
+// Inference reads the forward weights of a bf16 network in fragment order,
+// packed from the shadow into the workspace.  Over a rollout the shadow does
+// not change, so with PPO_OPT_KEEP_PACKED set on the context the pack is
+// skipped when the workspace still holds the fragments of the same shadow at
+// the same generation (the caller keeps its workspaces alive and writes them
+// only through this library).  Host-side records, process-wide:
+//   g_shadow_gen  per shadow, bumped by every write to it that this library
+//                 enqueues; -1 (never trusted again) once such a write was
+//                 enqueued under stream capture, since each replay of the
+//                 captured work writes it again without passing through here;
+//   g_frag_cache  which workspace ranges hold which (context, shadow,
+//                 generation, offset) forward fragments; dropped by every
+//                 other call whose workspace range overlaps.
+// Packing under stream capture always packs and records nothing.
+struct FragRecord {
+    uintptr_t lo, hi;
+    const ppo_ctx *ctx;
+    const uint16_t *shadow;
+    long long gen;
+    size_t off;
+};
+std::mutex g_cache_mu;
+std::map<const uint16_t *, long long> g_shadow_gen;
+std::vector<FragRecord> g_frag_cache;
+
+bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    // an error counts as capturing: nothing is cached then
+    return hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone;
+}
+
+void drop_overlapping(const void *ws, size_t bytes) {
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(ws), hi = lo + bytes;
+    for (size_t i = 0; i < g_frag_cache.size();) {
+        if (g_frag_cache[i].lo < hi && lo < g_frag_cache[i].hi)
+            g_frag_cache.erase(g_frag_cache.begin() + static_cast<long>(i));
+        else
+            ++i;
+    }
+}
+
+void note_ws_used(const void *ws, size_t bytes) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    drop_overlapping(ws, bytes);
+}
+
+void note_shadow_written(const uint16_t *shadow, hipStream_t s) {
+    if (!shadow) return;
+    const bool cap = stream_capturing(s);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    long long &g = g_shadow_gen[shadow];
+    if (cap)
+        g = -1;
+    else if (g >= 0)
+        ++g;
+}
+
+bool frags_current(const ppo_ctx *c, const uint16_t *shadow, const void *ws, size_t off) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_shadow_gen.find(shadow);
+    const long long gen = it == g_shadow_gen.end() ? 0 : it->second;
+    if (gen < 0) return false;
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(ws);
+    for (const FragRecord &r : g_frag_cache)
+        if (r.lo == lo && r.ctx == c && r.shadow == shadow && r.gen == gen && r.off == off) return true;
+    return false;
+}
+
+void note_frags_packed(const ppo_ctx *c, const uint16_t *shadow, const void *ws, size_t bytes, size_t off,
+                       hipStream_t s) {
+    const bool cap = stream_capturing(s);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    drop_overlapping(ws, bytes);
+    if (cap) return;
+    const long long gen = g_shadow_gen[shadow];
+    if (gen < 0) return;
+    const uintptr_t lo = reinterpret_cast<uintptr_t>(ws);
+    g_frag_cache.push_back(FragRecord{lo, lo + bytes, c, shadow, gen, off});
+}
+
 // --------------------------------------------------------------- device
 std::mutex g_dev_mu;
 std::map<int, int> g_dev_ok;  // device -> PPO_OK or error code
@@ -319,6 +400,7 @@ struct ppo_ctx {
     std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
     std::vector<std::vector<uint64_t>> graph_order;  // insertion order for eviction
     std::map<int, Tuning> tuned;                      // GEMM rows -> measured tile choices
+    bool keep_packed = false;                         // PPO_OPT_KEEP_PACKED
 };
 
 namespace {
@@ -1145,7 +1227,24 @@ int ppo_ctx_destroy(ppo_ctx *c) {
     if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     if (c->capture) (void)hipStreamDestroy(c->capture);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (size_t i = 0; i < g_frag_cache.size();) {
+            if (g_frag_cache[i].ctx == c)
+                g_frag_cache.erase(g_frag_cache.begin() + static_cast<long>(i));
+            else
+                ++i;
+        }
+    }
     delete c;
+    return PPO_OK;
+}
+
+int ppo_ctx_set_option(ppo_ctx *c, int32_t option, int32_t value) {
+    if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
+    if (option != PPO_OPT_KEEP_PACKED) return fail(PPO_E_INVAL, "unknown option %d", option);
+    if (value != 0 && value != 1) return fail(PPO_E_INVAL, "option value %d is not 0 or 1", value);
+    c->keep_packed = value == 1;
     return PPO_OK;
 }
 
@@ -1162,6 +1261,7 @@ int ppo_pack_weights(const ppo_ctx *c, void *stream, const float *theta, uint16_
     PPO_CHECK(check_ptr(theta, "theta"));
     PPO_CHECK(check_ptr(shadow, "shadow"));
     PPO_CHECK(check_device());
+    note_shadow_written(shadow, static_cast<hipStream_t>(stream));
     PPO_HIP(launch_pack_bf16(theta, shadow, c->g.P, static_cast<hipStream_t>(stream)), "pack_bf16");
     return PPO_OK;
 }
@@ -1190,7 +1290,11 @@ int ppo_rollout_infer(const ppo_ctx *c, void *stream, const ppo_params *p, const
     if (fsh.rows > 0) {
         // forward weights into fragment order, then one launch for the whole
         // forward pass and the sampling head
-        PPO_HIP(launch_pack_frags(build_frags(c, p, w, ws, false), s), "pack_frags");
+        // a captured call always packs: its replays may follow any shadow write
+        if (!(c->keep_packed && !stream_capturing(s) && frags_current(c, p->shadow, ws, w.frag.off))) {
+            PPO_HIP(launch_pack_frags(build_frags(c, p, w, ws, false), s), "pack_frags");
+            note_frags_packed(c, p->shadow, ws, ws_bytes, w.frag.off, s);
+        }
         const uint16_t *frag = reinterpret_cast<const uint16_t *>(wsp(ws, w.frag));
         FusedArgs a{};
         for (int net = 0; net < 2; ++net) {
@@ -1225,6 +1329,7 @@ int ppo_rollout_infer(const ppo_ctx *c, void *stream, const ppo_params *p, const
         PPO_HIP(launch_fused_infer(a, s), "fused inference");
         return PPO_OK;
     }
+    note_ws_used(ws, ws_bytes);
     Tuning tune;
     PPO_CHECK(ensure_tuned(c, p, w, ws, N, false, s, tune));
     PPO_HIP(launch_stage_weights(c->prec, build_stage(c, p, w, ws, false), s), "stage_weights");
@@ -1273,6 +1378,7 @@ int ppo_gae(const ppo_ctx *c, void *stream, const float *rewards, const uint8_t 
         return fail(PPO_E_INVAL, "gamma and lambda must lie in [0, 1]");
     if (normalize != 0 && normalize != 1) return fail(PPO_E_INVAL, "normalize must be 0 or 1");
     PPO_CHECK(validate_ws(c, N, T, 0, ws, ws_bytes));
+    note_ws_used(ws, ws_bytes);
     PPO_CHECK(check_device());
 
     const hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1308,6 +1414,7 @@ int ppo_loss_grad(const ppo_ctx *c, void *stream, const ppo_params *p, const ppo
     PPO_CHECK(check_ptr(grad_out, "grad_out"));
     PPO_CHECK(validate_ws(c, 0, 0, M, ws, ws_bytes));
     PPO_CHECK(check_device());
+    note_ws_used(ws, ws_bytes);
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
     StepBuffers sb{b, idx, M, grad_out, stats, 0, 0};
     Tuning tune;
@@ -1333,6 +1440,8 @@ int ppo_update_epoch(ppo_ctx *c, void *stream, const ppo_params *p, const ppo_ba
     PPO_CHECK(check_device());
 
     const hipStream_t s = static_cast<hipStream_t>(stream);
+    note_ws_used(ws, ws_bytes);
+    note_shadow_written(p->shadow, s);
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
     Tuning tune;
     PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, s, tune));
@@ -1412,6 +1521,8 @@ int ppo_update_epoch_profiled(ppo_ctx *c, void *stream, const ppo_params *p, con
     PPO_CHECK(check_device());
 
     const hipStream_t s = static_cast<hipStream_t>(stream);
+    note_ws_used(ws, ws_bytes);
+    note_shadow_written(p->shadow, s);
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
     Tuning tune;
     PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, s, tune));
@@ -1856,6 +1967,10 @@ int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_
     }
     PPO_CHECK(check_device());
     const hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < R; ++i) {
+        note_ws_used(ws[i], ws_bytes[i]);
+        note_shadow_written(params[i].shadow, s);
+    }
     BatchedTuning bt;
     {
         std::string key = std::string(autotune_enabled() ? "t" : "f");

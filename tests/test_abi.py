@@ -238,3 +238,13 @@ def test_assemble_obs_validation():
         assert call(terrain=_abi.Terrain(FAKE, 480, 480, inv_res, FAKE, 187)) == ppo.PPO_E_INVAL
     assert call(terrain=_abi.Terrain(None, 480, 480, 10.0, FAKE, 187)) == ppo.PPO_E_INVAL
     assert call(terrain=_abi.Terrain(FAKE, 480, 480, 10.0, None, 187)) == ppo.PPO_E_INVAL
+
+
+def test_ctx_set_option_validation():
+    lib = ppo.load()
+    ctx = ppo.Context(48, 12, (64, 64), "bf16")
+    assert lib.ppo_ctx_set_option(None, _abi.PPO_OPT_KEEP_PACKED, 1) == ppo.PPO_E_INVAL
+    assert lib.ppo_ctx_set_option(ctx.handle, 99, 1) == ppo.PPO_E_INVAL
+    assert lib.ppo_ctx_set_option(ctx.handle, _abi.PPO_OPT_KEEP_PACKED, 2) == ppo.PPO_E_INVAL
+    assert lib.ppo_ctx_set_option(ctx.handle, _abi.PPO_OPT_KEEP_PACKED, 1) == ppo.PPO_OK
+    assert lib.ppo_ctx_set_option(ctx.handle, _abi.PPO_OPT_KEEP_PACKED, 0) == ppo.PPO_OK

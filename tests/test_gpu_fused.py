@@ -195,3 +195,88 @@ def test_fused_rollout_matches_layered(name, N, shape):
         assert nw < 1e-5, (k, nw)
     np.testing.assert_array_equal(f["v_only"], f["values"])
     np.testing.assert_array_equal(f["a_only"], f["actions"])
+
+
+def test_keep_packed_follows_every_weight_change():
+    """With PPO_OPT_KEEP_PACKED the rollout reuses the forward weights it
+    packed; every path that changes the shadow or reuses the workspace must
+    still give what a context that packs on every call gives, bit for bit:
+    a repeated call, an update epoch, theta written by torch then repacked,
+    a GAE call on the same workspace, and a captured inference graph
+    replayed across an update."""
+    d = require_gpu()
+    _announce("keep-packed rollout")
+    cfg = synth.get_config("flat")
+    net = cfg.net
+    ctx_k = ppo.Context(net.obs_dim, net.act_dim, net.hidden, "bf16")
+    ctx_k.keep_packed(True)
+    ctx_r = ppo.Context(net.obs_dim, net.act_dim, net.hidden, "bf16")
+    params = ppo.Params(ctx_k, synth.xavier_theta(net, seed=5, logstd=-0.3), device=d)
+    N, B, K, T = 1000, 4096, 2, 4
+    rng = np.random.default_rng(0)
+    obs = dev(rng.standard_normal((N, net.obs_dim)).astype(np.float32), d)
+    ws = ctx_k.new_workspace(N=N, T=T, M=B // K, device=d)
+    ws_r = ctx_r.new_workspace(N=N, device=d)
+    A = net.act_dim
+    outs = {k: torch.empty(N, A, device=d) for k in ("actions", "mu")}
+    outs.update({k: torch.empty(N, device=d) for k in ("logp", "values")})
+
+    def infer(ctx, w):
+        ppo.ppo_rollout_infer(ctx, params, obs, 3, 11, 2, ws=w, **outs)
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy().copy() for k, v in outs.items()}
+
+    def same_as_reference(tag):
+        got = infer(ctx_k, ws)
+        ref = infer(ctx_r, ws_r)
+        for k in got:
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"{tag}: {k}")
+        return got
+
+    first = same_as_reference("first call")
+    again = same_as_reference("cached call")
+    np.testing.assert_array_equal(first["mu"], again["mu"])
+
+    batch = dict(obs=dev(rng.standard_normal((B, net.obs_dim)).astype(np.float32), d),
+                 actions=dev(rng.standard_normal((B, A)).astype(np.float32), d),
+                 logp=dev(rng.normal(-15, 1, B).astype(np.float32), d),
+                 adv=dev(rng.standard_normal(B).astype(np.float32), d),
+                 returns=dev(rng.standard_normal(B).astype(np.float32), d))
+    perm = dev(rng.permutation(B).astype(np.int32), d)
+    stats = torch.zeros(K, ppo.PPO_STATS_WIDTH, device=d)
+    hp = ppo.UpdateHParams(use_graph=True)
+    ppo.ppo_update_epoch(ctx_k, params, batch, perm, K, hp, stats, ws)
+    after_update = same_as_reference("after update")
+    assert not np.array_equal(after_update["mu"], first["mu"])
+
+    params.theta.mul_(0.9)
+    params.pack()
+    same_as_reference("after theta written and repacked")
+
+    r = dev(rng.standard_normal((T, N)).astype(np.float32), d)
+    v = dev(rng.standard_normal((T, N)).astype(np.float32), d)
+    dn = dev((rng.random((T, N)) < 0.1).astype(np.uint8), d)
+    last = dev(rng.standard_normal(N).astype(np.float32), d)
+    adv, ret = torch.empty(T, N, device=d), torch.empty(T, N, device=d)
+    st = torch.empty(2, dtype=torch.float64, device=d)
+    ppo.ppo_gae(ctx_k, r, dn, v, last, 0.99, 0.95, adv, ret, st, ws=ws)
+    same_as_reference("after GAE on the same workspace")
+
+    # inference captured into a graph packs inside the graph; replays follow updates
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            ppo.ppo_rollout_infer(ctx_k, params, obs, 3, 11, 2, ws=ws, **outs)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        ppo.ppo_update_epoch(ctx_k, params, batch, perm, K, hp, stats, ws)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = {k: v.cpu().numpy().copy() for k, v in outs.items()}
+        ref = infer(ctx_r, ws_r)
+        for k in got:
+            np.testing.assert_array_equal(got[k], ref[k], err_msg=f"graph replay {rep}: {k}")
+        same_as_reference(f"eager after replay {rep}")
