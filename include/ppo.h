@@ -368,7 +368,7 @@ typedef struct ppo_terrain {
  * (n * ceil(D/4) + g, t, iteration, 2) for column j = 4 g + i (draw i), mapped
  * as in ppo_rollout_infer; tag 2 keeps it apart from the action noise (tag 1).
  * terrain may be NULL when S = 0; proprio may be NULL when n_proprio = 0;
- * base may be NULL when S = 0.  N * ceil(D/4) < 2^31.  Asynchronous on
+ * base may be NULL when S = 0.  N <= 2^24 and N * ceil(D/4) < 2^31.  Asynchronous on
  * `stream`; the caller owns every buffer. */
 int ppo_assemble_obs(const ppo_ctx *ctx, void *stream, const float *proprio, int32_t n_proprio,
                      const float *base, const ppo_terrain *terrain, const float *noise_scale,

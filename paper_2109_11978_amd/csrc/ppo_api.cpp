@@ -2100,8 +2100,8 @@ int ppo_assemble_obs(const ppo_ctx *c, void *stream, const float *proprio, int32
     if (n_proprio < 0 || S < 0 || static_cast<long long>(n_proprio) + S != D)
         return fail(PPO_E_SHAPE, "n_proprio %d + n_scan %d must equal obs_dim %d", n_proprio, S, D);
     const long long groups = (D + 3) / 4;
-    if (N < 1 || N * groups > 0x7FFFFFFFLL)
-        return fail(PPO_E_SHAPE, "N = %d outside 1..%lld", N, 0x7FFFFFFFLL / groups);
+    const long long n_max = std::min(1LL << 24, 0x7FFFFFFFLL / groups);
+    if (N < 1 || N > n_max) return fail(PPO_E_SHAPE, "N = %d outside 1..%lld", N, n_max);
     if (t < 0) return fail(PPO_E_SHAPE, "t = %d must be non-negative", t);
     PPO_CHECK(check_ptr(proprio, "proprio", n_proprio == 0));
     PPO_CHECK(check_ptr(noise_scale, "noise_scale", true));

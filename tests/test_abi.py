@@ -226,6 +226,7 @@ def test_assemble_obs_validation():
     assert call(terrain=None) == ppo.PPO_E_SHAPE         # 48 + 0 != 235
     assert call(N=0) == ppo.PPO_E_SHAPE
     assert call(N=1 << 30) == ppo.PPO_E_SHAPE            # N * ceil(D/4) >= 2^31
+    assert call(N=(1 << 24) + 1) == ppo.PPO_E_SHAPE
     assert call(t=-1) == ppo.PPO_E_SHAPE
     assert call(obs=None) == ppo.PPO_E_INVAL
     assert call(obs=FAKE + 4) == ppo.PPO_E_INVAL
