@@ -442,6 +442,7 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
 // Each lane keeps a float64 Welford (count, mean, M2) of its advantages; the
 // block merges them (Chan et al.) in a fixed order into one partial.
 constexpr int kGaeThreads = 256;
+constexpr int kGaeChunk = 16;   // rollout steps whose inputs a lane loads together
 constexpr int kFinalizeThreads = 256;
 
 struct Welford { double n, mean, m2; };
@@ -465,23 +466,45 @@ __global__ __launch_bounds__(kGaeThreads) void gae_kernel(const GaeArgs a) {
         float next_v = a.last_values[n];
         float next_a = 0.0f;
         const float gl = a.gamma * a.lam;
-        for (int t = a.T - 1; t >= 0; --t) {
-            const long long s = static_cast<long long>(t) * a.N + n;
-            const float v = a.values[s];
-            float r = a.rewards[s];
-            if (a.timeouts && a.timeouts[s]) r += a.gamma * v;
-            const float nd = a.dones[s] ? 0.0f : 1.0f;
-            const float delta = r + a.gamma * nd * next_v - v;
-            const float adv = delta + gl * nd * next_a;
-            a.adv[s] = adv;
-            a.returns[s] = adv + v;
-            next_v = v;
-            next_a = adv;
-            const double x = adv;
-            w.n += 1.0;
-            const double d = x - w.mean;
-            w.mean += d / w.n;
-            w.m2 += d * (x - w.mean);
+        // the scan runs backwards in chunks of kGaeChunk steps whose inputs
+        // are all loaded before the chunk's arithmetic, so a lane waits for
+        // memory once per chunk rather than once per step
+        for (int t0 = a.T - 1; t0 >= 0; t0 -= kGaeChunk) {
+            float vv[kGaeChunk], rr[kGaeChunk];
+            uint8_t dd[kGaeChunk], tt[kGaeChunk];
+#pragma unroll
+            for (int i = 0; i < kGaeChunk; ++i) {
+                const int t = t0 - i;
+                if (t >= 0) {
+                    const long long s = static_cast<long long>(t) * a.N + n;
+                    vv[i] = a.values[s];
+                    rr[i] = a.rewards[s];
+                    dd[i] = a.dones[s];
+                    tt[i] = a.timeouts ? a.timeouts[s] : 0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kGaeChunk; ++i) {
+                const int t = t0 - i;
+                if (t >= 0) {
+                    const long long s = static_cast<long long>(t) * a.N + n;
+                    const float v = vv[i];
+                    float r = rr[i];
+                    if (tt[i]) r += a.gamma * v;
+                    const float nd = dd[i] ? 0.0f : 1.0f;
+                    const float delta = r + a.gamma * nd * next_v - v;
+                    const float adv = delta + gl * nd * next_a;
+                    a.adv[s] = adv;
+                    a.returns[s] = adv + v;
+                    next_v = v;
+                    next_a = adv;
+                    const double x = adv;
+                    w.n += 1.0;
+                    const double d = x - w.mean;
+                    w.mean += d / w.n;
+                    w.m2 += d * (x - w.mean);
+                }
+            }
         }
     }
 #pragma unroll
