@@ -193,6 +193,10 @@ def phase_model(cfg, precision, P):
         "weight_grad": (dw_f, dw_b),
         "head_loss": (M * H[-1] * (A + 1) * 4.0, head_b),
         "gather": (0.0, M * D * 4.0 + M * kpad * e + M * 4.0),
+        # fused path: one packing launch per epoch, bf16 weights read and written in
+        # fragment order (forward, and transposed for the input-gradient chain), per launch
+        "pack": (0.0, 2 * 2.0 * (sum(H[l] * ins_pad[l] for l in range(L))
+                                 + sum(H[l] * H[l - 1] for l in range(1, L))) * 2),
         "grad_reduce": (0.0, 4.0 * P),
         "adam": (0.0, (30.0 if precision == "bf16" else 28.0) * P),
     }
@@ -260,8 +264,11 @@ def roofline(wl, precision):
         if launches == 0:
             continue
         t = ms * 1e-3 / launches
-        f, b = model.get(name, (0.0, 0.0))
-        f, b = f * steps / launches, b * steps / launches
+        if name == "gather" and wl.ctx.fused_shape()[0] > 0:
+            f, b = model["pack"]          # already per launch
+        else:
+            f, b = model.get(name, (0.0, 0.0))
+            f, b = f * steps / launches, b * steps / launches
         t_f = f / (MFMA_PEAK_TFLOPS[precision] * 1e12)
         t_b = b / (HBM_PEAK_GBS * 1e9)
         phases[name] = {"ms_per_epoch": round(ms, 4), "launches": launches, "us_per_launch": round(t * 1e6, 2),

@@ -260,7 +260,18 @@ struct ReduceArgs {
 int reduce_blocks(long long total);  // includes the loss-partial block
 hipError_t launch_grad_reduce(const ReduceArgs &a, hipStream_t s);
 
+// A hidden-layer weight whose fragment copies (the layouts of
+// pack_frags_kernel) Adam refreshes with every updated element, so that the
+// next mini-batch step of the fused pass needs no packing launch.
+struct AdamFrag {
+    long long begin;        // flat offset of W_l [rows][cols] in theta
+    int rows, cols, S, S_t; // S: k-steps of the forward fragments, S_t: of the transposed ones
+    uint16_t *dst, *dst_t;  // forward and transposed fragments (dst_t null when not kept)
+};
+constexpr int kMaxAdamFrags = 2 * kMaxHidden;
 struct AdamArgs {
+    AdamFrag frag[kMaxAdamFrags];
+    int n_frag;                // 0: no fragment copies to refresh
     float *theta, *grad, *m, *v;
     uint16_t *shadow;          // may be null
     const int32_t *step;       // steps already taken before this epoch

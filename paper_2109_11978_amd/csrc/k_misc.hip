@@ -709,6 +709,24 @@ __global__ __launch_bounds__(kAdamThreads) void adam_kernel(const AdamArgs a) {
         const float th = a.theta[e] - lr * (m / bc1) / (sqrtf(v / bc2) + a.eps);
         a.theta[e] = th;
         if (a.shadow) a.shadow[e] = f32_to_bf16(th);
+        // the same bf16 value into the fragment copies of its weight matrix:
+        // element (r, c) of W [rows][cols] sits in fragment (r / 32, c / 16),
+        // lane r % 32 + 32 ((c % 16) / 8), element c % 8; in the transposed
+        // copy the roles of r and c swap
+        for (int j = 0; j < a.n_frag; ++j) {
+            const AdamFrag &F = a.frag[j];
+            const long long local = e - F.begin;
+            if (local < 0 || local >= static_cast<long long>(F.rows) * F.cols) continue;
+            const int r = static_cast<int>(local / F.cols), c = static_cast<int>(local - static_cast<long long>(r) * F.cols);
+            const uint16_t bits = f32_to_bf16(th);
+            F.dst[((static_cast<long long>(r >> 5) * F.S + (c >> 4)) * 64 + (r & 31) + 32 * ((c & 15) >> 3)) * 8 +
+                  (c & 7)] = bits;
+            if (F.dst_t)
+                F.dst_t[((static_cast<long long>(c >> 5) * F.S_t + (r >> 4)) * 64 + (c & 31) + 32 * ((r & 15) >> 3)) *
+                            8 +
+                        (r & 7)] = bits;
+            break;
+        }
     }
 }
 

@@ -853,6 +853,8 @@ struct StepBuffers {
     float *stats;        // [kStatsWidth]
     int apply;           // Adam step or statistics only
     int step_offset;
+    bool frags_ready = false;   // the fused pass's fragments already hold the current shadow
+    bool write_frags = false;   // Adam refreshes them for the next step
 };
 
 // Head/loss arguments of one mini-batch step over the rows idx[0 .. M).
@@ -1001,6 +1003,25 @@ FragArgs build_frags(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, voi
     return a;
 }
 
+// The fragment copies of every hidden-layer weight of both networks (the
+// same layouts and places as build_frags), for Adam to refresh.
+void add_adam_frags(AdamArgs &ad, const ppo_ctx *c, const WsPlan &w, void *ws) {
+    const NetLayout &g = c->g;
+    uint16_t *base = reinterpret_cast<uint16_t *>(wsp(ws, w.frag));
+    ad.n_frag = 0;
+    for (int net = 0; net < 2; ++net)
+        for (int l = 0; l < g.L; ++l) {
+            AdamFrag &F = ad.frag[ad.n_frag++];
+            F.begin = net == 0 ? g.Wa[l] : g.Wc[l];
+            F.rows = g.H[l];
+            F.cols = l == 0 ? g.D : g.H[l - 1];
+            F.S = (l == 0 ? w.kpad : F.cols) / 16;
+            F.S_t = g.H[l] / 16;
+            F.dst = base + w.frag_w[net][l];
+            F.dst_t = l >= 1 ? base + w.frag_wt[net][l] : nullptr;
+        }
+}
+
 FusedArgs fused_args(const ppo_ctx *c, const ppo_params *p, const ppo_hparams *hp, const WsPlan &w, void *ws,
                      const ppo_batch *b, const int32_t *idx, int M) {
     const NetLayout &g = c->g;
@@ -1060,7 +1081,7 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
     if (fused_r > 0) {
         // weights into fragment order, then gather, forward, loss and input
         // gradients of both networks in one launch
-        PROFILED(prof, PPO_PHASE_GATHER, launch_pack_frags(build_frags(c, p, w, ws), s));
+        if (!sb.frags_ready) PROFILED(prof, PPO_PHASE_GATHER, launch_pack_frags(build_frags(c, p, w, ws), s));
         FusedArgs fa = fused_args(c, p, hp, w, ws, sb.b, sb.idx, M);
         fa.R = fsh.rows;
         fa.NT = fsh.threads;
@@ -1089,7 +1110,8 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
     set_reduce_loss(red, c, p, hp, w, ws, sb.grad, M, sb.apply, fused_r);
     PROFILED(prof, PPO_PHASE_GRAD_REDUCE, launch_grad_reduce(red, s));
 
-    const AdamArgs ad = adam_args(c, p, hp, red, sb.grad, sb.stats, M, sb.step_offset, sb.apply);
+    AdamArgs ad = adam_args(c, p, hp, red, sb.grad, sb.stats, M, sb.step_offset, sb.apply);
+    if (fused_r > 0 && sb.write_frags && sb.apply) add_adam_frags(ad, c, w, ws);
     PROFILED(prof, PPO_PHASE_ADAM, launch_adam(ad, s));
     return hipSuccess;
 }
@@ -1448,6 +1470,9 @@ int ppo_update_epoch(ppo_ctx *c, void *stream, const ppo_params *p, const ppo_ba
     auto enqueue_all = [&](hipStream_t target) -> hipError_t {
         for (int k = 0; k < n_minibatches; ++k) {
             StepBuffers sb{b, perm + static_cast<long long>(k) * M, M, p->grad, stats + k * PPO_STATS_WIDTH, 1, k};
+            // after the first step, Adam leaves the fragments of the next one in place
+            sb.frags_ready = k > 0;
+            sb.write_frags = k + 1 < n_minibatches;
             hipError_t e = enqueue_step(c, p, hp, w, ws, sb, tune, target);
             if (e != hipSuccess) return e;
         }
@@ -1532,6 +1557,8 @@ int ppo_update_epoch_profiled(ppo_ctx *c, void *stream, const ppo_params *p, con
     prof.reduce_repeatable = !(hp->desired_kl > 0.0f);
     for (int k = 0; k < n_minibatches; ++k) {
         StepBuffers sb{b, perm + static_cast<long long>(k) * M, M, p->grad, stats + k * PPO_STATS_WIDTH, 1, k};
+        sb.frags_ready = k > 0;
+        sb.write_frags = k + 1 < n_minibatches;
         PPO_HIP(enqueue_step(c, p, hp, w, ws, sb, tune, s, &prof), "update_epoch (profiled)");
     }
     PPO_HIP(launch_step_advance(p->step, n_minibatches, s), "step_advance");
