@@ -606,16 +606,25 @@ __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(const Reduc
         const int cols = 7 + a.A;
         const int c = threadIdx.x & 31, st = threadIdx.x >> 5;
         if (c < cols) {
-            // four independent running sums keep four loads in flight; they are
-            // combined in a fixed order, so the result does not depend on timing
-            float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            int b = st;
-            for (; b + 24 < a.n_loss; b += 32)
+            // sixteen independent running sums keep sixteen loads in flight (the
+            // partials come from every XCD, so each round trip is long); they
+            // are combined in a fixed pairwise order, so the result does not
+            // depend on timing
+            constexpr int U = 16;
+            float acc[U];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < U; ++u) acc[u] = 0.0f;
+            int b = st;
+            for (; b + 8 * (U - 1) < a.n_loss; b += 8 * U)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
                     acc[u] += a.loss_partials[static_cast<long long>(b + 8 * u) * a.loss_width + c];
             for (; b < a.n_loss; b += 8) acc[0] += a.loss_partials[static_cast<long long>(b) * a.loss_width + c];
-            stripe[st][c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+            for (int w = 1; w < U; w *= 2)
+#pragma unroll
+                for (int u = 0; u < U; u += 2 * w) acc[u] += acc[u + w];
+            stripe[st][c] = acc[0];
         }
         __syncthreads();
         if (threadIdx.x < cols) {
