@@ -689,8 +689,8 @@ def main():
         "phases_bf16": phases,
         "gemm_tflops_bf16": gemm_tflops,
         "autotuned_tiles": {"update": wl.ctx.tuning(cfg.minibatch, True),
-                            "rollout": ("fused pass, %d environments x %d threads per workgroup" % wl.ctx.fused_shape()
-                                        if wl.ctx.fused_shape()[0] else wl.ctx.tuning(cfg.n_envs, False))},
+                            "rollout": ("fused pass, %d environments x %d threads per workgroup" % wl.ctx.fused_infer_shape()
+                                        if wl.ctx.fused_infer_shape()[0] else wl.ctx.tuning(cfg.n_envs, False))},
     }
     if not args.no_fp32:
         wl32 = Workload(cfg, "fp32", dev)

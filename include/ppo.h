@@ -339,6 +339,12 @@ int ppo_ctx_tuning(const ppo_ctx *ctx, int32_t rows, int32_t update, int32_t *ch
  * than 2^31 bytes of observations or misaligned biases.  Host only. */
 int ppo_fused_shape(const ppo_ctx *ctx, int32_t *rows, int32_t *threads);
 
+/* The same for bf16 inference (ppo_rollout_infer): without PPO_FUSED_ROWS /
+ * PPO_FUSED_THREADS it prefers 64 rows x 256 threads where that block fits,
+ * since a policy step is latency-bound and each weight fragment then feeds two
+ * products.  Host only. */
+int ppo_fused_infer_shape(const ppo_ctx *ctx, int32_t *rows, int32_t *threads);
+
 /* Terrain seen by the height scan: a height field on a uniform grid and the
  * scan pattern.  Cell (i, j) of `height` [nx, ny] (row-major, float32) is the
  * terrain height at world (i / inv_res, j / inv_res); `scan` [n_scan, 2] holds

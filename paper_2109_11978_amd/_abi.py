@@ -82,6 +82,7 @@ EXPORTS = {
                                      POINTER(c_void_p), POINTER(c_size_t)]),
     "ppo_ctx_tuning": (c_int32, [c_void_p, c_int32, c_int32, POINTER(c_int32), c_int32]),
     "ppo_fused_shape": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
+    "ppo_fused_infer_shape": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32)]),
     "ppo_assemble_obs": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, POINTER(Terrain), c_void_p,
                                    c_int32, c_int32, c_uint64, c_uint32, c_void_p]),
     "ppo_philox_blocks": (c_int32, [c_void_p, c_uint64, c_uint32, c_uint32, c_uint32, c_uint32, c_int64,

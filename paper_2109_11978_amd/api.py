@@ -144,6 +144,12 @@ class Context:
         check(_lib().ppo_fused_shape(self.handle, ctypes.byref(r), ctypes.byref(t)))
         return r.value, t.value
 
+    def fused_infer_shape(self) -> Tuple[int, int]:
+        """(environments, threads) per workgroup of bf16 fused inference, or (0, 0)."""
+        r, t = ctypes.c_int32(0), ctypes.c_int32(0)
+        check(_lib().ppo_fused_infer_shape(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        return r.value, t.value
+
     def keep_packed(self, enable: bool = True) -> None:
         """PPO_OPT_KEEP_PACKED: reuse the forward weights packed into a workspace
         across inference calls.  Only for workspaces kept alive and written by

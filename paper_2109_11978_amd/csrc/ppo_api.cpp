@@ -954,15 +954,22 @@ bool fused_env_enabled() {
 // covers, 16-byte aligned biases, and observation offsets that fit its
 // 32-bit buffer addressing.  PPO_FUSED=0 forces the layer-by-layer path;
 // PPO_FUSED_ROWS and PPO_FUSED_THREADS restrict the block shape.
-FusedShape fused_shape_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, int obs_rows) {
+FusedShape fused_shape_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, int obs_rows,
+                           bool inference = false) {
     const FusedShape none{0, 0, 0};
     if (c->prec != kBF16 || !fused_env_enabled()) return none;
     const NetLayout &g = c->g;
     const char *rows = std::getenv("PPO_FUSED_ROWS");
     const char *threads = std::getenv("PPO_FUSED_THREADS");
-    const FusedShape sh = fused_shape(g.L, g.H, w.kpad, g.A, rows ? std::atoi(rows) : 0,
-                                      threads ? std::atoi(threads) : 0);
+    FusedShape sh = fused_shape(g.L, g.H, w.kpad, g.A, rows ? std::atoi(rows) : 0, threads ? std::atoi(threads) : 0);
     if (sh.rows == 0) return none;
+    if (inference && !rows && !threads) {
+        // inference of a policy step is latency-bound (a few hundred
+        // workgroups): 64 rows per workgroup let each weight fragment feed two
+        // MFMAs, which shortens every workgroup's weight stream
+        const FusedShape wide = fused_shape(g.L, g.H, w.kpad, g.A, 64, 256);
+        if (wide.rows) sh = wide;
+    }
     if (static_cast<long long>(obs_rows) * g.D * 4 > 0x7FFFFFF0LL - 0x100000LL) return none;
     for (int net = 0; net < 2; ++net)
         for (int l = 0; l < g.L; ++l)
@@ -1308,7 +1315,7 @@ int ppo_rollout_infer(const ppo_ctx *c, void *stream, const ppo_params *p, const
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const NetLayout &g = c->g;
     const WsPlan w = plan_workspace(g, c->prec, N, 0, 0);
-    const FusedShape fsh = fused_shape_for(c, p, w, N);
+    const FusedShape fsh = fused_shape_for(c, p, w, N, true);
     if (fsh.rows > 0) {
         // forward weights into fragment order, then one launch for the whole
         // forward pass and the sampling head
@@ -2103,7 +2110,10 @@ int ppo_ctx_tuning(const ppo_ctx *c, int32_t rows, int32_t update, int32_t *choi
     return PPO_OK;
 }
 
-int ppo_fused_shape(const ppo_ctx *c, int32_t *rows, int32_t *threads) {
+}  // extern "C"
+
+namespace {
+int fused_shape_query(const ppo_ctx *c, int32_t *rows, int32_t *threads, bool inference) {
     if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
     if (!rows || !threads) return fail(PPO_E_INVAL, "rows or threads is NULL");
     *rows = 0;
@@ -2112,10 +2122,26 @@ int ppo_fused_shape(const ppo_ctx *c, int32_t *rows, int32_t *threads) {
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, 1);
     const char *r = std::getenv("PPO_FUSED_ROWS");
     const char *t = std::getenv("PPO_FUSED_THREADS");
-    const FusedShape sh = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, r ? std::atoi(r) : 0, t ? std::atoi(t) : 0);
+    FusedShape sh = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, r ? std::atoi(r) : 0, t ? std::atoi(t) : 0);
+    if (inference && sh.rows && !r && !t) {
+        const FusedShape wide = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, 64, 256);
+        if (wide.rows) sh = wide;
+    }
     *rows = sh.rows;
     *threads = sh.threads;
     return PPO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ppo_fused_shape(const ppo_ctx *c, int32_t *rows, int32_t *threads) {
+    return fused_shape_query(c, rows, threads, false);
+}
+
+int ppo_fused_infer_shape(const ppo_ctx *c, int32_t *rows, int32_t *threads) {
+    return fused_shape_query(c, rows, threads, true);
 }
 
 int ppo_assemble_obs(const ppo_ctx *c, void *stream, const float *proprio, int32_t n_proprio, const float *base,

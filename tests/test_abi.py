@@ -249,3 +249,22 @@ def test_ctx_set_option_validation():
     assert lib.ppo_ctx_set_option(ctx.handle, _abi.PPO_OPT_KEEP_PACKED, 2) == ppo.PPO_E_INVAL
     assert lib.ppo_ctx_set_option(ctx.handle, _abi.PPO_OPT_KEEP_PACKED, 1) == ppo.PPO_OK
     assert lib.ppo_ctx_set_option(ctx.handle, _abi.PPO_OPT_KEEP_PACKED, 0) == ppo.PPO_OK
+
+
+def test_fused_infer_shape_selection(monkeypatch):
+    """bf16 inference prefers 64 rows x 256 threads where that block fits and
+    the update would take the fused pass at all; shapes forced through the
+    environment apply to both."""
+    for k in ("PPO_FUSED", "PPO_FUSED_ROWS", "PPO_FUSED_THREADS"):
+        monkeypatch.delenv(k, raising=False)
+    flat = ppo.Context(48, 12, (512, 256, 128), "bf16")
+    assert flat.fused_infer_shape() == (64, 256)
+    assert flat.fused_shape() == (32, 256)
+    for H in ((1024, 512, 256), (64, 64)):
+        assert ppo.Context(235, 12, H, "bf16").fused_infer_shape() == (0, 0)
+    assert ppo.Context(48, 12, (512, 256, 128), "fp32").fused_infer_shape() == (0, 0)
+    monkeypatch.setenv("PPO_FUSED_ROWS", "32")
+    monkeypatch.setenv("PPO_FUSED_THREADS", "256")
+    assert flat.fused_infer_shape() == (32, 256)
+    monkeypatch.setenv("PPO_FUSED", "0")
+    assert flat.fused_infer_shape() == (0, 0)
