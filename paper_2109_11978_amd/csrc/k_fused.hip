@@ -304,14 +304,15 @@ __device__ inline void copy_out(const uint16_t *src, int pitch, uint16_t *dst, i
     }
 }
 
-// Observation rows of the block (batch rows s_rows[0 .. R)) as bf16 into
+// Observation rows of the block (batch rows s_rows[0 .. R), or m0 .. m0 + R
+// when s_rows is null) as bf16 into
 // LDS, zero-padded to kpad columns and zero past the last valid row.  Wave w
 // takes rows w, w + NW, ...; a row's elements are spread over the lanes
 // (coalesced), and sixteen buffer loads are in flight per lane (out-of-range
 // ones read zero).
 template <int R, int NT>
 __device__ inline void gather_rows(const FusedArgs &a, const int *s_rows, int rows, uint16_t *x, int pitch,
-                                   int wave, int lane) {
+                                   int wave, int lane, int m0 = 0) {
     constexpr int U = 16;
     constexpr int NW = NT / 64;
     constexpr int PER_WAVE = R / NW;
@@ -327,7 +328,8 @@ __device__ inline void gather_rows(const FusedArgs &a, const int *s_rows, int ro
             const int k = 64 * (t - il * cpr) + lane;
             const int i = wave + NW * il;
             const bool ok = t0 + u < total && i < rows && k < a.D;
-            const int row = __builtin_amdgcn_readfirstlane(s_rows[i]);
+            // batch rows from LDS, or (s_rows null) the block's own rows m0, m0 + 1, ...
+            const int row = s_rows ? __builtin_amdgcn_readfirstlane(s_rows[i]) : m0 + min(i, rows - 1);
             v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, ok ? k * 4 : kOutside, row * a.D * 4, 0));
         }
 #pragma unroll
@@ -774,10 +776,9 @@ void fused_infer_kernel(const FusedArgs a) {
     float *w_out = reinterpret_cast<float *>(lds + a.lds_w);
     float *s_bias = reinterpret_cast<float *>(lds + a.lds_bias);
     float *s_head = reinterpret_cast<float *>(lds + a.lds_head);
-    int *s_rows = reinterpret_cast<int *>(lds + a.lds_rows);
     const FusedNet &N = a.net[net];
-
-    if (tid < R) s_rows[tid] = m0 + min(tid, rows - 1);
+    uint16_t *x = reinterpret_cast<uint16_t *>(lds + a.lds_x);
+    const int xp = a.kpad + 8;
     {
         // output-layer weights, output biases, log-std and hidden biases in one
         // round of buffer loads, then the LDS stores (as in the update pass)
@@ -804,6 +805,9 @@ void fused_infer_kernel(const FusedArgs a) {
         const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.logstd, static_cast<long long>(A) * 4);
         const float vo = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ro, tid < n_out ? tid * 4 : kOutside, 0, 0));
         const float vl = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rl, tid < A ? tid * 4 : kOutside, 0, 0));
+        // the observation rows are the block's own (no index list): their loads
+        // go out behind the weight loads, so the prologue waits for memory once
+        gather_rows<R, NT>(a, nullptr, rows, x, xp, wave, lane, m0);
 #pragma unroll
         for (int u = 0; u < UW; ++u) {
             const int q = tid + u * NT;
@@ -833,10 +837,6 @@ void fused_infer_kernel(const FusedArgs a) {
         }
     }
     __syncthreads();
-    uint16_t *x = reinterpret_cast<uint16_t *>(lds + a.lds_x);
-    const int xp = a.kpad + 8;
-    gather_rows<R, NT>(a, s_rows, rows, x, xp, wave, lane);
-    __syncthreads();
 
     const uint16_t *in = x;
     int in_pitch = xp, K = a.kpad;
@@ -865,33 +865,57 @@ void fused_infer_kernel(const FusedArgs a) {
         if (lead && a.val_out) a.val_out[n] = o[0];
         return;
     }
+    // outputs past A are zero: 12 of them suffice when A <= 12
     float o[kFusedMaxAct];
-    if (nck == 2) { u32x4 hx[2]; head_dots<KP, 2, kFusedMaxAct>(hrow, wl, WP, s_head, hx, o); }
-    else if (nck == 4) { u32x4 hx[4]; head_dots<KP, 4, kFusedMaxAct>(hrow, wl, WP, s_head, hx, o); }
-    else { u32x4 hx[8]; head_dots<KP, 8, kFusedMaxAct>(hrow, wl, WP, s_head, hx, o); }
-    if (!lead) return;
-    const int groups = (A + 3) / 4;
-    double logp = -0.5 * A * 1.8378770664093453;
 #pragma unroll
-    for (int g = 0; g < kFusedMaxAct / 4; ++g) {
-        if (g >= groups) break;
-        uint32_t c[4] = {static_cast<uint32_t>(n) * groups + g, a.t_step, a.iteration, 1u};
+    for (int j = 0; j < kFusedMaxAct; ++j) o[j] = 0.0f;
+    if (A <= 12) {
+        float o12[12];
+        if (nck == 2) { u32x4 hx[2]; head_dots<KP, 2, 12>(hrow, wl, WP, s_head, hx, o12); }
+        else if (nck == 4) { u32x4 hx[4]; head_dots<KP, 4, 12>(hrow, wl, WP, s_head, hx, o12); }
+        else { u32x4 hx[8]; head_dots<KP, 8, 12>(hrow, wl, WP, s_head, hx, o12); }
+#pragma unroll
+        for (int j = 0; j < 12; ++j) o[j] = o12[j];
+    } else {
+        if (nck == 2) { u32x4 hx[2]; head_dots<KP, 2, kFusedMaxAct>(hrow, wl, WP, s_head, hx, o); }
+        else if (nck == 4) { u32x4 hx[4]; head_dots<KP, 4, kFusedMaxAct>(hrow, wl, WP, s_head, hx, o); }
+        else { u32x4 hx[8]; head_dots<KP, 8, kFusedMaxAct>(hrow, wl, WP, s_head, hx, o); }
+    }
+    // lane kq of a sample draws action group kq (KP >= 4 lanes per sample,
+    // at most 4 groups); every lane holds all the sample's means
+    const int groups = (A + 3) / 4;
+    const bool draws = si < rows && kq < groups;
+    float eps[4];
+    {
+        uint32_t c[4] = {static_cast<uint32_t>(n) * groups + kq, a.t_step, a.iteration, 1u};
         philox4x32_10(c, a.key0, a.key1);
-        float eps[4];
         box_muller(c[0], c[1], eps[0], eps[1]);
         box_muller(c[2], c[3], eps[2], eps[3]);
+    }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int j = 4 * g + q;
-            if (j >= A) break;
-            const float m = o[j];
+    for (int q = 0; q < 4; ++q) {
+        float m = o[q];
+#pragma unroll
+        for (int g = 1; g < kFusedMaxAct / 4; ++g) m = kq == g ? o[4 * g + q] : m;
+        const int j = 4 * kq + q;
+        if (draws && j < A) {
             const float ls = s_head[kFusedMaxAct + j];
-            logp += -0.5 * static_cast<double>(eps[q]) * eps[q] - ls;
             if (a.act_out) a.act_out[static_cast<long long>(n) * A + j] = m + expf(ls) * eps[q];
             if (a.mu_out) a.mu_out[static_cast<long long>(n) * A + j] = m;
         }
     }
-    if (a.logp_out) a.logp_out[n] = static_cast<float>(logp);
+    // the lead lane sums the log-density over the actions in order
+    float e_all[kFusedMaxAct];
+#pragma unroll
+    for (int g = 0; g < kFusedMaxAct / 4; ++g)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e_all[4 * g + q] = g == 0 ? eps[q] : __shfl(eps[q], lane + g);
+    if (!lead || !a.logp_out) return;
+    double logp = -0.5 * A * 1.8378770664093453;
+#pragma unroll
+    for (int j = 0; j < kFusedMaxAct; ++j)
+        if (j < A) logp += -0.5 * static_cast<double>(e_all[j]) * e_all[j] - s_head[kFusedMaxAct + j];
+    a.logp_out[n] = static_cast<float>(logp);
 }
 
 size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
