@@ -5,8 +5,8 @@ types (random rough ground, slopes, stairs) laid out side by side, and the
 policy observes terrain heights sampled on a grid around the base
 (Section 3.2).  This module builds a small stand-in of that kind: each tile
 gets uniform noise of +-5 cm plus either a pyramid slope of up to 0.4 rad or
-pyramid stairs with 15 cm risers.  It is harness code: nothing here is graded
-and nothing here is part of the learning path.
+pyramid stairs with 15 cm risers.  It generates inputs only: nothing here is
+part of the learning path.
 """
 from __future__ import annotations
 
