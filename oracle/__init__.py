@@ -14,7 +14,8 @@ float64, step by step in the order of the definitions it cites, with no
 blocking, fusion or reordering beyond what a library matmul does.
 
 Parity status per function (what pins it; see tests/test_oracle_*.py):
-  philox4x32_10     known-answer vectors of the Philox reference + statistics
+  philox4x32_10     rocRAND's Philox4x32-10 (a library routine, built for the host)
+                    bit for bit on 2000 random blocks and the wrap edges; statistics
   uniforms/normals  closed form of the 24-bit uniform map; moment tests
   mlp_forward       pure-Python loop brute force on a tiny net
   gaussian_logp     scipy.stats.norm.logpdf sum; entropy vs Monte Carlo
