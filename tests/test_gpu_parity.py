@@ -267,6 +267,49 @@ def test_update_epoch_teacher_forced(prec):
     assert st["grad_norm"] == pytest.approx(np.linalg.norm(ref["grad"]), rel=tol)
 
 
+def test_update_epoch_teacher_forced_full_minibatch():
+    """The bench's configuration at full size: bf16, the 4096 x 24 network,
+    one mini-batch step of 24576 samples through the graph-captured epoch
+    (fused pass, weight gradients, reduction, Adam), with the gradient gated
+    as for the other bf16 cases and the optimiser state teacher-forced with
+    the device's own gradient."""
+    d = require_gpu()
+    cfg = synth.get_config("flat")
+    M = cfg.minibatch
+    _announce(f"update_epoch flat bf16 M={M}")
+    spec = spec_of(cfg)
+    theta = synth.xavier_theta(cfg.net, seed=2, logstd=-0.3)
+    batch = teacher_batch(cfg, theta, M, seed=21, shift="mixed")
+    perm = np.random.default_rng(22).permutation(M).astype(np.int32)
+    hp = PPOHyper()
+    ctx = ppo.Context(cfg.net.obs_dim, cfg.net.act_dim, cfg.net.hidden, "bf16")
+    assert ctx.fused_shape()[0] > 0
+    params = ppo.Params(ctx, theta, lr=hp.lr, device=d)
+    params.step.fill_(7)
+    m0 = synth.rollout.gaussian_like((ctx.param_count,), seed=23, scale=1e-3)
+    v0 = np.abs(synth.rollout.gaussian_like((ctx.param_count,), seed=24, scale=1e-5))
+    params.adam_m.copy_(dev(m0, d))
+    params.adam_v.copy_(dev(v0, d))
+    tb = {k: dev(v, d) for k, v in batch.items()}
+    stats = torch.zeros(1, ppo.PPO_STATS_WIDTH, device=d)
+    ws = ctx.new_workspace(M=M)
+    ppo.ppo_update_epoch(ctx, params, tb, dev(perm, d), 1, ppo.UpdateHParams(use_graph=True), stats, ws)
+    torch.cuda.synchronize()
+    mb = minibatch(oracle_view(batch), perm)
+    ref = ppo_loss_grad(theta, spec, mb, hp)
+    g_gpu = params.grad.cpu().numpy().astype(np.float64)
+    _check_bf16_grad(g_gpu, theta, spec, mb, hp, ref["grad"])
+    c, _ = clip_coef(g_gpu, hp.max_grad_norm)
+    th_ref, m_ref, v_ref = adam_step(theta, m0, v0, c * g_gpu, 7, hp)
+    assert_close("adam_m", params.adam_m.cpu().numpy(), m_ref, TOL["fp32"])
+    assert_close("adam_v", params.adam_v.cpu().numpy(), v_ref, TOL["fp32"])
+    assert_close("theta", params.theta.cpu().numpy(), th_ref, TOL["fp32"])
+    assert int(params.step[0].item()) == 8
+    st = ppo.stats_dict(stats[0].cpu().numpy())
+    assert st["grad_norm"] == pytest.approx(np.linalg.norm(ref["grad"]), rel=TOL["bf16"])
+    assert st["policy_loss"] == pytest.approx(ref["policy_loss"], rel=TOL["bf16"], abs=2e-3)
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_update_epoch_graph_matches_eager_and_is_deterministic(prec):
     d = require_gpu()
