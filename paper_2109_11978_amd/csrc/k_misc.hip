@@ -560,9 +560,21 @@ __global__ __launch_bounds__(kFinalizeThreads) void adv_finalize_kernel(const do
     if (!normalize) return;
     const double mean = s_mean;
     const double inv = 1.0 / (s_std + 1e-8);
-    for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < count;
-         e += static_cast<long long>(gridDim.x) * blockDim.x)
-        adv[e] = static_cast<float>((static_cast<double>(adv[e]) - mean) * inv);
+    auto norm = [&](float x) { return static_cast<float>((static_cast<double>(x) - mean) * inv); };
+    // 16-byte accesses (adv is 16-byte aligned), then the tail of count % 4
+    const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+    const long long first = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+    const long long n4 = count / 4;
+    float4 *adv4 = reinterpret_cast<float4 *>(adv);
+    for (long long e = first; e < n4; e += stride) {
+        float4 v = adv4[e];
+        v.x = norm(v.x);
+        v.y = norm(v.y);
+        v.z = norm(v.z);
+        v.w = norm(v.w);
+        adv4[e] = v;
+    }
+    for (long long e = 4 * n4 + first; e < count; e += stride) adv[e] = norm(adv[e]);
 }
 
 // -------------------------------------------------------- gradient reduce
