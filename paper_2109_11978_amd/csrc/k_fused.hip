@@ -81,9 +81,14 @@ __device__ inline float wave_sum(float v) {
 // fragments.  The loop runs whole groups of PF steps; steps past K multiply
 // zero weight fragments (loaded from outside the buffer) with a clamped,
 // finite activation fragment.
-template <int FBW, int SB, int PF>
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+template <int FBW, int SB, int PF, class Hook = NoHook>
 __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16_t *W, int rows_w, int S, int f0,
-                                          int sb0, const uint16_t *act, int pitch, int lane) {
+                                          int sb0, const uint16_t *act, int pitch, int lane,
+                                          const Hook &hook = Hook()) {
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(W, static_cast<long long>(rows_w / 32) * S * 1024);
     const int kh = (lane >> 5) * 8;
     // per-block lane offsets in VGPRs, one scalar step offset per load
@@ -104,6 +109,9 @@ __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16
             w[p][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, p < S ? vo[f] : kOutside, so, 0);
         __builtin_amdgcn_sched_barrier(0);
     }
+    // work that needs no weights (e.g. copying the previous layer's output to
+    // global memory) runs while the first fragments are in flight
+    hook();
     u32x4 b[SB];
 #pragma unroll
     for (int j = 0; j < SB; ++j) b[j] = *reinterpret_cast<const u32x4 *>(bp + 32 * j * pitch);
@@ -184,11 +192,12 @@ __device__ __forceinline__ void epi_backward(const floatx16 (&acc)[FBW][SB], int
         }
 }
 
-template <int FBW, int SB, int PF, bool BWD>
+template <int FBW, int SB, int PF, bool BWD, class Hook>
 __device__ __forceinline__ void layer_impl(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
-                                           int in_pitch, uint16_t *out, int out_pitch, int f0, int sb0, int lane) {
+                                           int in_pitch, uint16_t *out, int out_pitch, int f0, int sb0, int lane,
+                                           const Hook &hook) {
     floatx16 acc[FBW][SB];
-    mma_layer<FBW, SB, PF>(acc, W, nout, K >> 4, f0, sb0, in, in_pitch, lane);
+    mma_layer<FBW, SB, PF>(acc, W, nout, K >> 4, f0, sb0, in, in_pitch, lane, hook);
     if constexpr (BWD)
         epi_backward<FBW, SB>(acc, f0, sb0, out, out_pitch, lane);
     else
@@ -198,18 +207,21 @@ __device__ __forceinline__ void layer_impl(const uint16_t *W, int K, int nout, c
 // Weight fragments in flight per lane: PF k-steps x FBW blocks, up to 32,
 // with PF no larger than the layer's k-step count S = K / 16 (a power of two
 // for hidden layers; a first layer of 3 or 15 steps takes PF = 4).
-template <int FBW, int SB, bool BWD, int PFMAX>
+template <int FBW, int SB, bool BWD, int PFMAX, class Hook>
 __device__ __forceinline__ void layer_pf(int S, const uint16_t *W, int K, int nout, const float *bias,
                                          const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
-                                         int sb0, int lane) {
+                                         int sb0, int lane, const Hook &hook) {
     if (PFMAX >= 32 && S >= 32)
-        layer_impl<FBW, SB, (PFMAX >= 32 ? 32 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane);
+        layer_impl<FBW, SB, (PFMAX >= 32 ? 32 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane,
+                                                         hook);
     else if (PFMAX >= 16 && S >= 16)
-        layer_impl<FBW, SB, (PFMAX >= 16 ? 16 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane);
+        layer_impl<FBW, SB, (PFMAX >= 16 ? 16 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane,
+                                                         hook);
     else if (PFMAX >= 8 && S >= 8)
-        layer_impl<FBW, SB, (PFMAX >= 8 ? 8 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane);
+        layer_impl<FBW, SB, (PFMAX >= 8 ? 8 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane,
+                                                       hook);
     else
-        layer_impl<FBW, SB, 4, BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane);
+        layer_impl<FBW, SB, 4, BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane, hook);
 }
 
 // Deepest weight prefetch (k-steps) that keeps the accumulators (FBW x SBW
@@ -222,27 +234,29 @@ constexpr int pf_max() {
     return pf;
 }
 
-template <int SBW, bool BWD, bool WIDE, int REGS>
+template <int SBW, bool BWD, bool WIDE, int REGS, class Hook>
 __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int K, int nout, const float *bias,
                                          const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
-                                         int sb0, int lane) {
+                                         int sb0, int lane, const Hook &hook) {
     switch (fbw) {
     case 1:
         layer_pf<1, SBW, BWD, pf_max<1, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0,
-                                                      lane);
+                                                      lane, hook);
         break;
     case 2:
         layer_pf<2, SBW, BWD, pf_max<2, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0,
-                                                      lane);
+                                                      lane, hook);
         break;
     case 4:
         layer_pf<4, SBW, BWD, pf_max<4, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0,
-                                                      lane);
+                                                      lane, hook);
         break;
     default:
         if constexpr (WIDE)
             layer_pf<8, SBW, BWD, pf_max<8, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
-                                                          sb0, lane);
+                                                          sb0, lane, hook);
+        else
+            hook();
         break;
     }
 }
@@ -251,9 +265,10 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
 // are split over the NT / 64 waves; when there are fewer blocks than waves,
 // the waves sharing a block split the sample blocks instead (each weight
 // fragment is then read by two waves, the second time from L1).
-template <int R, int NT, int WPE, bool BWD>
+template <int R, int NT, int WPE, bool BWD, class Hook = NoHook>
 __device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
-                                          int in_pitch, uint16_t *out, int out_pitch, int wave, int lane) {
+                                          int in_pitch, uint16_t *out, int out_pitch, int wave, int lane,
+                                          const Hook &hook = Hook()) {
     constexpr int NW = NT / 64;
     constexpr int SB = R / 32;
     // registers for accumulators and fragments: 512 / WPE per lane, less
@@ -267,11 +282,13 @@ __device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, co
     if (fb >= NW) {
         const int fbw = fb / NW;
         layer_fb<SB, BWD, WIDE, REGS>(fbw, S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave * fbw * 32, 0,
-                                      lane);
+                                      lane, hook);
     } else if constexpr (SB >= 2) {
         // two waves per feature block, each with half the sample blocks
         layer_fb<SB / 2, BWD, false, REGS>(1, S, W, K, nout, bias, in, in_pitch, out, out_pitch, (wave % fb) * 32,
-                                           (wave / fb) * (SB / 2), lane);
+                                           (wave / fb) * (SB / 2), lane, hook);
+    } else {
+        hook();   // a wave without a feature block still does its share of the hook
     }
 }
 
@@ -624,21 +641,30 @@ void fused_update_kernel(const FusedArgs a) {
         if (part < 4) s_in[i * kInW + 2 * kFusedMaxAct + part] = v[2 * (kFusedMaxAct / TPS)];
     }
     __syncthreads();
-    if (net == 0) copy_out<NT>(x, xp, a.xg + static_cast<long long>(m0) * a.kpad, a.kpad, a.kpad, rows);
 
     // --------------------------------------------------------- forward
+    // each layer's output goes to global memory while the next layer's first
+    // weight fragments are in flight (the gathered inputs during the first)
     const uint16_t *in = x;
     int in_pitch = xp, K = a.kpad;
     for (int l = 0; l < L; ++l) {
         const int H = a.H[l];
         uint16_t *out = reinterpret_cast<uint16_t *>(lds + a.lds_region[l]);
-        run_layer<R, NT, WPE, false>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave, lane);
+        const int Hp = l > 0 ? a.H[l - 1] : 0;
+        auto hook = [&]() {
+            if (l == 0) {
+                if (net == 0) copy_out<NT>(x, xp, a.xg + static_cast<long long>(m0) * a.kpad, a.kpad, a.kpad, rows);
+            } else {
+                copy_out<NT>(in, Hp + 8, N.h[l - 1] + static_cast<long long>(m0) * Hp, Hp, Hp, rows);
+            }
+        };
+        run_layer<R, NT, WPE, false>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave, lane, hook);
         __syncthreads();
-        copy_out<NT>(out, H + 8, N.h[l] + static_cast<long long>(m0) * H, H, H, rows);
         in = out;
         in_pitch = H + 8;
         K = H;
     }
+    copy_out<NT>(in, in_pitch, N.h[L - 1] + static_cast<long long>(m0) * Hl, Hl, Hl, rows);
 
     // ----------------------------------------- output layer and PPO loss
     uint16_t *hl = reinterpret_cast<uint16_t *>(lds + a.lds_region[L - 1]);
@@ -700,17 +726,22 @@ void fused_update_kernel(const FusedArgs a) {
             out[1] = t[1];
         }
     }
-    copy_out<NT>(hl, PL, N.dz[L - 1] + static_cast<long long>(m0) * Hl, Hl, Hl, rows);
-
     // ------------------------------------------------ input-gradient chain
+    // the gradient a layer reads goes to global memory while that layer's
+    // first weight fragments are in flight
     for (int l = L - 1; l >= 1; --l) {
         const int Hin = a.H[l], Hout = a.H[l - 1];
         const uint16_t *dz = reinterpret_cast<const uint16_t *>(lds + a.lds_region[l]);
         uint16_t *hz = reinterpret_cast<uint16_t *>(lds + a.lds_region[l - 1]);
-        run_layer<R, NT, WPE, true>(N.WT[l], Hin, Hout, nullptr, dz, Hin + 8, hz, Hout + 8, wave, lane);
+        auto hook = [&]() {
+            copy_out<NT>(dz, Hin + 8, N.dz[l] + static_cast<long long>(m0) * Hin, Hin, Hin, rows);
+        };
+        run_layer<R, NT, WPE, true>(N.WT[l], Hin, Hout, nullptr, dz, Hin + 8, hz, Hout + 8, wave, lane, hook);
         __syncthreads();
-        copy_out<NT>(hz, Hout + 8, N.dz[l - 1] + static_cast<long long>(m0) * Hout, Hout, Hout, rows);
     }
+    const int H0 = a.H[0];
+    copy_out<NT>(reinterpret_cast<const uint16_t *>(lds + a.lds_region[0]), H0 + 8,
+                 N.dz[0] + static_cast<long long>(m0) * H0, H0, H0, rows);
 }
 
 // Weights in MFMA A-fragment order.  For a matrix with `rows` output
