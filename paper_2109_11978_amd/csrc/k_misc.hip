@@ -684,9 +684,27 @@ constexpr int kAdamThreads = 256;
 __global__ __launch_bounds__(kAdamThreads) void adam_kernel(const AdamArgs a) {
     __shared__ double s_sumsq;
     __shared__ double red[kAdamThreads / 64];
+    __shared__ float s_bc[2];
+    // this thread's first element goes out before the norm is known
+    const long long first = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x;
+    const bool pre = a.apply && first < a.P;
+    const float g_first = pre ? a.grad[first] : 0.0f;
+    const float m_first = pre ? a.m[first] : 0.0f;
+    const float v_first = pre ? a.v[first] : 0.0f;
+    const float th_first = pre ? a.theta[first] : 0.0f;
     // global norm: every block sums the same partials in the same order
+    // (four loads in flight, added in index order)
     double ss = 0.0;
-    for (int p = threadIdx.x; p < a.n_sumsq; p += kAdamThreads) ss += a.sumsq_partials[p];
+    int p = threadIdx.x;
+    for (; p + 3 * kAdamThreads < a.n_sumsq; p += 4 * kAdamThreads) {
+        const double s0 = a.sumsq_partials[p], s1 = a.sumsq_partials[p + kAdamThreads];
+        const double s2 = a.sumsq_partials[p + 2 * kAdamThreads], s3 = a.sumsq_partials[p + 3 * kAdamThreads];
+        ss += s0;
+        ss += s1;
+        ss += s2;
+        ss += s3;
+    }
+    for (; p < a.n_sumsq; p += kAdamThreads) ss += a.sumsq_partials[p];
     ss = wave_sum_d(ss);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
     __syncthreads();
@@ -694,6 +712,12 @@ __global__ __launch_bounds__(kAdamThreads) void adam_kernel(const AdamArgs a) {
         double t = 0.0;
         for (int w = 0; w < kAdamThreads / 64; ++w) t += red[w];
         s_sumsq = t;
+        if (a.apply) {
+            // bias corrections of this step, once per block
+            const int step = *a.step + a.step_offset + 1;
+            s_bc[0] = static_cast<float>(1.0 - pow(static_cast<double>(a.beta1), step));
+            s_bc[1] = static_cast<float>(1.0 - pow(static_cast<double>(a.beta2), step));
+        }
     }
     __syncthreads();
     const double norm = sqrt(s_sumsq);
@@ -716,29 +740,30 @@ __global__ __launch_bounds__(kAdamThreads) void adam_kernel(const AdamArgs a) {
     }
     if (!a.apply || !finite) return;
 
-    const int t = *a.step + a.step_offset + 1;
-    const float bc1 = static_cast<float>(1.0 - pow(static_cast<double>(a.beta1), t));
-    const float bc2 = static_cast<float>(1.0 - pow(static_cast<double>(a.beta2), t));
+    const float bc1 = s_bc[0], bc2 = s_bc[1];
     const float lr = *a.lr;
-    for (long long e = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; e < a.P;
-         e += static_cast<long long>(gridDim.x) * blockDim.x) {
-        const float g = a.grad[e] * coef;
-        const float m = a.beta1 * a.m[e] + (1.0f - a.beta1) * g;
-        const float v = a.beta2 * a.v[e] + (1.0f - a.beta2) * g * g;
+    auto update = [&](long long e, float g_raw, float m_old, float v_old, float th_old) {
+        const float g = g_raw * coef;
+        const float m = a.beta1 * m_old + (1.0f - a.beta1) * g;
+        const float v = a.beta2 * v_old + (1.0f - a.beta2) * g * g;
         a.m[e] = m;
         a.v[e] = v;
-        const float th = a.theta[e] - lr * (m / bc1) / (sqrtf(v / bc2) + a.eps);
+        const float th = th_old - lr * (m / bc1) / (sqrtf(v / bc2) + a.eps);
         a.theta[e] = th;
         if (a.shadow) a.shadow[e] = f32_to_bf16(th);
         // the same bf16 value into the fragment copies of its weight matrix:
         // element (r, c) of W [rows][cols] sits in fragment (r / 32, c / 16),
         // lane r % 32 + 32 ((c % 16) / 8), element c % 8; in the transposed
-        // copy the roles of r and c swap
+        // copy the roles of r and c swap.  The matrices are disjoint, so at
+        // most one matches; every lane visits all of them, which keeps the
+        // matrix descriptors uniform across the wave
         for (int j = 0; j < a.n_frag; ++j) {
             const AdamFrag &F = a.frag[j];
             const long long local = e - F.begin;
             if (local < 0 || local >= static_cast<long long>(F.rows) * F.cols) continue;
-            const int r = static_cast<int>(local / F.cols), c = static_cast<int>(local - static_cast<long long>(r) * F.cols);
+            // rows * cols < 2^31 (width and observation limits): 32-bit division
+            const unsigned li = static_cast<unsigned>(local), cols = static_cast<unsigned>(F.cols);
+            const int r = static_cast<int>(li / cols), c = static_cast<int>(li - static_cast<unsigned>(r) * cols);
             const uint16_t bits = f32_to_bf16(th);
             F.dst[((static_cast<long long>(r >> 5) * F.S + (c >> 4)) * 64 + (r & 31) + 32 * ((c & 15) >> 3)) * 8 +
                   (c & 7)] = bits;
@@ -746,9 +771,11 @@ __global__ __launch_bounds__(kAdamThreads) void adam_kernel(const AdamArgs a) {
                 F.dst_t[((static_cast<long long>(c >> 5) * F.S_t + (r >> 4)) * 64 + (c & 31) + 32 * ((r & 15) >> 3)) *
                             8 +
                         (r & 7)] = bits;
-            break;
         }
-    }
+    };
+    const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+    if (pre) update(first, g_first, m_first, v_first, th_first);
+    for (long long e = first + stride; e < a.P; e += stride) update(e, a.grad[e], a.m[e], a.v[e], a.theta[e]);
 }
 
 // ------------------------------------------------------- weight staging
