@@ -756,6 +756,9 @@ __global__ __launch_bounds__(256) void pack_frags_kernel(const FragArgs a) {
 #pragma unroll 1
     for (int q = 1; q < a.count; ++q)
         if (t >= a.job[q].begin) j = q;
+    // jobs cover whole multiples of 64 lane chunks, so a wave never straddles
+    // two: the index is uniform and the descriptor comes through scalar loads
+    j = __builtin_amdgcn_readfirstlane(j);
     const FragJob &J = a.job[j];
     const int local = t - J.begin;
     const int lane = local & 63;
