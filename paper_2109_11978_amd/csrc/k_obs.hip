@@ -3,10 +3,11 @@
 // columns, then terrain heights sampled around each robot's base from a height
 // field on a uniform grid, each element plus uniform noise of its own scale.
 //
-// A block takes 16 robots: one thread per (robot, group of 4 columns) draws
-// one Philox4x32-10 block for the group's 4 noise values, as in the action
-// sampling, and puts the group's values in LDS; then the block writes its
-// robots' rows, one contiguous range of the output, with 16-byte stores.  The
+// A block takes up to 16 robots (fewer at small N, to fill the chip): one
+// thread per (robot, group of 4 columns) draws one Philox4x32-10 block for the
+// group's 4 noise values, as in the action sampling, and puts the group's
+// values in LDS; then the block writes its robots' rows, one contiguous range
+// of the output, with 16-byte stores.  The
 // height field (a few MB at most) stays in L2 across the scan points of
 // neighbouring robots.
 #include <algorithm>
@@ -67,9 +68,10 @@ __device__ inline float obs_value(const ObsArgs &a, long long n, int j, uint32_t
 // rows are one contiguous range of obs, written with 16-byte stores when the
 // range starts 16-byte aligned (always when rows_per_block * D is a multiple
 // of 4 and obs is aligned), else with 4-byte stores.
-constexpr int kObsRows = 16;                 // robots per block when D <= 1024
+constexpr int kObsRows = 16;                 // robots per block at most (D <= 1024)
 constexpr int kObsLdsFloats = 16 * 1024;     // 64 KB of staging at most
 constexpr int kObsThreads = 256;
+constexpr long long kObsMinBlocks = 1024;   // workgroups to aim for at small N
 
 __global__ __launch_bounds__(kObsThreads) void assemble_obs_kernel(ObsArgs a) {
 #pragma clang fp contract(off)
@@ -138,7 +140,13 @@ hipError_t launch_assemble_obs(hipStream_t s, const float *proprio, int P, const
     a.k1 = static_cast<uint32_t>(seed >> 32);
     a.t = t;
     a.iteration = iteration;
-    a.rows_per_block = std::max(1, std::min(kObsRows, kObsLdsFloats / a.D));
+    // fewer robots per workgroup when there are few robots: at least about
+    // 1024 workgroups (four per compute unit), so a thread's share of a block
+    // is one (robot, group) item with its chain of dependent loads rather
+    // than several in a row
+    const long long fill = (N + kObsMinBlocks - 1) / kObsMinBlocks;
+    a.rows_per_block = static_cast<int>(std::max<long long>(
+        1, std::min<long long>(std::min(kObsRows, kObsLdsFloats / a.D), fill)));
     const long long blocks = (N + a.rows_per_block - 1) / a.rows_per_block;
     const size_t lds = static_cast<size_t>(a.rows_per_block) * a.D * sizeof(float);
     hipLaunchKernelGGL(assemble_obs_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kObsThreads), lds, s, a);
