@@ -32,8 +32,10 @@ def _run(ctx, d, N, proprio, base, height, scan, noise, t=3, seed=0x5EED, it=7, 
     return obs.cpu().numpy()
 
 
+# 9001 robots: 9 per workgroup and a one-robot tail, rows of 9 * 235 floats
+# (not a multiple of 4: some blocks start unaligned for 16-byte stores)
 @pytest.mark.parametrize("N,P,S,margin", [(4096, 48, 187, 2.0), (333, 48, 187, -3.0), (1, 45, 190, 0.0),
-                                          (1000, 48, 108, -1.0), (65, 3, 0, 0.0)])
+                                          (1000, 48, 108, -1.0), (65, 3, 0, 0.0), (9001, 48, 187, 1.0)])
 def test_assemble_matches_oracle(N, P, S, margin):
     d = require_gpu()
     _announce(f"assemble_obs N={N} P={P} S={S} margin={margin}")
