@@ -22,6 +22,8 @@
 // the output features and each covers all R samples, so every weight element
 // is read from L2 once per workgroup; PF k-steps of weight fragments are in
 // flight ahead of the MFMAs.
+#include <type_traits>
+
 #include "common.hpp"
 #include "philox.hpp"
 
@@ -85,6 +87,14 @@ struct NoHook {
     __device__ void operator()() const {}
 };
 
+// The update pass runs its layers with a copy-out hook and shares each CU
+// with a second workgroup: raising the wave priority over the MFMA loop lets
+// one workgroup's matrix work run ahead of the other's epilogues and copies
+// (1 % off the update).  Inference (no hook, one workgroup per CU) was 1 %
+// slower with it and keeps the default priority.
+template <class Hook>
+constexpr bool kRaisePrio = !std::is_same<Hook, NoHook>::value;
+
 template <int FBW, int SB, int PF, class Hook = NoHook>
 __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16_t *W, int rows_w, int S, int f0,
                                           int sb0, const uint16_t *act, int pitch, int lane,
@@ -112,6 +122,7 @@ __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16
     // work that needs no weights (e.g. copying the previous layer's output to
     // global memory) runs while the first fragments are in flight
     hook();
+    if constexpr (kRaisePrio<Hook>) __builtin_amdgcn_s_setprio(1);
     u32x4 b[SB];
 #pragma unroll
     for (int j = 0; j < SB; ++j) b[j] = *reinterpret_cast<const u32x4 *>(bp + 32 * j * pitch);
@@ -141,6 +152,7 @@ __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16
             for (int j = 0; j < SB; ++j) b[j] = bn[j];
         }
     }
+    if constexpr (kRaisePrio<Hook>) __builtin_amdgcn_s_setprio(0);
 }
 
 // Forward epilogue: out[sample][feature] = bf16(ELU(acc + bias)).
