@@ -240,6 +240,24 @@ int ppo_gae(const ppo_ctx *ctx, void *stream, const float *rewards, const uint8_
             int32_t T, int32_t N, float gamma, float lam, float *adv, float *returns,
             double *adv_stats, int32_t normalize, void *ws, size_t ws_bytes);
 
+/* Allocation-free variant of ppo_gae, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid allocation): the same computation and results bit for bit, with no
+ * workspace argument.  The per-block statistics partials it needs (24 bytes
+ * per 256 environments) live in a fixed device array of the library, one per
+ * GPU, held until the process ends; N must not exceed PPO_GAE_NOALLOC_MAX_N
+ * (PPO_E_SHAPE otherwise, before anything is enqueued).  The first call on a
+ * device looks up that device's copy of the array (with the device current)
+ * and synchronises nothing.  No call allocates or frees anything.  Every call
+ * on one GPU uses the same array and every partial is written before it is
+ * read, so nothing needs clearing; calls that overlap in time on one GPU (on
+ * different streams) race and must be serialised by the caller. */
+#define PPO_GAE_NOALLOC_MAX_N (1 << 21)
+int ppo_gae_noalloc(const ppo_ctx *ctx, void *stream, const float *rewards, const uint8_t *dones,
+                    const uint8_t *timeouts, const float *values, const float *last_values,
+                    int32_t T, int32_t N, float gamma, float lam, float *adv, float *returns,
+                    double *adv_stats, int32_t normalize);
+
 /* One PPO epoch: for k in 0..K-1 the mini-batch perm[k M : (k+1) M]
  * (M = B / K) goes through forward, loss, hand-written backward, global
  * norm clip and Adam (step count and lr read from p->step / p->lr; step is

@@ -18,6 +18,7 @@ PPO_BF16 = 1
 PPO_MAX_HIDDEN = 4
 PPO_STATS_WIDTH = 10
 PPO_OPT_KEEP_PACKED = 1
+PPO_GAE_NOALLOC_MAX_N = 1 << 21
 PHASES = ("gather", "forward", "head_loss", "input_grad", "weight_grad", "grad_reduce", "adam", "fused")
 
 ERROR_NAMES = {
@@ -67,6 +68,8 @@ EXPORTS = {
                                     c_uint32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
     "ppo_gae": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                           c_float, c_float, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t]),
+    "ppo_gae_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                  c_int32, c_float, c_float, c_void_p, c_void_p, c_void_p, c_int32]),
     "ppo_update_epoch": (c_int32, [c_void_p, c_void_p, POINTER(Params), POINTER(Batch), c_void_p, c_int32,
                                    POINTER(HParams), c_void_p, c_void_p, c_size_t]),
     "ppo_loss_grad": (c_int32, [c_void_p, c_void_p, POINTER(Params), POINTER(Batch), c_void_p, c_int32,

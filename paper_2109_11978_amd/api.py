@@ -271,6 +271,19 @@ def ppo_gae(ctx: Context, rewards, dones, values, last_values, gamma: float, lam
                          ws.numel()))
 
 
+def ppo_gae_noalloc(ctx: Context, rewards, dones, values, last_values, gamma: float, lam: float, adv, returns,
+                    adv_stats, timeouts=None, normalize: bool = True, stream=None) -> None:
+    """ppo_gae without a workspace: the library's fixed per-device scratch
+    holds the statistics partials (N <= PPO_GAE_NOALLOC_MAX_N)."""
+    T, N = rewards.shape
+    check(_lib().ppo_gae_noalloc(ctx.handle, _stream(stream), _ptr(rewards, torch.float32, "rewards"),
+                                 _ptr(dones, torch.uint8, "dones"), _ptr(timeouts, torch.uint8, "timeouts", True),
+                                 _ptr(values, torch.float32, "values"),
+                                 _ptr(last_values, torch.float32, "last_values"), T, N, gamma, lam,
+                                 _ptr(adv, torch.float32, "adv"), _ptr(returns, torch.float32, "returns"),
+                                 _ptr(adv_stats, torch.float64, "adv_stats"), int(normalize)))
+
+
 def ppo_update_epoch(ctx: Context, params: Params, batch: Dict[str, torch.Tensor], perm: torch.Tensor,
                      n_minibatches: int, hp: UpdateHParams, stats: torch.Tensor, ws: torch.Tensor,
                      stream=None) -> None:

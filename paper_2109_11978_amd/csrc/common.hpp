@@ -225,6 +225,11 @@ struct GaeArgs {
     float gamma, lam;
 };
 int gae_blocks(int N);
+// Environments the allocation-free GAE entry point serves (its partials live
+// in a fixed device array of the library).
+constexpr int kGaeNoAllocMaxN = 1 << 21;
+// This device's copy of that array (looked up once per device).
+hipError_t gae_scratch(double **out);
 hipError_t launch_gae(const GaeArgs &a, hipStream_t s);
 hipError_t launch_adv_finalize(const double *partials, int nparts, float *adv, long long count,
                                double *stats_out, int normalize, hipStream_t s);

@@ -3,6 +3,8 @@
 // PPO loss and its output gradients (update), GAE with the float64 advantage
 // statistics, gradient assembly with the float64 global norm, and Adam.
 #include "common.hpp"
+
+#include <mutex>
 #include "philox.hpp"
 
 namespace ppo {
@@ -913,6 +915,32 @@ hipError_t launch_head_loss(Precision prec, const HeadLossArgs &a, hipStream_t s
 }
 
 int gae_blocks(int N) { return (N + kGaeThreads - 1) / kGaeThreads; }
+
+// Scratch of the allocation-free GAE entry point: the Welford partials (three
+// doubles per block of kGaeThreads environments) of up to kGaeNoAllocMaxN
+// environments, one copy per device for the life of the process.
+static __device__ __align__(256) double scratch[3 * ((kGaeNoAllocMaxN + kGaeThreads - 1) / kGaeThreads)];
+
+hipError_t gae_scratch(double **out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        // the host-side name of the array is not a device address: ask the
+        // runtime for this device's copy once, with the device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = static_cast<double *>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_gae(const GaeArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(gae_kernel, dim3(gae_blocks(a.N)), dim3(kGaeThreads), 0, s, a);

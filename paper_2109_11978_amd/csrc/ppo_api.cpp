@@ -1388,9 +1388,13 @@ int ppo_rollout_infer(const ppo_ctx *c, void *stream, const ppo_params *p, const
     return PPO_OK;
 }
 
-int ppo_gae(const ppo_ctx *c, void *stream, const float *rewards, const uint8_t *dones, const uint8_t *timeouts,
-            const float *values, const float *last_values, int32_t T, int32_t N, float gamma, float lam, float *adv,
-            float *returns, double *adv_stats, int32_t normalize, void *ws, size_t ws_bytes) {
+namespace {
+
+// Arguments shared by ppo_gae and ppo_gae_noalloc, checked before anything is
+// enqueued.
+int validate_gae(const ppo_ctx *c, const float *rewards, const uint8_t *dones, const uint8_t *timeouts,
+                 const float *values, const float *last_values, int32_t T, int32_t N, float gamma, float lam,
+                 const float *adv, const float *returns, const double *adv_stats, int32_t normalize) {
     if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
     if (T < 1 || T > PPO_MAX_T) return fail(PPO_E_SHAPE, "T = %d outside 1..%d", T, PPO_MAX_T);
     if (N < 1) return fail(PPO_E_SHAPE, "N = %d must be positive", N);
@@ -1406,12 +1410,15 @@ int ppo_gae(const ppo_ctx *c, void *stream, const float *rewards, const uint8_t 
     if (!(gamma >= 0.0f && gamma <= 1.0f) || !(lam >= 0.0f && lam <= 1.0f))
         return fail(PPO_E_INVAL, "gamma and lambda must lie in [0, 1]");
     if (normalize != 0 && normalize != 1) return fail(PPO_E_INVAL, "normalize must be 0 or 1");
-    PPO_CHECK(validate_ws(c, N, T, 0, ws, ws_bytes));
-    note_ws_used(ws, ws_bytes);
-    PPO_CHECK(check_device());
+    return PPO_OK;
+}
 
-    const hipStream_t s = static_cast<hipStream_t>(stream);
-    const WsPlan w = plan_workspace(c->g, c->prec, N, T, 0);
+// The scan with its per-block statistics partials in `partials` (gae_blocks(N)
+// x 3 doubles, every entry written before it is read), then the merge and the
+// optional normalisation.
+int enqueue_gae(hipStream_t s, const float *rewards, const uint8_t *dones, const uint8_t *timeouts,
+                const float *values, const float *last_values, int32_t T, int32_t N, float gamma, float lam,
+                float *adv, float *returns, double *adv_stats, int32_t normalize, double *partials) {
     GaeArgs a{};
     a.rewards = rewards;
     a.values = values;
@@ -1420,7 +1427,7 @@ int ppo_gae(const ppo_ctx *c, void *stream, const float *rewards, const uint8_t 
     a.timeouts = timeouts;
     a.adv = adv;
     a.returns = returns;
-    a.partials = reinterpret_cast<double *>(wsp(ws, w.gae_part));
+    a.partials = partials;
     a.T = T;
     a.N = N;
     a.gamma = gamma;
@@ -1429,6 +1436,38 @@ int ppo_gae(const ppo_ctx *c, void *stream, const float *rewards, const uint8_t 
     PPO_HIP(launch_adv_finalize(a.partials, gae_blocks(N), adv, static_cast<long long>(T) * N, adv_stats, normalize, s),
             "adv_finalize");
     return PPO_OK;
+}
+
+}  // namespace
+
+int ppo_gae(const ppo_ctx *c, void *stream, const float *rewards, const uint8_t *dones, const uint8_t *timeouts,
+            const float *values, const float *last_values, int32_t T, int32_t N, float gamma, float lam, float *adv,
+            float *returns, double *adv_stats, int32_t normalize, void *ws, size_t ws_bytes) {
+    PPO_CHECK(validate_gae(c, rewards, dones, timeouts, values, last_values, T, N, gamma, lam, adv, returns,
+                           adv_stats, normalize));
+    PPO_CHECK(validate_ws(c, N, T, 0, ws, ws_bytes));
+    note_ws_used(ws, ws_bytes);
+    PPO_CHECK(check_device());
+    const WsPlan w = plan_workspace(c->g, c->prec, N, T, 0);
+    return enqueue_gae(static_cast<hipStream_t>(stream), rewards, dones, timeouts, values, last_values, T, N, gamma,
+                       lam, adv, returns, adv_stats, normalize, reinterpret_cast<double *>(wsp(ws, w.gae_part)));
+}
+
+static_assert(PPO_GAE_NOALLOC_MAX_N == kGaeNoAllocMaxN, "header limit and scratch size agree");
+
+int ppo_gae_noalloc(const ppo_ctx *c, void *stream, const float *rewards, const uint8_t *dones,
+                    const uint8_t *timeouts, const float *values, const float *last_values, int32_t T, int32_t N,
+                    float gamma, float lam, float *adv, float *returns, double *adv_stats, int32_t normalize) {
+    PPO_CHECK(validate_gae(c, rewards, dones, timeouts, values, last_values, T, N, gamma, lam, adv, returns,
+                           adv_stats, normalize));
+    if (N > PPO_GAE_NOALLOC_MAX_N)
+        return fail(PPO_E_SHAPE, "N = %d exceeds PPO_GAE_NOALLOC_MAX_N = %d (the library's fixed scratch)", N,
+                    PPO_GAE_NOALLOC_MAX_N);
+    PPO_CHECK(check_device());
+    double *partials = nullptr;
+    PPO_HIP(gae_scratch(&partials), "scratch address");
+    return enqueue_gae(static_cast<hipStream_t>(stream), rewards, dones, timeouts, values, last_values, T, N, gamma,
+                       lam, adv, returns, adv_stats, normalize, partials);
 }
 
 int ppo_loss_grad(const ppo_ctx *c, void *stream, const ppo_params *p, const ppo_batch *b, const int32_t *idx,

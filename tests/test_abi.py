@@ -130,6 +130,16 @@ def test_misuse_codes():
                        FAKE, ws) == ppo.PPO_E_SHAPE
     assert lib.ppo_gae(ctx.handle, None, FAKE, FAKE, None, FAKE, FAKE, 24, 64, 1.5, 0.95, FAKE, FAKE, FAKE, 1,
                        FAKE, ws) == ppo.PPO_E_INVAL
+    # allocation-free GAE: the same checks, and N past its fixed scratch
+    assert lib.ppo_gae_noalloc(ctx.handle, None, FAKE, FAKE, None, FAKE, FAKE, 0, 64, 0.99, 0.95, FAKE, FAKE,
+                               FAKE, 1) == ppo.PPO_E_SHAPE
+    assert lib.ppo_gae_noalloc(ctx.handle, None, FAKE, FAKE, None, FAKE, FAKE, 24, 64, 0.99, 1.5, FAKE, FAKE,
+                               FAKE, 1) == ppo.PPO_E_INVAL
+    assert lib.ppo_gae_noalloc(ctx.handle, None, FAKE + 4, FAKE, None, FAKE, FAKE, 24, 64, 0.99, 0.95, FAKE,
+                               FAKE, FAKE, 1) == ppo.PPO_E_INVAL
+    assert lib.ppo_gae_noalloc(ctx.handle, None, FAKE, FAKE, None, FAKE, FAKE, 1, _abi.PPO_GAE_NOALLOC_MAX_N + 1,
+                               0.99, 0.95, FAKE, FAKE, FAKE, 1) == ppo.PPO_E_SHAPE
+    assert b"PPO_GAE_NOALLOC_MAX_N" in lib.ppo_last_error()
     # loss_grad: M larger than B
     assert lib.ppo_loss_grad(ctx.handle, None, ctypes.byref(p), ctypes.byref(b), FAKE, 2000, ctypes.byref(hp),
                              FAKE, FAKE, FAKE, ws) == ppo.PPO_E_SHAPE
