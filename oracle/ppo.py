@@ -98,11 +98,20 @@ def _mlp_backward(layers, zs, hs, g_out):
 
 
 def ppo_loss_grad(theta, spec: NetSpec, batch: Dict[str, np.ndarray], hp: PPOHyper,
-                  want_grad: bool = True):
+                  want_grad: bool = True, active_override=None, tie_delta: float = 0.0):
     """Loss terms, statistics and the flat gradient for one mini-batch.
 
     batch: obs [M, D], actions [M, A], logp_old [M], adv [M] (normalised),
     returns [M], and values_old [M] when hp.clip_value is set.
+
+    Clip-edge ties: a sample whose ratio lies within rounding of the clip
+    edge that decides its branch may legitimately take either branch in
+    another implementation's arithmetic.  With active_override (bool [M],
+    the other implementation's branches) and tie_delta > 0, samples whose
+    margin is below tie_delta take the override's branch; every other sample
+    keeps its own.  The result reports how many samples were adopted that way
+    ("ties_adopted") and how many disagree outside the band
+    ("disagree_outside", which a checker requires to be zero).
     """
     actor, logstd, critic = unpack(theta, spec)
     obs = np.asarray(batch["obs"], dtype=np.float64)
@@ -141,11 +150,19 @@ def ppo_loss_grad(theta, spec: NetSpec, batch: Dict[str, np.ndarray], hp: PPOHyp
     active = ((adv >= 0.0) & (ratio <= 1.0 + eps)) | ((adv < 0.0) & (ratio >= 1.0 - eps))
     # Distance of each ratio from the clip edge that decides its branch.
     margin = np.where(adv >= 0.0, np.abs(ratio - (1.0 + eps)), np.abs(ratio - (1.0 - eps)))
+    ties_adopted = disagree_outside = 0
+    if active_override is not None:
+        other = np.asarray(active_override, dtype=bool).reshape(M)
+        band = margin < tie_delta
+        ties_adopted = int(np.sum(band & (other != active)))
+        disagree_outside = int(np.sum(~band & (other != active)))
+        active = np.where(band, other, active)
     out = dict(
         loss=loss, policy_loss=policy_loss, value_loss=value_loss, entropy=entropy,
         clip_frac=float(np.mean(np.abs(ratio - 1.0) > eps)),
         approx_kl=float(np.mean((ratio - 1.0) - np.log(ratio))),
         ratio=ratio, active=active, margin=margin, mu=mu, values=V, logp=logp,
+        ties_adopted=ties_adopted, disagree_outside=disagree_outside,
     )
     if "mu_old" in batch and "logstd_old" in batch:
         out["kl"] = float(np.mean(gaussian_kl(batch["mu_old"], batch["logstd_old"], mu, logstd)))

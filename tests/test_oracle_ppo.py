@@ -139,6 +139,58 @@ def test_clip_band(sign):
     np.testing.assert_allclose(res2["ratio"], r, rtol=1e-12)
 
 
+def test_clip_tie_override():
+    """Samples within tie_delta of their clip edge take the override's branch
+    (the other implementation's decision), the rest keep their own.  Pinned by
+    finite differences: forcing sample i onto the unclipped branch adds
+    exactly the gradient of its unclipped surrogate -rho_i A_i / M, evaluated
+    here by central differences of a one-sample forward pass."""
+    theta = _theta(TINY, 31)
+    M = 10
+    batch = _batch(TINY, theta, M, 32, ratio_shift=0.0)
+    hp = O.PPOHyper(value_coef=0.0, entropy_coef=0.0)
+    base = O.ppo_loss_grad(theta, TINY, batch, hp)
+    eps = hp.clip
+    # samples 0..3 sit just past their deciding clip edge (inside the band,
+    # clipped: no gradient), samples 4..9 well inside the band (margin > 0.1)
+    edge = np.where(batch["adv"] >= 0, 1.0 + eps, 1.0 - eps)
+    want = np.exp(base["logp"] - batch["logp_old"])
+    target = want.copy()
+    target[:4] = edge[:4] * np.where(batch["adv"][:4] >= 0, 1.0 + 3e-3, 1.0 - 3e-3)
+    tb = dict(batch, logp_old=base["logp"] - np.log(target))
+    own = O.ppo_loss_grad(theta, TINY, tb, hp)
+    assert not own["active"][:4].any() and own["active"][4:].all()
+    assert np.all(own["margin"][:4] < 1e-2) and np.all(own["margin"][4:] > 0.1)
+
+    # the other side decided samples 0 and 2 were active, and sample 7 inactive
+    other = own["active"].copy()
+    other[[0, 2]] = True
+    other[7] = False
+    res = O.ppo_loss_grad(theta, TINY, tb, hp, active_override=other, tie_delta=2e-2)
+    assert res["ties_adopted"] == 2 and res["disagree_outside"] == 1
+    assert res["active"][[0, 2]].all() and res["active"][7]
+
+    def unclipped(th, i):
+        one = {k: (v[i:i + 1] if k != "logstd_old" else v) for k, v in tb.items()}
+        r = O.ppo_loss_grad(th, TINY, one, O.PPOHyper(clip=1e9, value_coef=0.0, entropy_coef=0.0),
+                            want_grad=False)
+        return r["policy_loss"] / M          # -rho_i A_i / M (one-sample mean)
+
+    h = 1e-6
+    expect = own["grad"].copy()
+    for c in range(len(theta)):
+        tp, tm = theta.copy(), theta.copy()
+        tp[c] += h
+        tm[c] -= h
+        for i in (0, 2):
+            expect[c] += (unclipped(tp, i) - unclipped(tm, i)) / (2 * h)
+    np.testing.assert_allclose(res["grad"], expect, rtol=1e-6, atol=1e-9)
+    # a zero band adopts nothing
+    res0 = O.ppo_loss_grad(theta, TINY, tb, hp, active_override=other, tie_delta=0.0)
+    assert res0["ties_adopted"] == 0 and res0["disagree_outside"] == 3
+    np.testing.assert_array_equal(res0["grad"], own["grad"])
+
+
 def test_value_and_entropy_closed_forms():
     theta = _theta(TINY, 11)
     lay = param_layout(TINY)
