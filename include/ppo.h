@@ -291,11 +291,20 @@ int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_
 
 /* Loss and gradient of one mini-batch (rows idx[0..M)) without an optimiser
  * step: writes stats[PPO_STATS_WIDTH] (entry 6 = gradient norm, entry 7 =
- * flags) and grad_out [P] (the raw gradient).  Used by the autograd wrapper
- * and gradient checks. */
+ * flags) and grad_out [P] (the raw gradient).  Optional per-row outputs for
+ * checkers (NULL = not written): ratio_out [M] float32 (4-byte aligned), the
+ * probability ratio rho = pi(a|s) / pi_old(a|s) this call computed, and
+ * active_out [M] uint8, 1 if the sample's clipped surrogate passes gradient
+ * (A >= 0 and rho <= 1 + clip, or A < 0 and rho >= 1 - clip: the PPO
+ * objective of Section 2.2 on the closed band) and 0 otherwise.  A sample
+ * whose ratio lies within rounding of a clip edge may legitimately take
+ * either branch; a checker adopts this call's branch exactly where the
+ * exported ratio and its own lie on different sides of the edge.  Used by
+ * the autograd wrapper and gradient checks. */
 int ppo_loss_grad(const ppo_ctx *ctx, void *stream, const ppo_params *p, const ppo_batch *b,
                   const int32_t *idx, int32_t M, const ppo_hparams *hp, float *stats,
-                  float *grad_out, void *ws, size_t ws_bytes);
+                  float *grad_out, uint8_t *active_out, float *ratio_out, void *ws,
+                  size_t ws_bytes);
 
 /* Kernel phases of one mini-batch step, in launch order. */
 #define PPO_PHASE_GATHER       0  /* mini-batch rows of obs -> GEMM operand     */

@@ -73,7 +73,7 @@ EXPORTS = {
     "ppo_update_epoch": (c_int32, [c_void_p, c_void_p, POINTER(Params), POINTER(Batch), c_void_p, c_int32,
                                    POINTER(HParams), c_void_p, c_void_p, c_size_t]),
     "ppo_loss_grad": (c_int32, [c_void_p, c_void_p, POINTER(Params), POINTER(Batch), c_void_p, c_int32,
-                                POINTER(HParams), c_void_p, c_void_p, c_void_p, c_size_t]),
+                                POINTER(HParams), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t]),
     "ppo_update_epoch_profiled": (c_int32, [c_void_p, c_void_p, POINTER(Params), POINTER(Batch), c_void_p, c_int32,
                                             POINTER(HParams), c_void_p, c_void_p, c_size_t, c_int32,
                                             POINTER(c_float), POINTER(c_int32)]),

@@ -314,14 +314,22 @@ def ppo_update_batched(ctxs: Sequence[Context], params: Sequence[Params], batche
 
 def ppo_loss_grad(ctx: Context, params: Params, batch: Dict[str, torch.Tensor], idx: torch.Tensor,
                   hp: UpdateHParams, stats: torch.Tensor, grad_out: torch.Tensor, ws: torch.Tensor,
-                  stream=None) -> None:
+                  stream=None, active_out: Optional[torch.Tensor] = None,
+                  ratio_out: Optional[torch.Tensor] = None) -> None:
+    """active_out (uint8 [M]) and ratio_out (float32 [M]), both optional,
+    receive each row's surrogate branch and probability ratio."""
     b = batch_abi(batch)
     p = params.abi()
     h = hp.abi()
+    for name, t in (("active_out", active_out), ("ratio_out", ratio_out)):
+        if t is not None and t.numel() != idx.numel():
+            raise ValueError(f"{name} needs one entry per mini-batch row")
     check(_lib().ppo_loss_grad(ctx.handle, _stream(stream), ctypes.byref(p), ctypes.byref(b),
                                _ptr(idx, torch.int32, "idx"), idx.numel(), ctypes.byref(h),
                                _ptr(stats, torch.float32, "stats"), _ptr(grad_out, torch.float32, "grad_out"),
-                               _ptr(ws, torch.uint8, "ws"), ws.numel()))
+                               _ptr(active_out, torch.uint8, "active_out", True),
+                               _ptr(ratio_out, torch.float32, "ratio_out", True), _ptr(ws, torch.uint8, "ws"),
+                               ws.numel()))
 
 
 def ppo_update_epoch_profiled(ctx: Context, params: Params, batch: Dict[str, torch.Tensor], perm: torch.Tensor,

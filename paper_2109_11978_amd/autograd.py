@@ -48,7 +48,7 @@ class PPOLoss(torch.autograd.Function):
         check(_abi.load().ppo_loss_grad(ctx.handle, _stream(None), ctypes.byref(p), ctypes.byref(b),
                                         _ptr(idx, torch.int32, "idx"), idx.numel(), ctypes.byref(h),
                                         _ptr(stats, torch.float32, "stats"), _ptr(grad, torch.float32, "grad"),
-                                        _ptr(ws, torch.uint8, "ws"), ws.numel()))
+                                        None, None, _ptr(ws, torch.uint8, "ws"), ws.numel()))
         fctx.save_for_backward(grad)
         fctx.stats = stats
         return stats[0].clone()

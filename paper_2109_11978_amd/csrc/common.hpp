@@ -32,6 +32,36 @@ __host__ __device__ inline uint16_t f32_to_bf16(float f) {
     return static_cast<uint16_t>((v.u + 0x7FFFu + lsb) >> 16);
 }
 
+// Log-density of a diagonal Gaussian in float32 with compensated summation.
+// s carries the sum, c the rounding errors of its additions (Neumaier's
+// variant of Kahan summation) plus the exact errors of the squares (from a
+// fused multiply-add) and the float32 residual of ln(2 pi) / 2, so the
+// result is within a few float32 ulps of the exact sum of the float32
+// inputs.  Contraction is off: each product and sum is rounded on its own,
+// as the error terms assume.
+constexpr float kHalfLog2PiHi = 0.918938517570495605f;
+constexpr float kHalfLog2PiLo = static_cast<float>(0.91893853320467274178 - static_cast<double>(kHalfLog2PiHi));
+struct CompSum {
+    float s = 0.0f, c = 0.0f;
+    __device__ inline void add(float x) {
+#pragma clang fp contract(off)
+        const float t = s + x;
+        c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    // one dimension of a diagonal-Gaussian log-density: -z^2 / 2 - log sigma - ln(2 pi) / 2
+    __device__ inline void add_gauss(float z, float logstd) {
+#pragma clang fp contract(off)
+        const float p = z * z;
+        const float e = __builtin_fmaf(z, z, -p);   // p + e = z^2 exactly
+        add(-0.5f * p);
+        add(-logstd);
+        add(-kHalfLog2PiHi);
+        c += -0.5f * e - kHalfLog2PiLo;
+    }
+    __device__ inline float value() const { return s + c; }
+};
+
 template <typename T> struct Elem;
 template <> struct Elem<float> {
     __device__ static inline float load(const float *p, long long i) { return p[i]; }
@@ -58,6 +88,12 @@ enum GemmEpilogue {
 struct GemmProblem {
     const void *A;
     const void *B;
+    // Optional second B operand of the same layout (bf16 only): the launch
+    // then computes A (B + B2)^T, running the k-range once with B and once with
+    // B2 into the same accumulators.  The critic's forward layers pass the
+    // bf16 residual theta - bf16(theta) here, so their weights carry about 16
+    // significant bits.
+    const void *B2;
     void *C;
     const float *bias;
     const void *H;
@@ -104,9 +140,13 @@ constexpr int kFusedMaxAct = 16;
 // 16 s + 8 (l / 32) .. + 7 (zero past K).
 struct FragJob {
     const uint16_t *src;   // row-major bf16 W [out][in] with row pitch ld
+    // split jobs: row-major float32 W instead; feature block fb stores its S
+    // fragments of bf16(W), then S of bf16(W - bf16(W)) (the split layout)
+    const float *src32;
     uint16_t *dst;
     int rows, K, S, ld;
     int transpose;         // 1: pack W^T (rows = in, K = out)
+    int split;             // 1: the split layout from src32 (no transpose)
     int begin;             // first lane chunk of this job
 };
 constexpr int kMaxFragJobs = 16;
@@ -119,7 +159,10 @@ void add_frag_job(FragArgs &a, const FragJob &j);
 hipError_t launch_pack_frags(const FragArgs &a, hipStream_t s);
 
 struct FusedNet {
-    const uint16_t *W[kMaxHidden];    // layer l weights, fragment order, K = kpad for l = 0
+    // layer l weights, fragment order, K = kpad for l = 0; the critic's (net
+    // 1) in the split layout of FragJob (all bf16 fragments of a feature
+    // block, then all residual fragments)
+    const uint16_t *W[kMaxHidden];
     const uint16_t *WT[kMaxHidden];   // W_l^T, fragment order ([H_{l-1}] x H_l), l >= 1
     const float *bias[kMaxHidden];    // [H_l], 16-byte aligned
     const float *Wout, *bout;         // output layer (float32) [n_out][H_{L-1}], [n_out]
@@ -138,6 +181,8 @@ struct FusedArgs {
     const float *actions, *logp_old, *adv, *returns, *values_old, *mu_old, *logstd_old, *logstd;
     uint16_t *xg;                     // [M][kpad] gathered inputs (written by the actor blocks)
     float *partials;                  // [blocks][A + 8], the layout of HeadLossArgs::partials
+    uint8_t *active_out;              // [M] or null: 1 where the sample's surrogate passes gradient
+    float *ratio_out;                 // [M] or null: the sample's probability ratio
     float clip, value_coef, inv_m;
     int clip_value;
     // rollout inference (launch_fused_infer): outputs for the M environments
@@ -208,6 +253,8 @@ struct HeadLossArgs {
     // entropy, mean-shift KL sum, log-std KL part (entropy and the log-std part
     // in block 0, zero in the other blocks)
     float *partials;
+    uint8_t *active_out;           // [M] or null: 1 where the sample's surrogate passes gradient
+    float *ratio_out;              // [M] or null: the sample's probability ratio
     int M, A, Hl;
     float clip, value_coef, inv_m;
     int clip_value;
@@ -271,6 +318,7 @@ hipError_t launch_grad_reduce(const ReduceArgs &a, hipStream_t s);
 struct AdamFrag {
     long long begin;        // flat offset of W_l [rows][cols] in theta
     int rows, cols, S, S_t; // S: k-steps of the forward fragments, S_t: of the transposed ones
+    int split;              // forward fragments in the split layout (hi and lo per k-step)
     uint16_t *dst, *dst_t;  // forward and transposed fragments (dst_t null when not kept)
 };
 constexpr int kMaxAdamFrags = 2 * kMaxHidden;
@@ -300,6 +348,9 @@ hipError_t launch_step_advance(int32_t *step, int k, hipStream_t s);
 // operand type (bf16 or float32).
 struct StageJob {
     const void *src;   // rows x cols, row pitch src_ld
+    // bf16 staging only: when set, the job reads float32 W from here instead
+    // of src and writes its bf16 residual bf16(W - bf16(W)) (no transpose)
+    const float *lo_src;
     void *dst;         // transpose ? cols x rows : rows x dst_ld (cols..dst_ld zero-filled)
     int rows, cols, src_ld, dst_ld;
     int transpose;

@@ -95,16 +95,22 @@ struct NoHook {
 template <class Hook>
 constexpr bool kRaisePrio = !std::is_same<Hook, NoHook>::value;
 
-template <int FBW, int SB, int PF, class Hook = NoHook>
+template <int FBW, int SB, int PF, int SPLIT, class Hook = NoHook>
 __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16_t *W, int rows_w, int S, int f0,
                                           int sb0, const uint16_t *act, int pitch, int lane,
                                           const Hook &hook = Hook()) {
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(W, static_cast<long long>(rows_w / 32) * S * 1024);
+    static_assert(SPLIT == 1 || SPLIT == 2, "one or two weight passes");
+    // SPLIT = 2: each feature block has S fragments of bf16(W), then S of the
+    // bf16 residual W - bf16(W); both passes multiply the same activation
+    // fragments into the same accumulators, in the order of the layer-by-layer
+    // GEMM (all of the first pass, then all of the second)
+    const int SW = S * SPLIT;   // weight fragments per feature block
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(W, static_cast<long long>(rows_w / 32) * SW * 1024);
     const int kh = (lane >> 5) * 8;
     // per-block lane offsets in VGPRs, one scalar step offset per load
     int vo[FBW];
 #pragma unroll
-    for (int f = 0; f < FBW; ++f) vo[f] = (f0 / 32 + f) * S * 1024 + lane * 16;
+    for (int f = 0; f < FBW; ++f) vo[f] = (f0 / 32 + f) * SW * 1024 + lane * 16;
     const uint16_t *bp = act + (32 * sb0 + (lane & 31)) * pitch + kh;
 #pragma unroll
     for (int f = 0; f < FBW; ++f)
@@ -116,7 +122,7 @@ __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16
         const int so = __builtin_amdgcn_readfirstlane(p * 1024);
 #pragma unroll
         for (int f = 0; f < FBW; ++f)
-            w[p][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, p < S ? vo[f] : kOutside, so, 0);
+            w[p][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, p < SW ? vo[f] : kOutside, so, 0);
         __builtin_amdgcn_sched_barrier(0);
     }
     // work that needs no weights (e.g. copying the previous layer's output to
@@ -126,11 +132,13 @@ __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16
     u32x4 b[SB];
 #pragma unroll
     for (int j = 0; j < SB; ++j) b[j] = *reinterpret_cast<const u32x4 *>(bp + 32 * j * pitch);
-    for (int s0 = 0; s0 < S; s0 += PF) {
+    for (int q0 = 0; q0 < SW; q0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
-            const int s = s0 + u;
-            const int s1 = s + 1 < S ? s + 1 : S - 1;
+            // activation fragment of weight fragment q + 1: k-step (q + 1) mod S,
+            // the last one again past the end
+            const int q1 = q0 + u + 1;
+            const int s1 = q1 < S ? q1 : (q1 < SW ? q1 - S : S - 1);
             u32x4 bn[SB];
 #pragma unroll
             for (int j = 0; j < SB; ++j) bn[j] = *reinterpret_cast<const u32x4 *>(bp + 32 * j * pitch + 16 * s1);
@@ -142,11 +150,11 @@ __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16
                     acc[f][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, w[u][f]),
                                                                       __builtin_bit_cast(bf16x8_t, b[j]), acc[f][j],
                                                                       0, 0, 0);
-            const int sn = s + PF;
-            const int so = __builtin_amdgcn_readfirstlane(sn * 1024);
+            const int qn = q0 + u + PF;
+            const int so = __builtin_amdgcn_readfirstlane(qn * 1024);
 #pragma unroll
             for (int f = 0; f < FBW; ++f)
-                w[u][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, sn < S ? vo[f] : kOutside, so, 0);
+                w[u][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, qn < SW ? vo[f] : kOutside, so, 0);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < SB; ++j) b[j] = bn[j];
@@ -204,36 +212,38 @@ __device__ __forceinline__ void epi_backward(const floatx16 (&acc)[FBW][SB], int
         }
 }
 
-template <int FBW, int SB, int PF, bool BWD, class Hook>
+template <int FBW, int SB, int PF, bool BWD, int SPLIT, class Hook>
 __device__ __forceinline__ void layer_impl(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
                                            int in_pitch, uint16_t *out, int out_pitch, int f0, int sb0, int lane,
                                            const Hook &hook) {
     floatx16 acc[FBW][SB];
-    mma_layer<FBW, SB, PF>(acc, W, nout, K >> 4, f0, sb0, in, in_pitch, lane, hook);
+    mma_layer<FBW, SB, PF, SPLIT>(acc, W, nout, K >> 4, f0, sb0, in, in_pitch, lane, hook);
     if constexpr (BWD)
         epi_backward<FBW, SB>(acc, f0, sb0, out, out_pitch, lane);
     else
         epi_forward<FBW, SB>(acc, bias, f0, sb0, out, out_pitch, lane);
 }
 
-// Weight fragments in flight per lane: PF k-steps x FBW blocks, up to 32,
-// with PF no larger than the layer's k-step count S = K / 16 (a power of two
-// for hidden layers; a first layer of 3 or 15 steps takes PF = 4).
-template <int FBW, int SB, bool BWD, int PFMAX, class Hook>
+// Weight fragments in flight per lane: PF fragments x FBW blocks, up to 32,
+// with PF no larger than the layer's fragment count S * SPLIT (S = K / 16, a
+// power of two for hidden layers; a first layer of 3 or 15 k-steps takes
+// PF = 4).
+template <int FBW, int SB, bool BWD, int PFMAX, int SPLIT, class Hook>
 __device__ __forceinline__ void layer_pf(int S, const uint16_t *W, int K, int nout, const float *bias,
                                          const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
                                          int sb0, int lane, const Hook &hook) {
-    if (PFMAX >= 32 && S >= 32)
-        layer_impl<FBW, SB, (PFMAX >= 32 ? 32 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane,
-                                                         hook);
-    else if (PFMAX >= 16 && S >= 16)
-        layer_impl<FBW, SB, (PFMAX >= 16 ? 16 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane,
-                                                         hook);
-    else if (PFMAX >= 8 && S >= 8)
-        layer_impl<FBW, SB, (PFMAX >= 8 ? 8 : 4), BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane,
-                                                       hook);
+    const int SW = S * SPLIT;
+    if (PFMAX >= 32 && SW >= 32)
+        layer_impl<FBW, SB, (PFMAX >= 32 ? 32 : 4), BWD, SPLIT>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
+                                                                sb0, lane, hook);
+    else if (PFMAX >= 16 && SW >= 16)
+        layer_impl<FBW, SB, (PFMAX >= 16 ? 16 : 4), BWD, SPLIT>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
+                                                                sb0, lane, hook);
+    else if (PFMAX >= 8 && SW >= 8)
+        layer_impl<FBW, SB, (PFMAX >= 8 ? 8 : 4), BWD, SPLIT>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
+                                                              sb0, lane, hook);
     else
-        layer_impl<FBW, SB, 4, BWD>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane, hook);
+        layer_impl<FBW, SB, 4, BWD, SPLIT>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane, hook);
 }
 
 // Deepest weight prefetch (k-steps) that keeps the accumulators (FBW x SBW
@@ -246,27 +256,27 @@ constexpr int pf_max() {
     return pf;
 }
 
-template <int SBW, bool BWD, bool WIDE, int REGS, class Hook>
+template <int SBW, bool BWD, bool WIDE, int REGS, int SPLIT, class Hook>
 __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int K, int nout, const float *bias,
                                          const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
                                          int sb0, int lane, const Hook &hook) {
     switch (fbw) {
     case 1:
-        layer_pf<1, SBW, BWD, pf_max<1, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0,
-                                                      lane, hook);
+        layer_pf<1, SBW, BWD, pf_max<1, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
+                                                             sb0, lane, hook);
         break;
     case 2:
-        layer_pf<2, SBW, BWD, pf_max<2, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0,
-                                                      lane, hook);
+        layer_pf<2, SBW, BWD, pf_max<2, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
+                                                             sb0, lane, hook);
         break;
     case 4:
-        layer_pf<4, SBW, BWD, pf_max<4, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0,
-                                                      lane, hook);
+        layer_pf<4, SBW, BWD, pf_max<4, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
+                                                             sb0, lane, hook);
         break;
     default:
         if constexpr (WIDE)
-            layer_pf<8, SBW, BWD, pf_max<8, SBW, REGS>()>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
-                                                          sb0, lane, hook);
+            layer_pf<8, SBW, BWD, pf_max<8, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch,
+                                                                 f0, sb0, lane, hook);
         else
             hook();
         break;
@@ -277,7 +287,7 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
 // are split over the NT / 64 waves; when there are fewer blocks than waves,
 // the waves sharing a block split the sample blocks instead (each weight
 // fragment is then read by two waves, the second time from L1).
-template <int R, int NT, int WPE, bool BWD, class Hook = NoHook>
+template <int R, int NT, int WPE, bool BWD, int SPLIT = 1, class Hook = NoHook>
 __device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
                                           int in_pitch, uint16_t *out, int out_pitch, int wave, int lane,
                                           const Hook &hook = Hook()) {
@@ -293,12 +303,12 @@ __device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, co
     const int fb = nout / 32;
     if (fb >= NW) {
         const int fbw = fb / NW;
-        layer_fb<SB, BWD, WIDE, REGS>(fbw, S, W, K, nout, bias, in, in_pitch, out, out_pitch, wave * fbw * 32, 0,
-                                      lane, hook);
+        layer_fb<SB, BWD, WIDE, REGS, SPLIT>(fbw, S, W, K, nout, bias, in, in_pitch, out, out_pitch,
+                                             wave * fbw * 32, 0, lane, hook);
     } else if constexpr (SB >= 2) {
         // two waves per feature block, each with half the sample blocks
-        layer_fb<SB / 2, BWD, false, REGS>(1, S, W, K, nout, bias, in, in_pitch, out, out_pitch, (wave % fb) * 32,
-                                           (wave / fb) * (SB / 2), lane, hook);
+        layer_fb<SB / 2, BWD, false, REGS, SPLIT>(1, S, W, K, nout, bias, in, in_pitch, out, out_pitch,
+                                                  (wave % fb) * 32, (wave / fb) * (SB / 2), lane, hook);
     } else {
         hook();   // a wave without a feature block still does its share of the hook
     }
@@ -455,24 +465,28 @@ __device__ __forceinline__ void head_pass(const FusedArgs &a, const FusedNet &N,
     for (int q = 0; q < kSums; ++q) sums[q] = 0.0f;
     if constexpr (ACTOR) {
         const int A = a.A;
-        // log-probability of the stored action in float64 (a sum of A terms of
-        // order 1 whose float32 rounding would dominate the ratio's error)
+        // log-ratio log pi(a|s) - lp_old: the A log-density terms and -lp_old
+        // summed with compensation in float32 (terms of order 1 that nearly
+        // cancel against lp_old)
         float z[NO], inv_sig[NO];
-        double logp = -0.5 * A * 1.8378770664093453;
+        CompSum lr;
         float kl_mu = 0.0f;
 #pragma unroll
         for (int j = 0; j < NO; ++j) {
             const float ls = s_head[kFusedMaxAct + j];
             inv_sig[j] = expf(-ls);
             z[j] = (in_s[j] - o[j]) * inv_sig[j];
-            logp += -0.5 * static_cast<double>(z[j]) * z[j] - ls;
+            if (j < A) lr.add_gauss(z[j], ls);
             const float dm = (in_s[kFusedMaxAct + j] - o[j]) * inv_sig[j];
             kl_mu += 0.5f * dm * dm;
         }
+        lr.add(-in_s[2 * kFusedMaxAct]);
         const float adv = in_s[2 * kFusedMaxAct + 1];
-        const float ratio = static_cast<float>(exp(logp - static_cast<double>(in_s[2 * kFusedMaxAct])));
+        const float ratio = expf(lr.value());
         const float lo = 1.0f - a.clip, hi = 1.0f + a.clip;
         const bool active = adv >= 0.0f ? (ratio <= hi) : (ratio >= lo);
+        if (lead && a.active_out) a.active_out[m0 + si] = active ? 1 : 0;
+        if (lead && a.ratio_out) a.ratio_out[m0 + si] = ratio;
         const float g_lp = valid && active ? -a.inv_m * adv * ratio : 0.0f;
         sums[0] = -fminf(ratio * adv, fminf(fmaxf(ratio, lo), hi) * adv);
         sums[2] = fabsf(ratio - 1.0f) > a.clip ? 1.0f : 0.0f;
@@ -670,7 +684,13 @@ void fused_update_kernel(const FusedArgs a) {
                 copy_out<NT>(in, Hp + 8, N.h[l - 1] + static_cast<long long>(m0) * Hp, Hp, Hp, rows);
             }
         };
-        run_layer<R, NT, WPE, false>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave, lane, hook);
+        // the critic's weights come in the split layout (hi and lo fragments)
+        if (net == 1)
+            run_layer<R, NT, WPE, false, 2>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave,
+                                            lane, hook);
+        else
+            run_layer<R, NT, WPE, false, 1>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave,
+                                            lane, hook);
         __syncthreads();
         in = out;
         in_pitch = H + 8;
@@ -748,7 +768,7 @@ void fused_update_kernel(const FusedArgs a) {
         auto hook = [&]() {
             copy_out<NT>(dz, Hin + 8, N.dz[l] + static_cast<long long>(m0) * Hin, Hin, Hin, rows);
         };
-        run_layer<R, NT, WPE, true>(N.WT[l], Hin, Hout, nullptr, dz, Hin + 8, hz, Hout + 8, wave, lane, hook);
+        run_layer<R, NT, WPE, true, 1>(N.WT[l], Hin, Hout, nullptr, dz, Hin + 8, hz, Hout + 8, wave, lane, hook);
         __syncthreads();
     }
     const int H0 = a.H[0];
@@ -760,7 +780,10 @@ void fused_update_kernel(const FusedArgs a) {
 // features and K inputs (zero-padded to 16 S), fragment (fb, s) holds, for
 // lane l, the 8 elements W[32 fb + l % 32][16 s + 8 (l / 32) .. + 7]; fragment
 // (fb, s) starts at element ((fb * S + s) * 64) * 8.  transpose = 1 packs
-// W^T from the row-major W: element (r, k) = src[k * ld + r].
+// W^T from the row-major W: element (r, k) = src[k * ld + r].  split = 1
+// reads float32 W and stores 2 S fragments per feature block fb: fragment
+// ((2 fb + part) * S + s) holds bf16(W) for part 0 and the bf16 residual
+// bf16(W - bf16(W)) for part 1 (the subtraction is exact in float32).
 __global__ __launch_bounds__(256) void pack_frags_kernel(const FragArgs a) {
     const int t = blockIdx.x * 256 + threadIdx.x;   // one 8-element lane chunk per thread
     if (t >= a.total) return;
@@ -775,7 +798,9 @@ __global__ __launch_bounds__(256) void pack_frags_kernel(const FragArgs a) {
     const int local = t - J.begin;
     const int lane = local & 63;
     const int frag = local >> 6;
-    const int fb = frag / J.S, s = frag - (frag / J.S) * J.S;
+    const int fbp = frag / J.S, s = frag - (frag / J.S) * J.S;
+    const int fb = J.split ? fbp >> 1 : fbp;
+    const int part = J.split ? fbp & 1 : 0;
     const int r = 32 * fb + (lane & 31);
     const int k0 = 16 * s + 8 * (lane >> 5);
     uint32_t v[4];
@@ -783,7 +808,16 @@ __global__ __launch_bounds__(256) void pack_frags_kernel(const FragArgs a) {
     for (int e = 0; e < 4; ++e) {
         uint32_t lo = 0, hi = 0;
         const int k = k0 + 2 * e;
-        if (J.transpose) {
+        if (J.split) {
+            auto piece = [&](int kk) -> uint32_t {
+                if (kk >= J.K) return 0u;
+                const float x = J.src32[static_cast<long long>(r) * J.ld + kk];
+                const uint16_t h = f32_to_bf16(x);
+                return part == 0 ? h : f32_to_bf16(x - bf16_to_f32(h));
+            };
+            lo = piece(k);
+            hi = piece(k + 1);
+        } else if (J.transpose) {
             if (k < J.K) lo = J.src[static_cast<long long>(k) * J.ld + r];
             if (k + 1 < J.K) hi = J.src[static_cast<long long>(k + 1) * J.ld + r];
         } else {
@@ -889,7 +923,12 @@ void fused_infer_kernel(const FusedArgs a) {
     for (int l = 0; l < L; ++l) {
         const int H = a.H[l];
         uint16_t *out = reinterpret_cast<uint16_t *>(lds + a.lds_region[l]);
-        run_layer<R, NT, WPE, false>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave, lane);
+        if (net == 1)
+            run_layer<R, NT, WPE, false, 2>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave,
+                                            lane);
+        else
+            run_layer<R, NT, WPE, false, 1>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave,
+                                            lane);
         __syncthreads();
         in = out;
         in_pitch = H + 8;
@@ -957,11 +996,11 @@ void fused_infer_kernel(const FusedArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) e_all[4 * g + q] = g == 0 ? eps[q] : __shfl(eps[q], lane + g);
     if (!lead || !a.logp_out) return;
-    double logp = -0.5 * A * 1.8378770664093453;
+    CompSum lp;
 #pragma unroll
     for (int j = 0; j < kFusedMaxAct; ++j)
-        if (j < A) logp += -0.5 * static_cast<double>(e_all[j]) * e_all[j] - s_head[kFusedMaxAct + j];
-    a.logp_out[n] = static_cast<float>(logp);
+        if (j < A) lp.add_gauss(e_all[j], s_head[kFusedMaxAct + j]);
+    a.logp_out[n] = lp.value();
 }
 
 size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
@@ -1064,7 +1103,7 @@ void add_frag_job(FragArgs &a, const FragJob &j) {
     FragJob q = j;
     q.begin = a.total;
     a.job[a.count++] = q;
-    a.total += (q.rows / 32) * q.S * 64;
+    a.total += (q.rows / 32) * q.S * 64 * (q.split ? 2 : 1);
 }
 
 hipError_t launch_pack_frags(const FragArgs &a, hipStream_t s) {

@@ -434,23 +434,28 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
             }
         }
     };
-    // Loads slab kt of a tile into a staging set.
+    // Loads slab kt of a tile into a staging set.  With a second B operand
+    // the k-range runs twice: slabs nkb .. 2 nkb - 1 pair A's slabs 0 ..
+    // nkb - 1 with B2 (slabs past the end read zeros either way).
     auto load_slab = [&](int pi, int m0, int n0, int kbeg, int kend, LA &la, LB &lb, int kt) {
         const GemmProblem &Q = args.p[pi];
-        const int k0 = kbeg + kt * BK;
+        const int nkb = (kend - kbeg + BK - 1) / BK;
+        const bool second = Q.B2 != nullptr && kt >= nkb;
+        const int k0 = kbeg + (second ? kt - nkb : kt) * BK;
+        const void *Bp = second ? Q.B2 : Q.B;
         if constexpr (FAST) {
             const __amdgpu_buffer_rsrc_t a_rs =
                 make_rsrc(Q.A, static_cast<long long>(AMODE == 0 ? Q.M : kend) * Q.lda * static_cast<int>(sizeof(T)));
             const __amdgpu_buffer_rsrc_t b_rs =
-                make_rsrc(Q.B, static_cast<long long>(BMODE == 0 ? Q.N : kend) * Q.ldb * static_cast<int>(sizeof(T)));
+                make_rsrc(Bp, static_cast<long long>(BMODE == 0 ? Q.N : kend) * Q.ldb * static_cast<int>(sizeof(T)));
             la.load_fast(a_rs, Q.lda, k0, kend, tid);
             lb.load_fast(b_rs, Q.ldb, k0, kend, tid - B_OFF);
         } else {
             // 16-byte vector loads need a 16-byte aligned base and row pitch.
             const bool a_vec = (Q.lda % VEC) == 0 && (reinterpret_cast<uintptr_t>(Q.A) & 15u) == 0;
-            const bool b_vec = (Q.ldb % VEC) == 0 && (reinterpret_cast<uintptr_t>(Q.B) & 15u) == 0;
+            const bool b_vec = (Q.ldb % VEC) == 0 && (reinterpret_cast<uintptr_t>(Bp) & 15u) == 0;
             la.load(static_cast<const T *>(Q.A), Q.lda, Q.M, m0, k0, kend, tid, a_vec);
-            lb.load(static_cast<const T *>(Q.B), Q.ldb, Q.N, n0, k0, kend, tid - B_OFF, b_vec);
+            lb.load(static_cast<const T *>(Bp), Q.ldb, Q.N, n0, k0, kend, tid - B_OFF, b_vec);
         }
     };
     // Stores a staging set into LDS buffer `buf`; k-major A tiles also feed
@@ -516,12 +521,13 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_kernel(const GemmArgs args) 
     // slabs past the end read as zeros (their offsets fall outside the buffer
     // resources) and land in a buffer nobody reads again.  Conditional loads
     // would make the compiler wait for them before the next LDS store.
+    auto slabs = [&](const GemmProblem &Q, int kb, int ke) { return ((ke - kb + BK - 1) / BK) * (Q.B2 ? 2 : 1); };
     load_slab(pi, m0, n0, kbeg, kend, la0, lb0, 0);
-    if (FAST || kend - kbeg > BK) load_slab(pi, m0, n0, kbeg, kend, la1, lb1, 1);
+    if (FAST || slabs(args.p[pi], kbeg, kend) > 1) load_slab(pi, m0, n0, kbeg, kend, la1, lb1, 1);
 
     while (true) {
         const GemmProblem &P = args.p[pi];
-        const int nk = (kend - kbeg + BK - 1) / BK;
+        const int nk = slabs(P, kbeg, kend);
         const bool do_rowsum = (EPI == kEpiPartial) && tn == 0;
 #pragma unroll
         for (int i = 0; i < MI; ++i)
@@ -733,6 +739,7 @@ bool all_fast(const GemmArgs &args) {
     for (int i = 0; i < args.count; ++i) {
         const GemmProblem &q = args.p[i];
         if (!ok(q.A, q.lda) || !ok(q.B, q.ldb) || q.K % VEC != 0) return false;
+        if (q.B2 && !ok(q.B2, q.ldb)) return false;
         if (q.splits > 1 && q.kps % VEC != 0) return false;
     }
     return true;

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kHeadThreads) void head_sample_kernel(const HeadSam
     if (a.values) a.values[n] = s_out[i][A];
     if (a.value_only) return;
     const int groups = (A + 3) / 4;
-    double logp = -0.5 * A * 1.8378770664093453;
+    CompSum lp;   // log-density in float32 with compensated summation
     for (int g = 0; g < groups; ++g) {
         uint32_t c[4] = {static_cast<uint32_t>(n) * groups + g, a.t, a.iteration, 1u};
         philox4x32_10(c, a.key0, a.key1);
@@ -236,12 +236,12 @@ __global__ __launch_bounds__(kHeadThreads) void head_sample_kernel(const HeadSam
             if (j >= A) break;
             const float m = s_out[i][j];
             const float ls = a.logstd[j];
-            logp += -0.5 * static_cast<double>(eps[q]) * eps[q] - ls;
+            lp.add_gauss(eps[q], ls);
             if (a.actions) a.actions[static_cast<long long>(n) * A + j] = m + expf(ls) * eps[q];
             if (a.mu) a.mu[static_cast<long long>(n) * A + j] = m;
         }
     }
-    if (a.logp) a.logp[n] = static_cast<float>(logp);
+    if (a.logp) a.logp[n] = lp.value();
 }
 
 // ------------------------------------------------------------- head + loss
@@ -284,10 +284,11 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
         if (tid < rows) {
             const int i = tid;
             const long long row = a.idx ? min(max(a.idx[r0 + i], 0), a.B - 1) : r0 + i;
-            // Log-probability of the stored action, accumulated in float64: a sum of A
-            // terms of order 1 whose float32 rounding would dominate the ratio's error.
+            // Log-ratio log pi(a|s) - lp_old: the A log-density terms and -lp_old
+            // summed with compensation in float32 (terms of order 1 that nearly
+            // cancel against lp_old).
             float z[kMaxAct];
-            double logp = -0.5 * A * 1.8378770664093453;
+            CompSum lr;
 #pragma unroll
             for (int j = 0; j < kMaxAct; ++j) {
                 z[j] = 0.0f;
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
                     const float ls = a.logstd[j];
                     const float inv_sigma = expf(-ls);
                     z[j] = (a.actions[row * A + j] - s_out[i][j]) * inv_sigma;
-                    logp += -0.5 * static_cast<double>(z[j]) * z[j] - ls;
+                    lr.add_gauss(z[j], ls);
                     if (a.mu_old) {
                         // mean-shift part of KL(pi_old || pi_new): (mu_old - mu)^2 / (2 sigma^2)
                         const float dm = (a.mu_old[row * A + j] - s_out[i][j]) * inv_sigma;
@@ -304,10 +305,13 @@ __global__ __launch_bounds__(kHeadThreads) void head_loss_kernel(const HeadLossA
                 }
             }
             const float adv = a.adv[row];
-            const float ratio = static_cast<float>(exp(logp - static_cast<double>(a.logp_old[row])));
+            lr.add(-a.logp_old[row]);
+            const float ratio = expf(lr.value());
             const float lo = 1.0f - a.clip, hi = 1.0f + a.clip;
             pl = -fminf(ratio * adv, fminf(fmaxf(ratio, lo), hi) * adv);
             const bool active = adv >= 0.0f ? (ratio <= hi) : (ratio >= lo);
+            if (a.active_out) a.active_out[r0 + i] = active ? 1 : 0;
+            if (a.ratio_out) a.ratio_out[r0 + i] = ratio;
             clipped = fabsf(ratio - 1.0f) > a.clip ? 1.0f : 0.0f;
             kl = (ratio - 1.0f) - logf(ratio);
             const float g_lp = active ? -a.inv_m * adv * ratio : 0.0f;
@@ -767,8 +771,17 @@ __global__ __launch_bounds__(kAdamThreads) void adam_kernel(const AdamArgs a) {
             const unsigned li = static_cast<unsigned>(local), cols = static_cast<unsigned>(F.cols);
             const int r = static_cast<int>(li / cols), c = static_cast<int>(li - static_cast<unsigned>(r) * cols);
             const uint16_t bits = f32_to_bf16(th);
-            F.dst[((static_cast<long long>(r >> 5) * F.S + (c >> 4)) * 64 + (r & 31) + 32 * ((c & 15) >> 3)) * 8 +
-                  (c & 7)] = bits;
+            const int li_in = (r & 31) + 32 * ((c & 15) >> 3);
+            if (F.split) {
+                // split layout: the feature block's S bf16 fragments, then its S
+                // residual fragments
+                const long long f0 = static_cast<long long>(2 * (r >> 5)) * F.S + (c >> 4);
+                F.dst[(f0 * 64 + li_in) * 8 + (c & 7)] = bits;
+                F.dst[((f0 + F.S) * 64 + li_in) * 8 + (c & 7)] = f32_to_bf16(th - bf16_to_f32(bits));
+            } else {
+                const long long fs = static_cast<long long>(r >> 5) * F.S + (c >> 4);
+                F.dst[(fs * 64 + li_in) * 8 + (c & 7)] = bits;
+            }
             if (F.dst_t)
                 F.dst_t[((static_cast<long long>(c >> 5) * F.S_t + (r >> 4)) * 64 + (c & 31) + 32 * ((r & 15) >> 3)) *
                             8 +
@@ -802,7 +815,21 @@ __global__ __launch_bounds__(256) void stage_weights_kernel(const StageArgs a) {
     for (int e = threadIdx.x; e < kStageTile * kStageTile; e += blockDim.x) {
         const int r = e / kStageTile, c = e % kStageTile;
         const int gr = r0 + r, gc = c0 + c;
-        tile[r][c] = (gr < j.rows && gc < j.cols) ? src[static_cast<long long>(gr) * j.src_ld + gc] : T(0);
+        T v = T(0);
+        if (gr < j.rows && gc < j.cols) {
+            if constexpr (sizeof(T) == 2) {
+                if (j.lo_src) {
+                    // bf16 residual of the float32 weight (exact subtraction)
+                    const float x = j.lo_src[static_cast<long long>(gr) * j.src_ld + gc];
+                    v = f32_to_bf16(x - bf16_to_f32(f32_to_bf16(x)));
+                } else {
+                    v = src[static_cast<long long>(gr) * j.src_ld + gc];
+                }
+            } else {
+                v = src[static_cast<long long>(gr) * j.src_ld + gc];
+            }
+        }
+        tile[r][c] = v;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < kStageTile * kStageTile; e += blockDim.x) {

@@ -144,6 +144,9 @@ struct WsPlan {
     bool pad_w0 = false;
     size_t wt_w0[2] = {0, 0};
     size_t wt_t[2][kMaxHidden] = {{0}};
+    // bf16: the critic's hidden weights' residuals theta - bf16(theta), row-major
+    // [H_l][K_l] (K_0 = kpad), the second B operand of its forward GEMMs
+    size_t wt_lo[kMaxHidden] = {0};
     int max_splits = 1;
     size_t total = 0;
 };
@@ -251,13 +254,19 @@ WsPlan plan_workspace(const NetLayout &g, Precision prec, int N, int T, int M) {
             wt_elems += align_up(static_cast<size_t>(g.H[l - 1]) * g.H[l], 64);
         }
     }
+    if (prec == kBF16)
+        for (int l = 0; l < g.L; ++l) {
+            w.wt_lo[l] = wt_elems;
+            wt_elems += align_up(static_cast<size_t>(g.H[l]) * (l == 0 ? w.kpad : g.H[l - 1]), 64);
+        }
     w.wt = a.take(std::max<size_t>(wt_elems, 1) * w.esz);
     size_t frag_elems = 0;
     if (prec == kBF16 && w.kpad % 16 == 0) {
         for (int net = 0; net < 2; ++net)
             for (int l = 0; l < g.L; ++l) {
                 w.frag_w[net][l] = frag_elems;
-                frag_elems += static_cast<size_t>(g.H[l]) * (l == 0 ? w.kpad : g.H[l - 1]);
+                // the critic's forward fragments in the split layout (twice the size)
+                frag_elems += static_cast<size_t>(g.H[l]) * (l == 0 ? w.kpad : g.H[l - 1]) * (net == 1 ? 2 : 1);
                 if (l >= 1) {
                     w.frag_wt[net][l] = frag_elems;
                     frag_elems += static_cast<size_t>(g.H[l - 1]) * g.H[l];
@@ -513,6 +522,19 @@ StageArgs build_stage(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, vo
             j.transpose = 0;
             add_stage_job(a, j);
         }
+        if (net == 1 && c->prec == kBF16)
+            for (int l = 0; l < g.L; ++l) {
+                // the critic's weight residuals for the second pass of its forward GEMMs
+                StageJob j{};
+                j.lo_src = p->theta + g.Wc[l];
+                j.dst = base + w.wt_lo[l] * w.esz;
+                j.rows = g.H[l];
+                j.cols = l == 0 ? g.D : g.H[l - 1];
+                j.src_ld = j.cols;
+                j.dst_ld = l == 0 ? w.kpad : j.cols;
+                j.transpose = 0;
+                add_stage_job(a, j);
+            }
         if (!transposes) continue;
         for (int l = 1; l < g.L; ++l) {
             StageJob j{};
@@ -551,6 +573,8 @@ GemmArgs build_fwd(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, void 
             q.K = w.kpad;
             q.ldb = w.kpad;
         }
+        if (net == 1 && c->prec == kBF16)
+            q.B2 = static_cast<char *>(wsp(ws, w.wt)) + w.wt_lo[l] * w.esz;   // same layout and ld as B
         q.C = wsp(ws, net == 0 ? w.h_a[l] : w.h_c[l]);
         q.ldc = g.H[l];
         q.bias = p->theta + (net == 0 ? g.ba[l] : g.bc[l]);
@@ -855,6 +879,8 @@ struct StepBuffers {
     int step_offset;
     bool frags_ready = false;   // the fused pass's fragments already hold the current shadow
     bool write_frags = false;   // Adam refreshes them for the next step
+    uint8_t *active_out = nullptr;  // per-sample surrogate branch (ppo_loss_grad only)
+    float *ratio_out = nullptr;     // per-sample probability ratio (ppo_loss_grad only)
 };
 
 // Head/loss arguments of one mini-batch step over the rows idx[0 .. M).
@@ -994,6 +1020,11 @@ FragArgs build_frags(const ppo_ctx *c, const ppo_params *p, const WsPlan &w, voi
             j.S = (l == 0 ? w.kpad : K) / 16;
             j.ld = K;
             j.transpose = 0;
+            if (net == 1) {
+                // the critic's forward weights: bf16 value and residual from theta
+                j.split = 1;
+                j.src32 = p->theta + g.Wc[l];
+            }
             add_frag_job(a, j);
             if (l >= 1 && transposes) {
                 FragJob t{};
@@ -1024,6 +1055,7 @@ void add_adam_frags(AdamArgs &ad, const ppo_ctx *c, const WsPlan &w, void *ws) {
             F.cols = l == 0 ? g.D : g.H[l - 1];
             F.S = (l == 0 ? w.kpad : F.cols) / 16;
             F.S_t = g.H[l] / 16;
+            F.split = net == 1 ? 1 : 0;
             F.dst = base + w.frag_w[net][l];
             F.dst_t = l >= 1 ? base + w.frag_wt[net][l] : nullptr;
         }
@@ -1090,6 +1122,8 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
         // gradients of both networks in one launch
         if (!sb.frags_ready) PROFILED(prof, PPO_PHASE_GATHER, launch_pack_frags(build_frags(c, p, w, ws), s));
         FusedArgs fa = fused_args(c, p, hp, w, ws, sb.b, sb.idx, M);
+        fa.active_out = sb.active_out;
+        fa.ratio_out = sb.ratio_out;
         fa.R = fsh.rows;
         fa.NT = fsh.threads;
         PROFILED(prof, PPO_PHASE_FUSED, launch_fused_update(fa, s));
@@ -1100,7 +1134,9 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
         e = enqueue_forward(c, p, w, ws, M, true, true, t, s, prof);
         if (e != hipSuccess) return e;
 
-        const HeadLossArgs hl = head_loss_args(c, p, hp, w, ws, sb.b, sb.idx, M);
+        HeadLossArgs hl = head_loss_args(c, p, hp, w, ws, sb.b, sb.idx, M);
+        hl.active_out = sb.active_out;
+        hl.ratio_out = sb.ratio_out;
         PROFILED(prof, PPO_PHASE_HEAD_LOSS, launch_head_loss(prec, hl, s));
 
         for (int l = L - 1; l >= 1; --l) {
@@ -1471,7 +1507,8 @@ int ppo_gae_noalloc(const ppo_ctx *c, void *stream, const float *rewards, const 
 }
 
 int ppo_loss_grad(const ppo_ctx *c, void *stream, const ppo_params *p, const ppo_batch *b, const int32_t *idx,
-                  int32_t M, const ppo_hparams *hp, float *stats, float *grad_out, void *ws, size_t ws_bytes) {
+                  int32_t M, const ppo_hparams *hp, float *stats, float *grad_out, uint8_t *active_out,
+                  float *ratio_out, void *ws, size_t ws_bytes) {
     if (!c) return fail(PPO_E_INVAL, "ctx is NULL");
     PPO_CHECK(validate_hparams(hp));
     PPO_CHECK(validate_params(c, p, false));
@@ -1480,11 +1517,15 @@ int ppo_loss_grad(const ppo_ctx *c, void *stream, const ppo_params *p, const ppo
     PPO_CHECK(check_ptr(idx, "idx"));
     PPO_CHECK(check_ptr(stats, "stats"));
     PPO_CHECK(check_ptr(grad_out, "grad_out"));
+    if (ratio_out && (reinterpret_cast<uintptr_t>(ratio_out) & 3u))
+        return fail(PPO_E_INVAL, "ratio_out is not 4-byte aligned");
     PPO_CHECK(validate_ws(c, 0, 0, M, ws, ws_bytes));
     PPO_CHECK(check_device());
     note_ws_used(ws, ws_bytes);
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
     StepBuffers sb{b, idx, M, grad_out, stats, 0, 0};
+    sb.active_out = active_out;
+    sb.ratio_out = ratio_out;
     Tuning tune;
     PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, static_cast<hipStream_t>(stream), tune));
     PPO_HIP(enqueue_step(c, p, hp, w, ws, sb, tune, static_cast<hipStream_t>(stream)), "loss_grad");

@@ -113,10 +113,21 @@ def bf16_round(x):
     return r.view(np.float32).astype(np.float64)
 
 
+def bf16_split_sum(x):
+    """bf16(x) + bf16(x - bf16(x)) for float32 x (the subtraction is exact in
+    float32), as float64: the value a weight stored as a bf16 pair carries."""
+    x32 = np.ascontiguousarray(x, dtype=np.float32)
+    hi = bf16_round(x32)
+    lo = bf16_round((x32.astype(np.float64) - hi).astype(np.float32))
+    return hi + lo
+
+
 def round_hidden_weights(theta, spec):
-    """theta with every hidden-layer weight matrix rounded to bf16: the
-    parameters the bf16 GEMMs multiply with (biases, output layers and
-    log-std stay float32)."""
+    """theta with every hidden-layer weight matrix replaced by the value the
+    bf16 GEMMs multiply with: bf16(W) for the actor, the bf16 pair
+    bf16(W) + bf16(W - bf16(W)) for the critic (biases, output layers and
+    log-std stay float32).  A diagnostic: the oracle at these parameters
+    separates weight quantisation from everything else."""
     from oracle import param_layout
     lay = param_layout(spec)
     out = np.asarray(theta, dtype=np.float64).copy()
@@ -124,5 +135,6 @@ def round_hidden_weights(theta, spec):
         for l in range(1, len(spec.hidden) + 1):
             off, shp = lay[f"{which}.W{l}"]
             n = int(np.prod(shp))
-            out[off:off + n] = bf16_round(np.asarray(theta[off:off + n], dtype=np.float32))
+            w32 = np.asarray(theta[off:off + n], dtype=np.float32)
+            out[off:off + n] = bf16_round(w32) if which == "actor" else bf16_split_sum(w32)
     return out

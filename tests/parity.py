@@ -76,3 +76,27 @@ def assert_grad_close(name, x, ref, tol, layout):
     bad = {k: v for k, v in per.items() if not v <= tol}
     assert nw <= tol and not bad, f"{name}: normwise {nw:.3e}, tensors over {tol:.0e}: {bad}"
     return per
+
+
+def tie_bands(gpu_ratio, ref_ratio):
+    """Per-sample clip-edge bands for the oracle's tie protocol: a sample may
+    take the GPU's branch when the GPU's ratio (itself gated against the
+    oracle's) could lie on the other side of the deciding edge, i.e. when the
+    oracle's margin is below the distance between the two ratios, plus the
+    float32 rounding of the edge 1 +- clip on the GPU (a few 1e-8)."""
+    g = np.asarray(gpu_ratio, np.float64)
+    r = np.asarray(ref_ratio, np.float64)
+    return np.abs(g - r) + 1e-7 * np.maximum(1.0, np.abs(r))
+
+
+def grad_report(x, ref, layout):
+    """{tensor: (normwise, elementwise with the rms floor)} of a gradient."""
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    out = {}
+    for name, (off, shp) in layout.items():
+        if name == "__total__":
+            continue
+        n = int(np.prod(shp))
+        out[name] = rel_errors(x[off:off + n], ref[off:off + n])
+    return out

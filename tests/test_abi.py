@@ -142,7 +142,13 @@ def test_misuse_codes():
     assert b"PPO_GAE_NOALLOC_MAX_N" in lib.ppo_last_error()
     # loss_grad: M larger than B
     assert lib.ppo_loss_grad(ctx.handle, None, ctypes.byref(p), ctypes.byref(b), FAKE, 2000, ctypes.byref(hp),
-                             FAKE, FAKE, FAKE, ws) == ppo.PPO_E_SHAPE
+                             FAKE, FAKE, None, None, FAKE, ws) == ppo.PPO_E_SHAPE
+    # loss_grad: misaligned gradient output
+    assert lib.ppo_loss_grad(ctx.handle, None, ctypes.byref(p), ctypes.byref(b), FAKE, 100, ctypes.byref(hp),
+                             FAKE, FAKE + 4, None, None, FAKE, ws) == ppo.PPO_E_INVAL
+    assert lib.ppo_loss_grad(ctx.handle, None, ctypes.byref(p), ctypes.byref(b), FAKE, 100, ctypes.byref(hp),
+                             FAKE, FAKE, FAKE + 1, FAKE + 2, FAKE, ws) == ppo.PPO_E_INVAL
+    assert b"ratio_out" in lib.ppo_last_error()
     # philox count
     assert lib.ppo_philox_blocks(None, 0, 0, 0, 0, 0, 0, FAKE) == ppo.PPO_E_SHAPE
     # null context
