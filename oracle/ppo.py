@@ -107,9 +107,9 @@ def ppo_loss_grad(theta, spec: NetSpec, batch: Dict[str, np.ndarray], hp: PPOHyp
     Clip-edge ties: a sample whose ratio lies within rounding of the clip
     edge that decides its branch may legitimately take either branch in
     another implementation's arithmetic.  With active_override (bool [M],
-    the other implementation's branches) and tie_delta > 0, samples whose
-    margin is below tie_delta take the override's branch; every other sample
-    keeps its own.  The result reports how many samples were adopted that way
+    the other implementation's branches) and tie_delta (a scalar, or one band
+    per sample), samples whose margin is below their band take the
+    override's branch; every other sample keeps its own.  The result reports how many samples were adopted that way
     ("ties_adopted") and how many disagree outside the band
     ("disagree_outside", which a checker requires to be zero).
     """
