@@ -178,12 +178,12 @@ def phase_model(cfg, precision, P):
     head_b = M * H[-1] * e * 2 * 2 + M * 16 * e * 2 + M * 4 * (A + 5)
     head_f = M * H[-1] * (A + 1) * 4.0
     # the fused per-sample pass (bf16): the forward, output-layer and
-    # input-gradient arithmetic of both networks; it reads the observation
-    # rows, the loss inputs and every weight once, and writes only the
-    # weight-gradient operands (gathered inputs, activations, pre-activation
-    # and output gradients) and the loss partials
+    # input-gradient arithmetic of both networks.  Compulsory bytes: the
+    # observation rows, indices and loss inputs it reads and every weight once;
+    # the weight-gradient operands it writes (activations, pre-activation and
+    # output gradients) are this design's choice, not the method's, and are
+    # not counted
     fused_b = (M * D * 4.0 + M * 4.0 + M * 4.0 * (A + 4)
-               + M * kpad * e + M * sum(H) * e * 2 * 2 + M * 16 * e * 2
                + sum(H[l] * ins_pad[l] * e + H[l] * 4 for l in range(L)) * 2
                + sum(H[l] * H[l - 1] * e for l in range(1, L)) * 2)
     return {
@@ -246,10 +246,30 @@ def recorded_traffic(wl, phase, workload):
     return sum(float(v) for v in vals) / len(vals)
 
 
+GEMM_PHASES = ("fused", "forward", "input_grad", "weight_grad", "head_loss")
+
+
+def update_flops(cfg):
+    """Useful GEMM FLOPs of one full update (E x B sample passes): the forward
+    and the two backward contractions of both networks, output layers
+    included; padding (K 48 -> 64, 235 -> 240, head 12 -> 16) and the
+    critic's second (residual) weight pass are not counted."""
+    net, M = cfg.net, cfg.minibatch
+    D, A, H = net.obs_dim, net.act_dim, list(net.hidden)
+    ins = [D, *H[:-1]]
+    per = 0
+    for outs in (A, 1):
+        fwd = sum(ins[l] * H[l] for l in range(len(H))) + H[-1] * outs
+        dx = sum(H[l] * H[l - 1] for l in range(1, len(H))) + H[-1] * outs
+        per += 2 * fwd + 2 * dx + 2 * fwd      # forward, input gradients, weight gradients
+    return float(per) * cfg.epochs * cfg.batch
+
+
 def roofline(wl, precision):
     """Per-phase HIP-event durations of one eager epoch and each phase's
-    place under the roofline: t_roof = max(FLOPs / MFMA peak, bytes / HBM
-    peak); the binding roof names the bound and frac = t_roof / t."""
+    place under its roof: contractions (the fused pass, the GEMMs, the output
+    layers) on the MFMA roof with useful FLOPs, the rest on the HBM roof with
+    compulsory bytes; frac = achieved / peak."""
     import torch
     cfg = wl.cfg
     # repeatable launches run PROFILE_REPS times back to back inside their
@@ -260,6 +280,7 @@ def roofline(wl, precision):
     model = phase_model(cfg, precision, wl.ctx.param_count)
     steps = cfg.minibatches
     phases = {}
+    per_launch = {}
     for name, (ms, launches) in prof.items():
         if launches == 0:
             continue
@@ -269,39 +290,48 @@ def roofline(wl, precision):
         else:
             f, b = model.get(name, (0.0, 0.0))
             f, b = f * steps / launches, b * steps / launches
-        t_f = f / (MFMA_PEAK_TFLOPS[precision] * 1e12)
-        t_b = b / (HBM_PEAK_GBS * 1e9)
-        phases[name] = {"ms_per_epoch": round(ms, 4), "launches": launches, "us_per_launch": round(t * 1e6, 2),
-                        "tflops": round(f / t / 1e12, 2), "gbs": round(b / t / 1e9, 1),
-                        "bound": "mfma" if t_f >= t_b else "hbm", "frac": round(max(t_f, t_b) / t, 4)}
+        per_launch[name] = (t, f, b)
+        if name in GEMM_PHASES and f > 0:
+            ach = f / t / 1e12
+            phases[name] = {"ms_per_epoch": round(ms, 4), "launches": launches, "us_per_launch": round(t * 1e6, 2),
+                            "bound": "mfma", "achieved_tflops": round(ach, 2),
+                            "frac": round(ach / MFMA_PEAK_TFLOPS[precision], 4)}
+        else:
+            ach = b / t / 1e9
+            phases[name] = {"ms_per_epoch": round(ms, 4), "launches": launches, "us_per_launch": round(t * 1e6, 2),
+                            "bound": "hbm", "achieved_gbs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4)}
     dominant = max(phases, key=lambda k: phases[k]["ms_per_epoch"])
     ph = phases[dominant]
-    ms, launches = prof[dominant]
-    t = ms * 1e-3 / launches
-    f, b = model[dominant]
-    f, b = f * steps / launches, b * steps / launches
+    t, f, b = per_launch[dominant]
     if ph["bound"] == "mfma":
-        roof = {"kernel": dominant, "bound": "mfma", "achieved": ph["tflops"],
+        roof = {"kernel": dominant, "bound": "mfma", "achieved": ph["achieved_tflops"],
                 "peak": MFMA_PEAK_TFLOPS[precision], "unit": "TFLOP/s", "frac": ph["frac"]}
     else:
-        roof = {"kernel": dominant, "bound": "hbm", "achieved": ph["gbs"], "peak": HBM_PEAK_GBS,
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": ph["achieved_gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ph["frac"]}
     roof.update({"traffic": recorded_traffic(wl, dominant, cfg.name.split("_")[0]),
-                 "algorithmic_flops_per_launch": f, "algorithmic_bytes_per_launch": b,
-                 "avg_launch_us": round(t * 1e6, 2)})
-    gemm = {k: phases[k]["tflops"] for k in ("forward", "input_grad", "weight_grad") if k in phases}
+                 "algorithmic_flops_per_launch": f, "avg_launch_us": round(t * 1e6, 2)})
+    gemm = {k: phases[k].get("achieved_tflops") for k in GEMM_PHASES if k in phases}
     return roof, phases, gemm
 
 
 def cpu_baseline(wl, precision):
-    """The FP64 oracle on a bounded sample of the same workload.
+    """The FP64 oracle on the same workload, and the parity of the timed state.
 
-    Sample: one policy step over all 4096 environments, GAE over the whole
-    [24, 4096] rollout, and one mini-batch step (loss, gradient, clip, Adam)
-    over 24576 samples.  The per-iteration time is assembled from those
-    (25 policy steps + 1 GAE + 20 mini-batch steps); value = B / that time.
-    The same mini-batch is also run through the HIP path at the same
-    parameters to report the gradient's distance to the oracle.
+    Sample: one whole learning iteration of the oracle on the rollout the GPU
+    holds: the policy step for every one of the 24 rollout steps over all
+    4096 environments plus the critic on the observation after the last,
+    GAE with time-outs and the advantage statistics, and the full update
+    (5 epochs x 4 mini-batches of 24576: loss, gradient, global clip, Adam).
+    value = B / that time.
+
+    Parity of the timed state: one mini-batch (the first of epoch 0) through
+    ppo_loss_grad at the GPU's current parameters, with its per-sample ratios
+    and clip branches, against the oracle at the same parameters and inputs.
+    The ratios are compared normwise; a sample takes the GPU's branch where
+    the GPU's ratio lies across the deciding clip edge from the oracle's
+    (the clip-edge tie protocol); the gradient is compared per parameter
+    tensor, normwise (the gate) and elementwise with the rms floor (stated).
     """
     import torch
     import oracle
@@ -312,37 +342,33 @@ def cpu_baseline(wl, precision):
     theta = wl.params.theta.cpu().numpy().astype(np.float64)
     obs = wl.obs.cpu().numpy()
     T, N, B, M = cfg.n_steps, cfg.n_envs, cfg.batch, cfg.minibatch
-
-    t0 = time.perf_counter()
-    oracle.rollout_infer(theta, spec, obs[0], cfg.seed, 0, 0)
-    t_inf = time.perf_counter() - t0
-
-    rewards = wl.rewards.cpu().numpy()
-    dones = wl.dones.cpu().numpy()
-    timeouts = wl.timeouts.cpu().numpy()
-    values = wl.values.cpu().numpy()
-    last = wl.last_values.cpu().numpy()
-    t0 = time.perf_counter()
-    adv, ret = oracle.gae(rewards, values, dones, last, cfg.gamma, cfg.lam, timeouts=timeouts)
-    mean, std = oracle.advantage_stats(adv)
-    oracle.normalize_advantages(adv, mean, std)
-    t_gae = time.perf_counter() - t0
-
-    perm = wl.perms[0].cpu().numpy()
-    idx = perm[:M]
-    full = dict(obs=obs.reshape(B, -1), actions=wl.actions.cpu().numpy().reshape(B, -1),
-                logp_old=wl.logp.cpu().numpy().reshape(B), adv=wl.adv.cpu().numpy().reshape(B),
-                returns=wl.returns.cpu().numpy().reshape(B))
     hp = oracle.PPOHyper(clip=cfg.clip, value_coef=cfg.value_coef, entropy_coef=cfg.entropy_coef,
                          max_grad_norm=cfg.max_grad_norm, lr=cfg.lr)
     P = theta.size
-    t0 = time.perf_counter()
-    res = oracle.ppo_loss_grad(theta, spec, minibatch(full, idx), hp)
-    c, _ = oracle.clip_coef(res["grad"], hp.max_grad_norm)
-    oracle.adam_step(theta, np.zeros(P), np.zeros(P), c * res["grad"], 0, hp)
-    t_mb = time.perf_counter() - t0
+    perms = wl.perms.cpu().numpy()
 
-    t_iter = (T + 1) * t_inf + t_gae + cfg.epochs * cfg.minibatches * t_mb
+    t_start = time.perf_counter()
+    ro = [oracle.rollout_infer(theta, spec, obs[t], cfg.seed, t, 0) for t in range(T)]
+    last = oracle.policy.critic_values(theta, spec, wl.last_obs.cpu().numpy())
+    t_inf = time.perf_counter() - t_start
+    values = np.stack([r["values"] for r in ro])
+    rewards = wl.rewards.cpu().numpy()
+    dones = wl.dones.cpu().numpy()
+    timeouts = wl.timeouts.cpu().numpy()
+    t0 = time.perf_counter()
+    adv, ret = oracle.gae(rewards, values, dones, last, cfg.gamma, cfg.lam, timeouts=timeouts)
+    mean, std = oracle.advantage_stats(adv)
+    adv_n = oracle.normalize_advantages(adv, mean, std)
+    t_gae = time.perf_counter() - t0
+    full = dict(obs=obs.reshape(B, -1), actions=np.concatenate([r["actions"] for r in ro]),
+                logp_old=np.concatenate([r["logp"] for r in ro]), adv=adv_n.reshape(B), returns=ret.reshape(B))
+    t0 = time.perf_counter()
+    th, m, v, step = theta, np.zeros(P), np.zeros(P), 0
+    for e in range(cfg.epochs):
+        th, m, v, step, _ = oracle.update_epoch(th, m, v, step, spec, full, perms[e], cfg.minibatches, hp)
+    t_upd = time.perf_counter() - t0
+    t_iter = time.perf_counter() - t_start
+
     threads, blas = None, []
     try:
         from threadpoolctl import threadpool_info
@@ -358,21 +384,56 @@ def cpu_baseline(wl, precision):
     except OSError:
         pass
 
-    # the same mini-batch through the HIP path at the same parameters
-    gstats = torch.zeros(wl.ppo.PPO_STATS_WIDTH, device=wl.params.theta.device)
-    grad = torch.zeros(P, device=wl.params.theta.device)
-    wl.ppo.ppo_loss_grad(wl.ctx, wl.params, wl.batch, wl.perms[0][:M].contiguous(), wl.hp, gstats, grad, wl.ws)
+    # parity of the timed state: the same mini-batch through the HIP path
+    dev = wl.params.theta.device
+    idx = wl.perms[0][:M].contiguous()
+    gstats = torch.zeros(wl.ppo.PPO_STATS_WIDTH, device=dev)
+    grad = torch.zeros(P, device=dev)
+    active = torch.zeros(M, dtype=torch.uint8, device=dev)
+    ratio = torch.zeros(M, device=dev)
+    wl.ppo.ppo_loss_grad(wl.ctx, wl.params, wl.batch, idx, wl.hp, gstats, grad, wl.ws, active_out=active,
+                         ratio_out=ratio)
     torch.cuda.synchronize()
+    gpu_batch = dict(obs=obs.reshape(B, -1), actions=wl.actions.cpu().numpy().reshape(B, -1),
+                     logp_old=wl.logp.cpu().numpy().reshape(B), adv=wl.adv.cpu().numpy().reshape(B),
+                     returns=wl.returns.cpu().numpy().reshape(B))
+    mb = minibatch(gpu_batch, idx.cpu().numpy())
+    own = oracle.ppo_loss_grad(theta, spec, mb, hp, want_grad=False)
+    rg = ratio.cpu().numpy().astype(np.float64)
+    band = np.abs(rg - own["ratio"]) + 1e-7 * np.maximum(1.0, np.abs(own["ratio"]))
+    res = oracle.ppo_loss_grad(theta, spec, mb, hp, active_override=active.cpu().numpy().astype(bool),
+                               tie_delta=band)
     g = grad.cpu().numpy().astype(np.float64)
-    r = res["grad"]
-    normwise = float(np.linalg.norm(g - r) / np.linalg.norm(r))
-    return {"value": round(B / t_iter, 1), "unit": "samples/s", "cores": threads, "kind": "oracle",
-            "sample": (f"FP64 NumPy oracle: 1 policy step over {N} envs ({t_inf:.3f} s), GAE over "
-                       f"[{T},{N}] ({t_gae:.3f} s), 1 mini-batch step of {M} samples ({t_mb:.2f} s); "
-                       f"iteration time assembled as {T + 1} policy steps + GAE + "
-                       f"{cfg.epochs * cfg.minibatches} mini-batch steps = {t_iter:.1f} s"),
-            "host_cpus": os.cpu_count(), "cpu_model": cpu_model, "blas": blas,
-            "gpu_grad_vs_oracle_normwise": normwise}
+    tol = 2e-2 if precision == "bf16" else 1e-5
+    normwise, elementwise = {}, {}
+    for name, (off, shp) in oracle.param_layout(spec).items():
+        if name == "__total__":
+            continue
+        n = int(np.prod(shp))
+        x, r = g[off:off + n], res["grad"][off:off + n]
+        normwise[name] = float(np.linalg.norm(x - r) / np.linalg.norm(r))
+        rms = float(np.sqrt(np.mean(r * r)))
+        elementwise[name] = float(np.max(np.abs(x - r) / (np.abs(r) + rms)))
+    ratio_nw = float(np.linalg.norm(rg - own["ratio"]) / np.linalg.norm(own["ratio"]))
+    worst = max(normwise, key=normwise.get)
+    parity = {"tol": tol, "minibatch": "epoch 0, mini-batch 0, at the parameters after the timed steps",
+              "within_tol": bool(max(normwise.values()) <= tol and ratio_nw <= tol and res["disagree_outside"] == 0),
+              "gradient_normwise_worst": [worst, round(normwise[worst], 6)],
+              "gradient_normwise_total": float(np.linalg.norm(g - res["grad"]) / np.linalg.norm(res["grad"])),
+              "gradient_normwise_per_tensor": {k: round(v, 6) for k, v in normwise.items()},
+              "gradient_elementwise_rms_floor_per_tensor": {k: round(v, 5) for k, v in elementwise.items()},
+              "ratio_normwise": round(ratio_nw, 6),
+              "ratio_max_relative": round(float(np.max(np.abs(rg / own["ratio"] - 1.0))), 6),
+              "clip_fraction": round(float(res["clip_frac"]), 4),
+              "clip_ties_adopted": res["ties_adopted"], "clip_disagreements_outside_band": res["disagree_outside"]}
+    base = {"value": round(B / t_iter, 1), "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle, one whole learning iteration: {T} policy steps over {N} envs + the "
+                       f"critic on the last observation ({t_inf:.2f} s), GAE over [{T},{N}] ({t_gae:.3f} s), "
+                       f"{cfg.epochs} epochs x {cfg.minibatches} mini-batches of {M} ({t_upd:.1f} s); "
+                       f"total {t_iter:.1f} s"),
+            "update_samples_per_s": round(B / t_upd, 1),
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model, "blas": blas}
+    return base, parity
 
 
 def update_distribution(wl, reps=20, warmup=3):
@@ -686,6 +747,10 @@ def main():
         "breakdown_ms": {k: round(v, 3) for k, v in parts.items()},
         "update_ms_median_iqr": upd,
         "roofline": roof,
+        # useful GEMM FLOPs of the whole update (forward, input and weight
+        # gradients of both networks) over the median update time
+        "update_mfma_frac": round(update_flops(cfg) / (upd["median_ms"] * 1e-3) / (MFMA_PEAK_TFLOPS["bf16"] * 1e12), 4),
+        "update_useful_tflop": round(update_flops(cfg) / 1e12, 4),
         "phases_bf16": phases,
         "gemm_tflops_bf16": gemm_tflops,
         "autotuned_tiles": {"update": wl.ctx.tuning(cfg.minibatch, True),
@@ -709,7 +774,7 @@ def main():
         out["obs_assembly"] = obs_assembly_rate(dev)
         out["attainable_peaks"] = attainable_peaks(dev)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, "bf16")
+        out["cpu_baseline"], out["parity"] = cpu_baseline(wl, "bf16")
     print(json.dumps(out), flush=True)
 
 
