@@ -194,6 +194,11 @@ struct FusedArgs {
     // filled in by launch_fused_update
     int blocks;
     int lds_region[kMaxHidden], lds_x, lds_w, lds_sum, lds_in, lds_rows, lds_bias, lds_head;
+    // update pass only: offsets in its shared activation region of the last
+    // hidden layer's output, of each backward layer's input gradient and of
+    // the staged activation it multiplies by ELU', and the feature chunk of
+    // the first hidden layer's input gradient
+    int lds_last, lds_g, lds_bdz[kMaxHidden], lds_bst[kMaxHidden], chunk;
     int bias_off[kMaxHidden];         // floats into the staged biases
 };
 // Samples per workgroup and threads per workgroup of the fused pass for this
@@ -204,7 +209,10 @@ struct FusedArgs {
 struct FusedShape {
     int rows, threads, per_cu;
 };
-FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows = 0, int prefer_threads = 0);
+// update = true: the shapes of the update pass (its LDS plan differs from
+// inference's).
+FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows = 0, int prefer_threads = 0,
+                       bool update = false);
 int fused_blocks(int M, int R);
 hipError_t launch_fused_update(FusedArgs a, hipStream_t s);
 // Forward pass and sampling head for M environments (rows of obs in order).

@@ -215,9 +215,12 @@ __device__ __forceinline__ void epi_backward(const floatx16 (&acc)[FBW][SB], int
 template <int FBW, int SB, int PF, bool BWD, int SPLIT, class Hook>
 __device__ __forceinline__ void layer_impl(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
                                            int in_pitch, uint16_t *out, int out_pitch, int f0, int sb0, int lane,
-                                           const Hook &hook) {
+                                           const Hook &hook, bool sync_epi) {
     floatx16 acc[FBW][SB];
     mma_layer<FBW, SB, PF, SPLIT>(acc, W, nout, K >> 4, f0, sb0, in, in_pitch, lane, hook);
+    // an output that overwrites the layer's input waits until every wave has
+    // read its input fragments
+    if (sync_epi) __syncthreads();
     if constexpr (BWD)
         epi_backward<FBW, SB>(acc, f0, sb0, out, out_pitch, lane);
     else
@@ -231,19 +234,19 @@ __device__ __forceinline__ void layer_impl(const uint16_t *W, int K, int nout, c
 template <int FBW, int SB, bool BWD, int PFMAX, int SPLIT, class Hook>
 __device__ __forceinline__ void layer_pf(int S, const uint16_t *W, int K, int nout, const float *bias,
                                          const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
-                                         int sb0, int lane, const Hook &hook) {
+                                         int sb0, int lane, const Hook &hook, bool sync_epi) {
     const int SW = S * SPLIT;
     if (PFMAX >= 32 && SW >= 32)
         layer_impl<FBW, SB, (PFMAX >= 32 ? 32 : 4), BWD, SPLIT>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
-                                                                sb0, lane, hook);
+                                                                sb0, lane, hook, sync_epi);
     else if (PFMAX >= 16 && SW >= 16)
         layer_impl<FBW, SB, (PFMAX >= 16 ? 16 : 4), BWD, SPLIT>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
-                                                                sb0, lane, hook);
+                                                                sb0, lane, hook, sync_epi);
     else if (PFMAX >= 8 && SW >= 8)
         layer_impl<FBW, SB, (PFMAX >= 8 ? 8 : 4), BWD, SPLIT>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
-                                                              sb0, lane, hook);
+                                                              sb0, lane, hook, sync_epi);
     else
-        layer_impl<FBW, SB, 4, BWD, SPLIT>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane, hook);
+        layer_impl<FBW, SB, 4, BWD, SPLIT>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0, sb0, lane, hook, sync_epi);
 }
 
 // Deepest weight prefetch (k-steps) that keeps the accumulators (FBW x SBW
@@ -259,26 +262,28 @@ constexpr int pf_max() {
 template <int SBW, bool BWD, bool WIDE, int REGS, int SPLIT, class Hook>
 __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int K, int nout, const float *bias,
                                          const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
-                                         int sb0, int lane, const Hook &hook) {
+                                         int sb0, int lane, const Hook &hook, bool sync_epi) {
     switch (fbw) {
     case 1:
         layer_pf<1, SBW, BWD, pf_max<1, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
-                                                             sb0, lane, hook);
+                                                             sb0, lane, hook, sync_epi);
         break;
     case 2:
         layer_pf<2, SBW, BWD, pf_max<2, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
-                                                             sb0, lane, hook);
+                                                             sb0, lane, hook, sync_epi);
         break;
     case 4:
         layer_pf<4, SBW, BWD, pf_max<4, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
-                                                             sb0, lane, hook);
+                                                             sb0, lane, hook, sync_epi);
         break;
     default:
         if constexpr (WIDE)
             layer_pf<8, SBW, BWD, pf_max<8, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch,
-                                                                 f0, sb0, lane, hook);
-        else
+                                                                 f0, sb0, lane, hook, sync_epi);
+        else {
             hook();
+            if (sync_epi) __syncthreads();
+        }
         break;
     }
 }
@@ -290,12 +295,12 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
 template <int R, int NT, int WPE, bool BWD, int SPLIT = 1, class Hook = NoHook>
 __device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
                                           int in_pitch, uint16_t *out, int out_pitch, int wave, int lane,
-                                          const Hook &hook = Hook()) {
+                                          const Hook &hook = Hook(), bool sync_epi = false) {
     constexpr int NW = NT / 64;
     constexpr int SB = R / 32;
     // registers for accumulators and fragments: 512 / WPE per lane, less
     // what the addresses, activation fragments and epilogue keep live
-    constexpr int REGS = WPE == 1 ? 320 : 192;
+    constexpr int REGS = WPE == 1 ? 320 : (SB >= 2 ? 160 : 192);
     // eight feature blocks per wave only with one sample block and a full
     // register file
     constexpr bool WIDE = SB == 1 && WPE == 1;
@@ -304,13 +309,14 @@ __device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, co
     if (fb >= NW) {
         const int fbw = fb / NW;
         layer_fb<SB, BWD, WIDE, REGS, SPLIT>(fbw, S, W, K, nout, bias, in, in_pitch, out, out_pitch,
-                                             wave * fbw * 32, 0, lane, hook);
+                                             wave * fbw * 32, 0, lane, hook, sync_epi);
     } else if constexpr (SB >= 2) {
         // two waves per feature block, each with half the sample blocks
         layer_fb<SB / 2, BWD, false, REGS, SPLIT>(1, S, W, K, nout, bias, in, in_pitch, out, out_pitch,
-                                                  (wave % fb) * 32, (wave / fb) * (SB / 2), lane, hook);
+                                                  (wave % fb) * 32, (wave / fb) * (SB / 2), lane, hook, sync_epi);
     } else {
         hook();   // a wave without a feature block still does its share of the hook
+        if (sync_epi) __syncthreads();
     }
 }
 
@@ -428,6 +434,46 @@ __device__ __forceinline__ void head_dots(const uint16_t *hrow, const float *wl,
     }
 #pragma unroll
     for (int j = 0; j < NO; ++j) o[j] = kpart_sum<KP>(o[j]) + s_head[j];
+}
+
+// Network and sample block of workgroup b when both networks run in one
+// grid.  Workgroups go round-robin over the 8 XCDs, so the network index
+// alternates every 8 workgroups rather than every one: each XCD then runs
+// both networks' blocks in equal numbers (the critic's forward makes its
+// blocks the longer ones) and keeps both networks' weights in its L2.
+// Returns false for the padding workgroups past the last sample block.
+__device__ inline bool net_block(int b, int blocks, int &net, int &sblk) {
+    net = (b >> 3) & 1;
+    sblk = (b >> 4) * 8 + (b & 7);
+    return sblk < blocks;
+}
+
+// rows x cols bf16 from global rows of `ld` elements into LDS (row pitch
+// `pitch`), the inverse of copy_out with the same thread mapping; rows past
+// `rows` are zero.  The source was written earlier in the same launch by this
+// workgroup's copy_out (visible after the workgroup barriers in between).
+template <int NT>
+__device__ inline void copy_in(const uint16_t *src, int ld, uint16_t *dst, int pitch, int cols, int rows, int R) {
+    constexpr int U = 4;
+    const int cpr = cols >> 3;
+    const int rpp = NT / cpr;
+    const int r0 = threadIdx.x / cpr;
+    const int c = (threadIdx.x - r0 * cpr) * 8;
+    if (r0 >= rpp) return;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, static_cast<long long>(rows) * ld * 2);
+    for (int i0 = r0; i0 < R; i0 += U * rpp) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * rpp;
+            v[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, i < rows ? (i * ld + c) * 2 : kOutside, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * rpp;
+            if (i < R) *reinterpret_cast<u32x4 *>(dst + i * pitch + c) = v[u];
+        }
+    }
 }
 
 // Output layer, PPO loss terms and output gradients of the block's samples.
@@ -548,52 +594,241 @@ __device__ __forceinline__ void head_pass(const FusedArgs &a, const FusedNet &N,
     }
 }
 
+// bf16 pieces of float32 values: hi = bf16(x), then the bf16 residuals.
+__device__ inline void split3(const float (&x)[8], u32x4 &hi, u32x4 &mid, u32x4 &lo) {
+    float r1[8], r2[8];
+    uint32_t h[8], m[8], l[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        h[e] = bf16_bits(x[e]);
+        r1[e] = x[e] - __uint_as_float(h[e] << 16);
+        m[e] = bf16_bits(r1[e]);
+        r2[e] = r1[e] - __uint_as_float(m[e] << 16);
+        l[e] = bf16_bits(r2[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        hi[e] = h[2 * e] | (h[2 * e + 1] << 16);
+        mid[e] = m[2 * e] | (m[2 * e + 1] << 16);
+        lo[e] = l[2 * e] | (l[2 * e + 1] << 16);
+    }
+}
+__device__ inline void split2(const float (&x)[8], u32x4 &hi, u32x4 &lo) {
+    u32x4 mid;
+    split3(x, hi, lo, mid);
+}
+__device__ inline floatx16 mfma16(const u32x4 &a, const u32x4 &b, const floatx16 &c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                   0, 0, 0);
+}
+
+// Output layer, PPO loss terms and output gradients of the block's samples on
+// MFMA (the update pass).  Wave w < R / 32 takes sample block w: the output
+// layer C[output][sample] = W_out[output, :] . h[sample, :] + b with the
+// float32 weights as three bf16 terms (their sum is the float32 weight
+// exactly, so each product is exact and the sums are float32 sums), which
+// leaves in lane l sample 32 w + l % 32 and outputs 8 g + 4 (l / 32) + e
+// (g = 0, 1; e = 0 .. 3): every sample's outputs sit in two lanes, l and
+// l ^ 32, which combine their partial sums with one lane swap.  Both lanes
+// then compute the loss terms and the output gradients of their outputs.
+// The gradient into the last hidden layer, dh[feature][sample] =
+// sum_j g_j W_out[j, feature], is a second MFMA pass over all waves (the
+// float32 gradients and weights as bf16 pairs, the three larger products;
+// the result is rounded to bf16 anyway), whose epilogue multiplies by ELU'
+// in place over h, as the hidden layers' backward epilogue does.  s_g holds
+// the output gradients [R][kFusedMaxAct] between the two passes.
+template <int R, int NT, bool ACTOR>
+__device__ __forceinline__ void head_mfma(const FusedArgs &a, const FusedNet &N, uint16_t *hl, int PL,
+                                          const float *w_out, int WP, const float *s_head, const float *s_in,
+                                          float *s_sum, float *s_g, int m0, int rows, int wave, int lane) {
+    constexpr int SB = R / 32;
+    constexpr int NW = NT / 64;
+    const int Hl = a.H[a.L - 1];
+    const int S = Hl / 16;
+    const int half = lane >> 5;
+    if (wave < SB) {
+        const int si = 32 * wave + (lane & 31);
+        const bool valid = si < rows;
+        // ---- output layer
+        floatx16 acc = floatx16{};
+        const int orow = lane & 31;   // output row of the A operand
+        const uint16_t *bp = hl + si * PL + 8 * half;
+        for (int s = 0; s < S; ++s) {
+            float w8[8];
+            const float *wr = w_out + orow * WP + 16 * s + 8 * half;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) w8[e] = orow < kFusedMaxAct ? wr[e] : 0.0f;
+            u32x4 hi, mid, lo;
+            split3(w8, hi, mid, lo);
+            const u32x4 b = *reinterpret_cast<const u32x4 *>(bp + 16 * s);
+            acc = mfma16(lo, b, acc);
+            acc = mfma16(mid, b, acc);
+            acc = mfma16(hi, b, acc);
+        }
+        // this lane's outputs: j(g, e) = 8 g + 4 half + e, g = 0, 1
+        float o[8];
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[4 * g + e] = acc[4 * g + e] + s_head[8 * g + 4 * half + e];
+        const float *in_s = s_in + si * kInW;
+        float g8[8];
+        float sums[kSums];
+#pragma unroll
+        for (int q = 0; q < kSums; ++q) sums[q] = 0.0f;
+        if constexpr (ACTOR) {
+            const int A = a.A;
+            CompSum lr;
+            float kl_mu = 0.0f, z[8], inv_sig[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = 8 * (t >> 2) + 4 * half + (t & 3);
+                const float ls = s_head[kFusedMaxAct + j];
+                inv_sig[t] = expf(-ls);
+                z[t] = (in_s[j] - o[t]) * inv_sig[t];
+                if (j < A) lr.add_gauss(z[t], ls);
+                // mean-shift part of KL(pi_old || pi), only with collection-time means
+                const float dm = (in_s[kFusedMaxAct + j] - o[t]) * inv_sig[t];
+                if (a.mu_old && j < A) kl_mu += 0.5f * dm * dm;
+            }
+            // the partner lane's half of the log-density and KL (the same
+            // result in both lanes: every combination below is symmetric)
+            {
+                const float ps = __shfl_xor(lr.s, 32), pc = __shfl_xor(lr.c, 32);
+                const float t = lr.s + ps;
+                const float err = fabsf(lr.s) >= fabsf(ps) ? (lr.s - t) + ps : (ps - t) + lr.s;
+                lr.c = (lr.c + pc) + err;
+                lr.s = t;
+                kl_mu += __shfl_xor(kl_mu, 32);
+            }
+            lr.add(-in_s[2 * kFusedMaxAct]);
+            const float adv = in_s[2 * kFusedMaxAct + 1];
+            const float ratio = expf(lr.value());
+            const float lo = 1.0f - a.clip, hi = 1.0f + a.clip;
+            const bool active = adv >= 0.0f ? (ratio <= hi) : (ratio >= lo);
+            const float g_lp = valid && active ? -a.inv_m * adv * ratio : 0.0f;
+            if (valid && half == 0) {
+                if (a.active_out) a.active_out[m0 + si] = active ? 1 : 0;
+                if (a.ratio_out) a.ratio_out[m0 + si] = ratio;
+            }
+            sums[0] = -fminf(ratio * adv, fminf(fmaxf(ratio, lo), hi) * adv);
+            sums[2] = fabsf(ratio - 1.0f) > a.clip ? 1.0f : 0.0f;
+            sums[3] = (ratio - 1.0f) - logf(ratio);
+            sums[4] = kl_mu;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int j = 8 * (t >> 2) + 4 * half + (t & 3);
+                g8[t] = g_lp * z[t] * inv_sig[t];
+                sums[5 + j] = g_lp * (z[t] * z[t] - 1.0f);
+            }
+        } else {
+            // the value is output 0: lane half 0, first accumulator
+            const float V = __shfl(o[0], lane & 31);
+            const float ret = in_s[2 * kFusedMaxAct + 2], v_old = in_s[2 * kFusedMaxAct + 3];
+            const float diff = V - ret;
+            float pass = 1.0f, vl = diff * diff;
+            if (a.clip_value) {
+                const float vc = v_old + fminf(fmaxf(V - v_old, -a.clip), a.clip);
+                const float sqc = (vc - ret) * (vc - ret);
+                pass = vl >= sqc ? 1.0f : 0.0f;
+                vl = fmaxf(vl, sqc);
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) g8[t] = 0.0f;
+            if (half == 0) g8[0] = valid ? 2.0f * a.value_coef * a.inv_m * diff * pass : 0.0f;
+            sums[1] = vl;
+        }
+        if (valid) {
+            // output-layer gradient row [kHeadPad] in bf16: this lane's 8 of 16
+            uint16_t *row = N.dzh + static_cast<long long>(m0 + si) * kHeadPad;
+            *reinterpret_cast<u32x2 *>(row + 4 * half) = u32x2{pack2(g8[0], g8[1]), pack2(g8[2], g8[3])};
+            *reinterpret_cast<u32x2 *>(row + 8 + 4 * half) = u32x2{pack2(g8[4], g8[5]), pack2(g8[6], g8[7])};
+        }
+        // per-sample loss terms (lane half 0: the scalars; both: their log-std terms)
+        float *ss = s_sum + si * kSums;
+        if (half == 0)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) ss[q] = sums[q];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int j = 8 * (t >> 2) + 4 * half + (t & 3);
+            ss[5 + j] = sums[5 + j];
+            s_g[si * kFusedMaxAct + j] = g8[t];
+        }
+    }
+    __syncthreads();
+    // ---- gradient into the last hidden layer, in place over h
+    const int FB = Hl / 32;
+    for (int tile = wave; tile < FB * SB; tile += NW) {
+        const int fb = tile % FB, sb = tile / FB;
+        // B: the output gradients of sample 32 sb + l % 32, outputs 8 half .. + 7
+        float gb[8], wa[8];
+        const float *gs = s_g + (32 * sb + (lane & 31)) * kFusedMaxAct + 8 * half;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) gb[e] = gs[e];
+        // A: W_out^T rows = features 32 fb + l % 32, k = outputs 8 half .. + 7
+        const float *wc = w_out + 32 * fb + (lane & 31);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) wa[e] = wc[(8 * half + e) * WP];
+        u32x4 bh, bl, ah, al;
+        split2(gb, bh, bl);
+        split2(wa, ah, al);
+        floatx16 acc[1][1];
+        acc[0][0] = floatx16{};
+        acc[0][0] = mfma16(al, bh, acc[0][0]);
+        acc[0][0] = mfma16(ah, bl, acc[0][0]);
+        acc[0][0] = mfma16(ah, bh, acc[0][0]);
+        epi_backward<1, 1>(acc, 32 * fb, sb, hl, PL, lane);
+    }
+}
+
 // R samples per workgroup of NT threads; WPE waves per SIMD (the NT / 256
 // waves of one workgroup times the workgroups that share a CU).
+//
+// LDS: one activation region shared by all layers (offsets from
+// fused_update_layout) plus the loss inputs, the hidden biases and the row
+// indices.  A hidden layer's output stays in the accumulators until every
+// wave has read the layer's input, then overwrites it; only the last hidden
+// layer's output goes elsewhere (it is the input of the head).  The
+// backward pass multiplies by ELU' of activations the forward pass already
+// copied to global memory (they are weight-gradient operands): each is
+// staged back into the region next to the incoming gradient, and the
+// gradient of the first hidden layer, which nothing else consumes, is
+// computed a feature chunk at a time and copied out.  The region then needs
+// room for about one wide layer rather than all of them, which lets 64
+// samples (or 32 of a 1024-wide network) share a CU two workgroups at a time.
 template <int R, int NT, int WPE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void fused_update_kernel(const FusedArgs a) {
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    constexpr int KP = NT / R;  // lanes per sample in the output layer
-    const int net = blockIdx.x & 1;
-    const int m0 = (blockIdx.x >> 1) * R;
+    int net, sblk;
+    if (!net_block(static_cast<int>(blockIdx.x), a.blocks, net, sblk)) return;
+    const int m0 = sblk * R;
     const int rows = min(R, a.M - m0);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int L = a.L, A = a.A;
     const int Hl = a.H[L - 1];
     const int n_out = net == 0 ? A : 1;
     const int WP = Hl + 4;                 // row pitch of the staged output-layer weights
-    float *w_out = reinterpret_cast<float *>(lds + a.lds_w);
-    float *s_sum = reinterpret_cast<float *>(lds + a.lds_sum);    // [R][kSums] per-sample loss terms
+    char *reg = lds;                       // the shared activation region at offset 0
     float *s_in = reinterpret_cast<float *>(lds + a.lds_in);      // [R][kInW] per-sample loss inputs
     float *s_bias = reinterpret_cast<float *>(lds + a.lds_bias);  // hidden-layer biases
     int *s_rows = reinterpret_cast<int *>(lds + a.lds_rows);      // [R] batch rows of the block
+    float *s_head = reinterpret_cast<float *>(lds + a.lds_head);  // output biases [n_out], log-std [A]
     const FusedNet &N = a.net[net];
 
     // ------------------------------------------------------- prologue
     // batch rows of the block (rows past the end repeat the last one; their
-    // results are discarded), then every global input of the block in one
-    // round of loads: observations, loss inputs, output-layer weights and
-    // hidden biases
+    // results are discarded), then the hidden biases, output bias and log-std
+    // in one round of buffer loads, then the observations and loss inputs
     if (tid < R) {
         int r = m0 + min(tid, rows - 1);
         if (a.idx) r = min(max(a.idx[r], 0), a.B - 1);
         s_rows[tid] = r;
     }
-    float *s_head = reinterpret_cast<float *>(lds + a.lds_head);  // output biases [n_out], log-std [A]
     {
-        // every float input of the block in one round of buffer loads (out of
-        // range ones read zero), then the LDS stores: output-layer weights
-        // (pitch WP), output biases, log-std, hidden-layer biases
-        constexpr int UW = 16, UB = 4;
-        const int nw = n_out * Hl;
-        const __amdgpu_buffer_rsrc_t rw = make_rsrc(N.Wout, static_cast<long long>(nw) * 4);
-        float vw[UW], vb[kMaxHidden][UB];
-#pragma unroll
-        for (int u = 0; u < UW; ++u) {
-            const int q = tid + u * NT;
-            vw[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, q < nw ? q * 4 : kOutside, 0, 0));
-        }
+        constexpr int UB = 4;
+        float vb[kMaxHidden][UB];
 #pragma unroll
         for (int l = 0; l < kMaxHidden; ++l) {
             const int H = l < L ? a.H[l] : 0;
@@ -609,12 +844,6 @@ void fused_update_kernel(const FusedArgs a) {
         const float vo = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ro, tid < n_out ? tid * 4 : kOutside, 0, 0));
         const float vl = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rl, tid < A ? tid * 4 : kOutside, 0, 0));
 #pragma unroll
-        for (int u = 0; u < UW; ++u) {
-            const int q = tid + u * NT;
-            const int j = q / Hl;
-            if (q < nw) w_out[j * WP + (q - j * Hl)] = vw[u];
-        }
-#pragma unroll
         for (int l = 0; l < kMaxHidden; ++l) {
             if (l >= L) continue;
 #pragma unroll
@@ -627,20 +856,9 @@ void fused_update_kernel(const FusedArgs a) {
             s_head[tid] = tid < n_out ? vo : 0.0f;
             s_head[kFusedMaxAct + tid] = tid < A ? vl : 0.0f;
         }
-        // zero rows of the output-layer weights past n_out (read by the
-        // actor's kFusedMaxAct-wide head)
-        for (int q = nw + tid; q < kFusedMaxAct * Hl; q += NT) {
-            const int j = q / Hl;
-            w_out[j * WP + (q - j * Hl)] = 0.0f;
-        }
-        // output layers wider than UW loads per thread (not the paper's shapes)
-        for (int q = tid + UW * NT; q < nw; q += NT) {
-            const int j = q / Hl;
-            w_out[j * WP + (q - j * Hl)] = N.Wout[q];
-        }
     }
     __syncthreads();
-    uint16_t *x = reinterpret_cast<uint16_t *>(lds + a.lds_x);
+    uint16_t *x = reinterpret_cast<uint16_t *>(reg);
     const int xp = a.kpad + 8;
     {
         // loss inputs: TPS threads per sample, columns part, part + TPS, ...
@@ -669,51 +887,89 @@ void fused_update_kernel(const FusedArgs a) {
     __syncthreads();
 
     // --------------------------------------------------------- forward
-    // each layer's output goes to global memory while the next layer's first
-    // weight fragments are in flight (the gathered inputs during the first)
-    const uint16_t *in = x;
-    int in_pitch = xp, K = a.kpad;
-    for (int l = 0; l < L; ++l) {
-        const int H = a.H[l];
-        uint16_t *out = reinterpret_cast<uint16_t *>(lds + a.lds_region[l]);
-        const int Hp = l > 0 ? a.H[l - 1] : 0;
-        auto hook = [&]() {
-            if (l == 0) {
-                if (net == 0) copy_out<NT>(x, xp, a.xg + static_cast<long long>(m0) * a.kpad, a.kpad, a.kpad, rows);
-            } else {
-                copy_out<NT>(in, Hp + 8, N.h[l - 1] + static_cast<long long>(m0) * Hp, Hp, Hp, rows);
-            }
-        };
-        // the critic's weights come in the split layout (hi and lo fragments)
-        if (net == 1)
-            run_layer<R, NT, WPE, false, 2>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave,
-                                            lane, hook);
-        else
-            run_layer<R, NT, WPE, false, 1>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8, wave,
-                                            lane, hook);
-        __syncthreads();
-        in = out;
-        in_pitch = H + 8;
-        K = H;
+    // hidden layers 0 .. L-2 write their output over their input (at the
+    // region's start) once every wave has read it; the last goes to
+    // lds_last.  Each layer's input goes to global memory while its first
+    // weight fragments are in flight (the gathered observations: actor only)
+    {
+        const uint16_t *in = x;
+        int in_pitch = xp, K = a.kpad;
+        for (int l = 0; l < L; ++l) {
+            const int H = a.H[l];
+            const bool last = l == L - 1;
+            uint16_t *out = reinterpret_cast<uint16_t *>(reg + (last ? a.lds_last : 0));
+            const int Hp = l > 0 ? a.H[l - 1] : 0;
+            auto hook = [&]() {
+                if (l == 0) {
+                    if (net == 0)
+                        copy_out<NT>(x, xp, a.xg + static_cast<long long>(m0) * a.kpad, a.kpad, a.kpad, rows);
+                } else {
+                    copy_out<NT>(in, Hp + 8, N.h[l - 1] + static_cast<long long>(m0) * Hp, Hp, Hp, rows);
+                }
+            };
+            // the critic's weights come in the split layout (bf16 and residual fragments)
+            if (net == 1)
+                run_layer<R, NT, WPE, false, 2>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8,
+                                                wave, lane, hook, !last);
+            else
+                run_layer<R, NT, WPE, false, 1>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8,
+                                                wave, lane, hook, !last);
+            __syncthreads();
+            in = out;
+            in_pitch = H + 8;
+            K = H;
+        }
     }
-    copy_out<NT>(in, in_pitch, N.h[L - 1] + static_cast<long long>(m0) * Hl, Hl, Hl, rows);
+    uint16_t *hl = reinterpret_cast<uint16_t *>(reg + a.lds_last);
+    const int PL = Hl + 8;
+    // the last hidden layer to global memory; the output-layer weights into
+    // the region's start (free once the last layer has read its input)
+    float *w_out = reinterpret_cast<float *>(reg + a.lds_w);
+    float *s_sum = reinterpret_cast<float *>(reg + a.lds_sum);   // [R][kSums] per-sample loss terms
+    {
+        constexpr int UW = 16;
+        const int nw = n_out * Hl;
+        const __amdgpu_buffer_rsrc_t rw = make_rsrc(N.Wout, static_cast<long long>(nw) * 4);
+        float vw[UW];
+#pragma unroll
+        for (int u = 0; u < UW; ++u) {
+            const int q = tid + u * NT;
+            vw[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, q < nw ? q * 4 : kOutside, 0, 0));
+        }
+        copy_out<NT>(hl, PL, N.h[L - 1] + static_cast<long long>(m0) * Hl, Hl, Hl, rows);
+#pragma unroll
+        for (int u = 0; u < UW; ++u) {
+            const int q = tid + u * NT;
+            const int j = q / Hl;
+            if (q < nw) w_out[j * WP + (q - j * Hl)] = vw[u];
+        }
+        // zero rows of the output-layer weights past n_out (read by the
+        // actor's kFusedMaxAct-wide head)
+        for (int q = nw + tid; q < kFusedMaxAct * Hl; q += NT) {
+            const int j = q / Hl;
+            w_out[j * WP + (q - j * Hl)] = 0.0f;
+        }
+        // output layers wider than UW loads per thread (not the paper's shapes)
+        for (int q = tid + UW * NT; q < nw; q += NT) {
+            const int j = q / Hl;
+            w_out[j * WP + (q - j * Hl)] = N.Wout[q];
+        }
+    }
+    __syncthreads();
 
     // ----------------------------------------- output layer and PPO loss
-    uint16_t *hl = reinterpret_cast<uint16_t *>(lds + a.lds_region[L - 1]);
-    const int PL = Hl + 8;
-    switch ((Hl / KP) / 8) {
-    case 2:
-        if (net == 0) head_pass<R, NT, 2, true>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
-        else head_pass<R, NT, 2, false>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
-        break;
-    case 4:
-        if (net == 0) head_pass<R, NT, 4, true>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
-        else head_pass<R, NT, 4, false>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
-        break;
-    default:
-        if (net == 0) head_pass<R, NT, 8, true>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
-        else head_pass<R, NT, 8, false>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows);
-        break;
+    float *s_g = reinterpret_cast<float *>(reg + a.lds_g);       // [R][kFusedMaxAct] output gradients
+    // the actor's 12-16 outputs on MFMA; the critic's single output on VALU
+    // dot products (KP lanes per sample), which is the shorter of the two
+    constexpr int KP = NT / R;
+    if (net == 0) {
+        head_mfma<R, NT, true>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, s_g, m0, rows, wave, lane);
+    } else {
+        switch ((Hl / KP) / 8) {
+        case 2: head_pass<R, NT, 2, false>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows); break;
+        case 4: head_pass<R, NT, 4, false>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows); break;
+        default: head_pass<R, NT, 8, false>(a, N, hl, PL, w_out, WP, s_head, s_in, s_sum, m0, rows); break;
+        }
     }
     __syncthreads();
     // block sums over the samples in order, one thread per term
@@ -758,22 +1014,41 @@ void fused_update_kernel(const FusedArgs a) {
             out[1] = t[1];
         }
     }
+    // the block sums were read by thread 0 before the staging below reuses
+    // their place
+    __syncthreads();
+
     // ------------------------------------------------ input-gradient chain
-    // the gradient a layer reads goes to global memory while that layer's
-    // first weight fragments are in flight
+    // layer l multiplies dz_l (at lds_bdz[l]) by W_l and by ELU' of h_{l-1},
+    // which is staged back from global memory at lds_bst[l] and overwritten
+    // in place by dz_{l-1}; dz_l goes to global memory while the layer's first
+    // weight fragments are in flight.  The first hidden layer's gradient is
+    // computed `chunk` features at a time and copied out.
     for (int l = L - 1; l >= 1; --l) {
         const int Hin = a.H[l], Hout = a.H[l - 1];
-        const uint16_t *dz = reinterpret_cast<const uint16_t *>(lds + a.lds_region[l]);
-        uint16_t *hz = reinterpret_cast<uint16_t *>(lds + a.lds_region[l - 1]);
-        auto hook = [&]() {
-            copy_out<NT>(dz, Hin + 8, N.dz[l] + static_cast<long long>(m0) * Hin, Hin, Hin, rows);
-        };
-        run_layer<R, NT, WPE, true, 1>(N.WT[l], Hin, Hout, nullptr, dz, Hin + 8, hz, Hout + 8, wave, lane, hook);
-        __syncthreads();
+        const uint16_t *dz = reinterpret_cast<const uint16_t *>(reg + a.lds_bdz[l]);
+        uint16_t *st = reinterpret_cast<uint16_t *>(reg + a.lds_bst[l]);
+        const int C = l == 1 ? a.chunk : Hout;
+        const int S = Hin / 16;
+        for (int c0 = 0; c0 < Hout; c0 += C) {
+            copy_in<NT>(N.h[l - 1] + static_cast<long long>(m0) * Hout + c0, Hout, st, C + 8, C, rows, R);
+            __syncthreads();
+            auto hook = [&]() {
+                if (c0 == 0) copy_out<NT>(dz, Hin + 8, N.dz[l] + static_cast<long long>(m0) * Hin, Hin, Hin, rows);
+            };
+            run_layer<R, NT, WPE, true, 1>(N.WT[l] + static_cast<long long>(c0 / 32) * S * 512, Hin, C, nullptr,
+                                           dz, Hin + 8, st, C + 8, wave, lane, hook);
+            __syncthreads();
+            if (l == 1) {
+                copy_out<NT>(st, C + 8, N.dz[0] + static_cast<long long>(m0) * Hout + c0, Hout, C, rows);
+                __syncthreads();
+            }
+        }
     }
-    const int H0 = a.H[0];
-    copy_out<NT>(reinterpret_cast<const uint16_t *>(lds + a.lds_region[0]), H0 + 8,
-                 N.dz[0] + static_cast<long long>(m0) * H0, H0, H0, rows);
+    if (L == 1) {
+        // one hidden layer: its gradient is the head's output, in place over h_0
+        copy_out<NT>(hl, PL, N.dz[0] + static_cast<long long>(m0) * Hl, Hl, Hl, rows);
+    }
 }
 
 // Weights in MFMA A-fragment order.  For a matrix with `rows` output
@@ -845,8 +1120,9 @@ void fused_infer_kernel(const FusedArgs a) {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     constexpr int KP = NT / R;
     const bool both = a.net_mask == 3;
-    const int net = both ? static_cast<int>(blockIdx.x & 1) : (a.net_mask == 1 ? 0 : 1);
-    const int m0 = static_cast<int>(both ? blockIdx.x >> 1 : blockIdx.x) * R;
+    int net = a.net_mask == 1 ? 0 : 1, sblk = static_cast<int>(blockIdx.x);
+    if (both && !net_block(static_cast<int>(blockIdx.x), a.blocks, net, sblk)) return;
+    const int m0 = sblk * R;
     const int rows = min(R, a.M - m0);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int L = a.L, A = a.A;
@@ -1005,6 +1281,9 @@ void fused_infer_kernel(const FusedArgs a) {
 
 size_t align16(size_t v) { return (v + 15) & ~static_cast<size_t>(15); }
 
+// Grid size for both networks over `blocks` sample blocks (see net_block).
+int two_net_grid(int blocks) { return 2 * ((blocks + 7) / 8) * 8; }
+
 // LDS layout for R rows; returns the total bytes (0 if a constraint fails).
 size_t fused_layout(int L, const int *H, int kpad, int A, int R, int NT, FusedArgs *a) {
     const int KP = NT / R;
@@ -1073,9 +1352,107 @@ bool fused_fits(int L, const int *H, int kpad, int A, int R, int NT, bool two_pe
     return bytes > 0 && bytes <= static_cast<size_t>(two_per_cu ? kMaxLdsBytes / 2 : kMaxLdsBytes);
 }
 
+// Whether `width` output features split over the waves as run_layer does.
+bool width_splits(int width, int NW, int SB, bool wide_ok) {
+    if (width <= 0 || width % 32 != 0) return false;
+    const int fb = width / 32;
+    if (fb >= NW) {
+        const int fbw = fb / NW;
+        return fb % NW == 0 && (fbw == 1 || fbw == 2 || fbw == 4 || (fbw == 8 && wide_ok));
+    }
+    return SB >= 2 && 2 * fb == NW;
+}
+
+// LDS plan of the update pass for R rows (see fused_update_kernel) within
+// `budget` bytes: the shared activation region (the gathered inputs and each
+// hidden layer's output at its start, the last hidden layer's output after
+// its input, the output-layer weights and loss terms wherever they fit during
+// the head, and per backward layer the incoming gradient next to the staged
+// activation), then the loss inputs, hidden biases, row indices and head
+// constants.  The first hidden layer's gradient is computed in the widest
+// feature chunk that fits.  Returns the total bytes, 0 if nothing fits.
+size_t fused_update_layout(int L, const int *H, int kpad, int A, int R, int NT, size_t budget, FusedArgs *a) {
+    (void)A;
+    const int Hl = H[L - 1];
+    const int NW = NT / 64, SB = R / 32;
+    // the critic's output layer: KP = NT / R lanes per sample, 16 to 64 activations each
+    const int KP = NT / R;
+    if (Hl % KP != 0 || (Hl / KP != 16 && Hl / KP != 32 && Hl / KP != 64)) return 0;
+    const bool wide_ok = SB == 1 && NT == 256 && budget >= static_cast<size_t>(kMaxLdsBytes);
+    for (int l = 0; l < L; ++l)
+        if (!width_splits(H[l], NW, SB, wide_ok)) return 0;
+    auto P = [&](int w) { return align16(static_cast<size_t>(R) * (w + 8) * 2); };
+    size_t fixed = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = fixed;
+        fixed += align16(bytes);
+        return at;
+    };
+    const size_t in_off = take(static_cast<size_t>(R) * kInW * 4);
+    int bias_off[kMaxHidden] = {0};
+    size_t nb = 0;
+    for (int l = 0; l < L; ++l) {
+        bias_off[l] = static_cast<int>(nb);
+        nb += (H[l] + 3) & ~3;
+    }
+    const size_t bias = take(nb * 4);
+    const size_t rows_off = take(static_cast<size_t>(R) * 4);
+    const size_t head = take(static_cast<size_t>(2 * kFusedMaxAct) * 4);
+    const int H0 = H[0];
+    for (int C = H0; C >= 32; C /= 2) {
+        if (H0 % C != 0 || (L >= 2 && !width_splits(C, NW, SB, wide_ok))) continue;
+        size_t ext = P(kpad);
+        for (int l = 0; l + 1 < L; ++l) ext = std::max(ext, P(H[l]));
+        const size_t last = L >= 2 ? P(H[L - 2]) : P(kpad);
+        ext = std::max(ext, last + P(Hl));
+        const size_t wb = align16(static_cast<size_t>(kFusedMaxAct) * (Hl + 4) * 4);
+        const size_t sb = align16(static_cast<size_t>(R + 1) * kSums * 4);
+        const size_t gb = align16(static_cast<size_t>(R) * kFusedMaxAct * 4);
+        size_t w_off = 0, s_off = wb, g_off = wb + sb;
+        if (wb + sb + gb > last) {
+            w_off = last + P(Hl);
+            s_off = w_off + wb;
+            g_off = s_off + sb;
+            ext = std::max(ext, g_off + gb);
+        }
+        size_t bdz[kMaxHidden] = {0}, bst[kMaxHidden] = {0};
+        size_t cur = last;
+        for (int l = L - 1; l >= 1; --l) {
+            const int Cl = l == 1 ? C : H[l - 1];
+            const size_t dz_size = P(H[l]), st_size = P(Cl);
+            const size_t st = cur >= st_size ? 0 : cur + dz_size;
+            ext = std::max(ext, st + st_size);
+            bdz[l] = cur;
+            bst[l] = st;
+            cur = st;
+        }
+        ext = align16(ext);
+        const size_t total = ext + fixed;
+        if (total > budget) continue;
+        if (a) {
+            a->lds_in = static_cast<int>(ext + in_off);
+            a->lds_bias = static_cast<int>(ext + bias);
+            a->lds_rows = static_cast<int>(ext + rows_off);
+            a->lds_head = static_cast<int>(ext + head);
+            a->lds_last = static_cast<int>(last);
+            a->lds_w = static_cast<int>(w_off);
+            a->lds_sum = static_cast<int>(s_off);
+            a->lds_g = static_cast<int>(g_off);
+            a->chunk = C;
+            for (int l = 0; l < L; ++l) {
+                a->bias_off[l] = bias_off[l];
+                a->lds_bdz[l] = static_cast<int>(bdz[l]);
+                a->lds_bst[l] = static_cast<int>(bst[l]);
+            }
+        }
+        return total;
+    }
+    return 0;
+}
+
 }  // namespace
 
-FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows, int prefer_threads) {
+FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows, int prefer_threads, bool update) {
     FusedShape none{0, 0, 0};
     if (L < 1 || L > kMaxHidden || A < 1 || A > kFusedMaxAct || kpad < 16 || kpad % 16 != 0) return none;
     // candidates in order of preference: 32 rows x 4 waves with two
@@ -1085,6 +1462,24 @@ FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows, in
     // workgroup of 32 rows per CU (wider networks, e.g. [1024, 512, 256]) or of
     // 4 waves lose to the layer-by-layer GEMMs, which those widths keep busy;
     // they run only when asked for by rows and threads.
+    if (update) {
+        // the update pass's LDS plan holds about one wide layer: 64 samples x
+        // 4 waves with two workgroups per CU first (each weight fragment feeds
+        // two MFMAs, and one workgroup's prologue, head and barriers overlap
+        // the other's MFMA phases), then 32 samples x 4 waves two per CU (the
+        // 1024-wide network); one workgroup of 8 waves per CU only when asked
+        const FusedShape cand[4] = {{64, 256, 2}, {32, 256, 2}, {64, 512, 1}, {32, 512, 1}};
+        const bool asked = prefer_rows && prefer_threads;
+        for (int i = 0; i < 4; ++i) {
+            const FusedShape &c = cand[i];
+            if (i >= 2 && !asked) break;
+            if (prefer_rows && c.rows != prefer_rows) continue;
+            if (prefer_threads && c.threads != prefer_threads) continue;
+            const size_t budget = kMaxLdsBytes / c.per_cu;
+            if (fused_update_layout(L, H, kpad, A, c.rows, c.threads, budget, nullptr) > 0) return c;
+        }
+        return none;
+    }
     const FusedShape cand[4] = {{32, 256, 2}, {64, 512, 1}, {32, 512, 1}, {64, 256, 1}};
     const bool asked = prefer_rows && prefer_threads;
     for (int i = 0; i < 4; ++i) {
@@ -1130,7 +1525,7 @@ hipError_t launch_fused_infer(FusedArgs a, hipStream_t s) {
         }
         attr_set = true;
     }
-    const dim3 grid((a.net_mask == 3 ? 2 : 1) * a.blocks), block(sh.threads);
+    const dim3 grid(a.net_mask == 3 ? two_net_grid(a.blocks) : a.blocks), block(sh.threads);
     if (sh.rows == 64 && sh.threads == 512)
         hipLaunchKernelGGL((fused_infer_kernel<64, 512, 2>), grid, block, bytes, s, a);
     else if (sh.rows == 32 && sh.threads == 256)
@@ -1143,32 +1538,33 @@ hipError_t launch_fused_infer(FusedArgs a, hipStream_t s) {
 }
 
 hipError_t launch_fused_update(FusedArgs a, hipStream_t s) {
-    const FusedShape sh = fused_shape(a.L, a.H, a.kpad, a.A, a.R, a.NT);
+    const FusedShape sh = fused_shape(a.L, a.H, a.kpad, a.A, a.R, a.NT, true);
     if (sh.rows == 0 || a.M < 1) return hipErrorInvalidValue;
-    const size_t bytes = fused_layout(a.L, a.H, a.kpad, a.A, sh.rows, sh.threads, &a);
+    const size_t budget = kMaxLdsBytes / sh.per_cu;
+    const size_t bytes = fused_update_layout(a.L, a.H, a.kpad, a.A, sh.rows, sh.threads, budget, &a);
     if (bytes == 0) return hipErrorInvalidValue;
     a.blocks = fused_blocks(a.M, sh.rows);
     static bool attr_set = false;
     if (!attr_set) {
-        const void *fns[4] = {reinterpret_cast<const void *>(&fused_update_kernel<64, 512, 2>),
+        const void *fns[4] = {reinterpret_cast<const void *>(&fused_update_kernel<64, 256, 2>),
                               reinterpret_cast<const void *>(&fused_update_kernel<32, 256, 2>),
-                              reinterpret_cast<const void *>(&fused_update_kernel<32, 512, 2>),
-                              reinterpret_cast<const void *>(&fused_update_kernel<64, 256, 1>)};
+                              reinterpret_cast<const void *>(&fused_update_kernel<64, 512, 2>),
+                              reinterpret_cast<const void *>(&fused_update_kernel<32, 512, 2>)};
         for (const void *fn : fns) {
             const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
             if (e != hipSuccess) return e;
         }
         attr_set = true;
     }
-    const dim3 grid(2 * a.blocks), block(sh.threads);
-    if (sh.rows == 64 && sh.threads == 512)
-        hipLaunchKernelGGL((fused_update_kernel<64, 512, 2>), grid, block, bytes, s, a);
+    const dim3 grid(two_net_grid(a.blocks)), block(sh.threads);
+    if (sh.rows == 64 && sh.threads == 256)
+        hipLaunchKernelGGL((fused_update_kernel<64, 256, 2>), grid, block, bytes, s, a);
     else if (sh.rows == 32 && sh.threads == 256)
         hipLaunchKernelGGL((fused_update_kernel<32, 256, 2>), grid, block, bytes, s, a);
-    else if (sh.rows == 32)
-        hipLaunchKernelGGL((fused_update_kernel<32, 512, 2>), grid, block, bytes, s, a);
+    else if (sh.rows == 64)
+        hipLaunchKernelGGL((fused_update_kernel<64, 512, 2>), grid, block, bytes, s, a);
     else
-        hipLaunchKernelGGL((fused_update_kernel<64, 256, 1>), grid, block, bytes, s, a);
+        hipLaunchKernelGGL((fused_update_kernel<32, 512, 2>), grid, block, bytes, s, a);
     return hipGetLastError();
 }
 

@@ -987,7 +987,8 @@ FusedShape fused_shape_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &
     const NetLayout &g = c->g;
     const char *rows = std::getenv("PPO_FUSED_ROWS");
     const char *threads = std::getenv("PPO_FUSED_THREADS");
-    FusedShape sh = fused_shape(g.L, g.H, w.kpad, g.A, rows ? std::atoi(rows) : 0, threads ? std::atoi(threads) : 0);
+    FusedShape sh = fused_shape(g.L, g.H, w.kpad, g.A, rows ? std::atoi(rows) : 0, threads ? std::atoi(threads) : 0,
+                                !inference);
     if (sh.rows == 0) return none;
     if (inference && !rows && !threads) {
         // inference of a policy step is latency-bound (a few hundred
@@ -2202,7 +2203,8 @@ int fused_shape_query(const ppo_ctx *c, int32_t *rows, int32_t *threads, bool in
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, 1);
     const char *r = std::getenv("PPO_FUSED_ROWS");
     const char *t = std::getenv("PPO_FUSED_THREADS");
-    FusedShape sh = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, r ? std::atoi(r) : 0, t ? std::atoi(t) : 0);
+    FusedShape sh = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, r ? std::atoi(r) : 0, t ? std::atoi(t) : 0,
+                                !inference);
     if (inference && sh.rows && !r && !t) {
         const FusedShape wide = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, 64, 256);
         if (wide.rows) sh = wide;
