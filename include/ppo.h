@@ -45,15 +45,28 @@
  *     host synchronisation outside ctx create/destroy); the choice is cached
  *     in the context, and in the file named by the environment variable
  *     PPO_TUNE_CACHE if set.  PPO_AUTOTUNE=0 keeps 128 x 128 tiles.
- *   - bf16 update steps of networks whose hidden widths are 128, 256, 512 or
- *     1024 (input width a multiple of 16) run everything that is independent
- *     per sample (gather, hidden layers, output layers with the loss,
- *     input-gradient chain) as one fused launch with the activations in LDS,
- *     then the split-sample weight-gradient GEMMs; other shapes, and the fp32
- *     path, run the layer-by-layer kernels.  The results agree to float32
- *     rounding (bf16 ulps downstream of it).  PPO_FUSED=0 forces the
- *     layer-by-layer kernels; PPO_FUSED_ROWS=32 or 64 overrides the fused
- *     pass's samples per workgroup.
+ *     PPO_GEMM_GRID_CAP=0 launches one workgroup per GEMM tile (by default
+ *     128 x 128-tile launches are persistent: as many workgroups as fit on
+ *     the device at once, each taking every G-th tile).
+ *   - bf16 update steps of networks whose hidden widths split evenly over
+ *     four waves (e.g. [512, 256, 128] or [64, 64]; input width a multiple
+ *     of 16) run everything that is independent per sample (gather, hidden
+ *     layers, output layers with the loss, input-gradient chain) as one fused
+ *     launch with the activations in LDS, then the split-sample
+ *     weight-gradient GEMMs; other shapes (e.g. a 1024-wide layer), and the
+ *     fp32 path, run the layer-by-layer kernels.  The results agree to
+ *     float32 rounding (bf16 ulps downstream of it).  PPO_FUSED=0 forces the
+ *     layer-by-layer kernels; PPO_FUSED_ROWS=32 or 64 (and
+ *     PPO_FUSED_THREADS=256 or 512) override the fused pass's block shape.
+ *   - bf16 precision: GEMM operands are bf16 with float32 accumulation,
+ *     except that the critic's hidden-layer weights enter its forward GEMMs
+ *     as two bf16 terms, bf16(W) and bf16(W - bf16(W)) (about 16 significant
+ *     bits): a common rounding of the weights would shift every sample's
+ *     value the same way, and the value loss's gradient is a mean of
+ *     (V - R) that such a shift biases directly.  Output layers, biases,
+ *     log-std, log-probabilities (float32 with compensated summation) and the
+ *     loss are float32; the advantage statistics and the gradient norm's sum
+ *     of squares are float64.
  */
 #ifndef PPO_MI355X_PPO_H
 #define PPO_MI355X_PPO_H
@@ -291,7 +304,9 @@ int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_
 
 /* Loss and gradient of one mini-batch (rows idx[0..M)) without an optimiser
  * step: writes stats[PPO_STATS_WIDTH] (entry 6 = gradient norm, entry 7 =
- * flags) and grad_out [P] (the raw gradient).  Optional per-row outputs for
+ * flags) and grad_out [P] (the raw gradient).  grad_out == NULL computes the
+ * loss terms only (no backward pass; stats entry 6 is then 0).  Optional
+ * per-row outputs for
  * checkers (NULL = not written): ratio_out [M] float32 (4-byte aligned), the
  * probability ratio rho = pi(a|s) / pi_old(a|s) this call computed, and
  * active_out [M] uint8, 1 if the sample's clipped surrogate passes gradient

@@ -4,7 +4,8 @@ PPOLoss.apply(theta, ...) returns the scalar PPO loss of one mini-batch
 (clipped surrogate + c_v value loss - c_e entropy) for the flat parameter
 vector `theta`; its backward is the library's own gradient (output-layer
 gradients, MFMA input-gradient chain and split-sample weight gradients),
-computed in the same launch sequence as the loss by ppo_loss_grad.  torch
+computed in the same launch sequence as the loss by ppo_loss_grad when theta
+requires a gradient, and skipped otherwise (the loss terms alone).  torch
 never traces the network: it only sees one opaque op of theta.
 """
 from __future__ import annotations
@@ -40,16 +41,21 @@ class PPOLoss(torch.autograd.Function):
             raise TypeError("theta must be a 1-D float32 tensor")
         view = _ParamsView(ctx, theta)
         stats = torch.zeros(_abi.PPO_STATS_WIDTH, dtype=torch.float32, device=theta.device)
-        grad = torch.empty_like(view.theta)
+        # the hand-written backward runs only when a gradient wrt theta will be
+        # asked for; otherwise the library computes the loss terms alone
+        want_grad = fctx.needs_input_grad[0]
+        grad = torch.empty_like(view.theta) if want_grad else None
         b = batch_abi(batch)
         p = view.abi()
         h = hp.abi()
         import ctypes
         check(_abi.load().ppo_loss_grad(ctx.handle, _stream(None), ctypes.byref(p), ctypes.byref(b),
                                         _ptr(idx, torch.int32, "idx"), idx.numel(), ctypes.byref(h),
-                                        _ptr(stats, torch.float32, "stats"), _ptr(grad, torch.float32, "grad"),
+                                        _ptr(stats, torch.float32, "stats"),
+                                        _ptr(grad, torch.float32, "grad", allow_none=True),
                                         None, None, _ptr(ws, torch.uint8, "ws"), ws.numel()))
-        fctx.save_for_backward(grad)
+        if want_grad:
+            fctx.save_for_backward(grad)
         fctx.stats = stats
         return stats[0].clone()
 

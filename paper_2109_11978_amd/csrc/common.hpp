@@ -185,6 +185,7 @@ struct FusedArgs {
     float *ratio_out;                 // [M] or null: the sample's probability ratio
     float clip, value_coef, inv_m;
     int clip_value;
+    int no_backward;                  // loss terms only: skip the input-gradient chain
     // rollout inference (launch_fused_infer): outputs for the M environments
     // of obs (each may be null), Philox key and counter words, networks to run
     float *act_out, *logp_out, *val_out, *mu_out;

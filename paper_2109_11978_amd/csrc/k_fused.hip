@@ -3,14 +3,15 @@
 // Everything in a mini-batch step that is independent per sample runs in
 // one launch: one workgroup takes R samples of one network (actor or critic)
 // through the gather of their observation rows, every hidden layer
-// (z = h W^T + b, h = ELU(z)), the output layer with the PPO loss of Sec. 3
-// and App. A (clipped surrogate, value loss, log-std gradient, KL statistic),
-// and the input-gradient chain dz_{l-1} = (dz_l W_l) * ELU'(z_{l-1}) back to
-// the first hidden layer.  The activations of all layers stay in LDS for the
-// whole pass; what leaves the chip is only what the split-sample weight
-// gradients read (gathered inputs, hidden activations, pre-activation and
-// output gradients), in the layouts of the layer-by-layer path, each written
-// once with coalesced 16-byte stores.
+// (z = h W^T + b, h = ELU(z)), the output layer with the PPO loss of Section
+// 2.2 and Appendix A.4, Table 3 (clipped surrogate, value loss, entropy
+// bonus through the log-std gradient, KL statistic), and the input-gradient
+// chain dz_{l-1} = (dz_l W_l) * ELU'(z_{l-1}) back to the first hidden layer.
+// The activations live in LDS while they are used (fused_update_kernel
+// shares one region between the layers); what leaves the chip is what the
+// split-sample weight gradients read (gathered inputs, hidden activations,
+// pre-activation and output gradients), in the layouts of the layer-by-layer
+// path, each written once with coalesced 16-byte stores.
 //
 // MFMA layout: every layer is computed transposed, C[feature][sample] =
 // W[feature, :] . act[sample, :], with v_mfma_f32_32x32x16_bf16.  The weights
@@ -1014,6 +1015,7 @@ void fused_update_kernel(const FusedArgs a) {
             out[1] = t[1];
         }
     }
+    if (a.no_backward) return;
     // the block sums were read by thread 0 before the staging below reuses
     // their place
     __syncthreads();

@@ -651,7 +651,7 @@ __global__ __launch_bounds__(kReduceThreads) void grad_reduce_kernel(const Reduc
             total[threadIdx.x] = v;
             if (threadIdx.x < 4) {
                 a.loss_sums[threadIdx.x] = v;
-            } else if (threadIdx.x < 4 + a.A) {
+            } else if (threadIdx.x < 4 + a.A && a.grad) {
                 const float g = v - a.entropy_coef;
                 a.grad[a.logstd_offset + threadIdx.x - 4] = g;
                 ss = static_cast<double>(g) * g;

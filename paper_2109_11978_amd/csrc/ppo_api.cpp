@@ -880,6 +880,7 @@ struct StepBuffers {
     bool frags_ready = false;   // the fused pass's fragments already hold the current shadow
     bool write_frags = false;   // Adam refreshes them for the next step
     uint8_t *active_out = nullptr;  // per-sample surrogate branch (ppo_loss_grad only)
+    bool loss_only = false;         // ppo_loss_grad without a gradient output
     float *ratio_out = nullptr;     // per-sample probability ratio (ppo_loss_grad only)
 };
 
@@ -1124,6 +1125,7 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
         if (!sb.frags_ready) PROFILED(prof, PPO_PHASE_GATHER, launch_pack_frags(build_frags(c, p, w, ws), s));
         FusedArgs fa = fused_args(c, p, hp, w, ws, sb.b, sb.idx, M);
         fa.active_out = sb.active_out;
+        fa.no_backward = sb.loss_only ? 1 : 0;
         fa.ratio_out = sb.ratio_out;
         fa.R = fsh.rows;
         fa.NT = fsh.threads;
@@ -1140,15 +1142,18 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
         hl.ratio_out = sb.ratio_out;
         PROFILED(prof, PPO_PHASE_HEAD_LOSS, launch_head_loss(prec, hl, s));
 
-        for (int l = L - 1; l >= 1; --l) {
+        for (int l = L - 1; l >= 1 && !sb.loss_only; --l) {
             const GemmArgs args = build_dx(c, p, w, ws, M, l, t.site[kSiteDx + l].tile);
             PROFILED(prof, PPO_PHASE_INPUT_GRAD, launch_gemm(prec, 0, 0, kEpiDElu, args, s));
         }
     }
 
-    DwPlan d = build_dw(c, w, ws, M, t.site[kSiteDw]);
-    for (int i = 0; i < d.n_launch; ++i)
-        PROFILED(prof, PPO_PHASE_WEIGHT_GRAD, launch_gemm(prec, 1, 1, kEpiPartial, d.launch[i], s));
+    DwPlan d{};
+    if (!sb.loss_only) {
+        d = build_dw(c, w, ws, M, t.site[kSiteDw]);
+        for (int i = 0; i < d.n_launch; ++i)
+            PROFILED(prof, PPO_PHASE_WEIGHT_GRAD, launch_gemm(prec, 1, 1, kEpiPartial, d.launch[i], s));
+    }
 
     ReduceArgs &red = d.red;
     set_reduce_loss(red, c, p, hp, w, ws, sb.grad, M, sb.apply, fused_r);
@@ -1517,7 +1522,7 @@ int ppo_loss_grad(const ppo_ctx *c, void *stream, const ppo_params *p, const ppo
     if (M < 1 || M > b->B) return fail(PPO_E_SHAPE, "M = %d outside 1..B", M);
     PPO_CHECK(check_ptr(idx, "idx"));
     PPO_CHECK(check_ptr(stats, "stats"));
-    PPO_CHECK(check_ptr(grad_out, "grad_out"));
+    PPO_CHECK(check_ptr(grad_out, "grad_out", true));
     if (ratio_out && (reinterpret_cast<uintptr_t>(ratio_out) & 3u))
         return fail(PPO_E_INVAL, "ratio_out is not 4-byte aligned");
     PPO_CHECK(validate_ws(c, 0, 0, M, ws, ws_bytes));
@@ -1526,6 +1531,7 @@ int ppo_loss_grad(const ppo_ctx *c, void *stream, const ppo_params *p, const ppo
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
     StepBuffers sb{b, idx, M, grad_out, stats, 0, 0};
     sb.active_out = active_out;
+    sb.loss_only = grad_out == nullptr;
     sb.ratio_out = ratio_out;
     Tuning tune;
     PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, static_cast<hipStream_t>(stream), tune));

@@ -201,16 +201,19 @@ def test_adaptive_rate_validation():
 
 
 @pytest.mark.parametrize("shape,prec,env,expect", [
-    ((48, 12, (512, 256, 128)), "bf16", {}, (32, 256)),
-    ((235, 12, (512, 256, 128)), "bf16", {}, (32, 256)),
-    ((235, 12, (1024, 512, 256)), "bf16", {}, (0, 0)),  # one 32-row workgroup per CU: GEMMs win
+    ((48, 12, (512, 256, 128)), "bf16", {}, (64, 256)),
+    ((235, 12, (512, 256, 128)), "bf16", {}, (64, 256)),
+    # a 1024-wide layer needs eight feature blocks per wave over four waves,
+    # which takes a workgroup's whole register file: the GEMMs run it
+    ((235, 12, (1024, 512, 256)), "bf16", {}, (0, 0)),
     ((235, 12, (1024, 512, 256)), "bf16", {"PPO_FUSED_ROWS": "32", "PPO_FUSED_THREADS": "512"}, (32, 512)),
-    ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "64"}, (64, 512)),
-    ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "64", "PPO_FUSED_THREADS": "256"}, (64, 256)),
+    ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "64"}, (64, 256)),
+    ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "32"}, (32, 256)),
+    ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "64", "PPO_FUSED_THREADS": "512"}, (64, 512)),
     ((235, 12, (1024, 512, 256)), "bf16", {"PPO_FUSED_ROWS": "64"}, (0, 0)),
     ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED": "0"}, (0, 0)),
     ((48, 12, (512, 256, 128)), "fp32", {}, (0, 0)),
-    ((48, 12, (64, 64)), "bf16", {}, (0, 0)),           # only 64 rows x 4 waves fits: not by default
+    ((48, 12, (64, 64)), "bf16", {}, (64, 256)),        # two feature blocks: two waves each over 64 rows
     ((48, 12, (64, 64)), "bf16", {"PPO_FUSED_ROWS": "64", "PPO_FUSED_THREADS": "256"}, (64, 256)),
     ((48, 12, (32, 32)), "bf16", {}, (0, 0)),           # one feature block for four waves
     ((40, 12, (512, 256, 128)), "bf16", {}, (0, 0)),    # input width not a multiple of 16
@@ -275,7 +278,7 @@ def test_fused_infer_shape_selection(monkeypatch):
         monkeypatch.delenv(k, raising=False)
     flat = ppo.Context(48, 12, (512, 256, 128), "bf16")
     assert flat.fused_infer_shape() == (64, 256)
-    assert flat.fused_shape() == (32, 256)
+    assert flat.fused_shape() == (64, 256)
     for H in ((1024, 512, 256), (64, 64)):
         assert ppo.Context(235, 12, H, "bf16").fused_infer_shape() == (0, 0)
     assert ppo.Context(48, 12, (512, 256, 128), "fp32").fused_infer_shape() == (0, 0)

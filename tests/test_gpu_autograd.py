@@ -103,3 +103,43 @@ def test_directional_derivatives_rough_shape(prec):
         dd = (lp - lm) / (2 * eps)
         tol = 1e-4 if prec == "fp32" else 3e-2
         assert abs(g @ u - dd) <= tol * (abs(dd) + 0.1 * np.linalg.norm(g)), (k, g @ u, dd)
+
+
+@pytest.mark.parametrize("prec,name", [("fp32", "tiny"), ("bf16", "flat")])
+def test_loss_without_gradient_skips_the_backward(prec, name):
+    """Without a gradient wanted (no requires_grad, or under no_grad) the loss
+    comes from the loss-only call and equals the loss of the full call; the
+    loss-only call leaves the gradient norm at 0 and writes no gradient."""
+    d = require_gpu()
+    cfg = synth.get_config(name)
+    print(f"[gpu-case] loss only {prec} {name}", flush=True)
+    theta = synth.xavier_theta(cfg.net, seed=5, logstd=-0.2)
+    M = 2048 if name == "flat" else 768
+    batch = teacher_batch(cfg, theta, 2 * M, seed=6, shift="mixed")
+    idx = dev(np.random.default_rng(7).permutation(2 * M)[:M].astype(np.int32), d)
+    tb = {k: dev(v, d) for k, v in batch.items()}
+    ctx = ppo.Context(cfg.net.obs_dim, cfg.net.act_dim, cfg.net.hidden, prec)
+    ws = ctx.new_workspace(M=M)
+    th = torch.tensor(theta, device=d, requires_grad=True)
+    full = ppo.ppo_loss(ctx, th, tb, idx, ws=ws)
+    with torch.no_grad():
+        l1 = ppo.ppo_loss(ctx, th, tb, idx, ws=ws)
+    l2 = ppo.ppo_loss(ctx, th.detach(), tb, idx, ws=ws)
+    assert float(l1) == float(full.detach()) and float(l2) == float(full.detach())
+    params = ppo.Params(ctx, theta, device=d)
+    st_full = torch.zeros(ppo.PPO_STATS_WIDTH, device=d)
+    st_loss = torch.zeros(ppo.PPO_STATS_WIDTH, device=d)
+    grad = torch.zeros(ctx.param_count, device=d)
+    ppo.ppo_loss_grad(ctx, params, tb, idx, ppo.UpdateHParams(), st_full, grad, ws)
+    from paper_2109_11978_amd import _abi
+    from paper_2109_11978_amd.api import _ptr, _stream, batch_abi
+    import ctypes
+    b, p, h = batch_abi(tb), params.abi(), ppo.UpdateHParams().abi()
+    _abi.check(_abi.load().ppo_loss_grad(ctx.handle, _stream(None), ctypes.byref(p), ctypes.byref(b),
+                                         _ptr(idx, torch.int32, "idx"), M, ctypes.byref(h),
+                                         _ptr(st_loss, torch.float32, "stats"), None, None, None,
+                                         _ptr(ws, torch.uint8, "ws"), ws.numel()))
+    torch.cuda.synchronize()
+    a, c = st_full.cpu().numpy(), st_loss.cpu().numpy()
+    np.testing.assert_array_equal(a[[0, 1, 2, 3, 4, 5, 7]], c[[0, 1, 2, 3, 4, 5, 7]])
+    assert a[6] > 0 and c[6] == 0.0
