@@ -1468,13 +1468,15 @@ FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows, in
         // the update pass's LDS plan holds about one wide layer: 64 samples x
         // 4 waves with two workgroups per CU first (each weight fragment feeds
         // two MFMAs, and one workgroup's prologue, head and barriers overlap
-        // the other's MFMA phases), then 32 samples x 4 waves two per CU (the
-        // 1024-wide network); one workgroup of 8 waves per CU only when asked
+        // the other's MFMA phases), then 32 samples x 4 waves two per CU, then
+        // 64 samples x 8 waves alone on a CU (the [1024, 512, 256] network: its
+        // update runs in 0.8x the time of the layer-by-layer GEMMs); 32 samples
+        // x 8 waves alone on a CU loses to those GEMMs and runs only when asked
         const FusedShape cand[4] = {{64, 256, 2}, {32, 256, 2}, {64, 512, 1}, {32, 512, 1}};
         const bool asked = prefer_rows && prefer_threads;
         for (int i = 0; i < 4; ++i) {
             const FusedShape &c = cand[i];
-            if (i >= 2 && !asked) break;
+            if (i >= 3 && !asked) break;
             if (prefer_rows && c.rows != prefer_rows) continue;
             if (prefer_threads && c.threads != prefer_threads) continue;
             const size_t budget = kMaxLdsBytes / c.per_cu;

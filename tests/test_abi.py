@@ -204,13 +204,14 @@ def test_adaptive_rate_validation():
     ((48, 12, (512, 256, 128)), "bf16", {}, (64, 256)),
     ((235, 12, (512, 256, 128)), "bf16", {}, (64, 256)),
     # a 1024-wide layer needs eight feature blocks per wave over four waves,
-    # which takes a workgroup's whole register file: the GEMMs run it
-    ((235, 12, (1024, 512, 256)), "bf16", {}, (0, 0)),
+    # which takes a workgroup's whole register file: 8 waves alone on a CU
+    ((235, 12, (1024, 512, 256)), "bf16", {}, (64, 512)),
     ((235, 12, (1024, 512, 256)), "bf16", {"PPO_FUSED_ROWS": "32", "PPO_FUSED_THREADS": "512"}, (32, 512)),
     ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "64"}, (64, 256)),
     ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "32"}, (32, 256)),
     ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_ROWS": "64", "PPO_FUSED_THREADS": "512"}, (64, 512)),
-    ((235, 12, (1024, 512, 256)), "bf16", {"PPO_FUSED_ROWS": "64"}, (0, 0)),
+    ((235, 12, (1024, 512, 256)), "bf16", {"PPO_FUSED_ROWS": "64"}, (64, 512)),
+    ((235, 12, (1024, 512, 256)), "bf16", {"PPO_FUSED_THREADS": "256"}, (0, 0)),
     ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED": "0"}, (0, 0)),
     ((48, 12, (512, 256, 128)), "fp32", {}, (0, 0)),
     ((48, 12, (64, 64)), "bf16", {}, (64, 256)),        # two feature blocks: two waves each over 64 rows

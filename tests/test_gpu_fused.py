@@ -74,9 +74,9 @@ def _loss_grad(ctx, theta, batch, idx, d, fused, hp=None, shape=None):
     return grad.cpu().numpy(), stats.cpu().numpy()
 
 
-# every block shape the library can launch: (32, 256) and (64, 512) by default,
-# (32, 512) and (64, 256) when asked for
-SHAPES = [("flat", 24576, None), ("flat", 1000, (64, 512)), ("rough", 777, None), ("large", 333, (32, 512)),
+# every block shape the library can launch: (64, 256), (32, 256) and (64, 512)
+# by default, (32, 512) when asked for
+SHAPES = [("flat", 24576, None), ("flat", 1000, (64, 512)), ("rough", 777, None), ("large", 333, None),
           ("flat", 10, (64, 256)), ("large", 31, (32, 512)), ("tiny", 1536, (64, 256)), ("rough", 4096, (64, 512))]
 
 
@@ -123,7 +123,7 @@ def test_fused_is_the_bf16_path_and_deterministic():
     assert ph["fused"][1] == 0 and ph["forward"][1] == K * len(cfg.net.hidden)
 
 
-@pytest.mark.parametrize("name,shape", [("flat", None), ("large", (32, 512))])
+@pytest.mark.parametrize("name,shape", [("flat", None), ("large", None), ("large", (32, 512))])
 def test_fused_epoch_graph_matches_eager_and_layered(name, shape):
     """A four-mini-batch epoch: the captured graph replays the eager launches
     bit for bit, and the gradient the fused epoch takes at its last step (at
