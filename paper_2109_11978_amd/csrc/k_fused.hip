@@ -213,15 +213,23 @@ __device__ __forceinline__ void epi_backward(const floatx16 (&acc)[FBW][SB], int
         }
 }
 
+// Between a layer's MMA loop and its epilogue.  sync_epi 1: an output that
+// overwrites the layer's input waits until every wave has read its input
+// fragments.  2: also until the LDS-direct loads this wave issued (the
+// epilogue's ELU' inputs, staged during the loop) have landed, which the
+// barrier then extends to every wave's.
+__device__ __forceinline__ void epi_sync(int sync_epi) {
+    if (sync_epi == 2) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+    if (sync_epi) __syncthreads();
+}
+
 template <int FBW, int SB, int PF, bool BWD, int SPLIT, class Hook>
 __device__ __forceinline__ void layer_impl(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
                                            int in_pitch, uint16_t *out, int out_pitch, int f0, int sb0, int lane,
-                                           const Hook &hook, bool sync_epi) {
+                                           const Hook &hook, int sync_epi) {
     floatx16 acc[FBW][SB];
     mma_layer<FBW, SB, PF, SPLIT>(acc, W, nout, K >> 4, f0, sb0, in, in_pitch, lane, hook);
-    // an output that overwrites the layer's input waits until every wave has
-    // read its input fragments
-    if (sync_epi) __syncthreads();
+    epi_sync(sync_epi);
     if constexpr (BWD)
         epi_backward<FBW, SB>(acc, f0, sb0, out, out_pitch, lane);
     else
@@ -235,7 +243,7 @@ __device__ __forceinline__ void layer_impl(const uint16_t *W, int K, int nout, c
 template <int FBW, int SB, bool BWD, int PFMAX, int SPLIT, class Hook>
 __device__ __forceinline__ void layer_pf(int S, const uint16_t *W, int K, int nout, const float *bias,
                                          const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
-                                         int sb0, int lane, const Hook &hook, bool sync_epi) {
+                                         int sb0, int lane, const Hook &hook, int sync_epi) {
     const int SW = S * SPLIT;
     if (PFMAX >= 32 && SW >= 32)
         layer_impl<FBW, SB, (PFMAX >= 32 ? 32 : 4), BWD, SPLIT>(W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
@@ -263,7 +271,7 @@ constexpr int pf_max() {
 template <int SBW, bool BWD, bool WIDE, int REGS, int SPLIT, class Hook>
 __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int K, int nout, const float *bias,
                                          const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
-                                         int sb0, int lane, const Hook &hook, bool sync_epi) {
+                                         int sb0, int lane, const Hook &hook, int sync_epi) {
     switch (fbw) {
     case 1:
         layer_pf<1, SBW, BWD, pf_max<1, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
@@ -283,7 +291,7 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
                                                                  f0, sb0, lane, hook, sync_epi);
         else {
             hook();
-            if (sync_epi) __syncthreads();
+            epi_sync(sync_epi);
         }
         break;
     }
@@ -296,7 +304,7 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
 template <int R, int NT, int WPE, bool BWD, int SPLIT = 1, class Hook = NoHook>
 __device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, const float *bias, const uint16_t *in,
                                           int in_pitch, uint16_t *out, int out_pitch, int wave, int lane,
-                                          const Hook &hook = Hook(), bool sync_epi = false) {
+                                          const Hook &hook = Hook(), int sync_epi = 0) {
     constexpr int NW = NT / 64;
     constexpr int SB = R / 32;
     // registers for accumulators and fragments: 512 / WPE per lane, less
@@ -317,7 +325,7 @@ __device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, co
                                                   (wave % fb) * 32, (wave / fb) * (SB / 2), lane, hook, sync_epi);
     } else {
         hook();   // a wave without a feature block still does its share of the hook
-        if (sync_epi) __syncthreads();
+        epi_sync(sync_epi);
     }
 }
 
@@ -450,30 +458,30 @@ __device__ inline bool net_block(int b, int blocks, int &net, int &sblk) {
 }
 
 // rows x cols bf16 from global rows of `ld` elements into LDS (row pitch
-// `pitch`), the inverse of copy_out with the same thread mapping; rows past
-// `rows` are zero.  The source was written earlier in the same launch by this
+// `pitch`; rows past `rows` up to R and the row pads zero), the inverse of
+// copy_out.  The source was written earlier in the same launch by this
 // workgroup's copy_out (visible after the workgroup barriers in between).
+// Each LDS-direct buffer load of a wave fills one
+// contiguous kilobyte of the padded tile, lane i its bytes 16 i .. 16 i + 15,
+// so every lane derives its source row and column from that position.  No
+// registers hold the data, so the loads can be issued ahead of an MMA loop;
+// the tile is complete once every wave has waited for its loads (vmcnt) and
+// the workgroup has synchronised.  pitch and cols are multiples of 8.
 template <int NT>
-__device__ inline void copy_in(const uint16_t *src, int ld, uint16_t *dst, int pitch, int cols, int rows, int R) {
-    constexpr int U = 4;
-    const int cpr = cols >> 3;
-    const int rpp = NT / cpr;
-    const int r0 = threadIdx.x / cpr;
-    const int c = (threadIdx.x - r0 * cpr) * 8;
-    if (r0 >= rpp) return;
+__device__ inline void copy_in_async(const uint16_t *src, int ld, uint16_t *dst, int pitch, int cols, int rows,
+                                     int R, int wave, int lane) {
+    constexpr int NW = NT / 64;
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, static_cast<long long>(rows) * ld * 2);
-    for (int i0 = r0; i0 < R; i0 += U * rpp) {
-        u32x4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * rpp;
-            v[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, i < rows ? (i * ld + c) * 2 : kOutside, 0, 0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * rpp;
-            if (i < R) *reinterpret_cast<u32x4 *>(dst + i * pitch + c) = v[u];
-        }
+    const int row_bytes = pitch * 2;
+    const int total = R * row_bytes;
+    typedef __attribute__((address_space(3))) void lds_void;
+    for (int b = wave; b * 1024 < total; b += NW) {
+        const int o = b * 1024 + lane * 16;
+        const int r = o / row_bytes, cb = o - r * row_bytes;
+        const int voff = r < rows && cb < cols * 2 ? r * ld * 2 + cb : kOutside;
+        if (o < total)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void *)(reinterpret_cast<char *>(dst) + b * 1024), 16,
+                                                     voff, 0, 0, 0);
     }
 }
 
@@ -1022,10 +1030,12 @@ void fused_update_kernel(const FusedArgs a) {
 
     // ------------------------------------------------ input-gradient chain
     // layer l multiplies dz_l (at lds_bdz[l]) by W_l and by ELU' of h_{l-1},
-    // which is staged back from global memory at lds_bst[l] and overwritten
-    // in place by dz_{l-1}; dz_l goes to global memory while the layer's first
-    // weight fragments are in flight.  The first hidden layer's gradient is
-    // computed `chunk` features at a time and copied out.
+    // which is staged back from global memory at lds_bst[l] during the
+    // layer's MMA loop (LDS-direct loads issued while its first weight
+    // fragments are in flight, waited for before the epilogue) and
+    // overwritten in place by dz_{l-1}; dz_l goes to global memory at the same
+    // point.  The first hidden layer's gradient is computed `chunk` features
+    // at a time and copied out.
     for (int l = L - 1; l >= 1; --l) {
         const int Hin = a.H[l], Hout = a.H[l - 1];
         const uint16_t *dz = reinterpret_cast<const uint16_t *>(reg + a.lds_bdz[l]);
@@ -1033,13 +1043,13 @@ void fused_update_kernel(const FusedArgs a) {
         const int C = l == 1 ? a.chunk : Hout;
         const int S = Hin / 16;
         for (int c0 = 0; c0 < Hout; c0 += C) {
-            copy_in<NT>(N.h[l - 1] + static_cast<long long>(m0) * Hout + c0, Hout, st, C + 8, C, rows, R);
-            __syncthreads();
             auto hook = [&]() {
+                copy_in_async<NT>(N.h[l - 1] + static_cast<long long>(m0) * Hout + c0, Hout, st, C + 8, C, rows, R,
+                                  wave, lane);
                 if (c0 == 0) copy_out<NT>(dz, Hin + 8, N.dz[l] + static_cast<long long>(m0) * Hin, Hin, Hin, rows);
             };
             run_layer<R, NT, WPE, true, 1>(N.WT[l] + static_cast<long long>(c0 / 32) * S * 512, Hin, C, nullptr,
-                                           dz, Hin + 8, st, C + 8, wave, lane, hook);
+                                           dz, Hin + 8, st, C + 8, wave, lane, hook, 2);
             __syncthreads();
             if (l == 1) {
                 copy_out<NT>(st, C + 8, N.dz[0] + static_cast<long long>(m0) * Hout + c0, Hout, C, rows);
