@@ -368,7 +368,8 @@ int ppo_gemm_check(void *stream, int32_t precision, int32_t a_mode, int32_t b_mo
 
 /* Tile choices recorded for `rows` GEMM rows (update != 0: the update's
  * sites, else inference).  choices[2 s] = tile shape (as in
- * ppo_gemm_check), choices[2 s + 1] = split rounds, for sites
+ * ppo_gemm_check), choices[2 s + 1] = weight-gradient splits in half rounds
+ * of resident workgroups (1, 2 or 4; 2 elsewhere), for sites
  * s = 0..3 forward layer s, 4..7 input gradient of layer s - 4, 8 weight
  * gradients.  capacity >= 18.  PPO_E_SHAPE if nothing was tuned yet. */
 int ppo_ctx_tuning(const ppo_ctx *ctx, int32_t rows, int32_t update, int32_t *choices, int32_t capacity);

@@ -134,7 +134,7 @@ class Context:
         if update:
             for l in range(1, len(self.hidden)):
                 out[f"input_grad_{l + 1}"] = self.TILE_NAMES[arr[2 * (4 + l)]]
-            out["weight_grad"] = f"{self.TILE_NAMES[arr[16]]} x {arr[17]} round(s) of splits"
+            out["weight_grad"] = f"{self.TILE_NAMES[arr[16]]} x {arr[17]} half round(s) of splits"
         return out
 
     def fused_shape(self) -> Tuple[int, int]:

@@ -185,12 +185,14 @@ int dw_tiles(const NetLayout &g, int tile) {
 // Two workgroups are resident on each of 256 CUs.  A weight-gradient
 // workgroup streams its k-range at a roughly fixed time per k-slab, so a
 // launch takes (rounds of resident workgroups) x (slabs per workgroup):
-// split into `rounds` whole rounds, never a partial extra round.
+// split into `rounds` half rounds (1: one workgroup per CU, 2: one full
+// round, 4: two), never a partial extra one.  Fewer splits write fewer
+// partials for the reduction to read.
 constexpr int kResidentSlots = 512;
 
 void dw_splits(const NetLayout &g, Precision prec, int M, int tile, int rounds, int &splits, int &kps) {
     const int bk = gemm_bk(prec);
-    int s = std::max(1, rounds * kResidentSlots / dw_tiles(g, tile));
+    int s = std::max(1, rounds * (kResidentSlots / 2) / dw_tiles(g, tile));
     s = std::min(s, std::max(1, M / (2 * bk)));
     kps = cdiv(cdiv(M, s), bk) * bk;
     splits = cdiv(M, kps);
@@ -200,7 +202,7 @@ void dw_splits(const NetLayout &g, Precision prec, int M, int tile, int rounds, 
 int dw_max_splits(const NetLayout &g, Precision prec, int M) {
     int best = 1;
     for (int t = 0; t < kNumTileShapes; ++t)
-        for (int rounds = 1; rounds <= 2; ++rounds) {
+        for (int rounds : {1, 2, 4}) {
             int sp, kps;
             dw_splits(g, prec, M, t, rounds, sp, kps);
             best = std::max(best, sp);
@@ -389,7 +391,7 @@ enum Site { kSiteFwd = 0, kSiteDx = kMaxHidden, kSiteDw = 2 * kMaxHidden, kNumSi
 
 struct TileChoice {
     int tile = kTile128x128;
-    int rounds = 1;  // weight-gradient splits: whole rounds of resident workgroups
+    int rounds = 2;  // weight-gradient splits: half rounds of resident workgroups (1, 2 or 4)
 };
 
 struct Tuning {
@@ -704,7 +706,7 @@ std::string tune_key(const ppo_ctx *c, int rows, bool update) {
     std::string k = std::string(c->prec == kBF16 ? "bf16" : "fp32") + "|" + std::to_string(c->g.D) + "|" +
                     std::to_string(c->g.A) + "|";
     for (int l = 0; l < c->g.L; ++l) k += std::to_string(c->g.H[l]) + ",";
-    k += "|" + std::to_string(rows) + (update ? "|u" : "|r");
+    k += "|" + std::to_string(rows) + (update ? "|u" : "|r") + "|2";
     return k;
 }
 
@@ -726,8 +728,8 @@ bool tune_file_lookup(const std::string &key, Tuning &t) {
         for (int i = 0; i < kNumSites && ok; ++i) {
             int used = 0;
             ok = std::sscanf(q, "%d %d%n", &tmp.site[i].tile, &tmp.site[i].rounds, &used) == 2 &&
-                 tmp.site[i].tile >= 0 && tmp.site[i].tile < kNumTileShapes && tmp.site[i].rounds >= 1 &&
-                 tmp.site[i].rounds <= 2;
+                 tmp.site[i].tile >= 0 && tmp.site[i].tile < kNumTileShapes &&
+                 (tmp.site[i].rounds == 1 || tmp.site[i].rounds == 2 || tmp.site[i].rounds == 4);
             q += used;
         }
         if (ok) {
@@ -780,9 +782,12 @@ bool autotune_enabled() {
 }
 
 // Tile choices for `rows` GEMM rows; `update` adds the input- and
-// weight-gradient sites.  Must not be called while the stream is captured.
+// weight-gradient sites.  grad_scratch: a [P] float buffer the caller is
+// about to overwrite (the step's gradient), into which the weight-gradient
+// candidates are reduced while they are timed; null times the GEMMs alone.
+// Must not be called while the stream is captured.
 int ensure_tuned(const ppo_ctx *cc, const ppo_params *p, const WsPlan &w, void *ws, int rows, bool update,
-                 hipStream_t s, Tuning &out) {
+                 hipStream_t s, Tuning &out, float *grad_scratch = nullptr) {
     ppo_ctx *c = const_cast<ppo_ctx *>(cc);
     const int key_rows = update ? -rows : rows;
     {
@@ -826,13 +831,27 @@ int ensure_tuned(const ppo_ctx *cc, const ppo_params *p, const WsPlan &w, void *
                     }
                 }
             }
+            // each candidate is timed with the reduction of its partials (no
+            // rate update), since fewer splits trade GEMM parallelism for
+            // fewer partial bytes
             float best = 1e30f;
             for (int tile = 0; tile < kNumTileShapes; ++tile)
-                for (int rounds = 1; rounds <= 2; ++rounds) {
+                for (int rounds : {1, 2, 4}) {
                     TileChoice tc;
                     tc.tile = tile;
                     tc.rounds = rounds;
                     DwPlan d = build_dw(c, w, ws, rows, tc);
+                    ReduceArgs &red = d.red;
+                    red.grad = grad_scratch;
+                    red.sumsq_partials = reinterpret_cast<double *>(wsp(ws, w.sumsq));
+                    red.loss_partials = reinterpret_cast<const float *>(wsp(ws, w.loss_part));
+                    red.n_loss = head_loss_blocks(rows);
+                    red.loss_width = head_loss_partial_width(g.A);
+                    red.A = g.A;
+                    red.logstd_offset = g.logstd;
+                    red.loss_sums = reinterpret_cast<float *>(wsp(ws, w.loss_sums));
+                    red.inv_m = 1.0f / static_cast<float>(rows);
+                    red.lr = nullptr;
                     float ms = 0.0f;
                     PPO_HIP(time_launch(
                                 s,
@@ -840,6 +859,7 @@ int ensure_tuned(const ppo_ctx *cc, const ppo_params *p, const WsPlan &w, void *
                                     hipError_t r = hipSuccess;
                                     for (int i = 0; i < d.n_launch && r == hipSuccess; ++i)
                                         r = launch_gemm(prec, 1, 1, kEpiPartial, d.launch[i], s);
+                                    if (r == hipSuccess && grad_scratch) r = launch_grad_reduce(red, s);
                                     return r;
                                 },
                                 reps, ms),
@@ -1534,7 +1554,7 @@ int ppo_loss_grad(const ppo_ctx *c, void *stream, const ppo_params *p, const ppo
     sb.loss_only = grad_out == nullptr;
     sb.ratio_out = ratio_out;
     Tuning tune;
-    PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, static_cast<hipStream_t>(stream), tune));
+    PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, static_cast<hipStream_t>(stream), tune, grad_out));
     PPO_HIP(enqueue_step(c, p, hp, w, ws, sb, tune, static_cast<hipStream_t>(stream)), "loss_grad");
     return PPO_OK;
 }
@@ -1560,7 +1580,7 @@ int ppo_update_epoch(ppo_ctx *c, void *stream, const ppo_params *p, const ppo_ba
     note_shadow_written(p->shadow, s);
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
     Tuning tune;
-    PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, s, tune));
+    PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, s, tune, p->grad));
     auto enqueue_all = [&](hipStream_t target) -> hipError_t {
         for (int k = 0; k < n_minibatches; ++k) {
             StepBuffers sb{b, perm + static_cast<long long>(k) * M, M, p->grad, stats + k * PPO_STATS_WIDTH, 1, k};
@@ -1644,7 +1664,7 @@ int ppo_update_epoch_profiled(ppo_ctx *c, void *stream, const ppo_params *p, con
     note_shadow_written(p->shadow, s);
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, M);
     Tuning tune;
-    PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, s, tune));
+    PPO_CHECK(ensure_tuned(c, p, w, ws, M, true, s, tune, p->grad));
     Profiler prof;
     prof.s = s;
     prof.reps = reps;
@@ -1933,7 +1953,7 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
     for (int i = 0; i < R; ++i) {
         TileChoice tc;
         tc.tile = bt.dw;
-        tc.rounds = 1;
+        tc.rounds = 2;
         plans[i] = build_dw(runs[i].c, runs[i].w, runs[i].ws, runs[i].M, tc, bt.dw_kps);
     }
     const std::vector<GemmArgs> launches = batched_dw_launches(plans, L, bt.dw, bk);
