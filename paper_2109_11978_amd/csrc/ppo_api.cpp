@@ -2112,8 +2112,42 @@ int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_
         note_ws_used(ws[i], ws_bytes[i]);
         note_shadow_written(params[i].shadow, s);
     }
+    // When every run takes the fused pass, each run's whole epoch (its own
+    // tuned steps, as ppo_update_epoch enqueues them) goes to one of the side
+    // streams, the runs spread over them by work (largest first onto the
+    // least loaded stream), with one fork and one join: the runs proceed
+    // independently and the small ones fill the slots the large ones leave
+    // free.  Otherwise step k of every run is enqueued together (grouped
+    // GEMM launches across runs).  PPO_BATCHED_GROUPED=1 forces the latter.
+    bool per_run = R > 1;
+    if (const char *v = std::getenv("PPO_BATCHED_GROUPED")) per_run = per_run && std::strcmp(v, "1") != 0;
+    for (int i = 0; i < R && per_run; ++i)
+        per_run = fused_shape_for(runs[i].c, runs[i].p, runs[i].w, runs[i].b->B).rows > 0;
     BatchedTuning bt;
-    {
+    std::vector<Tuning> tunes(R);
+    std::vector<int> order(R), lane(R, 0);
+    if (per_run) {
+        std::vector<double> work(R);
+        for (int i = 0; i < R; ++i) {
+            PPO_CHECK(ensure_tuned(runs[i].c, runs[i].p, runs[i].w, runs[i].ws, runs[i].M, true, s, tunes[i],
+                                   runs[i].p->grad));
+            const NetLayout &g = runs[i].c->g;
+            double per_sample = static_cast<double>(g.D) * g.H[0];
+            for (int l = 1; l < g.L; ++l) per_sample += static_cast<double>(g.H[l - 1]) * g.H[l];
+            work[i] = per_sample * runs[i].b->B;
+            order[i] = i;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+        double load[kSideStreams] = {};
+        const int n_side = std::min(R, kSideStreams);
+        for (int i : order) {
+            int j = 0;
+            for (int q = 1; q < n_side; ++q)
+                if (load[q] < load[j]) j = q;
+            lane[i] = j;
+            load[j] += work[i];
+        }
+    } else {
         std::string key = std::string(autotune_enabled() ? "t" : "f");
         for (const BatchedRun &r : runs) key += "|" + tune_key(r.c, r.M, true);
         std::lock_guard<std::mutex> lk(g_batched_mu);
@@ -2126,12 +2160,30 @@ int ppo_update_batched(ppo_ctx *const *ctxs, int32_t R, void *stream, const ppo_
         }
     }
     auto enqueue_all = [&](hipStream_t target) -> hipError_t {
+        hipError_t e;
+        if (per_run) {
+            const int n_side = std::min(R, kSideStreams);
+            if ((e = fork_to(g_side, target, n_side)) != hipSuccess) return e;
+            for (int i : order) {
+                const BatchedRun &r = runs[i];
+                const hipStream_t st = g_side.st[lane[i]];
+                for (int k = 0; k < n_minibatches; ++k) {
+                    StepBuffers sb{r.b, r.perm + static_cast<long long>(k) * r.M, r.M, r.p->grad,
+                                   r.stats + k * PPO_STATS_WIDTH, 1, k};
+                    sb.frags_ready = k > 0;
+                    sb.write_frags = k + 1 < n_minibatches;
+                    if ((e = enqueue_step(r.c, r.p, hp, r.w, r.ws, sb, tunes[i], st)) != hipSuccess) return e;
+                }
+                if ((e = launch_step_advance(r.p->step, n_minibatches, st)) != hipSuccess) return e;
+            }
+            return join_from(g_side, target, n_side);
+        }
         for (int k = 0; k < n_minibatches; ++k) {
-            hipError_t e = enqueue_batched_step(runs, hp, k, bt, target, R > 1 ? &g_side : nullptr);
+            e = enqueue_batched_step(runs, hp, k, bt, target, R > 1 ? &g_side : nullptr);
             if (e != hipSuccess) return e;
         }
         for (int i = 0; i < R; ++i) {
-            hipError_t e = launch_step_advance(params[i].step, n_minibatches, target);
+            e = launch_step_advance(params[i].step, n_minibatches, target);
             if (e != hipSuccess) return e;
         }
         return hipSuccess;

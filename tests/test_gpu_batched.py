@@ -1,12 +1,14 @@
-"""Uneven concurrent runs in shared grouped launches (needs an MI355X).
+"""Uneven concurrent runs updated together (needs an MI355X).
 
 Every run's epoch in ppo_update_batched must equal the same run updated alone
 by ppo_update_epoch with the same (128 x 128) tiles, bit for bit, and the
 graph-replayed batched epoch must equal its eager launch.  Two network
-shapes: hidden (128, 64, 32), which the bf16 fused pass does not cover (the
-grouped layer-by-layer launches), and the sweep workload's (512, 256, 128),
-which it does (one fused pass per run on side streams, then the grouped
-weight-gradient launch)."""
+shapes: hidden (128, 64, 32), which the bf16 fused pass does not cover (step k
+of every run together, in grouped layer-by-layer launches), and the sweep
+workload's (512, 256, 128), which it does (each run's whole epoch on one of
+the side streams; with PPO_BATCHED_GROUPED=1 step k of every run together:
+one fused pass per run on the side streams, then the grouped weight-gradient
+launch)."""
 import os
 
 import numpy as np
@@ -52,14 +54,17 @@ def fixed_tiles(monkeypatch):
     monkeypatch.setenv("PPO_AUTOTUNE", "0")
 
 
-@pytest.mark.parametrize("prec,desired_kl,hidden", [("fp32", 0.0, (128, 64, 32)), ("bf16", 0.0, (128, 64, 32)),
-                                                    ("bf16", 0.01, (128, 64, 32)), ("bf16", 0.0, (512, 256, 128)),
-                                                    ("bf16", 0.01, (512, 256, 128))])
-def test_batched_equals_solo(prec, desired_kl, hidden, fixed_tiles):
+@pytest.mark.parametrize("prec,desired_kl,hidden,grouped", [
+    ("fp32", 0.0, (128, 64, 32), False), ("bf16", 0.0, (128, 64, 32), False), ("bf16", 0.01, (128, 64, 32), False),
+    ("bf16", 0.0, (512, 256, 128), False), ("bf16", 0.01, (512, 256, 128), False),
+    ("bf16", 0.0, (512, 256, 128), True), ("bf16", 0.01, (512, 256, 128), True)])
+def test_batched_equals_solo(prec, desired_kl, hidden, grouped, fixed_tiles, monkeypatch):
     d = require_gpu()
+    if grouped:
+        monkeypatch.setenv("PPO_BATCHED_GROUPED", "1")
     runs = _runs(prec, hidden)
-    print(f"[gpu-case] batched vs solo {prec} desired_kl={desired_kl} hidden={hidden} runs={SHAPES[hidden]}",
-          flush=True)
+    print(f"[gpu-case] batched vs solo {prec} desired_kl={desired_kl} hidden={hidden} grouped={grouped} "
+          f"runs={SHAPES[hidden]}", flush=True)
     hp = ppo.UpdateHParams(desired_kl=desired_kl)
     ctxs, solo_state, solo_stats = [], [], []
     for cfg, theta, batch, perm in runs:
