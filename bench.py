@@ -202,12 +202,23 @@ def phase_model(cfg, precision, P):
     }
 
 
+def code_sha256(path):
+    """SHA-256 of a C++/HIP source with its comments and whitespace removed, so
+    that recorded counters stay tied to the code rather than to its comments
+    (string literals in the kernels hold no comment markers)."""
+    import hashlib
+    import re
+    src = open(path, encoding="utf-8").read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return hashlib.sha256("".join(src.split()).encode()).hexdigest()
+
+
 def recorded_traffic(wl, phase, workload):
     """HBM bytes per launch of the fused, forward or input-gradient phase, from
     the committed rocprofv3 counter summary (per kernel and grid, at the tiles
     this run chose), or None when the summary is missing, lacks one of those
-    launches, or was taken on another version of the kernel's source."""
-    import hashlib
+    launches, or was taken on another version of the kernel's code."""
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", f"traffic_{workload}.txt")
     if phase not in ("fused", "forward", "input_grad") or not os.path.exists(path):
@@ -219,8 +230,8 @@ def recorded_traffic(wl, phase, workload):
             fields[k.strip()] = v.strip()
     src_name = "k_fused.hip" if phase == "fused" else "k_gemm.hip"
     src = os.path.join(here, "paper_2109_11978_amd", "csrc", src_name)
-    sha_key = src_name.replace(".hip", "_sha256")
-    if fields.get(sha_key) != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    sha_key = src_name.replace(".hip", "_code_sha256")
+    if fields.get(sha_key) != code_sha256(src):
         return None
     cfg = wl.cfg
     M, H = cfg.minibatch, list(cfg.net.hidden)
