@@ -981,28 +981,38 @@ void fused_update_kernel(const FusedArgs a) {
         }
     }
     __syncthreads();
-    // block sums over the samples in order, one thread per term
-    if (tid < kSums) {
-        float v = 0.0f;
-        for (int i0 = 0; i0 < rows; i0 += 8) {
-            float t8[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) t8[u] = s_sum[min(i0 + u, R - 1) * kSums + tid];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (i0 + u < rows) v += t8[u];
-        }
-        s_sum[R * kSums + tid] = v;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        const float *t = s_sum + R * kSums;
+    // block sums of the loss terms: eight lanes per term, lane p adding the
+    // samples p, p + 8, ... in order, then a fixed three-level lane tree;
+    // each term's first lane writes its slot of the block's partials row
+    // (shared by the block's actor and critic workgroups, which write
+    // disjoint slots).  The order is fixed, so the result does not depend
+    // on timing.
+    {
         float *out = a.partials + static_cast<long long>(m0 / R) * (A + 8);
-        if (net == 0) {
-            out[0] = t[0];
-            out[2] = t[2];
-            out[3] = t[3];
-            for (int j = 0; j < A; ++j) out[4 + j] = t[5 + j];
+        const int q = tid >> 3, p = tid & 7;
+        float v = 0.0f;
+        if (q < kSums) {
+            float t8[R / 8];
+#pragma unroll
+            for (int u = 0; u < R / 8; ++u) t8[u] = s_sum[min(p + 8 * u, R - 1) * kSums + q];
+#pragma unroll
+            for (int u = 0; u < R / 8; ++u)
+                if (p + 8 * u < rows) v += t8[u];
+        }
+        // the 8 lanes of a term are adjacent lanes of one wave
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        if (q < kSums && p == 0) {
+            if (net == 0) {
+                if (q == 0 || q == 2 || q == 3) out[q] = v;
+                else if (q == 4) out[5 + A] = v;
+                else if (q >= 5 && q - 5 < A) out[4 + (q - 5)] = v;
+            } else if (q == 1) {
+                out[1] = v;
+            }
+        }
+        if (net == 0 && tid == 0) {
             float ent = 0.0f, kl_ls = 0.0f;
             if (m0 == 0) {
                 // entropy of the state-independent policy, and the
@@ -1017,14 +1027,11 @@ void fused_update_kernel(const FusedArgs a) {
                     }
             }
             out[4 + A] = ent;
-            out[5 + A] = t[4];
             out[6 + A] = kl_ls;
-        } else {
-            out[1] = t[1];
         }
     }
     if (a.no_backward) return;
-    // the block sums were read by thread 0 before the staging below reuses
+    // every lane has read its block sums before the staging below reuses
     // their place
     __syncthreads();
 
