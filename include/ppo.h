@@ -49,15 +49,19 @@
  *     128 x 128-tile launches are persistent: as many workgroups as fit on
  *     the device at once, each taking every G-th tile).
  *   - bf16 update steps of networks whose hidden widths split evenly over
- *     four waves (e.g. [512, 256, 128] or [64, 64]; input width a multiple
- *     of 16) run everything that is independent per sample (gather, hidden
- *     layers, output layers with the loss, input-gradient chain) as one fused
- *     launch with the activations in LDS, then the split-sample
- *     weight-gradient GEMMs; other shapes (e.g. a 1024-wide layer), and the
+ *     the waves of a workgroup (e.g. [512, 256, 128], [64, 64] or
+ *     [1024, 512, 256]; input width a multiple of 16) run everything that is
+ *     independent per sample (gather, hidden layers, output layers with the
+ *     loss, input-gradient chain) as one fused launch with the activations in
+ *     LDS, then the split-sample weight-gradient GEMMs; other shapes, and the
  *     fp32 path, run the layer-by-layer kernels.  The results agree to
- *     float32 rounding (bf16 ulps downstream of it).  PPO_FUSED=0 forces the
- *     layer-by-layer kernels; PPO_FUSED_ROWS=32 or 64 (and
- *     PPO_FUSED_THREADS=256 or 512) override the fused pass's block shape.
+ *     float32 rounding (bf16 ulps downstream of it).  Where it fits, the
+ *     fused pass runs three 64-sample workgroups per CU with the first hidden
+ *     layer computed in 128-feature chunks, each added into the second
+ *     layer's accumulators at once (e.g. [512, 256, 128] with 48 inputs).
+ *     PPO_FUSED=0 forces the layer-by-layer kernels; PPO_FUSED_ROWS=32 or 64
+ *     (and PPO_FUSED_THREADS=256 or 512, PPO_FUSED_PER_CU=2 or 3) override
+ *     the fused pass's block shape.
  *   - bf16 precision: GEMM operands are bf16 with float32 accumulation,
  *     except that the critic's hidden-layer weights enter its forward GEMMs
  *     as two bf16 terms, bf16(W) and bf16(W - bf16(W)) (about 16 significant

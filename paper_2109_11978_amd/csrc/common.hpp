@@ -191,7 +191,7 @@ struct FusedArgs {
     float *act_out, *logp_out, *val_out, *mu_out;
     uint32_t key0, key1, t_step, iteration;
     int net_mask;                     // bit 0: actor, bit 1: critic
-    int R, NT;                        // samples and threads per workgroup (a fused_shape)
+    int R, NT, per_cu;                // samples, threads and workgroups per CU (a fused_shape)
     // filled in by launch_fused_update
     int blocks;
     int lds_region[kMaxHidden], lds_x, lds_w, lds_sum, lds_in, lds_rows, lds_bias, lds_head;
@@ -200,20 +200,24 @@ struct FusedArgs {
     // the staged activation it multiplies by ELU', and the feature chunk of
     // the first hidden layer's input gradient
     int lds_last, lds_g, lds_bdz[kMaxHidden], lds_bst[kMaxHidden], chunk;
+    // three workgroups per CU (streamed first layer): the first hidden
+    // layer's output comes in chunks of chunk0 features at lds_cb, each added
+    // into the second layer's accumulators as soon as it is written
+    int lds_cb, chunk0;
     int bias_off[kMaxHidden];         // floats into the staged biases
 };
 // Samples per workgroup and threads per workgroup of the fused pass for this
 // network shape ({0, 0} when it does not apply: hidden widths that do not
 // split over the waves, an input width that is not a multiple of 16, or
 // activations that do not fit in LDS); per_cu = workgroups sharing a CU.
-// Nonzero prefer_rows / prefer_threads restrict the candidates.
+// Nonzero prefer_rows / prefer_threads / prefer_per_cu restrict the candidates.
 struct FusedShape {
     int rows, threads, per_cu;
 };
 // update = true: the shapes of the update pass (its LDS plan differs from
 // inference's).
 FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows = 0, int prefer_threads = 0,
-                       bool update = false);
+                       bool update = false, int prefer_per_cu = 0);
 int fused_blocks(int M, int R);
 hipError_t launch_fused_update(FusedArgs a, hipStream_t s);
 // Forward pass and sampling head for M environments (rows of obs in order).

@@ -99,13 +99,19 @@ constexpr bool kRaisePrio = !std::is_same<Hook, NoHook>::value;
 template <int FBW, int SB, int PF, int SPLIT, class Hook = NoHook>
 __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16_t *W, int rows_w, int S, int f0,
                                           int sb0, const uint16_t *act, int pitch, int lane,
-                                          const Hook &hook = Hook()) {
+                                          const Hook &hook = Hook(), int s0 = 0, int Sc = -1, bool zero = true) {
     static_assert(SPLIT == 1 || SPLIT == 2, "one or two weight passes");
     // SPLIT = 2: each feature block has S fragments of bf16(W), then S of the
     // bf16 residual W - bf16(W); both passes multiply the same activation
     // fragments into the same accumulators, in the order of the layer-by-layer
-    // GEMM (all of the first pass, then all of the second)
-    const int SW = S * SPLIT;   // weight fragments per feature block
+    // GEMM (all of the first pass, then all of the second).
+    // A call may take the k-steps s0 .. s0 + Sc of the layer only (its
+    // activation fragments then start at act's column 0) and add to the
+    // accumulators instead of starting from zero.
+    if (Sc < 0) Sc = S;
+    const int SW = S * SPLIT;     // weight fragments per feature block
+    const int SWc = Sc * SPLIT;   // fragments this call multiplies
+    auto frag = [&](int q) { return SPLIT == 1 || q < Sc ? s0 + q : S + s0 + (q - Sc); };
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(W, static_cast<long long>(rows_w / 32) * SW * 1024);
     const int kh = (lane >> 5) * 8;
     // per-block lane offsets in VGPRs, one scalar step offset per load
@@ -113,17 +119,18 @@ __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16
 #pragma unroll
     for (int f = 0; f < FBW; ++f) vo[f] = (f0 / 32 + f) * SW * 1024 + lane * 16;
     const uint16_t *bp = act + (32 * sb0 + (lane & 31)) * pitch + kh;
+    if (zero)
 #pragma unroll
-    for (int f = 0; f < FBW; ++f)
+        for (int f = 0; f < FBW; ++f)
 #pragma unroll
-        for (int j = 0; j < SB; ++j) acc[f][j] = floatx16{};
+            for (int j = 0; j < SB; ++j) acc[f][j] = floatx16{};
     u32x4 w[PF][FBW];
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-        const int so = __builtin_amdgcn_readfirstlane(p * 1024);
+        const int so = __builtin_amdgcn_readfirstlane(frag(p) * 1024);
 #pragma unroll
         for (int f = 0; f < FBW; ++f)
-            w[p][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, p < SW ? vo[f] : kOutside, so, 0);
+            w[p][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, p < SWc ? vo[f] : kOutside, so, 0);
         __builtin_amdgcn_sched_barrier(0);
     }
     // work that needs no weights (e.g. copying the previous layer's output to
@@ -133,13 +140,13 @@ __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16
     u32x4 b[SB];
 #pragma unroll
     for (int j = 0; j < SB; ++j) b[j] = *reinterpret_cast<const u32x4 *>(bp + 32 * j * pitch);
-    for (int q0 = 0; q0 < SW; q0 += PF) {
+    for (int q0 = 0; q0 < SWc; q0 += PF) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
-            // activation fragment of weight fragment q + 1: k-step (q + 1) mod S,
+            // activation fragment of weight fragment q + 1: k-step (q + 1) mod Sc,
             // the last one again past the end
             const int q1 = q0 + u + 1;
-            const int s1 = q1 < S ? q1 : (q1 < SW ? q1 - S : S - 1);
+            const int s1 = q1 < Sc ? q1 : (q1 < SWc ? q1 - Sc : Sc - 1);
             u32x4 bn[SB];
 #pragma unroll
             for (int j = 0; j < SB; ++j) bn[j] = *reinterpret_cast<const u32x4 *>(bp + 32 * j * pitch + 16 * s1);
@@ -152,10 +159,10 @@ __device__ __forceinline__ void mma_layer(floatx16 (&acc)[FBW][SB], const uint16
                                                                       __builtin_bit_cast(bf16x8_t, b[j]), acc[f][j],
                                                                       0, 0, 0);
             const int qn = q0 + u + PF;
-            const int so = __builtin_amdgcn_readfirstlane(qn * 1024);
+            const int so = __builtin_amdgcn_readfirstlane(frag(qn) * 1024);
 #pragma unroll
             for (int f = 0; f < FBW; ++f)
-                w[u][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, qn < SW ? vo[f] : kOutside, so, 0);
+                w[u][f] = __builtin_amdgcn_raw_buffer_load_b128(rs, qn < SWc ? vo[f] : kOutside, so, 0);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int j = 0; j < SB; ++j) b[j] = bn[j];
@@ -268,6 +275,11 @@ constexpr int pf_max() {
     return pf;
 }
 
+// Feature blocks per wave whose accumulators (16 registers per block and
+// sample block) fit a register budget; the shape checks (width_splits with
+// the same budget) keep other widths from being launched.
+constexpr bool acc_fits(int fbw, int sbw, int regs) { return fbw * sbw * 16 <= regs; }
+
 template <int SBW, bool BWD, bool WIDE, int REGS, int SPLIT, class Hook>
 __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int K, int nout, const float *bias,
                                          const uint16_t *in, int in_pitch, uint16_t *out, int out_pitch, int f0,
@@ -278,12 +290,22 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
                                                              sb0, lane, hook, sync_epi);
         break;
     case 2:
-        layer_pf<2, SBW, BWD, pf_max<2, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
-                                                             sb0, lane, hook, sync_epi);
+        if constexpr (acc_fits(2, SBW, REGS)) {
+            layer_pf<2, SBW, BWD, pf_max<2, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch,
+                                                                 f0, sb0, lane, hook, sync_epi);
+            break;
+        }
+        hook();
+        epi_sync(sync_epi);
         break;
     case 4:
-        layer_pf<4, SBW, BWD, pf_max<4, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch, f0,
-                                                             sb0, lane, hook, sync_epi);
+        if constexpr (acc_fits(4, SBW, REGS)) {
+            layer_pf<4, SBW, BWD, pf_max<4, SBW, REGS>(), SPLIT>(S, W, K, nout, bias, in, in_pitch, out, out_pitch,
+                                                                 f0, sb0, lane, hook, sync_epi);
+            break;
+        }
+        hook();
+        epi_sync(sync_epi);
         break;
     default:
         if constexpr (WIDE)
@@ -297,6 +319,11 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
     }
 }
 
+// Registers for a layer's accumulators and fragment ring per lane: 512 /
+// WPE, less what the addresses, activation fragments and epilogue keep live
+// (and, at three workgroups per CU, the streamed first layer's accumulators).
+constexpr int layer_regs(int wpe, int sb) { return wpe == 1 ? 320 : (wpe >= 3 ? 112 : (sb >= 2 ? 160 : 192)); }
+
 // One layer for all R samples of the block.  The layer's 32-feature blocks
 // are split over the NT / 64 waves; when there are fewer blocks than waves,
 // the waves sharing a block split the sample blocks instead (each weight
@@ -309,7 +336,7 @@ __device__ __forceinline__ void run_layer(const uint16_t *W, int K, int nout, co
     constexpr int SB = R / 32;
     // registers for accumulators and fragments: 512 / WPE per lane, less
     // what the addresses, activation fragments and epilogue keep live
-    constexpr int REGS = WPE == 1 ? 320 : (SB >= 2 ? 160 : 192);
+    constexpr int REGS = layer_regs(WPE, SB);
     // eight feature blocks per wave only with one sample block and a full
     // register file
     constexpr bool WIDE = SB == 1 && WPE == 1;
@@ -791,6 +818,46 @@ __device__ __forceinline__ void head_mfma(const FusedArgs &a, const FusedNet &N,
     }
 }
 
+// The first two hidden layers with the first one's output in chunks of
+// chunk0 features (one feature block per wave): each chunk goes through
+// ELU into the chunk buffer, is copied to global memory (a weight-gradient
+// operand) while the second layer's fragments for its k-range are in
+// flight, and is added into the second layer's accumulators, which stay in
+// registers across the chunks; then the second layer's epilogue writes h_1 at
+// the region's start, over the inputs and the chunk buffer.  The actor's
+// gathered inputs go to global memory during the first chunk.
+template <int R, int NT, int WPE, int SPLIT, int FBW1>
+__device__ __forceinline__ void stream_first_layers(const FusedArgs &a, const FusedNet &N, int net, const uint16_t *x,
+                                                    int xp, char *reg, const float *s_bias, int m0, int rows,
+                                                    int wave, int lane) {
+    constexpr int SB = R / 32;
+    const int H0 = a.H[0], H1 = a.H[1], C0 = a.chunk0;
+    const int S0 = a.kpad >> 4, S1 = H0 >> 4;
+    uint16_t *cb = reinterpret_cast<uint16_t *>(reg + a.lds_cb);
+    const int cbp = C0 + 8;
+    const int f1 = wave * FBW1 * 32;
+    floatx16 acc1[FBW1][SB];
+    for (int c0 = 0; c0 < H0; c0 += C0) {
+        {
+            floatx16 acc0[1][SB];
+            auto hook0 = [&]() {
+                if (c0 == 0 && net == 0)
+                    copy_out<NT>(x, xp, a.xg + static_cast<long long>(m0) * a.kpad, a.kpad, a.kpad, rows);
+            };
+            mma_layer<1, SB, 4, SPLIT>(acc0, N.W[0] + static_cast<long long>(c0 / 32) * S0 * SPLIT * 512, C0, S0,
+                                       32 * wave, 0, x, xp, lane, hook0);
+            epi_forward<1, SB>(acc0, s_bias + a.bias_off[0] + c0, 32 * wave, 0, cb, cbp, lane);
+        }
+        __syncthreads();
+        auto hook1 = [&]() { copy_out<NT>(cb, cbp, N.h[0] + static_cast<long long>(m0) * H0 + c0, H0, C0, rows); };
+        mma_layer<FBW1, SB, 4, SPLIT>(acc1, N.W[1], H1, S1, f1, 0, cb, cbp, lane, hook1, c0 >> 4, C0 >> 4, c0 == 0);
+        // every wave has read the chunk before the next one overwrites it
+        __syncthreads();
+    }
+    epi_forward<FBW1, SB>(acc1, s_bias + a.bias_off[1], f1, 0, reinterpret_cast<uint16_t *>(reg), H1 + 8, lane);
+    __syncthreads();
+}
+
 // R samples per workgroup of NT threads; WPE waves per SIMD (the NT / 256
 // waves of one workgroup times the workgroups that share a CU).
 //
@@ -806,7 +873,7 @@ __device__ __forceinline__ void head_mfma(const FusedArgs &a, const FusedNet &N,
 // computed a feature chunk at a time and copied out.  The region then needs
 // room for about one wide layer rather than all of them, which lets 64
 // samples (or 32 of a 1024-wide network) share a CU two workgroups at a time.
-template <int R, int NT, int WPE>
+template <int R, int NT, int WPE, bool STREAM = false>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, WPE)))
 void fused_update_kernel(const FusedArgs a) {
     extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -898,15 +965,33 @@ void fused_update_kernel(const FusedArgs a) {
     // --------------------------------------------------------- forward
     // hidden layers 0 .. L-2 write their output over their input (at the
     // region's start) once every wave has read it; the last goes to
-    // lds_last.  Each layer's input goes to global memory while its first
-    // weight fragments are in flight (the gathered observations: actor only)
+    // lds_last (over its input too when that is the region's start).  Each
+    // layer's input goes to global memory while its first weight fragments
+    // are in flight (the gathered observations: actor only).  STREAM: the
+    // first two layers as stream_first_layers computes them.
     {
         const uint16_t *in = x;
         int in_pitch = xp, K = a.kpad;
-        for (int l = 0; l < L; ++l) {
+        int l0 = 0;
+        if constexpr (STREAM) {
+            const bool two = a.H[1] / 32 / (NT / 64) == 2;
+            if (net == 1) {
+                if (two) stream_first_layers<R, NT, WPE, 2, 2>(a, N, net, x, xp, reg, s_bias, m0, rows, wave, lane);
+                else stream_first_layers<R, NT, WPE, 2, 1>(a, N, net, x, xp, reg, s_bias, m0, rows, wave, lane);
+            } else {
+                if (two) stream_first_layers<R, NT, WPE, 1, 2>(a, N, net, x, xp, reg, s_bias, m0, rows, wave, lane);
+                else stream_first_layers<R, NT, WPE, 1, 1>(a, N, net, x, xp, reg, s_bias, m0, rows, wave, lane);
+            }
+            in = reinterpret_cast<const uint16_t *>(reg);
+            in_pitch = a.H[1] + 8;
+            K = a.H[1];
+            l0 = 2;
+        }
+        for (int l = l0; l < L; ++l) {
             const int H = a.H[l];
             const bool last = l == L - 1;
             uint16_t *out = reinterpret_cast<uint16_t *>(reg + (last ? a.lds_last : 0));
+            const int sync = !last || a.lds_last == 0 ? 1 : 0;
             const int Hp = l > 0 ? a.H[l - 1] : 0;
             auto hook = [&]() {
                 if (l == 0) {
@@ -919,10 +1004,10 @@ void fused_update_kernel(const FusedArgs a) {
             // the critic's weights come in the split layout (bf16 and residual fragments)
             if (net == 1)
                 run_layer<R, NT, WPE, false, 2>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8,
-                                                wave, lane, hook, !last);
+                                                wave, lane, hook, sync);
             else
                 run_layer<R, NT, WPE, false, 1>(N.W[l], K, H, s_bias + a.bias_off[l], in, in_pitch, out, H + 8,
-                                                wave, lane, hook, !last);
+                                                wave, lane, hook, sync);
             __syncthreads();
             in = out;
             in_pitch = H + 8;
@@ -1372,12 +1457,12 @@ bool fused_fits(int L, const int *H, int kpad, int A, int R, int NT, bool two_pe
 }
 
 // Whether `width` output features split over the waves as run_layer does.
-bool width_splits(int width, int NW, int SB, bool wide_ok) {
+bool width_splits(int width, int NW, int SB, bool wide_ok, int regs = 320) {
     if (width <= 0 || width % 32 != 0) return false;
     const int fb = width / 32;
     if (fb >= NW) {
         const int fbw = fb / NW;
-        return fb % NW == 0 && (fbw == 1 || fbw == 2 || fbw == 4 || (fbw == 8 && wide_ok));
+        return fb % NW == 0 && acc_fits(fbw, SB, regs) && (fbw == 1 || fbw == 2 || fbw == 4 || (fbw == 8 && wide_ok));
     }
     return SB >= 2 && 2 * fb == NW;
 }
@@ -1469,9 +1554,108 @@ size_t fused_update_layout(int L, const int *H, int kpad, int A, int R, int NT, 
     return 0;
 }
 
+// LDS plan of the update pass with a streamed first layer (three workgroups
+// per CU, `budget` bytes each): the first hidden layer's output is never held
+// whole.  Forward: the gathered inputs at the region's start, followed by a
+// chunk buffer of chunk0 = 32 NW features (one feature block per wave); the
+// second layer's output at the start once every chunk has been added in,
+// and each later layer's output over its input.  Head: the last hidden layer
+// at the start, then the output-layer weights, the per-sample loss terms and
+// the output gradients.  Then the loss inputs, biases, row indices and head
+// constants, which the backward chain may overwrite (none of them is read
+// after the head): dz_{L-1} in place over h_{L-1} at the start, each staged
+// ELU' input next to its incoming gradient, the first hidden layer's
+// gradient in the widest chunk that fits.  Returns the total bytes, 0 if the
+// network does not fit or does not split this way.
+size_t fused_stream_layout(int L, const int *H, int kpad, int A, int R, int NT, size_t budget, FusedArgs *a) {
+    (void)A;
+    if (L < 2) return 0;
+    const int Hl = H[L - 1];
+    const int NW = NT / 64, SB = R / 32;
+    const int regs = layer_regs(3, SB);
+    const int KP = NT / R;
+    if (Hl % KP != 0 || (Hl / KP != 16 && Hl / KP != 32 && Hl / KP != 64)) return 0;
+    const int C0 = 32 * NW;
+    // the first layer one feature block per wave per chunk; the second
+    // layer's accumulators live across the chunks (at most two feature blocks)
+    if (H[0] % C0 != 0 || H[1] % 32 != 0 || H[1] / 32 < NW || (H[1] / 32) % NW != 0 || H[1] / 32 / NW > 2)
+        return 0;
+    for (int l = 1; l < L; ++l)
+        if (!width_splits(H[l], NW, SB, false, regs)) return 0;
+    auto P = [&](int w) { return align16(static_cast<size_t>(R) * (w + 8) * 2); };
+    size_t fixed = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = fixed;
+        fixed += align16(bytes);
+        return at;
+    };
+    const size_t in_off = take(static_cast<size_t>(R) * kInW * 4);
+    int bias_off[kMaxHidden] = {0};
+    size_t nb = 0;
+    for (int l = 0; l < L; ++l) {
+        bias_off[l] = static_cast<int>(nb);
+        nb += (H[l] + 3) & ~3;
+    }
+    const size_t bias = take(nb * 4);
+    const size_t rows_off = take(static_cast<size_t>(R) * 4);
+    const size_t head = take(static_cast<size_t>(2 * kFusedMaxAct) * 4);
+    size_t fwd = P(kpad) + P(C0);
+    for (int l = 1; l < L; ++l) fwd = std::max(fwd, P(H[l]));
+    const size_t wb = align16(static_cast<size_t>(kFusedMaxAct) * (Hl + 4) * 4);
+    const size_t sbytes = align16(static_cast<size_t>(R + 1) * kSums * 4);
+    const size_t gb = align16(static_cast<size_t>(R) * kFusedMaxAct * 4);
+    const size_t w_off = P(Hl), s_off = w_off + wb, g_off = s_off + sbytes;
+    const size_t pers = align16(std::max(fwd, g_off + gb));
+    for (int C = H[0]; C >= 32; C /= 2) {
+        if (H[0] % C != 0 || !width_splits(C, NW, SB, false, regs)) continue;
+        size_t bdz[kMaxHidden] = {0}, bst[kMaxHidden] = {0};
+        size_t cur = 0, ext = pers + fixed;
+        for (int l = L - 1; l >= 1; --l) {
+            const int Cl = l == 1 ? C : H[l - 1];
+            const size_t dz_size = P(H[l]), st_size = P(Cl);
+            const size_t st = cur >= st_size ? 0 : cur + dz_size;
+            ext = std::max(ext, st + st_size);
+            bdz[l] = cur;
+            bst[l] = st;
+            cur = st;
+        }
+        const size_t total = align16(ext);
+        if (total > budget) continue;
+        if (a) {
+            a->lds_in = static_cast<int>(pers + in_off);
+            a->lds_bias = static_cast<int>(pers + bias);
+            a->lds_rows = static_cast<int>(pers + rows_off);
+            a->lds_head = static_cast<int>(pers + head);
+            a->lds_last = 0;
+            a->lds_w = static_cast<int>(w_off);
+            a->lds_sum = static_cast<int>(s_off);
+            a->lds_g = static_cast<int>(g_off);
+            a->lds_cb = static_cast<int>(P(kpad));
+            a->chunk0 = C0;
+            a->chunk = C;
+            for (int l = 0; l < L; ++l) {
+                a->bias_off[l] = bias_off[l];
+                a->lds_bdz[l] = static_cast<int>(bdz[l]);
+                a->lds_bst[l] = static_cast<int>(bst[l]);
+            }
+        }
+        return total;
+    }
+    return 0;
+}
+
+// The update pass's LDS plan for a shape: streamed first layer at three
+// workgroups per CU, else the shared-region plan.
+size_t update_layout(int L, const int *H, int kpad, int A, const FusedShape &sh, FusedArgs *a) {
+    const size_t budget = kMaxLdsBytes / sh.per_cu;
+    return sh.per_cu == 3 ? fused_stream_layout(L, H, kpad, A, sh.rows, sh.threads, budget, a)
+                          : fused_update_layout(L, H, kpad, A, sh.rows, sh.threads, budget, a);
+}
+
 }  // namespace
 
-FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows, int prefer_threads, bool update) {
+FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows, int prefer_threads, bool update,
+                       int prefer_per_cu) {
     FusedShape none{0, 0, 0};
     if (L < 1 || L > kMaxHidden || A < 1 || A > kFusedMaxAct || kpad < 16 || kpad % 16 != 0) return none;
     // inference candidates (the update pass's are below) in order of
@@ -1490,15 +1674,15 @@ FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows, in
         // 64 samples x 8 waves alone on a CU (the [1024, 512, 256] network: its
         // update runs in 0.8x the time of the layer-by-layer GEMMs); 32 samples
         // x 8 waves alone on a CU loses to those GEMMs and runs only when asked
-        const FusedShape cand[4] = {{64, 256, 2}, {32, 256, 2}, {64, 512, 1}, {32, 512, 1}};
+        const FusedShape cand[5] = {{64, 256, 3}, {64, 256, 2}, {32, 256, 2}, {64, 512, 1}, {32, 512, 1}};
         const bool asked = prefer_rows && prefer_threads;
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 5; ++i) {
             const FusedShape &c = cand[i];
-            if (i >= 3 && !asked) break;
+            if (i >= 4 && !asked) break;
             if (prefer_rows && c.rows != prefer_rows) continue;
             if (prefer_threads && c.threads != prefer_threads) continue;
-            const size_t budget = kMaxLdsBytes / c.per_cu;
-            if (fused_update_layout(L, H, kpad, A, c.rows, c.threads, budget, nullptr) > 0) return c;
+            if (prefer_per_cu && c.per_cu != prefer_per_cu) continue;
+            if (update_layout(L, H, kpad, A, c, nullptr) > 0) return c;
         }
         return none;
     }
@@ -1560,18 +1744,19 @@ hipError_t launch_fused_infer(FusedArgs a, hipStream_t s) {
 }
 
 hipError_t launch_fused_update(FusedArgs a, hipStream_t s) {
-    const FusedShape sh = fused_shape(a.L, a.H, a.kpad, a.A, a.R, a.NT, true);
+    const FusedShape sh = fused_shape(a.L, a.H, a.kpad, a.A, a.R, a.NT, true, a.per_cu);
+    if (sh.per_cu != a.per_cu) return hipErrorInvalidValue;
     if (sh.rows == 0 || a.M < 1) return hipErrorInvalidValue;
-    const size_t budget = kMaxLdsBytes / sh.per_cu;
-    const size_t bytes = fused_update_layout(a.L, a.H, a.kpad, a.A, sh.rows, sh.threads, budget, &a);
+    const size_t bytes = update_layout(a.L, a.H, a.kpad, a.A, sh, &a);
     if (bytes == 0) return hipErrorInvalidValue;
     a.blocks = fused_blocks(a.M, sh.rows);
     static bool attr_set = false;
     if (!attr_set) {
-        const void *fns[4] = {reinterpret_cast<const void *>(&fused_update_kernel<64, 256, 2>),
+        const void *fns[5] = {reinterpret_cast<const void *>(&fused_update_kernel<64, 256, 2>),
                               reinterpret_cast<const void *>(&fused_update_kernel<32, 256, 2>),
                               reinterpret_cast<const void *>(&fused_update_kernel<64, 512, 2>),
-                              reinterpret_cast<const void *>(&fused_update_kernel<32, 512, 2>)};
+                              reinterpret_cast<const void *>(&fused_update_kernel<32, 512, 2>),
+                              reinterpret_cast<const void *>(&fused_update_kernel<64, 256, 3, true>)};
         for (const void *fn : fns) {
             const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
             if (e != hipSuccess) return e;
@@ -1579,7 +1764,9 @@ hipError_t launch_fused_update(FusedArgs a, hipStream_t s) {
         attr_set = true;
     }
     const dim3 grid(two_net_grid(a.blocks)), block(sh.threads);
-    if (sh.rows == 64 && sh.threads == 256)
+    if (sh.per_cu == 3)
+        hipLaunchKernelGGL((fused_update_kernel<64, 256, 3, true>), grid, block, bytes, s, a);
+    else if (sh.rows == 64 && sh.threads == 256)
         hipLaunchKernelGGL((fused_update_kernel<64, 256, 2>), grid, block, bytes, s, a);
     else if (sh.rows == 32 && sh.threads == 256)
         hipLaunchKernelGGL((fused_update_kernel<32, 256, 2>), grid, block, bytes, s, a);

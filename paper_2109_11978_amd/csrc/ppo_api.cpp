@@ -1008,8 +1008,9 @@ FusedShape fused_shape_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &
     const NetLayout &g = c->g;
     const char *rows = std::getenv("PPO_FUSED_ROWS");
     const char *threads = std::getenv("PPO_FUSED_THREADS");
+    const char *per_cu = inference ? nullptr : std::getenv("PPO_FUSED_PER_CU");
     FusedShape sh = fused_shape(g.L, g.H, w.kpad, g.A, rows ? std::atoi(rows) : 0, threads ? std::atoi(threads) : 0,
-                                !inference);
+                                !inference, per_cu ? std::atoi(per_cu) : 0);
     if (sh.rows == 0) return none;
     if (inference && !rows && !threads) {
         // inference of a policy step is latency-bound (a few hundred
@@ -1149,6 +1150,7 @@ hipError_t enqueue_step(const ppo_ctx *c, const ppo_params *p, const ppo_hparams
         fa.ratio_out = sb.ratio_out;
         fa.R = fsh.rows;
         fa.NT = fsh.threads;
+        fa.per_cu = fsh.per_cu;
         PROFILED(prof, PPO_PHASE_FUSED, launch_fused_update(fa, s));
     } else {
         PROFILED(prof, PPO_PHASE_GATHER, launch_stage_weights(prec, build_stage(c, p, w, ws, true), s));
@@ -1909,6 +1911,7 @@ hipError_t enqueue_batched_step(std::vector<BatchedRun> &runs, const ppo_hparams
             FusedArgs fa = fused_args(r.c, r.p, hp, r.w, r.ws, r.b, idx, r.M);
             fa.R = fsh[i].rows;
             fa.NT = fsh[i].threads;
+            fa.per_cu = fsh[i].per_cu;
             e = launch_fused_update(fa, run_stream(i));
             if (e != hipSuccess) return e;
             continue;
@@ -2281,8 +2284,9 @@ int fused_shape_query(const ppo_ctx *c, int32_t *rows, int32_t *threads, bool in
     const WsPlan w = plan_workspace(c->g, c->prec, 0, 0, 1);
     const char *r = std::getenv("PPO_FUSED_ROWS");
     const char *t = std::getenv("PPO_FUSED_THREADS");
+    const char *pc = inference ? nullptr : std::getenv("PPO_FUSED_PER_CU");
     FusedShape sh = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, r ? std::atoi(r) : 0, t ? std::atoi(t) : 0,
-                                !inference);
+                                !inference, pc ? std::atoi(pc) : 0);
     if (inference && sh.rows && !r && !t) {
         const FusedShape wide = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, 64, 256);
         if (wide.rows) sh = wide;

@@ -217,13 +217,18 @@ def test_adaptive_rate_validation():
     ((48, 12, (64, 64)), "bf16", {}, (64, 256)),        # two feature blocks: two waves each over 64 rows
     ((48, 12, (64, 64)), "bf16", {"PPO_FUSED_ROWS": "64", "PPO_FUSED_THREADS": "256"}, (64, 256)),
     ((48, 12, (32, 32)), "bf16", {}, (0, 0)),           # one feature block for four waves
+    # three workgroups per CU stream the first layer in 128-feature chunks
+    ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_PER_CU": "3"}, (64, 256)),
+    ((48, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_PER_CU": "2"}, (64, 256)),
+    ((235, 12, (512, 256, 128)), "bf16", {"PPO_FUSED_PER_CU": "3"}, (0, 0)),   # 240-wide inputs: over a third of LDS
+    ((48, 12, (64, 64)), "bf16", {"PPO_FUSED_PER_CU": "3"}, (0, 0)),           # first layer narrower than a chunk
     ((40, 12, (512, 256, 128)), "bf16", {}, (0, 0)),    # input width not a multiple of 16
     ((48, 12, (384, 256, 128)), "bf16", {}, (0, 0)),    # 12 feature blocks over 4 waves: 3 per wave
 ])
 def test_fused_shape_selection(monkeypatch, shape, prec, env, expect):
     """Which bf16 update steps take the fused per-sample pass, and its block
     shape (host-side rule; no GPU needed)."""
-    for k in ("PPO_FUSED", "PPO_FUSED_ROWS", "PPO_FUSED_THREADS"):
+    for k in ("PPO_FUSED", "PPO_FUSED_ROWS", "PPO_FUSED_THREADS", "PPO_FUSED_PER_CU"):
         monkeypatch.delenv(k, raising=False)
     for k, v in env.items():
         monkeypatch.setenv(k, v)

@@ -27,7 +27,7 @@ class _Fused:
     """Sets PPO_FUSED (and optionally the block shape) for the duration of a
     block; the library reads them at every call."""
 
-    KEYS = ("PPO_FUSED", "PPO_FUSED_ROWS", "PPO_FUSED_THREADS")
+    KEYS = ("PPO_FUSED", "PPO_FUSED_ROWS", "PPO_FUSED_THREADS", "PPO_FUSED_PER_CU")
 
     def __init__(self, on, shape=None):
         self.on = on
@@ -41,6 +41,8 @@ class _Fused:
         if self.shape:
             os.environ["PPO_FUSED_ROWS"] = str(self.shape[0])
             os.environ["PPO_FUSED_THREADS"] = str(self.shape[1])
+            if len(self.shape) > 2:
+                os.environ["PPO_FUSED_PER_CU"] = str(self.shape[2])
 
     def __exit__(self, *exc):
         for k, v in self.old.items():
@@ -68,16 +70,18 @@ def _loss_grad(ctx, theta, batch, idx, d, fused, hp=None, shape=None):
     grad = torch.zeros(ctx.param_count, device=d)
     ws = ctx.new_workspace(M=len(idx))
     with _Fused(fused, shape):
-        assert (ctx.fused_shape() == tuple(shape or ctx.fused_shape())) and (ctx.fused_shape()[0] > 0) == fused
+        assert (ctx.fused_shape() == tuple(shape or ctx.fused_shape())[:2]) and (ctx.fused_shape()[0] > 0) == fused
         ppo.ppo_loss_grad(ctx, params, tb, dev(idx, d), hp or ppo.UpdateHParams(), stats, grad, ws)
     torch.cuda.synchronize()
     return grad.cpu().numpy(), stats.cpu().numpy()
 
 
-# every block shape the library can launch: (64, 256), (32, 256) and (64, 512)
-# by default, (32, 512) when asked for
+# every block shape the library can launch: 64 x 256 three per CU (the first
+# layer streamed), 64 x 256 and 32 x 256 two per CU and 64 x 512 by default,
+# 32 x 512 when asked for
 SHAPES = [("flat", 24576, None), ("flat", 1000, (64, 512)), ("rough", 777, None), ("large", 333, None),
-          ("flat", 10, (64, 256)), ("large", 31, (32, 512)), ("tiny", 1536, (64, 256)), ("rough", 4096, (64, 512))]
+          ("flat", 10, (64, 256)), ("large", 31, (32, 512)), ("tiny", 1536, (64, 256)), ("rough", 4096, (64, 512)),
+          ("flat", 24576, (64, 256, 2)), ("flat", 1000, (64, 256, 3)), ("flat", 77, (64, 256, 3))]
 
 
 @pytest.mark.parametrize("name,M,shape", SHAPES)
