@@ -387,9 +387,9 @@ int ppo_ctx_tuning(const ppo_ctx *ctx, int32_t rows, int32_t update, int32_t *ch
 int ppo_fused_shape(const ppo_ctx *ctx, int32_t *rows, int32_t *threads);
 
 /* The same for bf16 inference (ppo_rollout_infer): without PPO_FUSED_ROWS /
- * PPO_FUSED_THREADS it prefers 64 rows x 256 threads where that block fits,
- * since a policy step is latency-bound and each weight fragment then feeds two
- * products.  Host only. */
+ * PPO_FUSED_THREADS it prefers 32 rows x 256 threads (two workgroups per
+ * CU): a policy step over a few thousand environments is latency-bound, and
+ * more, shorter workgroups finish it sooner.  Host only. */
 int ppo_fused_infer_shape(const ppo_ctx *ctx, int32_t *rows, int32_t *threads);
 
 /* Terrain seen by the height scan: a height field on a uniform grid and the

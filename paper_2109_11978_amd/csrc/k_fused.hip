@@ -1659,13 +1659,12 @@ FusedShape fused_shape(int L, const int *H, int kpad, int A, int prefer_rows, in
     FusedShape none{0, 0, 0};
     if (L < 1 || L > kMaxHidden || A < 1 || A > kFusedMaxAct || kpad < 16 || kpad % 16 != 0) return none;
     // inference candidates (the update pass's are below) in order of
-    // preference: 32 rows x 4 waves with two workgroups per CU (one hides the
-    // other's prologue, head and barrier latencies); 64 rows x 8 waves (each
-    // weight fragment feeds two MFMAs, two waves per SIMD, one workgroup per
-    // CU).  Inference shapes with one workgroup of 32 rows per CU (wider
-    // networks, e.g. [1024, 512, 256]) or of 4 waves lose to the
-    // layer-by-layer GEMMs, which those widths keep busy; they run only when
-    // asked for by rows and threads.
+    // preference: 32 rows x 4 waves with two workgroups per CU (a policy step
+    // is latency-bound: more, shorter workgroups; one hides the other's
+    // prologue, head and barrier latencies); 64 rows x 8 waves (each weight
+    // fragment feeds two MFMAs, two waves per SIMD, one workgroup per CU).
+    // The shapes with one workgroup of 32 rows or of 4 waves per CU run only
+    // when asked for by rows and threads.
     if (update) {
         // the update pass's LDS plan holds about one wide layer: 64 samples x
         // 4 waves with two workgroups per CU first (each weight fragment feeds

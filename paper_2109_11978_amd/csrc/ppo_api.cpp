@@ -1012,13 +1012,6 @@ FusedShape fused_shape_for(const ppo_ctx *c, const ppo_params *p, const WsPlan &
     FusedShape sh = fused_shape(g.L, g.H, w.kpad, g.A, rows ? std::atoi(rows) : 0, threads ? std::atoi(threads) : 0,
                                 !inference, per_cu ? std::atoi(per_cu) : 0);
     if (sh.rows == 0) return none;
-    if (inference && !rows && !threads) {
-        // inference of a policy step is latency-bound (a few hundred
-        // workgroups): 64 rows per workgroup let each weight fragment feed two
-        // MFMAs, which shortens every workgroup's weight stream
-        const FusedShape wide = fused_shape(g.L, g.H, w.kpad, g.A, 64, 256);
-        if (wide.rows) sh = wide;
-    }
     if (static_cast<long long>(obs_rows) * g.D * 4 > 0x7FFFFFF0LL - 0x100000LL) return none;
     for (int net = 0; net < 2; ++net)
         for (int l = 0; l < g.L; ++l)
@@ -2287,10 +2280,6 @@ int fused_shape_query(const ppo_ctx *c, int32_t *rows, int32_t *threads, bool in
     const char *pc = inference ? nullptr : std::getenv("PPO_FUSED_PER_CU");
     FusedShape sh = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, r ? std::atoi(r) : 0, t ? std::atoi(t) : 0,
                                 !inference, pc ? std::atoi(pc) : 0);
-    if (inference && sh.rows && !r && !t) {
-        const FusedShape wide = fused_shape(c->g.L, c->g.H, w.kpad, c->g.A, 64, 256);
-        if (wide.rows) sh = wide;
-    }
     *rows = sh.rows;
     *threads = sh.threads;
     return PPO_OK;

@@ -277,19 +277,19 @@ def test_ctx_set_option_validation():
 
 
 def test_fused_infer_shape_selection(monkeypatch):
-    """bf16 inference prefers 64 rows x 256 threads where that block fits and
-    the update would take the fused pass at all; shapes forced through the
-    environment apply to both."""
-    for k in ("PPO_FUSED", "PPO_FUSED_ROWS", "PPO_FUSED_THREADS"):
+    """bf16 inference prefers 32 rows x 256 threads (two workgroups per CU)
+    where that block fits; shapes forced through the environment apply to
+    both inference and the update."""
+    for k in ("PPO_FUSED", "PPO_FUSED_ROWS", "PPO_FUSED_THREADS", "PPO_FUSED_PER_CU"):
         monkeypatch.delenv(k, raising=False)
     flat = ppo.Context(48, 12, (512, 256, 128), "bf16")
-    assert flat.fused_infer_shape() == (64, 256)
+    assert flat.fused_infer_shape() == (32, 256)
     assert flat.fused_shape() == (64, 256)
     for H in ((1024, 512, 256), (64, 64)):
         assert ppo.Context(235, 12, H, "bf16").fused_infer_shape() == (0, 0)
     assert ppo.Context(48, 12, (512, 256, 128), "fp32").fused_infer_shape() == (0, 0)
-    monkeypatch.setenv("PPO_FUSED_ROWS", "32")
-    monkeypatch.setenv("PPO_FUSED_THREADS", "256")
-    assert flat.fused_infer_shape() == (32, 256)
+    monkeypatch.setenv("PPO_FUSED_ROWS", "64")
+    monkeypatch.setenv("PPO_FUSED_THREADS", "512")
+    assert flat.fused_infer_shape() == (64, 512)
     monkeypatch.setenv("PPO_FUSED", "0")
     assert flat.fused_infer_shape() == (0, 0)
