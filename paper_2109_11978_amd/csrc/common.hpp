@@ -204,6 +204,7 @@ struct FusedArgs {
     // layer's output comes in chunks of chunk0 features at lds_cb, each added
     // into the second layer's accumulators as soon as it is written
     int lds_cb, chunk0;
+    int defer_in;                     // the loss inputs load during the first layer after the streamed pair
     int bias_off[kMaxHidden];         // floats into the staged biases
 };
 // Samples per workgroup and threads per workgroup of the fused pass for this

@@ -818,6 +818,41 @@ __device__ __forceinline__ void head_mfma(const FusedArgs &a, const FusedNet &N,
     }
 }
 
+// Loss inputs of the block's samples into s_in [R][kInW]: TPS = NT / R
+// threads per sample, each loading columns part, part + TPS, ... of the
+// actions and collection-time means and one of the four per-sample scalars
+// (log-probability and advantage for the actor, return and old value for the
+// critic).  load() only issues the loads; store() writes them to LDS.
+template <int R, int NT>
+struct LossInputs {
+    static constexpr int TPS = NT / R;
+    float v[2 * (kFusedMaxAct / TPS) + 1];
+    __device__ __forceinline__ void load(const FusedArgs &a, const int *s_rows, int net, int tid) {
+        const int i = tid / TPS, part = tid - (tid / TPS) * TPS;
+        const int A = a.A;
+        const long long row = s_rows[i];
+#pragma unroll
+        for (int u = 0; u < kFusedMaxAct / TPS; ++u) {
+            const int j = part + TPS * u;
+            v[2 * u] = net == 0 && j < A ? a.actions[row * A + j] : 0.0f;
+            v[2 * u + 1] = net == 0 && j < A && a.mu_old ? a.mu_old[row * A + j] : 0.0f;
+        }
+        const float *sc = part == 0 ? a.logp_old : part == 1 ? a.adv : part == 2 ? a.returns : a.values_old;
+        const bool want = part < 4 && (part < 2 ? net == 0 : net == 1) && (part != 3 || a.clip_value);
+        v[2 * (kFusedMaxAct / TPS)] = want ? sc[row] : 0.0f;
+    }
+    __device__ __forceinline__ void store(float *s_in, int tid) const {
+        const int i = tid / TPS, part = tid - (tid / TPS) * TPS;
+#pragma unroll
+        for (int u = 0; u < kFusedMaxAct / TPS; ++u) {
+            const int j = part + TPS * u;
+            s_in[i * kInW + j] = v[2 * u];
+            s_in[i * kInW + kFusedMaxAct + j] = v[2 * u + 1];
+        }
+        if (part < 4) s_in[i * kInW + 2 * kFusedMaxAct + part] = v[2 * (kFusedMaxAct / TPS)];
+    }
+};
+
 // The first two hidden layers with the first one's output in chunks of
 // chunk0 features (one feature block per wave): each chunk goes through
 // ELU into the chunk buffer, is copied to global memory (a weight-gradient
@@ -937,28 +972,13 @@ void fused_update_kernel(const FusedArgs a) {
     uint16_t *x = reinterpret_cast<uint16_t *>(reg);
     const int xp = a.kpad + 8;
     {
-        // loss inputs: TPS threads per sample, columns part, part + TPS, ...
-        constexpr int TPS = NT / R;
-        const int i = tid / TPS, part = tid - (tid / TPS) * TPS;
-        const long long row = s_rows[i];
-        float v[2 * (kFusedMaxAct / TPS) + 1];
-#pragma unroll
-        for (int u = 0; u < kFusedMaxAct / TPS; ++u) {
-            const int j = part + TPS * u;
-            v[2 * u] = net == 0 && j < A ? a.actions[row * A + j] : 0.0f;
-            v[2 * u + 1] = net == 0 && j < A && a.mu_old ? a.mu_old[row * A + j] : 0.0f;
-        }
-        const float *sc = part == 0 ? a.logp_old : part == 1 ? a.adv : part == 2 ? a.returns : a.values_old;
-        const bool want = part < 4 && (part < 2 ? net == 0 : net == 1) && (part != 3 || a.clip_value);
-        v[2 * (kFusedMaxAct / TPS)] = want ? sc[row] : 0.0f;
+        // the loss inputs in the same round as the observation rows, unless
+        // the LDS plan defers them (their place is in use until the head's
+        // last layer: they load during that layer's MMA loop)
+        LossInputs<R, NT> li;
+        if (!a.defer_in) li.load(a, s_rows, net, tid);
         gather_rows<R, NT>(a, s_rows, rows, x, xp, wave, lane);
-#pragma unroll
-        for (int u = 0; u < kFusedMaxAct / TPS; ++u) {
-            const int j = part + TPS * u;
-            s_in[i * kInW + j] = v[2 * u];
-            s_in[i * kInW + kFusedMaxAct + j] = v[2 * u + 1];
-        }
-        if (part < 4) s_in[i * kInW + 2 * kFusedMaxAct + part] = v[2 * (kFusedMaxAct / TPS)];
+        if (!a.defer_in) li.store(s_in, tid);
     }
     __syncthreads();
 
@@ -1000,6 +1020,11 @@ void fused_update_kernel(const FusedArgs a) {
                 } else {
                     copy_out<NT>(in, Hp + 8, N.h[l - 1] + static_cast<long long>(m0) * Hp, Hp, Hp, rows);
                 }
+                if (a.defer_in && l == l0 && l0 > 0) {
+                    LossInputs<R, NT> li;
+                    li.load(a, s_rows, net, tid);
+                    li.store(s_in, tid);
+                }
             };
             // the critic's weights come in the split layout (bf16 and residual fragments)
             if (net == 1)
@@ -1021,6 +1046,12 @@ void fused_update_kernel(const FusedArgs a) {
     float *w_out = reinterpret_cast<float *>(reg + a.lds_w);
     float *s_sum = reinterpret_cast<float *>(reg + a.lds_sum);   // [R][kSums] per-sample loss terms
     {
+        if (a.defer_in && L == 2) {
+            // deferred loss inputs with no layer after the streamed pair to hide them
+            LossInputs<R, NT> li;
+            li.load(a, s_rows, net, tid);
+            li.store(s_in, tid);
+        }
         constexpr int UW = 16;
         const int nw = n_out * Hl;
         const __amdgpu_buffer_rsrc_t rw = make_rsrc(N.Wout, static_cast<long long>(nw) * 4);
@@ -1561,12 +1592,15 @@ size_t fused_update_layout(int L, const int *H, int kpad, int A, int R, int NT, 
 // second layer's output at the start once every chunk has been added in,
 // and each later layer's output over its input.  Head: the last hidden layer
 // at the start, then the output-layer weights, the per-sample loss terms and
-// the output gradients.  Then the loss inputs, biases, row indices and head
-// constants, which the backward chain may overwrite (none of them is read
-// after the head): dz_{L-1} in place over h_{L-1} at the start, each staged
-// ELU' input next to its incoming gradient, the first hidden layer's
-// gradient in the widest chunk that fits.  Returns the total bytes, 0 if the
-// network does not fit or does not split this way.
+// the output gradients.  The loss inputs load during the first layer after
+// the streamed pair (defer_in) into space that is free from then until the
+// head: behind the head's areas and that layer's input and output.  The
+// biases, row indices and head constants, needed from the prologue on, sit
+// behind everything the forward pass uses.  The backward chain may overwrite
+// all of these (none is read after the head): dz_{L-1} in place over h_{L-1}
+// at the start, each staged ELU' input next to its incoming gradient, the
+// first hidden layer's gradient in the widest chunk that fits.  Returns the
+// total bytes, 0 if the network does not fit or does not split this way.
 size_t fused_stream_layout(int L, const int *H, int kpad, int A, int R, int NT, size_t budget, FusedArgs *a) {
     (void)A;
     if (L < 2) return 0;
@@ -1589,7 +1623,6 @@ size_t fused_stream_layout(int L, const int *H, int kpad, int A, int R, int NT, 
         fixed += align16(bytes);
         return at;
     };
-    const size_t in_off = take(static_cast<size_t>(R) * kInW * 4);
     int bias_off[kMaxHidden] = {0};
     size_t nb = 0;
     for (int l = 0; l < L; ++l) {
@@ -1605,7 +1638,13 @@ size_t fused_stream_layout(int L, const int *H, int kpad, int A, int R, int NT, 
     const size_t sbytes = align16(static_cast<size_t>(R + 1) * kSums * 4);
     const size_t gb = align16(static_cast<size_t>(R) * kFusedMaxAct * 4);
     const size_t w_off = P(Hl), s_off = w_off + wb, g_off = s_off + sbytes;
-    const size_t pers = align16(std::max(fwd, g_off + gb));
+    // from the layer the loss inputs load during to the head: each layer's
+    // input at the start and its output over it
+    size_t late = 0;
+    for (int l = 1; l < L; ++l) late = std::max(late, P(H[l]));
+    const size_t in_off = align16(std::max(late, g_off + gb));
+    const size_t in_end = in_off + align16(static_cast<size_t>(R) * kInW * 4);
+    const size_t pers = align16(std::max(fwd, in_end));
     for (int C = H[0]; C >= 32; C /= 2) {
         if (H[0] % C != 0 || !width_splits(C, NW, SB, false, regs)) continue;
         size_t bdz[kMaxHidden] = {0}, bst[kMaxHidden] = {0};
@@ -1622,7 +1661,8 @@ size_t fused_stream_layout(int L, const int *H, int kpad, int A, int R, int NT, 
         const size_t total = align16(ext);
         if (total > budget) continue;
         if (a) {
-            a->lds_in = static_cast<int>(pers + in_off);
+            a->lds_in = static_cast<int>(in_off);
+            a->defer_in = 1;
             a->lds_bias = static_cast<int>(pers + bias);
             a->lds_rows = static_cast<int>(pers + rows_off);
             a->lds_head = static_cast<int>(pers + head);
