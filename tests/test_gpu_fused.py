@@ -77,11 +77,13 @@ def _loss_grad(ctx, theta, batch, idx, d, fused, hp=None, shape=None):
 
 
 # every block shape the library can launch: 64 x 256 three per CU (the first
-# layer streamed), 64 x 256 and 32 x 256 two per CU and 64 x 512 by default,
-# 32 x 512 when asked for
+# layer streamed; for rough's 240-wide inputs with the loss inputs loaded
+# after the streamed pair), 64 x 256 and 32 x 256 two per CU and 64 x 512 by
+# default, 32 x 512 when asked for
 SHAPES = [("flat", 24576, None), ("flat", 1000, (64, 512)), ("rough", 777, None), ("large", 333, None),
           ("flat", 10, (64, 256)), ("large", 31, (32, 512)), ("tiny", 1536, (64, 256)), ("rough", 4096, (64, 512)),
-          ("flat", 24576, (64, 256, 2)), ("flat", 1000, (64, 256, 3)), ("flat", 77, (64, 256, 3))]
+          ("flat", 24576, (64, 256, 2)), ("flat", 1000, (64, 256, 3)), ("flat", 77, (64, 256, 3)),
+          ("rough", 24576, (64, 256, 2)), ("rough", 77, (64, 256, 3))]
 
 
 @pytest.mark.parametrize("name,M,shape", SHAPES)
