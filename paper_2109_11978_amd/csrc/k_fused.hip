@@ -973,8 +973,9 @@ void fused_update_kernel(const FusedArgs a) {
     const int xp = a.kpad + 8;
     {
         // the loss inputs in the same round as the observation rows, unless
-        // the LDS plan defers them (their place is in use until the head's
-        // last layer: they load during that layer's MMA loop)
+        // the LDS plan defers them (their place is in use until the streamed
+        // pair is done: they load during the next layer's MMA loop, or before
+        // the head when no layer follows the pair)
         LossInputs<R, NT> li;
         if (!a.defer_in) li.load(a, s_rows, net, tid);
         gather_rows<R, NT>(a, s_rows, rows, x, xp, wave, lane);
