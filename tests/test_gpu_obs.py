@@ -60,24 +60,27 @@ def test_assemble_matches_oracle(N, P, S, margin):
             assert_close(f"obs N={N} S={S}", got, ref, TOL["fp32"])
 
 
-def test_cell_choices_bit_exact():
+# 2048 robots: 2 per workgroup; 16384: full workgroups of 16 robots, with and
+# without the far random scan points
+@pytest.mark.parametrize("N,far", [(2048, True), (16384, True), (16384, False)])
+def test_cell_choices_bit_exact(N, far):
     """A height field whose every cell is a distinct integer, z = 0 and no
     noise: the output names the cell each scan point read; it must be the
     oracle's float32 decision, including exact half-cell positions (round half
     to even), robots far off the field (clamped) and a NaN position (cell 0)."""
     d = require_gpu()
-    _announce("assemble_obs cell choices")
+    _announce(f"assemble_obs cell choices N={N} far={far}")
     rng = np.random.default_rng(5)
     nx, ny = 300, 200
     H = (np.arange(nx)[:, None] * 1024 + np.arange(ny)[None, :]).astype(f32)
-    N = 2048
     base = shf.base_poses(rng, N, 30.0, margin=-15.0)
     base[:, 2] = 0.0
     # exact halves in binary on the heading-0 axis with a zero offset point
     base[:8] = np.array([[0.25, 0.75, 0, 1, 0], [1.25, 0.25, 0, 1, 0], [2.75, 3.25, 0, 1, 0],
                          [-0.25, 0.05, 0, 1, 0], [29.95, 19.95, 0, 1, 0], [1e9, -1e9, 0, 1, 0],
                          [np.nan, 0.5, 0, 1, 0], [0.5, np.nan, 0, -0.0, 1]], dtype=f32)
-    scan = np.concatenate([np.zeros((1, 2), f32), shf.scan_pattern(), rng.uniform(-3, 3, (12, 2)).astype(f32)])
+    far_points = rng.uniform(-3, 3, (12, 2)).astype(f32)
+    scan = np.concatenate([np.zeros((1, 2), f32), shf.scan_pattern()] + ([far_points] if far else []))
     S = len(scan)
     ctx = ppo.Context(S, 12, (64,), "bf16")
     got = _run(ctx, d, N, None, base, H, scan, None)
