@@ -322,7 +322,11 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
 // Registers for a layer's accumulators and fragment ring per lane: 512 /
 // WPE, less what the addresses, activation fragments and epilogue keep live
 // (and, at three workgroups per CU, the streamed first layer's accumulators).
-constexpr int layer_regs(int wpe, int sb) { return wpe == 1 ? 320 : (wpe >= 3 ? 112 : (sb >= 2 ? 160 : 192)); }
+// At three workgroups per CU the budget is lower than that on purpose: a
+// one-block layer then keeps 8 fragments in flight rather than 16, and the
+// twelve waves' shorter bursts queue less at the CU's shared memory pipe
+// (measured faster).
+constexpr int layer_regs(int wpe, int sb) { return wpe == 1 ? 320 : (wpe >= 3 ? 80 : (sb >= 2 ? 160 : 192)); }
 
 // One layer for all R samples of the block.  The layer's 32-feature blocks
 // are split over the NT / 64 waves; when there are fewer blocks than waves,
