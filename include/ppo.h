@@ -58,7 +58,8 @@
  *     float32 rounding (bf16 ulps downstream of it).  Where it fits, the
  *     fused pass runs three 64-sample workgroups per CU with the first hidden
  *     layer computed in 128-feature chunks, each added into the second
- *     layer's accumulators at once (e.g. [512, 256, 128] with 48 inputs).
+ *     layer's accumulators at once (e.g. [512, 256, 128] with 48 or 235
+ *     inputs; with 235 the loss inputs load after the first two layers).
  *     PPO_FUSED=0 forces the layer-by-layer kernels; PPO_FUSED_ROWS=32 or 64
  *     (and PPO_FUSED_THREADS=256 or 512, PPO_FUSED_PER_CU=2 or 3) override
  *     the fused pass's block shape.
@@ -289,11 +290,16 @@ int ppo_update_epoch(ppo_ctx *ctx, void *stream, const ppo_params *p, const ppo_
  * (sweep-style training of several policies at once, each with its own
  * network shape, data, permutation, optimiser state and workspace).  Runs
  * must share the precision, the number of hidden layers and n_minibatches;
- * observation widths, hidden widths and batch sizes may differ.  Mini-batch
- * step k of every run goes through one grouped launch per GEMM site (all
- * runs' actor and critic problems in one grid) with per-run gather, loss,
- * gradient-reduce and Adam kernels in between; with hp->use_graph the whole
- * batched epoch is one cached HIP graph.  The first call for a set of run
+ * observation widths, hidden widths and batch sizes may differ.  When every
+ * run takes the fused pass (bf16, widths it covers), each run's whole epoch
+ * runs on one of four side streams forked from `stream` and joined back to
+ * it, runs placed largest first on the least-loaded stream, so the runs
+ * proceed independently and the small ones fill the workgroup slots the
+ * large ones leave free.  Otherwise (or with PPO_BATCHED_GROUPED=1),
+ * mini-batch step k of every run goes through one grouped launch per GEMM
+ * site (all runs' actor and critic problems in one grid) with per-run
+ * gather, loss, gradient-reduce and Adam kernels in between.  With
+ * hp->use_graph the whole batched epoch is one cached HIP graph.  The first call for a set of run
  * shapes times the tile candidates of every grouped site (see autotuning
  * above) and gives the weight-gradient workgroups of all runs one common
  * k-length.  With PPO_AUTOTUNE=0 every site uses 128 x 128 tiles and each
