@@ -325,8 +325,10 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
 // At three workgroups per CU the budget is lower than that on purpose: a
 // one-block layer then keeps 8 fragments in flight rather than 16, and the
 // twelve waves' shorter bursts queue less at the CU's shared memory pipe
-// (measured faster).
-constexpr int layer_regs(int wpe, int sb) { return wpe == 1 ? 320 : (wpe >= 3 ? 80 : (sb >= 2 ? 160 : 192)); }
+// (measured faster).  Likewise for one sample block at two per CU (rollout
+// inference): 128, not 192, so the first layer's four feature blocks keep 4
+// k-steps in flight rather than 8 (measured faster).
+constexpr int layer_regs(int wpe, int sb) { return wpe == 1 ? 320 : (wpe >= 3 ? 80 : (sb >= 2 ? 160 : 128)); }
 
 // One layer for all R samples of the block.  The layer's 32-feature blocks
 // are split over the NT / 64 waves; when there are fewer blocks than waves,
