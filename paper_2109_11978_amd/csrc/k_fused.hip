@@ -326,9 +326,10 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
 // one-block layer then keeps 8 fragments in flight rather than 16, and the
 // twelve waves' shorter bursts queue less at the CU's shared memory pipe
 // (measured faster).  Likewise for one sample block at two per CU (rollout
-// inference): 128, not 192, so the first layer's four feature blocks keep 4
-// k-steps in flight rather than 8 (measured faster).
-constexpr int layer_regs(int wpe, int sb) { return wpe == 1 ? 320 : (wpe >= 3 ? 80 : (sb >= 2 ? 160 : 128)); }
+// inference): 64, not 192, so a layer of four or two feature blocks per wave
+// keeps 4 k-steps in flight rather than 8 or 16, and a one-block layer 8
+// rather than 32 (measured faster at each step down).
+constexpr int layer_regs(int wpe, int sb) { return wpe == 1 ? 320 : (wpe >= 3 ? 80 : (sb >= 2 ? 160 : 64)); }
 
 // One layer for all R samples of the block.  The layer's 32-feature blocks
 // are split over the NT / 64 waves; when there are fewer blocks than waves,
