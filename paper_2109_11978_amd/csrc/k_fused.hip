@@ -328,8 +328,10 @@ __device__ __forceinline__ void layer_fb(int fbw, int S, const uint16_t *W, int 
 // (measured faster).  Likewise for one sample block at two per CU (rollout
 // inference): 64, not 192, so a layer of four or two feature blocks per wave
 // keeps 4 k-steps in flight rather than 8 or 16, and a one-block layer 8
-// rather than 32 (measured faster at each step down).
-constexpr int layer_regs(int wpe, int sb) { return wpe == 1 ? 320 : (wpe >= 3 ? 80 : (sb >= 2 ? 160 : 64)); }
+// rather than 32 (measured faster at each step down); and for two sample
+// blocks at two waves per SIMD (the [1024, 512, 256] update): 128, not 160,
+// so its one-block layer keeps 16 rather than 32 (measured faster).
+constexpr int layer_regs(int wpe, int sb) { return wpe == 1 ? 320 : (wpe >= 3 ? 80 : (sb >= 2 ? 128 : 64)); }
 
 // One layer for all R samples of the block.  The layer's 32-feature blocks
 // are split over the NT / 64 waves; when there are fewer blocks than waves,
