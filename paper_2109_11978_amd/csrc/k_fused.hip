@@ -267,11 +267,13 @@ __device__ __forceinline__ void layer_pf(int S, const uint16_t *W, int K, int no
 
 // Deepest weight prefetch (k-steps) that keeps the accumulators (FBW x SBW
 // blocks of 16 registers) and the fragment ring (PF x FBW x 4 registers)
-// within REGS registers, at most 32 fragments, at least 4 steps.
+// within REGS registers, at most 8 fragments in flight per wave (deeper rings
+// measured slower: the waves of a CU share its memory pipe, and long bursts
+// queue there), at least 4 steps.
 template <int FBW, int SBW, int REGS>
 constexpr int pf_max() {
     int pf = 32 / FBW;
-    while (pf > 4 && FBW * SBW * 16 + pf * FBW * 4 > REGS) pf /= 2;
+    while (pf > 4 && (FBW * SBW * 16 + pf * FBW * 4 > REGS || pf * FBW > 8)) pf /= 2;
     return pf;
 }
 
