@@ -409,6 +409,39 @@ __device__ inline void gather_rows(const FusedArgs &a, const int *s_rows, int ro
     constexpr int NW = NT / 64;
     constexpr int PER_WAVE = R / NW;
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.obs, static_cast<long long>(a.B) * a.D * 4);
+    if ((a.D & 3) == 0) {
+        // rows start 16-byte aligned: four elements per lane and load, the
+        // wave's rows one after another over its lanes (four loads in flight)
+        constexpr int V = 4;
+        const int n4 = a.kpad >> 2;         // 4-element chunks per row (padded)
+        const int d4 = a.D >> 2;
+        const int total = PER_WAVE * n4;    // chunks per wave
+        for (int t0 = 0; t0 < total; t0 += V * 64) {
+            float4 v[V];
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const int t = min(t0 + 64 * u + lane, total - 1);
+                const int il = t / n4, c4 = t - il * n4;
+                const int i = wave + NW * il;
+                const bool ok = t0 + 64 * u + lane < total && i < rows && c4 < d4;
+                const int row = s_rows ? s_rows[i] : m0 + min(i, rows - 1);
+                const u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(rs, ok ? (row * a.D + 4 * c4) * 4 : kOutside, 0, 0);
+                v[u] = make_float4(__uint_as_float(w[0]), __uint_as_float(w[1]), __uint_as_float(w[2]),
+                                   __uint_as_float(w[3]));
+            }
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                const int t = t0 + 64 * u + lane;
+                if (t < total) {
+                    const int il = t / n4, c4 = t - il * n4;
+                    const int i = wave + NW * il;
+                    *reinterpret_cast<u32x2 *>(x + i * pitch + 4 * c4) =
+                        u32x2{pack2(v[u].x, v[u].y), pack2(v[u].z, v[u].w)};
+                }
+            }
+        }
+        return;
+    }
     const int cpr = (a.kpad + 63) >> 6;     // 64-element chunks per row
     const int total = PER_WAVE * cpr;       // loads per lane
     for (int t0 = 0; t0 < total; t0 += U) {
