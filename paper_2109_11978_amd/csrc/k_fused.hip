@@ -399,13 +399,12 @@ __device__ inline void copy_out(const uint16_t *src, int pitch, uint16_t *dst, i
 // Observation rows of the block (batch rows s_rows[0 .. R), or m0 .. m0 + R
 // when s_rows is null) as bf16 into
 // LDS, zero-padded to kpad columns and zero past the last valid row.  Wave w
-// takes rows w, w + NW, ...; a row's elements are spread over the lanes
-// (coalesced), and sixteen buffer loads are in flight per lane (out-of-range
-// ones read zero).
+// takes rows w, w + NW, ...; its lanes take consecutive 16-byte chunks of
+// those rows (coalesced), four loads in flight per lane (out-of-range ones
+// read zero).
 template <int R, int NT>
 __device__ inline void gather_rows(const FusedArgs &a, const int *s_rows, int rows, uint16_t *x, int pitch,
                                    int wave, int lane, int m0 = 0) {
-    constexpr int U = 16;
     constexpr int NW = NT / 64;
     constexpr int PER_WAVE = R / NW;
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(a.obs, static_cast<long long>(a.B) * a.D * 4);
@@ -442,28 +441,44 @@ __device__ inline void gather_rows(const FusedArgs &a, const int *s_rows, int ro
         }
         return;
     }
-    const int cpr = (a.kpad + 63) >> 6;     // 64-element chunks per row
-    const int total = PER_WAVE * cpr;       // loads per lane
-    for (int t0 = 0; t0 < total; t0 += U) {
-        float v[U];
+    // rows at any alignment: each lane loads one 16-byte aligned chunk of
+    // the buffer that overlaps the row and writes the row's elements in it.
+    // Row element k sits in chunk (k + off) / 4, slot (k + off) % 4, where
+    // off = (row D) mod 4, so chunks 0 .. kpad / 4 cover every padded column
+    // once; columns past D and rows past the block's last read as zero.
+    // The last row's last chunk may run up to 12 bytes past the buffer: the
+    // range is rounded up to 16 bytes (the same 16-byte granule, so the same
+    // page), and those elements fall in columns past D.
+    constexpr int V = 4;
+    const int n4 = (a.kpad >> 2) + 1;       // chunks per row
+    const int total = PER_WAVE * n4;        // chunks per wave
+    const __amdgpu_buffer_rsrc_t ru = make_rsrc(a.obs, (static_cast<long long>(a.B) * a.D * 4 + 15) & ~15LL);
+    for (int t0 = 0; t0 < total; t0 += V * 64) {
+        u32x4 w[V];
+        int e0[V];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = min(t0 + u, total - 1);
-            const int il = t / cpr;
-            const int k = 64 * (t - il * cpr) + lane;
+        for (int u = 0; u < V; ++u) {
+            const int t = min(t0 + 64 * u + lane, total - 1);
+            const int il = t / n4, c = t - il * n4;
             const int i = wave + NW * il;
-            const bool ok = t0 + u < total && i < rows && k < a.D;
-            // batch rows from LDS, or (s_rows null) the block's own rows m0, m0 + 1, ...
-            const int row = s_rows ? __builtin_amdgcn_readfirstlane(s_rows[i]) : m0 + min(i, rows - 1);
-            v[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, ok ? k * 4 : kOutside, row * a.D * 4, 0));
+            const int row = s_rows ? s_rows[i] : m0 + min(i, rows - 1);
+            e0[u] = row * a.D;
+            const bool ok = t0 + 64 * u + lane < total && i < rows;
+            w[u] = __builtin_amdgcn_raw_buffer_load_b128(ru, ok ? ((e0[u] >> 2) + c) * 16 : kOutside, 0, 0);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int t = t0 + u;
-            const int il = t / cpr;
-            const int k = 64 * (t - il * cpr) + lane;
+        for (int u = 0; u < V; ++u) {
+            const int t = t0 + 64 * u + lane;
+            if (t >= total) continue;
+            const int il = t / n4, c = t - il * n4;
             const int i = wave + NW * il;
-            if (t < total && k < a.kpad) x[i * pitch + k] = static_cast<uint16_t>(bf16_bits(v[u]));
+            const int k0 = 4 * c - (e0[u] & 3);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + q;
+                if (k >= 0 && k < a.kpad)
+                    x[i * pitch + k] = static_cast<uint16_t>(k < a.D ? bf16_bits(__uint_as_float(w[u][q])) : 0u);
+            }
         }
     }
 }
