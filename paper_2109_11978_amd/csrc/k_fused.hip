@@ -997,31 +997,22 @@ void fused_update_kernel(const FusedArgs a) {
         s_rows[tid] = r;
     }
     {
-        constexpr int UB = 4;
-        float vb[kMaxHidden][UB];
+        // hidden biases: one 16-byte load per thread and layer (the biases
+        // are 16-byte aligned and at most 4 NT wide)
+        u32x4 vb[kMaxHidden];
 #pragma unroll
         for (int l = 0; l < kMaxHidden; ++l) {
             const int H = l < L ? a.H[l] : 0;
             const __amdgpu_buffer_rsrc_t rb = make_rsrc(N.bias[l], static_cast<long long>(H) * 4);
-#pragma unroll
-            for (int u = 0; u < UB; ++u) {
-                const int q = tid + u * NT;
-                vb[l][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, q < H ? q * 4 : kOutside, 0, 0));
-            }
+            vb[l] = __builtin_amdgcn_raw_buffer_load_b128(rb, 4 * tid < H ? tid * 16 : kOutside, 0, 0);
         }
         const __amdgpu_buffer_rsrc_t ro = make_rsrc(N.bout, static_cast<long long>(n_out) * 4);
         const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.logstd, static_cast<long long>(A) * 4);
         const float vo = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ro, tid < n_out ? tid * 4 : kOutside, 0, 0));
         const float vl = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rl, tid < A ? tid * 4 : kOutside, 0, 0));
 #pragma unroll
-        for (int l = 0; l < kMaxHidden; ++l) {
-            if (l >= L) continue;
-#pragma unroll
-            for (int u = 0; u < UB; ++u) {
-                const int q = tid + u * NT;
-                if (q < a.H[l]) s_bias[a.bias_off[l] + q] = vb[l][u];
-            }
-        }
+        for (int l = 0; l < kMaxHidden; ++l)
+            if (l < L && 4 * tid < a.H[l]) *reinterpret_cast<u32x4 *>(s_bias + a.bias_off[l] + 4 * tid) = vb[l];
         if (tid < kFusedMaxAct) {
             s_head[tid] = tid < n_out ? vo : 0.0f;
             s_head[kFusedMaxAct + tid] = tid < A ? vl : 0.0f;
@@ -1112,21 +1103,21 @@ void fused_update_kernel(const FusedArgs a) {
             li.load(a, s_rows, net, tid);
             li.store(s_in, tid);
         }
-        constexpr int UW = 16;
+        constexpr int UW = 4;   // 4-element chunks (16-byte loads) of the output-layer weights per thread
         const int nw = n_out * Hl;
         const __amdgpu_buffer_rsrc_t rw = make_rsrc(N.Wout, static_cast<long long>(nw) * 4);
-        float vw[UW];
+        u32x4 vw[UW];
 #pragma unroll
         for (int u = 0; u < UW; ++u) {
-            const int q = tid + u * NT;
-            vw[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, q < nw ? q * 4 : kOutside, 0, 0));
+            const int q4 = tid + u * NT;
+            vw[u] = __builtin_amdgcn_raw_buffer_load_b128(rw, 4 * q4 < nw ? q4 * 16 : kOutside, 0, 0);
         }
         copy_out<NT>(hl, PL, N.h[L - 1] + static_cast<long long>(m0) * Hl, Hl, Hl, rows);
 #pragma unroll
         for (int u = 0; u < UW; ++u) {
-            const int q = tid + u * NT;
+            const int q = 4 * (tid + u * NT);
             const int j = q / Hl;
-            if (q < nw) w_out[j * WP + (q - j * Hl)] = vw[u];
+            if (q < nw) *reinterpret_cast<u32x4 *>(w_out + j * WP + (q - j * Hl)) = vw[u];
         }
         // zero rows of the output-layer weights past n_out (read by the
         // actor's kFusedMaxAct-wide head)
@@ -1134,8 +1125,8 @@ void fused_update_kernel(const FusedArgs a) {
             const int j = q / Hl;
             w_out[j * WP + (q - j * Hl)] = 0.0f;
         }
-        // output layers wider than UW loads per thread (not the paper's shapes)
-        for (int q = tid + UW * NT; q < nw; q += NT) {
+        // output layers wider than 4 UW elements per thread (not the paper's shapes)
+        for (int q = tid + 4 * UW * NT; q < nw; q += NT) {
             const int j = q / Hl;
             w_out[j * WP + (q - j * Hl)] = N.Wout[q];
         }
@@ -1333,24 +1324,22 @@ void fused_infer_kernel(const FusedArgs a) {
     {
         // output-layer weights, output biases, log-std and hidden biases in one
         // round of buffer loads, then the LDS stores (as in the update pass)
-        constexpr int UW = 16, UB = 4;
+        // 16-byte loads: the output-layer weights and the hidden biases are
+        // 16-byte aligned, rows of a multiple of 32 elements
+        constexpr int UW = 4;   // 4-element chunks of the output-layer weights per thread
         const int nw = n_out * Hl;
         const __amdgpu_buffer_rsrc_t rw = make_rsrc(N.Wout, static_cast<long long>(nw) * 4);
-        float vw[UW], vb[kMaxHidden][UB];
+        u32x4 vw[UW], vb[kMaxHidden];
 #pragma unroll
         for (int u = 0; u < UW; ++u) {
-            const int q = tid + u * NT;
-            vw[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rw, q < nw ? q * 4 : kOutside, 0, 0));
+            const int q4 = tid + u * NT;
+            vw[u] = __builtin_amdgcn_raw_buffer_load_b128(rw, 4 * q4 < nw ? q4 * 16 : kOutside, 0, 0);
         }
 #pragma unroll
         for (int l = 0; l < kMaxHidden; ++l) {
             const int H = l < L ? a.H[l] : 0;
             const __amdgpu_buffer_rsrc_t rb = make_rsrc(N.bias[l], static_cast<long long>(H) * 4);
-#pragma unroll
-            for (int u = 0; u < UB; ++u) {
-                const int q = tid + u * NT;
-                vb[l][u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rb, q < H ? q * 4 : kOutside, 0, 0));
-            }
+            vb[l] = __builtin_amdgcn_raw_buffer_load_b128(rb, 4 * tid < H ? tid * 16 : kOutside, 0, 0);
         }
         const __amdgpu_buffer_rsrc_t ro = make_rsrc(N.bout, static_cast<long long>(n_out) * 4);
         const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.logstd, static_cast<long long>(A) * 4);
@@ -1361,19 +1350,13 @@ void fused_infer_kernel(const FusedArgs a) {
         gather_rows<R, NT>(a, nullptr, rows, x, xp, wave, lane, m0);
 #pragma unroll
         for (int u = 0; u < UW; ++u) {
-            const int q = tid + u * NT;
+            const int q = 4 * (tid + u * NT);
             const int j = q / Hl;
-            if (q < nw) w_out[j * WP + (q - j * Hl)] = vw[u];
+            if (q < nw) *reinterpret_cast<u32x4 *>(w_out + j * WP + (q - j * Hl)) = vw[u];
         }
 #pragma unroll
-        for (int l = 0; l < kMaxHidden; ++l) {
-            if (l >= L) continue;
-#pragma unroll
-            for (int u = 0; u < UB; ++u) {
-                const int q = tid + u * NT;
-                if (q < a.H[l]) s_bias[a.bias_off[l] + q] = vb[l][u];
-            }
-        }
+        for (int l = 0; l < kMaxHidden; ++l)
+            if (l < L && 4 * tid < a.H[l]) *reinterpret_cast<u32x4 *>(s_bias + a.bias_off[l] + 4 * tid) = vb[l];
         if (tid < kFusedMaxAct) {
             s_head[tid] = tid < n_out ? vo : 0.0f;
             s_head[kFusedMaxAct + tid] = tid < A ? vl : 0.0f;
@@ -1382,7 +1365,7 @@ void fused_infer_kernel(const FusedArgs a) {
             const int j = q / Hl;
             w_out[j * WP + (q - j * Hl)] = 0.0f;
         }
-        for (int q = tid + UW * NT; q < nw; q += NT) {
+        for (int q = tid + 4 * UW * NT; q < nw; q += NT) {
             const int j = q / Hl;
             w_out[j * WP + (q - j * Hl)] = N.Wout[q];
         }
