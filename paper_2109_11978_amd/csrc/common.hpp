@@ -205,6 +205,7 @@ struct FusedArgs {
     // into the second layer's accumulators as soon as it is written
     int lds_cb, chunk0;
     int defer_in;                     // the loss inputs load during the first layer after the streamed pair
+    int vec_out;                      // inference: actions and means by 16-byte stores (A % 4 == 0, 16-byte aligned)
     int bias_off[kMaxHidden];         // floats into the staged biases
 };
 // Samples per workgroup and threads per workgroup of the fused pass for this

@@ -1431,16 +1431,31 @@ void fused_infer_kernel(const FusedArgs a) {
         box_muller(c[0], c[1], eps[0], eps[1]);
         box_muller(c[2], c[3], eps[2], eps[3]);
     }
+    float act4[4], mu4[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         float m = o[q];
 #pragma unroll
         for (int g = 1; g < kFusedMaxAct / 4; ++g) m = kq == g ? o[4 * g + q] : m;
         const int j = 4 * kq + q;
-        if (draws && j < A) {
-            const float ls = s_head[kFusedMaxAct + j];
-            if (a.act_out) a.act_out[static_cast<long long>(n) * A + j] = m + expf(ls) * eps[q];
-            if (a.mu_out) a.mu_out[static_cast<long long>(n) * A + j] = m;
+        mu4[q] = m;
+        act4[q] = m + expf(s_head[kFusedMaxAct + min(j, kFusedMaxAct - 1)]) * eps[q];
+    }
+    if (a.vec_out) {
+        // the lane's group of four actions and means, one 16-byte store each
+        if (draws) {
+            const long long e = static_cast<long long>(n) * A + 4 * kq;
+            if (a.act_out) *reinterpret_cast<float4 *>(a.act_out + e) = make_float4(act4[0], act4[1], act4[2], act4[3]);
+            if (a.mu_out) *reinterpret_cast<float4 *>(a.mu_out + e) = make_float4(mu4[0], mu4[1], mu4[2], mu4[3]);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * kq + q;
+            if (draws && j < A) {
+                if (a.act_out) a.act_out[static_cast<long long>(n) * A + j] = act4[q];
+                if (a.mu_out) a.mu_out[static_cast<long long>(n) * A + j] = mu4[q];
+            }
         }
     }
     // the lead lane sums the log-density over the actions in order

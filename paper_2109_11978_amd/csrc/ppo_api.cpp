@@ -1410,6 +1410,7 @@ int ppo_rollout_infer(const ppo_ctx *c, void *stream, const ppo_params *p, const
         a.t_step = static_cast<uint32_t>(t);
         a.iteration = iteration;
         a.net_mask = (value_only ? 0 : 1) | (values ? 2 : 0);
+        a.vec_out = g.A % 4 == 0 && (!actions || aligned16(actions)) && (!mu || aligned16(mu)) ? 1 : 0;
         a.R = fsh.rows;
         a.NT = fsh.threads;
         PPO_HIP(launch_fused_infer(a, s), "fused inference");
